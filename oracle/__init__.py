@@ -1,0 +1,214 @@
+"""CPU FP64 oracle for the direct speckle-intensity method (arXiv:2204.13241).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  The product path
+(``paper_2204_13241_amd`` and its HIP library) never imports, links or calls
+it, and it shares no code with that path: the arithmetic lives in
+``xs_oracle.c`` (plain C, FP64), written from the paper.
+
+Functions (each cites the passage it follows in ``xs_oracle.c``):
+
+- ``intensity``          Sec. 3.1 Algorithm 1, Eqs. (pe_ri), (Iq_pq); FP64 form
+- ``intensity_libm``     same sum with long-double libm sin/cos (accuracy reference)
+- ``intensity_pairsum``  Sec. 2.1 Eq. (Iq_rij), brute-force pair sum
+- ``intensity_grad``     chain rule through Eqs. (pe_ri), (Iq_pq); FP64 form
+- ``fd_grad``            central differences of sum_p w_p I_p (rank-one updates)
+- ``ring_index``         |q| shells of Sec. 2.3 Eq. (bq_Iq)
+- ``g2_rings``           Sec. 2.3 Eq. (g2_def), ring mean of Sec. 4.2
+- ``xsvs_contrast``      Sec. 2.3 Eqs. (inte_Iq), (bq_Iq), dyadic exposure windows
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-Wall",
+           "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (contraction off, explicit fma only)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, d = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    c_int = ctypes.c_int
+    sig = {
+        "or_max_threads": (i32, []),
+        "or_constants": (None, [P]),
+        "or_sincos_rev_n": (None, [i64, P, P, P]),
+        "or_intensity": (c_int, [i64, P, P, i64, P, P, P, c_int]),
+        "or_intensity_libm": (c_int, [i64, P, P, i64, P, P, P, c_int]),
+        "or_intensity_pairsum": (c_int, [i64, P, P, i64, P, P]),
+        "or_intensity_grad": (c_int, [i64, P, P, i64, P, P, P, P, c_int]),
+        "or_fd_grad": (c_int, [i64, P, P, i64, P, P, i64, P, d, P, c_int]),
+        "or_ring_index": (c_int, [i64, P, i32, P, P]),
+        "or_g2_rings": (c_int, [P, i64, i64, P, P, i32, i32, P, P, c_int]),
+        "or_xsvs_contrast": (c_int, [P, i64, i64, P, P, i32, i32, P, P, c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _f64(a, shape_last=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape_last is not None and (a.ndim == 0 or a.shape[-1] != shape_last):
+        raise ValueError("expected trailing dimension %d, got %s" % (shape_last, a.shape))
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError("oracle %s failed with status %d" % (what, rc))
+
+
+def max_threads() -> int:
+    return int(_load().or_max_threads())
+
+
+def constants():
+    """(RN(1/2pi), RN(2pi), RN(2pi - RN(2pi))) as used by the FP64 form."""
+    out = np.zeros(3)
+    _load().or_constants(_ptr(out))
+    return tuple(float(x) for x in out)
+
+
+def sincos_rev(t):
+    """FP64-form (sin(2 pi t), cos(2 pi t)) for t in revolutions."""
+    t = _f64(np.atleast_1d(t))
+    s = np.empty_like(t)
+    c = np.empty_like(t)
+    _load().or_sincos_rev_n(t.size, _ptr(t), _ptr(s), _ptr(c))
+    return s, c
+
+
+def _intensity(fn, pos, f, q, threads, want_amp=True):
+    pos = _f64(pos, 3).reshape(-1, 3)
+    f = _f64(f).reshape(-1)
+    q = _f64(q, 3).reshape(-1, 3)
+    if f.shape[0] != pos.shape[0]:
+        raise ValueError("f and pos disagree on the atom count")
+    I = np.empty(q.shape[0])
+    amp = np.empty((q.shape[0], 2)) if want_amp else None
+    _check(fn(pos.shape[0], _ptr(pos), _ptr(f), q.shape[0], _ptr(q), _ptr(I), _ptr(amp),
+              int(threads)), fn.__name__)
+    return I, amp
+
+
+def intensity(pos, f, q, threads: int = 0):
+    """FP64 form of the direct method: returns (I [Q], amp [Q, 2]) for one frame."""
+    return _intensity(_load().or_intensity, pos, f, q, threads)
+
+
+def intensity_libm(pos, f, q, threads: int = 0):
+    """Long-double libm reference of the same sum: (I, amp)."""
+    return _intensity(_load().or_intensity_libm, pos, f, q, threads)
+
+
+def intensity_pairsum(pos, f, q):
+    """Brute-force pair double sum, Eq. (Iq_rij): I [Q]."""
+    pos = _f64(pos, 3).reshape(-1, 3)
+    f = _f64(f).reshape(-1)
+    q = _f64(q, 3).reshape(-1, 3)
+    I = np.empty(q.shape[0])
+    _check(_load().or_intensity_pairsum(pos.shape[0], _ptr(pos), _ptr(f), q.shape[0],
+                                        _ptr(q), _ptr(I)), "pairsum")
+    return I
+
+
+def intensity_grad(pos, f, q, amp, dL_dI, threads: int = 0):
+    """FP64-form dL/dr [N, 3] from the amplitude of the same positions and dL/dI [Q]."""
+    pos = _f64(pos, 3).reshape(-1, 3)
+    f = _f64(f).reshape(-1)
+    q = _f64(q, 3).reshape(-1, 3)
+    amp = _f64(amp, 2).reshape(-1, 2)
+    w = _f64(dL_dI).reshape(-1)
+    if amp.shape[0] != q.shape[0] or w.shape[0] != q.shape[0]:
+        raise ValueError("amp / dL_dI do not match the pixel count")
+    out = np.empty_like(pos)
+    _check(_load().or_intensity_grad(pos.shape[0], _ptr(pos), _ptr(f), q.shape[0], _ptr(q),
+                                     _ptr(amp), _ptr(w), _ptr(out), int(threads)), "grad")
+    return out
+
+
+def fd_grad(pos, f, q, dL_dI, atoms, h: float = 1e-4, threads: int = 0):
+    """Central differences of sum_p w_p I_p for the selected atoms: [n_sel, 3]."""
+    pos = _f64(pos, 3).reshape(-1, 3)
+    f = _f64(f).reshape(-1)
+    q = _f64(q, 3).reshape(-1, 3)
+    w = _f64(dL_dI).reshape(-1)
+    atoms = np.ascontiguousarray(atoms, dtype=np.int64).reshape(-1)
+    out = np.empty((atoms.shape[0], 3))
+    _check(_load().or_fd_grad(pos.shape[0], _ptr(pos), _ptr(f), q.shape[0], _ptr(q), _ptr(w),
+                              atoms.shape[0], _ptr(atoms), float(h), _ptr(out), int(threads)),
+           "fd_grad")
+    return out
+
+
+def ring_index(q, edges):
+    """Ring of each pixel (-1 outside [e_0, e_R))."""
+    q = _f64(q, 3).reshape(-1, 3)
+    edges = _f64(edges).reshape(-1)
+    ring = np.empty(q.shape[0], dtype=np.int32)
+    _check(_load().or_ring_index(q.shape[0], _ptr(q), edges.shape[0] - 1, _ptr(edges),
+                                 _ptr(ring)), "ring_index")
+    return ring
+
+
+def g2_rings(I, q, edges, n_tau: int, threads: int = 0):
+    """g2 [n_rings, n_tau] and pixel counts [n_rings] from I [F, Q]."""
+    I = _f64(I)
+    if I.ndim != 2:
+        raise ValueError("I must be [frames, pixels]")
+    q = _f64(q, 3).reshape(-1, 3)
+    edges = _f64(edges).reshape(-1)
+    nr = edges.shape[0] - 1
+    g2 = np.empty((nr, n_tau))
+    cnt = np.empty(nr, dtype=np.int32)
+    _check(_load().or_g2_rings(_ptr(I), I.shape[0], I.shape[1], _ptr(q), _ptr(edges), nr,
+                               int(n_tau), _ptr(g2), _ptr(cnt), int(threads)), "g2_rings")
+    return g2, cnt
+
+
+def xsvs_contrast(I, q, edges, n_levels: int, threads: int = 0, want_windows: bool = False):
+    """beta [n_levels, n_rings] (and per-window [n_levels, F, n_rings] if asked)."""
+    I = _f64(I)
+    if I.ndim != 2:
+        raise ValueError("I must be [frames, pixels]")
+    q = _f64(q, 3).reshape(-1, 3)
+    edges = _f64(edges).reshape(-1)
+    nr = edges.shape[0] - 1
+    beta = np.empty((n_levels, nr))
+    win = np.empty((n_levels, I.shape[0], nr)) if want_windows else None
+    _check(_load().or_xsvs_contrast(_ptr(I), I.shape[0], I.shape[1], _ptr(q), _ptr(edges), nr,
+                                    int(n_levels), _ptr(beta), _ptr(win), int(threads)),
+           "xsvs_contrast")
+    return (beta, win) if want_windows else beta

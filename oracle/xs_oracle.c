@@ -1,0 +1,482 @@
+/*
+ * xs_oracle.c -- CPU FP64 oracle for the direct speckle-intensity method.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+ * its Python binding) may include, link, load or call this file; only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark do.  It
+ * shares no code, header or constant with the GPU library: every formula here
+ * is written out again from the paper (Mohanty, Cooper, Wang, Liang, Cai,
+ * "Computational approaches to model X-ray photon correlation spectroscopy
+ * from molecular dynamics", arXiv:2204.13241).
+ *
+ * Conventions (paper notation):
+ *   - positions r_j: double [N][3] (Angstrom), used verbatim (no wrapping).
+ *   - form factors f_j: double [N], q-independent per atom.
+ *   - wavevectors q: double [Q][3] (1/Angstrom).
+ *   - scattering amplitude, Sec. 2.2 Eq. (pe_ri):
+ *         p^e(q) = sum_j f_j exp(-i q.r_j) = a + i b,
+ *     stored as amp[p][0] = a, amp[p][1] = b.
+ *   - intensity, Sec. 2.2 Eq. (Iq_pq): I(q) = |p^e(q)|^2.
+ *
+ * The "FP64 form" below fixes one exact operation sequence for the direct
+ * method of Sec. 3.1 (Algorithm 1): it is the definition of Eq. (pe_ri) and
+ * Eq. (Iq_pq) with the phase kept in revolutions and a sine/cosine built from
+ * the Taylor series of sin and cos (coefficients (-1)^k/(2k+1)! and
+ * (-1)^k/(2k)!) after an exact reduction to |angle| <= pi/4.  The GPU FP64
+ * path implements the same sequence independently, so the two agree bit for
+ * bit.  The libm and pair-sum variants are independent accuracy references.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC
+ * (contraction off so that every fused multiply-add is an explicit fma()).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_EINVAL 1
+#define OR_ENOMEM 2
+
+/* RN(1/(2 pi)), RN(2 pi), RN(2 pi - RN(2 pi)). */
+static const double OR_INV2PI = 0x1.45f306dc9c883p-3;
+static const double OR_TWOPI_HI = 0x1.921fb54442d18p+2;
+static const double OR_TWOPI_LO = 0x1.1a62633145c07p-52;
+
+/* Taylor coefficients RN((-1)^k/(2k+1)!) for sin (k = 1..7) and
+ * RN((-1)^k/(2k)!) for cos (k = 1..8): each is one correctly rounded
+ * division of exactly representable integers. */
+static const double OR_S1 = -1.0 / 6.0;
+static const double OR_S2 = 1.0 / 120.0;
+static const double OR_S3 = -1.0 / 5040.0;
+static const double OR_S4 = 1.0 / 362880.0;
+static const double OR_S5 = -1.0 / 39916800.0;
+static const double OR_S6 = 1.0 / 6227020800.0;
+static const double OR_S7 = -1.0 / 1307674368000.0;
+static const double OR_C1 = -1.0 / 2.0;
+static const double OR_C2 = 1.0 / 24.0;
+static const double OR_C3 = -1.0 / 720.0;
+static const double OR_C4 = 1.0 / 40320.0;
+static const double OR_C5 = -1.0 / 3628800.0;
+static const double OR_C6 = 1.0 / 479001600.0;
+static const double OR_C7 = -1.0 / 87178291200.0;
+static const double OR_C8 = 1.0 / 20922789888000.0;
+
+static int or_threads(int n_threads)
+{
+#ifdef _OPENMP
+    return n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+    (void)n_threads;
+    return 1;
+#endif
+}
+
+int32_t or_max_threads(void) { return or_threads(0); }
+
+void or_constants(double *out)
+{
+    out[0] = OR_INV2PI;
+    out[1] = OR_TWOPI_HI;
+    out[2] = OR_TWOPI_LO;
+}
+
+/*
+ * sin(2 pi t) and cos(2 pi t) for t in revolutions (the FP64 form).
+ *   n = rint(t), u = t - n            exact, |u| <= 1/2
+ *   m = rint(4u), v = u - m/4          exact (Sterbenz), |v| <= 1/8
+ *   x = 2 pi v (two-term constant), z = x^2
+ *   s = x + x z P_s(z), c = 1 + z P_c(z)   Taylor series, Horner with fma
+ *   quadrant m mod 4 rotates (s, c) by m quarter turns.
+ */
+void or_sincos_rev(double t, double *sin_out, double *cos_out)
+{
+    double n = rint(t);
+    double u = t - n;
+    double mq = rint(4.0 * u);
+    double v = u - mq * 0.25;
+    double x = fma(OR_TWOPI_HI, v, OR_TWOPI_LO * v);
+    double z = x * x;
+    double ps = fma(z, OR_S7, OR_S6);
+    ps = fma(z, ps, OR_S5);
+    ps = fma(z, ps, OR_S4);
+    ps = fma(z, ps, OR_S3);
+    ps = fma(z, ps, OR_S2);
+    ps = fma(z, ps, OR_S1);
+    double s = fma(x * z, ps, x);
+    double pc = fma(z, OR_C8, OR_C7);
+    pc = fma(z, pc, OR_C6);
+    pc = fma(z, pc, OR_C5);
+    pc = fma(z, pc, OR_C4);
+    pc = fma(z, pc, OR_C3);
+    pc = fma(z, pc, OR_C2);
+    pc = fma(z, pc, OR_C1);
+    double c = fma(z, pc, 1.0);
+    int quadrant = ((int)mq) & 3;
+    switch (quadrant) {
+    case 0: *sin_out = s;  *cos_out = c;  break;
+    case 1: *sin_out = c;  *cos_out = -s; break;
+    case 2: *sin_out = -s; *cos_out = -c; break;
+    default: *sin_out = -c; *cos_out = s; break;
+    }
+}
+
+void or_sincos_rev_n(int64_t n, const double *t, double *s, double *c)
+{
+    for (int64_t i = 0; i < n; ++i) or_sincos_rev(t[i], &s[i], &c[i]);
+}
+
+/* Phase of atom r under wavevector q, in revolutions: q.r / (2 pi). */
+static inline double or_phase_rev(const double *qrev, const double *r)
+{
+    return fma(qrev[2], r[2], fma(qrev[1], r[1], qrev[0] * r[0]));
+}
+
+/*
+ * Direct method (Sec. 3.1, Algorithm 1; Eqs. (pe_ri), (Iq_pq)), FP64 form.
+ * For every pixel p, atoms are summed in input order starting from +0.0:
+ *   ac += f_j cos(q.r_j), as += f_j sin(q.r_j)   (fma)
+ *   a = ac, b = -as  (the amplitude carries exp(-i q.r)),  I = a*a + b*b.
+ * amp may be NULL.
+ */
+int or_intensity(int64_t n_atoms, const double *pos, const double *f,
+                 int64_t n_q, const double *q, double *I, double *amp,
+                 int n_threads)
+{
+    if (n_atoms < 0 || n_q < 0 || (n_q > 0 && (!q || !I)) ||
+        (n_atoms > 0 && (!pos || !f)))
+        return OR_EINVAL;
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t p = 0; p < n_q; ++p) {
+        double qrev[3];
+        for (int k = 0; k < 3; ++k) qrev[k] = q[3 * p + k] * OR_INV2PI;
+        double ac = 0.0, as = 0.0;
+        for (int64_t j = 0; j < n_atoms; ++j) {
+            double s, c;
+            or_sincos_rev(or_phase_rev(qrev, pos + 3 * j), &s, &c);
+            ac = fma(f[j], c, ac);
+            as = fma(f[j], s, as);
+        }
+        double a = ac, b = -as;
+        I[p] = fma(a, a, b * b);
+        if (amp) { amp[2 * p] = a; amp[2 * p + 1] = b; }
+    }
+    return OR_OK;
+}
+
+/*
+ * Same sum with the C library's long-double sine and cosine of the phase in
+ * radians: an independent accuracy reference for the FP64 form.
+ */
+int or_intensity_libm(int64_t n_atoms, const double *pos, const double *f,
+                      int64_t n_q, const double *q, double *I, double *amp,
+                      int n_threads)
+{
+    if (n_atoms < 0 || n_q < 0) return OR_EINVAL;
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t p = 0; p < n_q; ++p) {
+        long double ac = 0.0L, as = 0.0L;
+        for (int64_t j = 0; j < n_atoms; ++j) {
+            long double ph = (long double)q[3 * p] * pos[3 * j] +
+                             (long double)q[3 * p + 1] * pos[3 * j + 1] +
+                             (long double)q[3 * p + 2] * pos[3 * j + 2];
+            ac += f[j] * cosl(ph);
+            as += f[j] * sinl(ph);
+        }
+        double a = (double)ac, b = (double)(-as);
+        I[p] = (double)(ac * ac + as * as);
+        if (amp) { amp[2 * p] = a; amp[2 * p + 1] = b; }
+    }
+    return OR_OK;
+}
+
+/*
+ * Pair double sum, Sec. 2.1 Eq. (Iq_rij):
+ *   I(q) = sum_i sum_j f_i f_j exp(-i q.(r_i - r_j)) = sum_i sum_j f_i f_j cos(q.(r_i - r_j)),
+ * the sine terms cancelling pairwise.  O(N^2) per pixel: brute force for small N.
+ */
+int or_intensity_pairsum(int64_t n_atoms, const double *pos, const double *f,
+                         int64_t n_q, const double *q, double *I)
+{
+    if (n_atoms < 0 || n_q < 0) return OR_EINVAL;
+    for (int64_t p = 0; p < n_q; ++p) {
+        long double acc = 0.0L;
+        for (int64_t i = 0; i < n_atoms; ++i)
+            for (int64_t j = 0; j < n_atoms; ++j) {
+                long double ph = 0.0L;
+                for (int k = 0; k < 3; ++k)
+                    ph += (long double)q[3 * p + k] *
+                          ((long double)pos[3 * i + k] - (long double)pos[3 * j + k]);
+                acc += (long double)f[i] * f[j] * cosl(ph);
+            }
+        I[p] = (double)acc;
+    }
+    return OR_OK;
+}
+
+/*
+ * Gradient of a functional of the intensities with respect to the positions
+ * (the chain rule through Eqs. (pe_ri) and (Iq_pq)).  Given w_p = dL/dI_p and
+ * the amplitude a_p + i b_p of the same positions:
+ *   dI_p/dr_j = -2 f_j q_p (a_p sin(q_p.r_j) + b_p cos(q_p.r_j)),
+ *   dL/dr_j   = sum_p w_p dI_p/dr_j.
+ * FP64 form: per atom, pixels in input order from +0.0;
+ *   h = fma(a, s, b*c); k = w*h; g += k*q (fma per component);
+ *   dL/dr_j = (-2 f_j) * g.
+ */
+int or_intensity_grad(int64_t n_atoms, const double *pos, const double *f,
+                      int64_t n_q, const double *q, const double *amp,
+                      const double *dL_dI, double *dL_dr, int n_threads)
+{
+    if (n_atoms < 0 || n_q < 0 || (n_atoms > 0 && (!pos || !f || !dL_dr)) ||
+        (n_q > 0 && (!q || !amp || !dL_dI)))
+        return OR_EINVAL;
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t j = 0; j < n_atoms; ++j) {
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int64_t p = 0; p < n_q; ++p) {
+            double qrev[3];
+            for (int k = 0; k < 3; ++k) qrev[k] = q[3 * p + k] * OR_INV2PI;
+            double s, c;
+            or_sincos_rev(or_phase_rev(qrev, pos + 3 * j), &s, &c);
+            double h = fma(amp[2 * p], s, amp[2 * p + 1] * c);
+            double k = dL_dI[p] * h;
+            gx = fma(k, q[3 * p], gx);
+            gy = fma(k, q[3 * p + 1], gy);
+            gz = fma(k, q[3 * p + 2], gz);
+        }
+        double m = -2.0 * f[j];
+        dL_dr[3 * j] = m * gx;
+        dL_dr[3 * j + 1] = m * gy;
+        dL_dr[3 * j + 2] = m * gz;
+    }
+    return OR_OK;
+}
+
+/* Kahan-Babuska (Neumaier) compensated sum step in long double. */
+static inline void or_nsum(long double *sum, long double *comp, long double x)
+{
+    long double t = *sum + x;
+    if (fabsl(*sum) >= fabsl(x)) *comp += (*sum - t) + x;
+    else *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+/*
+ * Central finite differences of L(r) = sum_p w_p I_p(r) for selected atoms:
+ *   dL/dr_{j,c} ~ (L(r + h e_{jc}) - L(r - h e_{jc})) / (2h).
+ * Displacing one atom changes the amplitude by a rank-one term,
+ *   p'(q) = p(q) + f_j (exp(-i q.r_j') - exp(-i q.r_j)),
+ * so each evaluation costs O(Q); the difference of the two sums is formed
+ * term by term, sum_p w_p (I+ - I-), with a compensated long-double sum.
+ * Sines and cosines come from the C library (independent of the FP64 form).
+ * out: [n_sel][3].
+ */
+int or_fd_grad(int64_t n_atoms, const double *pos, const double *f,
+               int64_t n_q, const double *q, const double *dL_dI,
+               int64_t n_sel, const int64_t *atoms, double h, double *out,
+               int n_threads)
+{
+    if (n_atoms <= 0 || n_q < 0 || n_sel < 0 || !(h > 0.0)) return OR_EINVAL;
+    for (int64_t s = 0; s < n_sel; ++s)
+        if (atoms[s] < 0 || atoms[s] >= n_atoms) return OR_EINVAL;
+    long double *ar = malloc(sizeof(long double) * (size_t)(n_q > 0 ? n_q : 1));
+    long double *ai = malloc(sizeof(long double) * (size_t)(n_q > 0 ? n_q : 1));
+    if (!ar || !ai) { free(ar); free(ai); return OR_ENOMEM; }
+    /* Amplitude of the unperturbed positions, long double. */
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t p = 0; p < n_q; ++p) {
+        long double sr = 0.0L, si = 0.0L;
+        for (int64_t j = 0; j < n_atoms; ++j) {
+            long double ph = (long double)q[3 * p] * pos[3 * j] +
+                             (long double)q[3 * p + 1] * pos[3 * j + 1] +
+                             (long double)q[3 * p + 2] * pos[3 * j + 2];
+            sr += f[j] * cosl(ph);
+            si -= f[j] * sinl(ph);
+        }
+        ar[p] = sr; ai[p] = si;
+    }
+    for (int64_t s = 0; s < n_sel; ++s) {
+        int64_t j = atoms[s];
+        for (int c = 0; c < 3; ++c) {
+            long double sum = 0.0L, comp = 0.0L;
+#pragma omp parallel num_threads(or_threads(n_threads))
+            {
+                long double lsum = 0.0L, lcomp = 0.0L;
+#pragma omp for schedule(static)
+                for (int64_t p = 0; p < n_q; ++p) {
+                    long double r0[3] = {pos[3 * j], pos[3 * j + 1], pos[3 * j + 2]};
+                    long double ph0 = q[3 * p] * r0[0] + q[3 * p + 1] * r0[1] + q[3 * p + 2] * r0[2];
+                    long double dph = (long double)q[3 * p + c] * h;
+                    long double php = ph0 + dph, phm = ph0 - dph;
+                    /* p(r +/- h e) = p(r) + f_j (exp(-i ph+-) - exp(-i ph0)) */
+                    long double br = ar[p] - f[j] * cosl(ph0);
+                    long double bi = ai[p] + f[j] * sinl(ph0);
+                    long double pr = br + f[j] * cosl(php), pi = bi - f[j] * sinl(php);
+                    long double mr = br + f[j] * cosl(phm), mi = bi - f[j] * sinl(phm);
+                    long double Ip = pr * pr + pi * pi, Im = mr * mr + mi * mi;
+                    or_nsum(&lsum, &lcomp, (long double)dL_dI[p] * (Ip - Im));
+                }
+#pragma omp critical
+                {
+                    or_nsum(&sum, &comp, lsum);
+                    or_nsum(&sum, &comp, lcomp);
+                }
+            }
+            out[3 * s + c] = (double)((sum + comp) / (2.0L * h));
+        }
+    }
+    free(ar); free(ai);
+    return OR_OK;
+}
+
+/*
+ * |q| ring of every pixel: ring r holds e_r <= |q| < e_{r+1} (the half-open
+ * shell q - dq/2 <= |q| < q + dq/2 of Sec. 2.3, Eq. (bq_Iq)); pixels outside
+ * [e_0, e_R) get -1.  |q| = sqrt(fma(qz, qz, fma(qy, qy, qx*qx))).
+ */
+int or_ring_index(int64_t n_q, const double *q, int32_t n_rings,
+                  const double *edges, int32_t *ring)
+{
+    if (n_q < 0 || n_rings <= 0 || !edges || (n_q > 0 && (!q || !ring))) return OR_EINVAL;
+    for (int32_t r = 0; r < n_rings; ++r)
+        if (!(edges[r] < edges[r + 1])) return OR_EINVAL;
+    for (int64_t p = 0; p < n_q; ++p) {
+        double qx = q[3 * p], qy = q[3 * p + 1], qz = q[3 * p + 2];
+        double qn = sqrt(fma(qz, qz, fma(qy, qy, qx * qx)));
+        int32_t idx = -1;
+        for (int32_t r = 0; r < n_rings; ++r)
+            if (edges[r] <= qn && qn < edges[r + 1]) { idx = r; break; }
+        ring[p] = idx;
+    }
+    return OR_OK;
+}
+
+/*
+ * Intensity autocorrelation on |q| rings, Sec. 2.3 Eq. (g2_def) with the
+ * ring average of Sec. 4.2:
+ *   per pixel  G_p(tau) = [ sum_{t < F-tau} I_t I_{t+tau} / (F - tau) ] / <I>_t^2,
+ *              <I>_t = sum_t I_t / F   (all F frames),
+ *   per ring   g2(r, tau) = mean of G_p(tau) over the ring's pixels.
+ * I: [F][Q] (pixel fastest).  Pixels whose <I>_t^2 is zero are left out and
+ * not counted.  Fixed order: time sums sequential in t (products by fma),
+ * ring sums sequential in ascending pixel index.  Empty rings give NaN.
+ * g2: [n_rings][n_tau]; count (may be NULL): [n_rings].
+ */
+int or_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                const double *edges, int32_t n_rings, int32_t n_tau,
+                double *g2, int32_t *count, int n_threads)
+{
+    if (n_frames <= 0 || n_q < 0 || n_rings <= 0 || n_tau <= 0 || n_tau > n_frames ||
+        !g2)
+        return OR_EINVAL;
+    int32_t *ring = malloc(sizeof(int32_t) * (size_t)(n_q > 0 ? n_q : 1));
+    double *G = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1) * (size_t)n_tau);
+    unsigned char *used = malloc((size_t)(n_q > 0 ? n_q : 1));
+    if (!ring || !G || !used) { free(ring); free(G); free(used); return OR_ENOMEM; }
+    int rc = or_ring_index(n_q, q, n_rings, edges, ring);
+    if (rc != OR_OK) { free(ring); free(G); free(used); return rc; }
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t p = 0; p < n_q; ++p) {
+        double S = 0.0;
+        for (int64_t t = 0; t < n_frames; ++t) S = S + I[t * n_q + p];
+        double mean = S / (double)n_frames;
+        double den = mean * mean;
+        used[p] = (den != 0.0);
+        for (int32_t tau = 0; tau < n_tau; ++tau) {
+            double acc = 0.0;
+            for (int64_t t = 0; t + tau < n_frames; ++t)
+                acc = fma(I[t * n_q + p], I[(t + tau) * n_q + p], acc);
+            G[p * n_tau + tau] = (acc / (double)(n_frames - tau)) / den;
+        }
+    }
+    for (int32_t r = 0; r < n_rings; ++r) {
+        int32_t cnt = 0;
+        for (int64_t p = 0; p < n_q; ++p) if (ring[p] == r && used[p]) ++cnt;
+        if (count) count[r] = cnt;
+        for (int32_t tau = 0; tau < n_tau; ++tau) {
+            double sum = 0.0;
+            for (int64_t p = 0; p < n_q; ++p)
+                if (ring[p] == r && used[p]) sum = sum + G[p * n_tau + tau];
+            g2[(int64_t)r * n_tau + tau] = cnt > 0 ? sum / (double)cnt : NAN;
+        }
+    }
+    free(ring); free(G); free(used);
+    return OR_OK;
+}
+
+/*
+ * XSVS contrast versus exposure, Sec. 2.3 Eqs. (inte_Iq), (bq_Iq):
+ *   exposure integral over W = 2^l frames as non-overlapping windows from
+ *   frame 0 (trailing partial window dropped), built pairwise:
+ *       J_0[k] = I_k,   J_{l+1}[k] = J_l[2k] + J_l[2k+1],  K_l = floor(F / 2^l);
+ *   per (level l, window k, ring r) over the ring's pixels in ascending order:
+ *       mu = sum J / n,  var = sum (J - mu)^2 / n  (two-pass; fma),
+ *       beta = var / mu^2;
+ *   beta_out[l][r] = sum_k beta / K_l  (sequential in k).
+ * I: [F][Q].  beta_out: [n_levels][n_rings].  beta_win (may be NULL):
+ * [n_levels][F][n_rings], entries k >= K_l set to NaN.  Empty rings: NaN.
+ */
+int or_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                     const double *edges, int32_t n_rings, int32_t n_levels,
+                     double *beta_out, double *beta_win, int n_threads)
+{
+    if (n_frames <= 0 || n_q < 0 || n_rings <= 0 || n_levels <= 0 || n_levels > 62 ||
+        ((int64_t)1 << (n_levels - 1)) > n_frames || !beta_out)
+        return OR_EINVAL;
+    int32_t *ring = malloc(sizeof(int32_t) * (size_t)(n_q > 0 ? n_q : 1));
+    double *J = malloc(sizeof(double) * (size_t)n_frames * (size_t)(n_q > 0 ? n_q : 1));
+    if (!ring || !J) { free(ring); free(J); return OR_ENOMEM; }
+    int rc = or_ring_index(n_q, q, n_rings, edges, ring);
+    if (rc != OR_OK) { free(ring); free(J); return rc; }
+    memcpy(J, I, sizeof(double) * (size_t)n_frames * (size_t)n_q);
+    int32_t *cnt = calloc((size_t)n_rings, sizeof(int32_t));
+    if (!cnt) { free(ring); free(J); return OR_ENOMEM; }
+    for (int64_t p = 0; p < n_q; ++p) if (ring[p] >= 0) cnt[ring[p]]++;
+    if (beta_win)
+        for (int64_t i = 0; i < (int64_t)n_levels * n_frames * n_rings; ++i) beta_win[i] = NAN;
+    int64_t K = n_frames;
+    for (int32_t l = 0; l < n_levels; ++l) {
+        if (l > 0) {
+            int64_t Kn = K / 2;
+            for (int64_t k = 0; k < Kn; ++k)
+                for (int64_t p = 0; p < n_q; ++p)
+                    J[k * n_q + p] = J[(2 * k) * n_q + p] + J[(2 * k + 1) * n_q + p];
+            K = Kn;
+        }
+        double *bw = malloc(sizeof(double) * (size_t)K * (size_t)n_rings);
+        if (!bw) { free(ring); free(J); free(cnt); return OR_ENOMEM; }
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+        for (int64_t k = 0; k < K; ++k) {
+            for (int32_t r = 0; r < n_rings; ++r) {
+                double b = NAN;
+                if (cnt[r] > 0) {
+                    double s = 0.0;
+                    for (int64_t p = 0; p < n_q; ++p)
+                        if (ring[p] == r) s = s + J[k * n_q + p];
+                    double mu = s / (double)cnt[r];
+                    double v = 0.0;
+                    for (int64_t p = 0; p < n_q; ++p)
+                        if (ring[p] == r) { double d = J[k * n_q + p] - mu; v = fma(d, d, v); }
+                    double var = v / (double)cnt[r];
+                    b = var / (mu * mu);
+                }
+                bw[k * n_rings + r] = b;
+            }
+        }
+        for (int32_t r = 0; r < n_rings; ++r) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < K; ++k) acc = acc + bw[k * n_rings + r];
+            beta_out[(int64_t)l * n_rings + r] = cnt[r] > 0 ? acc / (double)K : NAN;
+            if (beta_win)
+                for (int64_t k = 0; k < K; ++k)
+                    beta_win[((int64_t)l * n_frames + k) * n_rings + r] = bw[k * n_rings + r];
+        }
+        free(bw);
+    }
+    free(ring); free(J); free(cnt);
+    return OR_OK;
+}

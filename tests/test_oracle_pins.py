@@ -1,0 +1,345 @@
+"""Pins of the CPU oracle to facts outside itself (CPU only).
+
+Each test checks the oracle against something the oracle does not compute:
+mpmath at 200 bits, closed forms of the paper's definitions (Sec. 2.1-2.2),
+brute-force pair sums, lattice sums, symmetries, and statistical laws.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+mp.mp.prec = 200
+
+
+def scaled_err(I, I_ref, f):
+    """max |I - I_ref| / max(I_ref, sum f^2): the error scale used for intensities."""
+    inc = float(np.sum(np.asarray(f) ** 2))
+    return float(np.max(np.abs(I - I_ref) / np.maximum(I_ref, inc)))
+
+
+# ---------------------------------------------------------------- constants, sincos
+
+def test_constants_are_correctly_rounded():
+    inv2pi, hi, lo = oracle.constants()
+    twopi = 2 * mp.pi
+    assert inv2pi == float(1 / twopi)
+    assert hi == float(twopi)
+    assert lo == float(twopi - mp.mpf(hi))
+
+
+def _sincos_points():
+    rng = np.random.default_rng(7)
+    pts = [0.0, 1e-300, -1e-300, 1e-12, 0.125, -0.125, 0.25, 0.375, 0.5, -0.5, 0.625, 0.875,
+           1.0 / 3.0, 0.1, 0.2, 0.3, 0.7, 130.1, -129.77, 1000.0 + 1.0 / 8.0]
+    pts += list(rng.uniform(-0.5, 0.5, 600))
+    pts += list(rng.uniform(-200, 200, 600))
+    pts += list(np.nextafter(0.125, 1.0) * np.array([1, -1]))
+    pts += list(np.nextafter(0.375, 0.0) * np.array([1, -1]))
+    return np.array(pts, dtype=np.float64)
+
+
+def test_sincos_rev_against_mpmath():
+    t = _sincos_points()
+    s, c = oracle.sincos_rev(t)
+    worst = 0.0
+    for ti, si, ci in zip(t, s, c):
+        ang = 2 * mp.pi * mp.mpf(float(ti))
+        for got, ref in ((si, mp.sin(ang)), (ci, mp.cos(ang))):
+            ref_f = float(ref)
+            err = abs(mp.mpf(float(got)) - ref)
+            # ulps of the true value; an absolute floor of 2^-55 covers values near 0
+            ulp = max(math.ulp(abs(ref_f)) if ref_f != 0 else 0.0, 2.0 ** -55)
+            worst = max(worst, float(err / ulp))
+    assert worst <= 2.0, worst
+
+
+def test_sincos_rev_exact_points_and_symmetry():
+    s, c = oracle.sincos_rev([0.0, 0.25, 0.5, 0.75, -0.25, 1.0, 2.0])
+    assert list(s) == [0.0, 1.0, 0.0, -1.0, -1.0, 0.0, 0.0]
+    assert [abs(x) for x in c] == [1.0, 0.0, 1.0, 0.0, 0.0, 1.0, 1.0]
+    t = _sincos_points()
+    s1, c1 = oracle.sincos_rev(t)
+    s2, c2 = oracle.sincos_rev(-t)
+    assert np.array_equal(s1, -s2) and np.array_equal(c1, c2)
+    # period one revolution, bit for bit, where t + 1 is exact
+    tt = np.linspace(-0.49, 0.49, 99)
+    s3, c3 = oracle.sincos_rev(tt + 4.0)
+    s4, c4 = oracle.sincos_rev(tt)
+    exact = (tt + 4.0) - 4.0 == tt
+    assert np.array_equal(s3[exact], s4[exact]) and np.array_equal(c3[exact], c4[exact])
+
+
+# ---------------------------------------------------------------- intensity closed forms
+
+def test_single_atom_gives_f_squared_and_amplitude_sign():
+    rng = np.random.default_rng(1)
+    q = rng.uniform(-3, 3, (500, 3))
+    r = np.array([[3.7, -12.25, 40.1]])
+    I, amp = oracle.intensity(r, [2.5], q)
+    assert np.max(np.abs(I - 6.25)) <= 4 * math.ulp(6.25)
+    # amplitude carries exp(-i q.r): a = f cos(q.r), b = -f sin(q.r)
+    ph = q @ r[0]
+    assert np.allclose(amp[:, 0], 2.5 * np.cos(ph), rtol=0, atol=1e-12)
+    assert np.allclose(amp[:, 1], -2.5 * np.sin(ph), rtol=0, atol=1e-12)
+
+
+def test_q_zero_gives_total_form_factor_squared_exactly():
+    rng = np.random.default_rng(2)
+    pos = rng.uniform(0, 50, (777, 3))
+    f = np.where(rng.random(777) < 0.2, 2.5, 1.0)
+    I, amp = oracle.intensity(pos, f, np.zeros((3, 3)))
+    assert np.all(I == f.sum() ** 2)
+    assert np.all(amp[:, 1] == 0.0)
+
+
+def test_two_atoms_closed_form():
+    rng = np.random.default_rng(3)
+    q = rng.uniform(-4, 4, (200, 3))
+    pos = np.array([[1.0, 2.0, 3.0], [7.5, -4.25, 11.0]])
+    f = np.array([1.0, 2.5])
+    I, _ = oracle.intensity(pos, f, q)
+    for p in range(q.shape[0]):
+        ph = sum(mp.mpf(q[p, k]) * (mp.mpf(pos[0, k]) - mp.mpf(pos[1, k])) for k in range(3))
+        ref = f[0] ** 2 + f[1] ** 2 + 2 * f[0] * f[1] * mp.cos(ph)
+        assert abs(I[p] - float(ref)) <= 1e-14 * (f ** 2).sum()
+
+
+def test_simple_cubic_laue_function_and_bragg_peaks():
+    n, a = 5, 3.1
+    pos = X.simple_cubic(n, a)
+    rng = np.random.default_rng(4)
+    q = rng.uniform(-2, 2, (60, 3))
+    I, _ = oracle.intensity(pos, np.ones(len(pos)), q)
+    for p in range(q.shape[0]):
+        ref = mp.mpf(1)
+        for k in range(3):
+            x = mp.mpf(q[p, k]) * a / 2
+            ref *= (mp.sin(n * x) / mp.sin(x)) ** 2
+        assert abs(I[p] - float(ref)) <= 1e-12 * max(float(ref), len(pos))
+    hkl = np.array([[1, 0, 0], [0, 2, -1], [3, 1, 2], [-2, -2, 1]], dtype=float)
+    I2, _ = oracle.intensity(pos, np.ones(len(pos)), hkl * 2 * math.pi / a)
+    assert np.allclose(I2, len(pos) ** 2, rtol=1e-12, atol=0)
+
+
+def test_fcc_structure_factor_selection_rule():
+    nc, a = 4, 5.75
+    pos = X.fcc_lattice(nc, a)
+    N = len(pos)
+    allowed = np.array([[1, 1, 1], [2, 0, 0], [2, 2, 0], [3, 1, 1], [-1, 1, -1]], float)
+    forbidden = np.array([[1, 0, 0], [1, 1, 0], [2, 1, 0], [3, 2, 1]], float)
+    Ia, _ = oracle.intensity(pos, np.ones(N), allowed * 2 * math.pi / a)
+    If, _ = oracle.intensity(pos, np.ones(N), forbidden * 2 * math.pi / a)
+    assert np.allclose(Ia, N ** 2, rtol=1e-12, atol=0)
+    assert np.all(If <= 1e-12 * N ** 2)
+    # general q: Laue function of the cubic cells times the four-site basis factor
+    rng = np.random.default_rng(5)
+    q = rng.uniform(-1.5, 1.5, (20, 3))
+    I, _ = oracle.intensity(pos, np.ones(N), q)
+    basis = [(0, 0, 0), (0, .5, .5), (.5, 0, .5), (.5, .5, 0)]
+    for p in range(q.shape[0]):
+        laue = mp.mpf(1)
+        for k in range(3):
+            x = mp.mpf(q[p, k]) * a / 2
+            laue *= (mp.sin(nc * x) / mp.sin(x)) ** 2
+        bf = sum(mp.expj(-sum(mp.mpf(q[p, k]) * a * b[k] for k in range(3))) for b in basis)
+        ref = laue * abs(bf) ** 2
+        assert abs(I[p] - float(ref)) <= 1e-12 * max(float(ref), N)
+
+
+def test_friedel_pairs_bitwise():
+    w = X.workload_plain(n_atoms=300, n_det=16)
+    q = w.q[0]
+    I1, a1 = oracle.intensity(w.positions[0][0], w.f[0], q)
+    I2, a2 = oracle.intensity(w.positions[0][0], w.f[0], -q)
+    assert np.array_equal(I1, I2)
+    assert np.array_equal(a1[:, 0], a2[:, 0]) and np.array_equal(a1[:, 1], -a2[:, 1])
+
+
+def test_translation_and_permutation_invariance():
+    rng = np.random.default_rng(6)
+    L = 20.0
+    pos = rng.uniform(0, L, (200, 3))
+    f = np.where(rng.random(200) < 0.3, 2.5, 1.0)
+    q_lat = X.reciprocal_grid(L, 3)[:200]
+    q_any = rng.uniform(-3, 3, (100, 3))
+    I0, _ = oracle.intensity(pos, f, q_lat)
+    # periodic images: shift one atom by a box vector; exact at reciprocal-lattice q
+    pos2 = pos.copy()
+    pos2[17] += np.array([L, -L, 2 * L])
+    I1, _ = oracle.intensity(pos2, f, q_lat)
+    assert scaled_err(I1, I0, f) <= 1e-12
+    # rigid translation (unwrapped) at arbitrary q
+    Ia, _ = oracle.intensity(pos, f, q_any)
+    Ib, _ = oracle.intensity(pos + np.array([3.3, -1.7, 8.25]), f, q_any)
+    assert scaled_err(Ib, Ia, f) <= 1e-12
+    perm = rng.permutation(200)
+    Ic, _ = oracle.intensity(pos[perm], f[perm], q_any)
+    assert scaled_err(Ic, Ia, f) <= 1e-13
+
+
+def test_pairsum_brute_force_small_n():
+    rng = np.random.default_rng(8)
+    for n in (1, 2, 7, 64):
+        pos = rng.uniform(0, 15, (n, 3))
+        f = rng.choice([1.0, 2.5], n)
+        q = rng.uniform(-4, 4, (40, 3))
+        I, _ = oracle.intensity(pos, f, q)
+        Ip = oracle.intensity_pairsum(pos, f, q)
+        assert scaled_err(I, Ip, f) <= 1e-13
+
+
+def test_fp64_form_against_long_double_libm():
+    w = X.workload_plain(n_atoms=1000, n_det=32)
+    pos, f, q = w.positions[0][0], w.f[0], w.q[0]
+    I, amp = oracle.intensity(pos, f, q)
+    Il, ampl = oracle.intensity_libm(pos, f, q)
+    # phases here reach |q.r| ~ 4*36*sqrt(2) rad; FP64 phase rounding bounds the gap
+    assert scaled_err(I, Il, f) <= 1e-13
+    assert np.max(np.abs(amp - ampl)) <= 1e-12 * math.sqrt(f.size)
+
+
+def test_uniform_ensemble_mean_at_reciprocal_lattice_vectors():
+    # E[I(q)] = sum f^2 at nonzero reciprocal-lattice q for positions uniform in the box
+    L, n, draws = 10.0, 50, 4000
+    q = X.reciprocal_grid(L, 1)
+    q = q[np.any(q != 0, axis=1)][:6]
+    rng = np.random.default_rng(9)
+    acc = np.zeros(len(q))
+    for _ in range(draws):
+        I, _ = oracle.intensity(rng.uniform(0, L, (n, 3)), np.ones(n), q, threads=1)
+        acc += I
+    mean = acc / draws
+    # I is ~ exponential with mean n: standard error n / sqrt(draws)
+    assert np.all(np.abs(mean - n) <= 5 * n / math.sqrt(draws))
+
+
+# ---------------------------------------------------------------- gradient
+
+def test_gradient_two_atoms_closed_form_and_single_atom():
+    rng = np.random.default_rng(10)
+    q = rng.uniform(-3, 3, (64, 3))
+    w = rng.standard_normal(64)
+    pos = np.array([[0.5, 1.5, -2.0], [3.25, -1.0, 4.0]])
+    f = np.array([1.0, 2.5])
+    _, amp = oracle.intensity(pos, f, q)
+    g = oracle.intensity_grad(pos, f, q, amp, w)
+    # I = f1^2 + f2^2 + 2 f1 f2 cos(q.(r1 - r2))  =>  dI/dr1 = -2 f1 f2 sin(q.(r1-r2)) q
+    ref = np.zeros(3)
+    for p in range(64):
+        ph = float(sum(mp.mpf(q[p, k]) * (mp.mpf(pos[0, k]) - mp.mpf(pos[1, k])) for k in range(3)))
+        ref += w[p] * (-2 * f[0] * f[1] * math.sin(ph)) * q[p]
+    assert np.allclose(g[0], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert np.allclose(g[1], -ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    _, amp1 = oracle.intensity(pos[:1], f[:1], q)
+    g1 = oracle.intensity_grad(pos[:1], f[:1], q, amp1, w)
+    assert np.max(np.abs(g1)) <= 1e-13 * np.abs(w).sum() * 3
+
+
+def test_gradient_sums_to_zero_and_planar_z_is_zero():
+    w_ = X.workload_plain(n_atoms=300, n_det=16)
+    pos, f, q = w_.positions[0][0], w_.f[0], w_.q[0]
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal(q.shape[0])
+    _, amp = oracle.intensity(pos, f, q)
+    g = oracle.intensity_grad(pos, f, q, amp, w)
+    rms = math.sqrt(np.mean(np.sum(g * g, axis=1)))
+    assert np.all(np.abs(g.sum(axis=0)) <= 1e-10 * rms * len(pos))
+    assert np.all(g[:, 2] == 0.0)
+
+
+def test_gradient_against_central_differences():
+    rng = np.random.default_rng(12)
+    L = 25.0
+    pos = rng.uniform(0, L, (400, 3))
+    f = np.where(rng.random(400) < 0.2, 2.5, 1.0)
+    q = X.ewald_detector(24, 1.5)
+    w = rng.standard_normal(q.shape[0])
+    _, amp = oracle.intensity(pos, f, q)
+    g = oracle.intensity_grad(pos, f, q, amp, w)
+    atoms = rng.choice(400, 32, replace=False)
+    fd = oracle.fd_grad(pos, f, q, w, atoms, h=1e-4)
+    rms = math.sqrt(np.mean(np.sum(g * g, axis=1)))
+    err = np.max(np.linalg.norm(fd - g[atoms], axis=1)) / rms
+    assert err <= 1e-6, err
+
+
+# ---------------------------------------------------------------- rings, g2, XSVS
+
+def _fractions(v):
+    from fractions import Fraction
+    return np.array([float(Fraction(x)) for x in v])
+
+
+def test_ring_index_edges_half_open():
+    q = np.array([[0.5, 0, 0], [1.0, 0, 0], [0, 0, 1.5], [1.49999, 0, 0], [0, 0.0, 0.0],
+                  [0, 3.0, 4.0]])
+    ring = oracle.ring_index(q, [0.0, 1.0, 1.5])
+    assert list(ring) == [0, 1, -1, 1, 0, -1]
+
+
+def test_g2_hand_example():
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "g2_hand_3x2.json")))
+    I = np.array(d["I_frames_by_pixels"], dtype=float)
+    q = np.array([[0.1, 0, 0], [0, 0.2, 0]])
+    g2, cnt = oracle.g2_rings(I, q, [0.0, 1.0], n_tau=3)
+    assert cnt[0] == 2
+    assert np.allclose(g2[0], _fractions(d["g2_ring"]), rtol=1e-15, atol=1e-15)
+    # one pixel per ring reproduces the per-pixel values
+    g2b, _ = oracle.g2_rings(I, q, [0.0, 0.15, 1.0], n_tau=3)
+    G = [_fractions(x) for x in d["G_pixel"]]
+    assert np.allclose(g2b[0], G[0], rtol=1e-15, atol=1e-15)
+    assert np.allclose(g2b[1], G[1], rtol=1e-15, atol=1e-15)
+
+
+def test_g2_constant_is_one_and_empty_ring_is_nan():
+    I = np.full((10, 5), 2.0)
+    q = np.array([[0.1, 0, 0]] * 5)
+    g2, cnt = oracle.g2_rings(I, q, [0.0, 1.0, 2.0], n_tau=6)
+    assert np.all(g2[0] == 1.0) and cnt[0] == 5
+    assert np.all(np.isnan(g2[1])) and cnt[1] == 0
+    I[:, 2] = 0.0   # a dark pixel is left out
+    g2, cnt = oracle.g2_rings(I, q, [0.0, 1.0, 2.0], n_tau=6)
+    assert cnt[0] == 4 and np.all(g2[0] == 1.0)
+
+
+def test_g2_iid_exponential_statistics():
+    rng = np.random.default_rng(13)
+    F, Q = 400, 3000
+    I = rng.exponential(1.0, (F, Q))
+    q = np.tile([[0.5, 0, 0]], (Q, 1))
+    g2, _ = oracle.g2_rings(I, q, [0.0, 1.0], n_tau=4)
+    # g2(0) = <I^2>/<I>^2 = 2 for exponential speckle (beta0 = 1, Eq. (bq_g2)); g2(tau>0) = 1
+    assert abs(g2[0, 0] - 2.0) < 0.02
+    assert np.all(np.abs(g2[0, 1:] - 1.0) < 0.01)
+
+
+def test_xsvs_hand_example():
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "xsvs_hand_4x3.json")))
+    I = np.array(d["I_frames_by_pixels"], dtype=float)
+    q = np.array([[0.1, 0, 0], [0, 0.2, 0], [0, 0, 0.3]])
+    beta, win = oracle.xsvs_contrast(I, q, [0.0, 1.0], n_levels=3, want_windows=True)
+    assert np.allclose(beta[:, 0], _fractions(d["beta"]), rtol=1e-14, atol=1e-16)
+    assert np.allclose(win[0, :, 0], _fractions(d["beta_windows_W1"]), rtol=1e-14, atol=1e-16)
+    assert np.all(np.isnan(win[1, 2:, 0])) and np.all(np.isnan(win[2, 1:, 0]))
+
+
+def test_xsvs_erlang_contrast_one_over_w():
+    # iid exponential frames: a window of W frames is an Erlang(W) sum, beta = 1/W (Eq. (Erlang))
+    rng = np.random.default_rng(14)
+    F, Q = 64, 20000
+    I = rng.exponential(1.0, (F, Q))
+    q = np.tile([[0.5, 0, 0]], (Q, 1))
+    beta = oracle.xsvs_contrast(I, q, [0.0, 1.0], n_levels=5)
+    for lvl in range(5):
+        W = 2 ** lvl
+        assert abs(beta[lvl, 0] * W - 1.0) < 0.03, (W, beta[lvl, 0])
+    assert np.all(oracle.xsvs_contrast(np.full((4, 3), 3.0), q[:3], [0.0, 1.0], 3) == 0.0)
