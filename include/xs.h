@@ -1,0 +1,211 @@
+/*
+ * xs.h -- C ABI of the MI355X (gfx950) library for the direct X-ray speckle
+ * method of Mohanty, Cooper, Wang, Liang, Cai, "Computational approaches to
+ * model X-ray photon correlation spectroscopy from molecular dynamics"
+ * (arXiv:2204.13241).
+ *
+ * The library computes, for every detector pixel q and every frame t of an
+ * atomic trajectory, the scattering amplitude and intensity of the direct
+ * method (Sec. 3.1, Algorithm 1):
+ *     p^e(q,t) = sum_j f_j exp(-i q . r_j(t))          Sec. 2.2, Eq. (pe_ri)
+ *     I(q,t)   = |p^e(q,t)|^2                          Sec. 2.2, Eq. (Iq_pq)
+ * its gradient with respect to the positions, and the reductions of I to the
+ * intensity autocorrelation g2(|q|, tau) (Sec. 2.3, Eq. (g2_def)) and to the
+ * exposure-time speckle contrast beta (Sec. 2.3, Eqs. (inte_Iq), (bq_Iq)).
+ *
+ * General conventions
+ *   - Every array argument documented "device" is a pointer to GPU memory on
+ *     the current HIP device, owned by the caller; the library reads or writes
+ *     it only during the enqueued work and never frees or retains it.
+ *     "host" arguments are read before the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = legacy default
+ *     stream).  Calls return once the work is enqueued; results are valid
+ *     after the stream is synchronised.
+ *   - Argument validation is synchronous: XS_EINVAL / XS_ENOTSUP return before
+ *     anything is enqueued.  HIP failures return XS_EDEVICE.  Scratch memory
+ *     the library cannot obtain returns XS_ENOMEM.  xs_last_error() gives a
+ *     thread-local message for the last non-OK status of the calling thread.
+ *   - Scratch memory (binning tiles, partial sums, ring lists) is owned by the
+ *     library, cached per (device, stream) and released by xs_shutdown().
+ *     Concurrent calls on the same stream from different host threads are not
+ *     supported.
+ *   - Lengths are in Angstrom, wavevectors in 1/Angstrom.  Positions are used
+ *     verbatim: the library never wraps or images them.
+ *   - Nothing is printed; no C++ exception crosses the ABI.
+ */
+#ifndef XS_H
+#define XS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xs_status;
+enum {
+    XS_OK = 0,       /* success                                                   */
+    XS_EINVAL = 1,   /* bad argument (size, pointer, layout, non-finite scalar)   */
+    XS_ENOMEM = 2,   /* scratch allocation failed                                  */
+    XS_EDEVICE = 3,  /* HIP runtime / kernel launch failure                        */
+    XS_ENOTSUP = 4   /* valid request this build does not support                  */
+};
+
+/* Arithmetic of the pair sums. */
+enum {
+    /* Exact FP64 form: phase q.r/(2 pi) in FP64, sine and cosine from the
+     * Taylor series after exact reduction to |angle| <= pi/4, atoms (forward)
+     * or pixels (gradient) summed sequentially in input order.  Bit-for-bit
+     * reproducible and equal to the CPU FP64 oracle's result.               */
+    XS_FP64 = 0,
+    /* FP32 compensated form: atoms are binned into compact spatial tiles;
+     * the phase of each tile origin is reduced in FP64 per (pixel, tile),
+     * the in-tile phase, sine/cosine (hardware, revolutions) and the tile
+     * partial sums run in FP32, and tile partials are folded into FP64.     */
+    XS_FP32C = 1
+};
+
+/*
+ * Layout of a batch of independent systems (one system = one sample with its
+ * own atoms, pixels and frames).  All members are host arrays of n_sys
+ * entries; `box` has 3 entries per system.
+ *
+ *   system s, frame t, atom j  -> pos[(pos_off[s] + t * n_atoms[s] + j) * 3 + {0,1,2}]
+ *   system s, atom j           -> f[f_off[s] + j]            (same for every frame)
+ *   system s, pixel p          -> q[(q_off[s] + p) * 3 + {0,1,2}]
+ *   system s, frame t, pixel p -> out[out_off[s] + t * n_q[s] + p]   (I, dL/dI)
+ *                                 amp[(out_off[s] + t * n_q[s] + p) * 2 + {re, im}]
+ *
+ * box[s*3 + c] is the orthorhombic box edge of system s (Sec. 3.1: the
+ * simulation cell; Algorithm 1 takes q on its reciprocal lattice, but any q
+ * is accepted).  The FP32C form uses it to size its spatial bins; atoms
+ * outside [0, box) are clamped into the edge bins, which changes nothing but
+ * tile compactness.  The FP64 form ignores it.
+ *
+ * Limits: 1 <= n_sys; 0 <= n_atoms[s] < 2^31; 0 <= n_q[s] < 2^31;
+ * 1 <= n_frames[s]; offsets >= 0.
+ */
+typedef struct xs_batch {
+    int32_t n_sys;
+    const int64_t *n_atoms;
+    const int64_t *n_q;
+    const int32_t *n_frames;
+    const int64_t *pos_off;
+    const int64_t *f_off;
+    const int64_t *q_off;
+    const int64_t *out_off;
+    const double *box;
+} xs_batch;
+
+/*
+ * Direct method, Sec. 3.1 Algorithm 1 with Eqs. (pe_ri) and (Iq_pq): for every
+ * system, frame and pixel,
+ *     amp = a + i b = sum_j f_j exp(-i q.r_j),   I = a^2 + b^2.
+ *   b         host   batch layout (see xs_batch)
+ *   pos       device double, positions (Angstrom)
+ *   f         device double, per-atom form factors (q-independent)
+ *   q         device double, wavevectors (1/Angstrom)
+ *   precision XS_FP64 or XS_FP32C
+ *   I_out     device double, intensities
+ *   amp_out   device double [..][2] amplitudes (a, b), or NULL
+ * A system with n_atoms = 0 gives I = 0 and amp = 0.  All systems and frames
+ * of the batch run in one persistent launch per phase (binning, pair sum,
+ * combine).
+ */
+xs_status xs_intensity_direct(const xs_batch *b, const double *pos, const double *f,
+                              const double *q, int32_t precision, double *I_out,
+                              double *amp_out, void *stream);
+
+/*
+ * Gradient of a scalar L(I) with respect to the positions, through
+ * Eqs. (pe_ri) and (Iq_pq):
+ *     dI/dr_j = -2 f_j q (a sin(q.r_j) + b cos(q.r_j)),
+ *     dL/dr_j = sum_{t-independent pixels p} (dL/dI_p) dI_p/dr_j   (per frame).
+ *   amp       device double [..][2], the amplitude of the same positions
+ *             (from xs_intensity_direct), batch output layout
+ *   dL_dI     device double, upstream gradient, batch output layout
+ *   precision XS_FP32C: the sum over pixels runs as
+ *             sum_p W_p sin(q_p.r_j + arg amp_p), W_p = -2 f_j w_p |amp_p| q_p,
+ *             in FP32 with FP64 folding of pixel-chunk partials;
+ *             XS_FP64: the exact FP64 form, pixels in input order.
+ *   dL_dr     device float [..][3] (positions layout), or NULL
+ *   dL_dr64   device double [..][3] (positions layout), or NULL
+ * At least one of dL_dr / dL_dr64 must be non-NULL.
+ */
+xs_status xs_intensity_grad(const xs_batch *b, const double *pos, const double *f,
+                            const double *q, const double *amp, const double *dL_dI,
+                            int32_t precision, float *dL_dr, double *dL_dr64, void *stream);
+
+/*
+ * Intensity autocorrelation on |q| rings, Sec. 2.3 Eq. (g2_def), ring mean of
+ * Sec. 4.2:
+ *     G_p(tau) = [sum_{t < F - tau} I_t,p I_t+tau,p / (F - tau)] / <I_p>_t^2,
+ *     <I_p>_t  = sum_t I_t,p / F,
+ *     g2(r, tau) = mean over pixels p of ring r of G_p(tau).
+ *   I          device double [n_frames][n_q] (pixel fastest)
+ *   q          device double [n_q][3]; ring r holds e_r <= |q| < e_{r+1}
+ *   ring_edges host double [n_rings + 1], strictly increasing
+ *   n_tau      lags 0 .. n_tau - 1, 1 <= n_tau <= n_frames
+ *   g2_out     device double [n_rings][n_tau]; NaN for rings with no pixel
+ *   ring_count device int32 [n_rings] pixels used per ring, or NULL
+ * Pixels whose <I>_t^2 is zero are left out.  Every sum has a fixed order
+ * (time sums sequential in t; ring sums sequential in ascending pixel index),
+ * so the result is bit-for-bit reproducible and equal to the oracle's.
+ */
+xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                      const double *ring_edges, int32_t n_rings, int32_t n_tau,
+                      double *g2_out, int32_t *ring_count, void *stream);
+
+/*
+ * XSVS contrast versus exposure time, Sec. 2.3 Eqs. (inte_Iq) and (bq_Iq):
+ * exposure windows of W = 2^l frames (l = 0 .. n_levels-1), non-overlapping
+ * from frame 0, trailing partial window dropped, window sums built pairwise
+ * (J_{l+1}[k] = J_l[2k] + J_l[2k+1]);
+ *     beta(l, k, r) = var_r(J_l[k]) / mean_r(J_l[k])^2   (population variance,
+ *                                                        two-pass),
+ *     beta_out[l][r] = mean over the K_l = floor(F / 2^l) windows.
+ *   I          device double [n_frames][n_q]
+ *   q, ring_edges, n_rings as for xs_g2_rings
+ *   n_levels   1 <= n_levels, 2^(n_levels-1) <= n_frames
+ *   beta_out   device double [n_levels][n_rings]; NaN for empty rings
+ *   beta_win   device double [n_levels][n_frames][n_rings] per-window values
+ *              (entries k >= K_l are NaN), or NULL
+ * Fixed summation order as for xs_g2_rings: bit-for-bit equal to the oracle.
+ */
+xs_status xs_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                           const double *ring_edges, int32_t n_rings, int32_t n_levels,
+                           double *beta_out, double *beta_win, void *stream);
+
+/* Thread-local message for the last non-OK status returned to this thread. */
+const char *xs_last_error(void);
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int32_t xs_version(void);
+
+/* Release every cached scratch buffer on every device.  Call with no work of
+ * this library in flight.  Safe to call more than once. */
+xs_status xs_shutdown(void);
+
+/*
+ * Tile shape of the FP32C pair kernels (the autotuner's search space):
+ *   atoms_per_tile  atoms in one spatial tile (32, 64 or 128)
+ *   q_per_lane      pixels (forward) or atoms (gradient) per lane (1, 2, 4, 8)
+ *   atom_split      atom tiles per forward work item (>= 1)
+ *   pixel_split     pixels per gradient work item (multiple of 64)
+ */
+typedef struct xs_tile_shape {
+    int32_t atoms_per_tile;
+    int32_t q_per_lane;
+    int32_t atom_split;
+    int32_t pixel_split;
+} xs_tile_shape;
+
+/* kind: 0 = forward pair kernel, 1 = gradient pair kernel. */
+xs_status xs_get_tile_shape(int32_t kind, xs_tile_shape *out);
+xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XS_H */

@@ -1,0 +1,97 @@
+"""ctypes binding of libxs.so (the C ABI declared in include/xs.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  If libxs.so is missing, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxs.so")
+
+XS_OK, XS_EINVAL, XS_ENOMEM, XS_EDEVICE, XS_ENOTSUP = 0, 1, 2, 3, 4
+XS_FP64, XS_FP32C = 0, 1
+STATUS_NAMES = {0: "XS_OK", 1: "XS_EINVAL", 2: "XS_ENOMEM", 3: "XS_EDEVICE", 4: "XS_ENOTSUP"}
+
+EXPORTS = [
+    "xs_intensity_direct", "xs_intensity_grad", "xs_g2_rings", "xs_xsvs_contrast",
+    "xs_last_error", "xs_version", "xs_shutdown", "xs_get_tile_shape", "xs_set_tile_shape",
+]
+
+_P = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class XsBatch(ctypes.Structure):
+    _fields_ = [
+        ("n_sys", ctypes.c_int32),
+        ("n_atoms", _i64p),
+        ("n_q", _i64p),
+        ("n_frames", _i32p),
+        ("pos_off", _i64p),
+        ("f_off", _i64p),
+        ("q_off", _i64p),
+        ("out_off", _i64p),
+        ("box", _dp),
+    ]
+
+
+class XsTileShape(ctypes.Structure):
+    _fields_ = [
+        ("atoms_per_tile", ctypes.c_int32),
+        ("q_per_lane", ctypes.c_int32),
+        ("atom_split", ctypes.c_int32),
+        ("pixel_split", ctypes.c_int32),
+    ]
+
+
+class XsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libxs.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            "libxs.so is not built (%s); run __graft_entry__.build() or "
+            "python -m paper_2204_13241_amd.build" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i32 = ctypes.c_int32
+    i64 = ctypes.c_int64
+    bp = ctypes.POINTER(XsBatch)
+    sp = ctypes.POINTER(XsTileShape)
+    sig = {
+        "xs_intensity_direct": (i32, [bp, _P, _P, _P, i32, _P, _P, _P]),
+        "xs_intensity_grad": (i32, [bp, _P, _P, _P, _P, _P, i32, _P, _P, _P]),
+        "xs_g2_rings": (i32, [_P, i64, i64, _P, _P, i32, i32, _P, _P, _P]),
+        "xs_xsvs_contrast": (i32, [_P, i64, i64, _P, _P, i32, i32, _P, _P, _P]),
+        "xs_last_error": (ctypes.c_char_p, []),
+        "xs_version": (i32, []),
+        "xs_shutdown": (i32, []),
+        "xs_get_tile_shape": (i32, [i32, sp]),
+        "xs_set_tile_shape": (i32, [i32, sp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != XS_OK:
+        msg = load().xs_last_error()
+        raise XsError(status, msg.decode() if msg else "")

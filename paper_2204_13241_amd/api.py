@@ -1,0 +1,266 @@
+"""Python API over the HIP library: torch tensors in device memory in, results out.
+
+PyTorch supplies device memory and the current stream; every computation runs
+in libxs.so (see include/xs.h).  Tensors must be CUDA (HIP) tensors of the
+documented dtype; nothing is moved to or computed on the CPU here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+PRECISIONS = {"fp64": _lib.XS_FP64, "fp32c": _lib.XS_FP32C}
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, int):
+        return precision
+    try:
+        return PRECISIONS[precision]
+    except KeyError:
+        raise ValueError("precision must be 'fp64' or 'fp32c', got %r" % (precision,))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t: torch.Tensor, name: str, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live in GPU memory (got device %s)" % (name, t.device))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+@dataclass
+class Batch:
+    """Host-side batch descriptor (xs_batch) with the arrays it points to."""
+    n_atoms: np.ndarray
+    n_q: np.ndarray
+    n_frames: np.ndarray
+    pos_off: np.ndarray
+    f_off: np.ndarray
+    q_off: np.ndarray
+    out_off: np.ndarray
+    box: np.ndarray
+
+    def struct(self) -> _lib.XsBatch:
+        def p64(a):
+            return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        b = _lib.XsBatch()
+        b.n_sys = int(self.n_atoms.shape[0])
+        b.n_atoms = p64(self.n_atoms)
+        b.n_q = p64(self.n_q)
+        b.n_frames = self.n_frames.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        b.pos_off = p64(self.pos_off)
+        b.f_off = p64(self.f_off)
+        b.q_off = p64(self.q_off)
+        b.out_off = p64(self.out_off)
+        b.box = self.box.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return b
+
+    @property
+    def total_out(self) -> int:
+        return int(np.sum(self.n_q * self.n_frames))
+
+
+def make_batch(n_atoms: Sequence[int], n_q: Sequence[int], n_frames: Sequence[int],
+               box: Sequence) -> Batch:
+    """Packed layout: systems back to back in pos, f, q and outputs."""
+    na = np.ascontiguousarray(n_atoms, dtype=np.int64)
+    nq = np.ascontiguousarray(n_q, dtype=np.int64)
+    nf = np.ascontiguousarray(n_frames, dtype=np.int32)
+    bx = np.asarray(box, dtype=np.float64)
+    if bx.size == 1:
+        bx = np.full((len(na), 3), float(bx.reshape(-1)[0]))
+    bx = np.ascontiguousarray(bx.reshape(len(na), 3))
+    pos_off = np.concatenate([[0], np.cumsum(na * nf)[:-1]]).astype(np.int64)
+    f_off = np.concatenate([[0], np.cumsum(na)[:-1]]).astype(np.int64)
+    q_off = np.concatenate([[0], np.cumsum(nq)[:-1]]).astype(np.int64)
+    out_off = np.concatenate([[0], np.cumsum(nq * nf)[:-1]]).astype(np.int64)
+    return Batch(na, nq, nf, pos_off, f_off, q_off, out_off, bx.reshape(-1))
+
+
+def _box3(box, pos: torch.Tensor) -> np.ndarray:
+    if box is None:
+        raise ValueError("box (edge or 3 edges, Angstrom) is required")
+    b = np.asarray(box, dtype=np.float64).reshape(-1)
+    return np.full(3, b[0]) if b.size == 1 else b
+
+
+def intensity(pos: torch.Tensor, f: torch.Tensor, q: torch.Tensor, precision="fp32c",
+              box=None, return_amp: bool = False):
+    """Direct-method intensity of every frame and pixel.
+
+    pos [F, N, 3] or [N, 3] float64, f [N] float64, q [Q, 3] float64, all on the
+    GPU; box: cube edge or 3 edges (Angstrom; required for 'fp32c').
+    Returns I [F, Q] (or [Q]) float64, and the amplitude [F, Q, 2] if asked.
+    """
+    _need(pos, "pos"), _need(f, "f"), _need(q, "q")
+    single = pos.dim() == 2
+    p3 = pos.unsqueeze(0) if single else pos
+    if p3.dim() != 3 or p3.shape[-1] != 3:
+        raise ValueError("pos must be [F, N, 3] or [N, 3]")
+    F, N = int(p3.shape[0]), int(p3.shape[1])
+    if f.shape != (N,):
+        raise ValueError("f must be [N]")
+    if q.dim() != 2 or q.shape[1] != 3:
+        raise ValueError("q must be [Q, 3]")
+    Q = int(q.shape[0])
+    bx = _box3(box, pos) if _prec(precision) == _lib.XS_FP32C else np.ones(3)
+    b = make_batch([N], [Q], [F], bx)
+    I = torch.empty((F, Q), dtype=torch.float64, device=pos.device)
+    amp = torch.empty((F, Q, 2), dtype=torch.float64, device=pos.device) if return_amp else None
+    lib = _lib.load()
+    st = b.struct()
+    _lib.check(lib.xs_intensity_direct(ctypes.byref(st), _ptr(p3), _ptr(f), _ptr(q), _prec(precision),
+                                       _ptr(I), _ptr(amp), _stream()))
+    if single:
+        I = I[0]
+        amp = amp[0] if amp is not None else None
+    return (I, amp) if return_amp else I
+
+
+def intensity_systems(systems: List[tuple], precision="fp32c", return_amp: bool = False):
+    """Many independent systems in one call (one persistent launch per phase).
+
+    systems: list of (pos [F_s, N_s, 3], f [N_s], q [Q_s, 3], box) on the GPU.
+    Returns a list of I [F_s, Q_s] (and amplitudes).
+    """
+    if not systems:
+        return []
+    dev = systems[0][0].device
+    for i, (p, f, q, _) in enumerate(systems):
+        _need(p, "pos[%d]" % i), _need(f, "f[%d]" % i), _need(q, "q[%d]" % i)
+        if p.dim() != 3 or p.shape[-1] != 3 or f.shape != (p.shape[1],) or q.dim() != 2 or q.shape[1] != 3:
+            raise ValueError("system %d has inconsistent shapes" % i)
+    n_atoms = [int(p.shape[1]) for p, _, _, _ in systems]
+    n_frames = [int(p.shape[0]) for p, _, _, _ in systems]
+    n_q = [int(q.shape[0]) for _, _, q, _ in systems]
+    boxes = np.stack([_box3(bx, None) for _, _, _, bx in systems])
+    b = make_batch(n_atoms, n_q, n_frames, boxes)
+    pos = torch.cat([p.reshape(-1, 3) for p, _, _, _ in systems]).contiguous()
+    ff = torch.cat([f for _, f, _, _ in systems]).contiguous()
+    qq = torch.cat([q for _, _, q, _ in systems]).contiguous()
+    I = torch.empty(b.total_out, dtype=torch.float64, device=dev)
+    amp = torch.empty((b.total_out, 2), dtype=torch.float64, device=dev) if return_amp else None
+    st = b.struct()
+    _lib.check(_lib.load().xs_intensity_direct(ctypes.byref(st), _ptr(pos), _ptr(ff), _ptr(qq),
+                                               _prec(precision), _ptr(I), _ptr(amp), _stream()))
+    outs, amps = [], []
+    for s in range(len(systems)):
+        o = int(b.out_off[s])
+        n = n_q[s] * n_frames[s]
+        outs.append(I[o:o + n].view(n_frames[s], n_q[s]))
+        if return_amp:
+            amps.append(amp[o:o + n].view(n_frames[s], n_q[s], 2))
+    return (outs, amps) if return_amp else outs
+
+
+def intensity_grad(pos: torch.Tensor, f: torch.Tensor, q: torch.Tensor, amp: torch.Tensor,
+                   dL_dI: torch.Tensor, precision="fp32c", box=None, out_dtype=torch.float32):
+    """dL/dpos from the amplitude of the same positions and dL/dI (same shape as I)."""
+    _need(pos, "pos"), _need(f, "f"), _need(q, "q"), _need(amp, "amp"), _need(dL_dI, "dL_dI")
+    single = pos.dim() == 2
+    p3 = pos.unsqueeze(0) if single else pos
+    F, N = int(p3.shape[0]), int(p3.shape[1])
+    Q = int(q.shape[0])
+    if amp.numel() != F * Q * 2 or dL_dI.numel() != F * Q:
+        raise ValueError("amp must be [F, Q, 2] and dL_dI [F, Q]")
+    bx = _box3(box, pos) if _prec(precision) == _lib.XS_FP32C else np.ones(3)
+    b = make_batch([N], [Q], [F], bx)
+    g32 = torch.empty(p3.shape, dtype=torch.float32, device=pos.device) if out_dtype == torch.float32 else None
+    g64 = torch.empty(p3.shape, dtype=torch.float64, device=pos.device) if out_dtype == torch.float64 else None
+    if g32 is None and g64 is None:
+        raise ValueError("out_dtype must be torch.float32 or torch.float64")
+    st = b.struct()
+    _lib.check(_lib.load().xs_intensity_grad(ctypes.byref(st), _ptr(p3), _ptr(f), _ptr(q), _ptr(amp),
+                                             _ptr(dL_dI), _prec(precision), _ptr(g32), _ptr(g64),
+                                             _stream()))
+    g = g32 if g32 is not None else g64
+    return g[0] if single else g
+
+
+def g2_rings(I: torch.Tensor, q: torch.Tensor, edges, n_tau: int):
+    """g2 [n_rings, n_tau] (float64) and the pixel count per ring (int32)."""
+    _need(I, "I"), _need(q, "q")
+    if I.dim() != 2 or q.shape != (I.shape[1], 3):
+        raise ValueError("I must be [F, Q] and q [Q, 3]")
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    R = e.shape[0] - 1
+    g2 = torch.empty((R, n_tau), dtype=torch.float64, device=I.device)
+    cnt = torch.empty(R, dtype=torch.int32, device=I.device)
+    _lib.check(_lib.load().xs_g2_rings(_ptr(I), I.shape[0], I.shape[1], _ptr(q),
+                                       e.ctypes.data_as(ctypes.c_void_p), R, int(n_tau), _ptr(g2),
+                                       _ptr(cnt), _stream()))
+    return g2, cnt
+
+
+def xsvs_contrast(I: torch.Tensor, q: torch.Tensor, edges, n_levels: int,
+                  return_windows: bool = False):
+    """beta [n_levels, n_rings] (and per-window values [n_levels, F, n_rings])."""
+    _need(I, "I"), _need(q, "q")
+    if I.dim() != 2 or q.shape != (I.shape[1], 3):
+        raise ValueError("I must be [F, Q] and q [Q, 3]")
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    R = e.shape[0] - 1
+    beta = torch.empty((n_levels, R), dtype=torch.float64, device=I.device)
+    win = torch.empty((n_levels, I.shape[0], R), dtype=torch.float64, device=I.device) if return_windows else None
+    _lib.check(_lib.load().xs_xsvs_contrast(_ptr(I), I.shape[0], I.shape[1], _ptr(q),
+                                            e.ctypes.data_as(ctypes.c_void_p), R, int(n_levels),
+                                            _ptr(beta), _ptr(win), _stream()))
+    return (beta, win) if return_windows else beta
+
+
+def get_tile_shape(kind: int) -> dict:
+    s = _lib.XsTileShape()
+    _lib.check(_lib.load().xs_get_tile_shape(int(kind), ctypes.byref(s)))
+    return {"atoms_per_tile": s.atoms_per_tile, "q_per_lane": s.q_per_lane,
+            "atom_split": s.atom_split, "pixel_split": s.pixel_split}
+
+
+def set_tile_shape(kind: int, atoms_per_tile=64, q_per_lane=4, atom_split=64, pixel_split=8192):
+    s = _lib.XsTileShape(int(atoms_per_tile), int(q_per_lane), int(atom_split), int(pixel_split))
+    _lib.check(_lib.load().xs_set_tile_shape(int(kind), ctypes.byref(s)))
+
+
+class IntensityFn(torch.autograd.Function):
+    """I = |sum_j f_j exp(-i q.r_j)|^2 with a hand-written adjoint for dL/dpos.
+
+    forward(pos [F,N,3] or [N,3] float64, f, q, box, precision) -> I;
+    backward calls xs_intensity_grad with the saved amplitude.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, f, q, box, precision="fp32c"):
+        I, amp = intensity(pos.detach(), f.detach(), q.detach(), precision, box, return_amp=True)
+        ctx.save_for_backward(pos.detach(), f.detach(), q.detach(), amp)
+        ctx.box = box
+        ctx.precision = precision
+        return I
+
+    @staticmethod
+    def backward(ctx, grad_I):
+        pos, f, q, amp = ctx.saved_tensors
+        g = intensity_grad(pos, f, q, amp, grad_I.contiguous().to(torch.float64), ctx.precision,
+                           ctx.box, out_dtype=torch.float64)
+        return g, None, None, None, None
+
+
+def shutdown():
+    _lib.check(_lib.load().xs_shutdown())

@@ -1,0 +1,352 @@
+// Host side of the xs C ABI: argument validation, batch -> segment expansion,
+// scratch management and dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "xs_internal.h"
+
+namespace xs {
+
+// ---------------------------------------------------------------- errors
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+xs_status set_error(xs_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+xs_status hip_error(hipError_t e, const char *what) {
+    return set_error(e == hipErrorOutOfMemory ? XS_ENOMEM : XS_EDEVICE, "%s: %s (%d)", what,
+                     hipGetErrorString(e), static_cast<int>(e));
+}
+
+// ---------------------------------------------------------------- scratch
+
+namespace {
+
+struct Buffer {
+    void *dev = nullptr;
+    size_t bytes = 0;
+    void *pinned = nullptr;      // host staging for uploads into this slot
+    size_t pinned_bytes = 0;
+    hipEvent_t copied = nullptr;  // last upload from `pinned` has been read
+};
+
+struct StreamScratch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Buffer slot[SLOT_COUNT];
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, StreamScratch *> g_scratch;
+
+StreamScratch *scratch_for(hipStream_t s) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, s);
+    auto it = g_scratch.find(key);
+    if (it != g_scratch.end()) return it->second;
+    auto *ss = new StreamScratch();
+    ss->device = dev;
+    ss->stream = s;
+    g_scratch[key] = ss;
+    return ss;
+}
+
+xs_status refuse_if_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+        return set_error(XS_EINVAL,
+                         "scratch must grow while the stream is being captured; run the same "
+                         "call once outside capture first");
+    return XS_OK;
+}
+
+}  // namespace
+
+xs_status scratch(hipStream_t s, Slot slot, size_t bytes, void **ptr) {
+    StreamScratch *ss = scratch_for(s);
+    Buffer &b = ss->slot[slot];
+    if (bytes == 0) bytes = 1;
+    if (b.bytes < bytes) {
+        XS_TRY(refuse_if_capturing(s));
+        XS_HIP(hipStreamSynchronize(s));  // earlier work on this stream may use the old buffer
+        if (b.dev) XS_HIP(hipFree(b.dev));
+        b.dev = nullptr;
+        b.bytes = 0;
+        const size_t want = bytes + bytes / 4;  // headroom against frequent regrowth
+        hipError_t e = hipMalloc(&b.dev, want);
+        if (e != hipSuccess) {
+            b.dev = nullptr;
+            (void)hipGetLastError();
+            return set_error(XS_ENOMEM, "scratch slot %d: cannot allocate %zu bytes (%s)", int(slot),
+                             want, hipGetErrorString(e));
+        }
+        b.bytes = want;
+    }
+    *ptr = b.dev;
+    return XS_OK;
+}
+
+xs_status upload(hipStream_t s, Slot slot, const void *host, size_t bytes, void **dev) {
+    XS_TRY(scratch(s, slot, bytes, dev));
+    StreamScratch *ss = scratch_for(s);
+    Buffer &b = ss->slot[slot];
+    if (b.pinned_bytes < bytes) {
+        XS_TRY(refuse_if_capturing(s));
+        if (b.copied) XS_HIP(hipEventSynchronize(b.copied));
+        if (b.pinned) XS_HIP(hipHostFree(b.pinned));
+        b.pinned = nullptr;
+        b.pinned_bytes = 0;
+        XS_HIP(hipHostMalloc(&b.pinned, bytes + bytes / 4, hipHostMallocDefault));
+        b.pinned_bytes = bytes + bytes / 4;
+    }
+    if (!b.copied) XS_HIP(hipEventCreateWithFlags(&b.copied, hipEventDisableTiming));
+    else XS_HIP(hipEventSynchronize(b.copied));  // previous copy out of `pinned` finished
+    std::memcpy(b.pinned, host, bytes);
+    XS_HIP(hipMemcpyAsync(*dev, b.pinned, bytes, hipMemcpyHostToDevice, s));
+    XS_HIP(hipEventRecord(b.copied, s));
+    return XS_OK;
+}
+
+void release_all_scratch() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_scratch) {
+        StreamScratch *ss = kv.second;
+        (void)hipSetDevice(ss->device);
+        (void)hipDeviceSynchronize();
+        for (auto &b : ss->slot) {
+            if (b.dev) (void)hipFree(b.dev);
+            if (b.pinned) (void)hipHostFree(b.pinned);
+            if (b.copied) (void)hipEventDestroy(b.copied);
+        }
+        delete ss;
+    }
+    g_scratch.clear();
+    (void)hipSetDevice(cur);
+}
+
+// ---------------------------------------------------------------- validation
+
+namespace {
+
+xs_tile_shape g_shape[2] = {{64, 4, 64, 0}, {64, 4, 0, 8192}};
+std::mutex g_shape_mu;
+
+xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
+                       int &max_q) {
+    if (!b) return set_error(XS_EINVAL, "batch descriptor is NULL");
+    if (b->n_sys < 1) return set_error(XS_EINVAL, "n_sys must be >= 1 (got %d)", b->n_sys);
+    if (!b->n_atoms || !b->n_q || !b->n_frames || !b->pos_off || !b->f_off || !b->q_off ||
+        !b->out_off)
+        return set_error(XS_EINVAL, "batch descriptor has a NULL array");
+    max_atoms = 0;
+    max_q = 0;
+    segs.clear();
+    for (int s = 0; s < b->n_sys; ++s) {
+        const int64_t n = b->n_atoms[s], nq = b->n_q[s];
+        const int32_t nf = b->n_frames[s];
+        if (n < 0 || n >= (int64_t(1) << 31))
+            return set_error(XS_EINVAL, "system %d: n_atoms %lld out of range", s, (long long)n);
+        if (nq < 0 || nq >= (int64_t(1) << 31))
+            return set_error(XS_EINVAL, "system %d: n_q %lld out of range", s, (long long)nq);
+        if (nf < 1) return set_error(XS_EINVAL, "system %d: n_frames must be >= 1", s);
+        if (b->pos_off[s] < 0 || b->f_off[s] < 0 || b->q_off[s] < 0 || b->out_off[s] < 0)
+            return set_error(XS_EINVAL, "system %d: negative offset", s);
+        for (int32_t t = 0; t < nf; ++t) {
+            Segment sg;
+            sg.pos = b->pos_off[s] + static_cast<int64_t>(t) * n;
+            sg.f = b->f_off[s];
+            sg.q = b->q_off[s];
+            sg.out = b->out_off[s] + static_cast<int64_t>(t) * nq;
+            sg.n_atoms = static_cast<int32_t>(n);
+            sg.n_q = static_cast<int32_t>(nq);
+            sg.sys = s;
+            sg.frame = t;
+            segs.push_back(sg);
+        }
+        max_atoms = std::max<int>(max_atoms, static_cast<int>(n));
+        max_q = std::max<int>(max_q, static_cast<int>(nq));
+    }
+    if (segs.size() > 65535)
+        return set_error(XS_ENOTSUP, "at most 65535 (system, frame) segments per call (got %zu)",
+                         segs.size());
+    return XS_OK;
+}
+
+xs_status check_box(const xs_batch *b) {
+    if (!b->box) return set_error(XS_EINVAL, "FP32C needs the box edges (box is NULL)");
+    for (int s = 0; s < b->n_sys; ++s)
+        for (int c = 0; c < 3; ++c) {
+            const double L = b->box[3 * s + c];
+            if (!(L > 0.0) || !std::isfinite(L))
+                return set_error(XS_EINVAL, "system %d: box edge %d must be finite and > 0", s, c);
+        }
+    return XS_OK;
+}
+
+xs_status read_edges(const double *edges, int32_t n_rings, RingEdges &out) {
+    if (!edges) return set_error(XS_EINVAL, "ring_edges is NULL");
+    if (n_rings < 1 || n_rings > kMaxRings)
+        return set_error(n_rings > kMaxRings ? XS_ENOTSUP : XS_EINVAL,
+                         "n_rings must be in [1, %d] (got %d)", kMaxRings, n_rings);
+    for (int r = 0; r <= n_rings; ++r) {
+        if (!std::isfinite(edges[r])) return set_error(XS_EINVAL, "ring edge %d is not finite", r);
+        if (r > 0 && !(edges[r - 1] < edges[r]))
+            return set_error(XS_EINVAL, "ring edges must increase strictly (edge %d)", r);
+        out.e[r] = edges[r];
+    }
+    for (int r = n_rings + 1; r <= kMaxRings; ++r) out.e[r] = 0.0;
+    out.n_rings = n_rings;
+    return XS_OK;
+}
+
+xs_status begin(void *stream) {
+    (void)stream;
+    g_last_error.clear();
+    return XS_OK;
+}
+
+}  // namespace
+}  // namespace xs
+
+using namespace xs;
+
+extern "C" {
+
+xs_status xs_intensity_direct(const xs_batch *b, const double *pos, const double *f,
+                              const double *q, int32_t precision, double *I_out,
+                              double *amp_out, void *stream) {
+    XS_TRY(begin(stream));
+    std::vector<Segment> segs;
+    int max_atoms = 0, max_q = 0;
+    XS_TRY(expand_batch(b, segs, max_atoms, max_q));
+    if (max_q > 0 && (!q || !I_out)) return set_error(XS_EINVAL, "q / I_out is NULL");
+    if (max_atoms > 0 && (!pos || !f)) return set_error(XS_EINVAL, "pos / f is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == XS_FP64)
+        return fp64_forward(s, segs.data(), static_cast<int>(segs.size()), max_q, pos, f, q, I_out,
+                            amp_out);
+    if (precision == XS_FP32C) {
+        XS_TRY(check_box(b));
+        xs_tile_shape sh;
+        {
+            std::lock_guard<std::mutex> lk(g_shape_mu);
+            sh = g_shape[0];
+        }
+        return fp32c_forward(s, segs.data(), static_cast<int>(segs.size()), b->box, pos, f, q, I_out,
+                             amp_out, sh);
+    }
+    return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
+}
+
+xs_status xs_intensity_grad(const xs_batch *b, const double *pos, const double *f,
+                            const double *q, const double *amp, const double *dL_dI,
+                            int32_t precision, float *dL_dr, double *dL_dr64, void *stream) {
+    XS_TRY(begin(stream));
+    std::vector<Segment> segs;
+    int max_atoms = 0, max_q = 0;
+    XS_TRY(expand_batch(b, segs, max_atoms, max_q));
+    if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
+    if (max_atoms > 0 && (!pos || !f)) return set_error(XS_EINVAL, "pos / f is NULL");
+    if (max_q > 0 && (!q || !amp || !dL_dI)) return set_error(XS_EINVAL, "q / amp / dL_dI is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == XS_FP64)
+        return fp64_grad(s, segs.data(), static_cast<int>(segs.size()), max_atoms, pos, f, q, amp,
+                         dL_dI, dL_dr, dL_dr64);
+    if (precision == XS_FP32C) {
+        XS_TRY(check_box(b));
+        xs_tile_shape sh;
+        {
+            std::lock_guard<std::mutex> lk(g_shape_mu);
+            sh = g_shape[1];
+        }
+        return fp32c_grad(s, segs.data(), static_cast<int>(segs.size()), b->box, pos, f, q, amp,
+                          dL_dI, dL_dr, dL_dr64, sh);
+    }
+    return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
+}
+
+xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                      const double *ring_edges, int32_t n_rings, int32_t n_tau, double *g2_out,
+                      int32_t *ring_count, void *stream) {
+    XS_TRY(begin(stream));
+    if (n_frames < 1) return set_error(XS_EINVAL, "n_frames must be >= 1");
+    if (n_q < 0 || n_q >= (int64_t(1) << 31)) return set_error(XS_EINVAL, "n_q out of range");
+    if (n_tau < 1 || n_tau > n_frames) return set_error(XS_EINVAL, "n_tau must be in [1, n_frames]");
+    if (!g2_out) return set_error(XS_EINVAL, "g2_out is NULL");
+    if (n_q > 0 && (!I || !q)) return set_error(XS_EINVAL, "I / q is NULL");
+    RingEdges e;
+    XS_TRY(read_edges(ring_edges, n_rings, e));
+    return g2_rings(static_cast<hipStream_t>(stream), I, n_frames, n_q, q, e, n_tau, g2_out,
+                    ring_count);
+}
+
+xs_status xs_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                           const double *ring_edges, int32_t n_rings, int32_t n_levels,
+                           double *beta_out, double *beta_win, void *stream) {
+    XS_TRY(begin(stream));
+    if (n_frames < 1) return set_error(XS_EINVAL, "n_frames must be >= 1");
+    if (n_q < 0 || n_q >= (int64_t(1) << 31)) return set_error(XS_EINVAL, "n_q out of range");
+    if (n_levels < 1 || n_levels > 62 || (int64_t(1) << (n_levels - 1)) > n_frames)
+        return set_error(XS_EINVAL, "n_levels must satisfy 1 <= n_levels and 2^(n_levels-1) <= n_frames");
+    if (!beta_out) return set_error(XS_EINVAL, "beta_out is NULL");
+    if (n_q > 0 && (!I || !q)) return set_error(XS_EINVAL, "I / q is NULL");
+    RingEdges e;
+    XS_TRY(read_edges(ring_edges, n_rings, e));
+    return xsvs_contrast(static_cast<hipStream_t>(stream), I, n_frames, n_q, q, e, n_levels,
+                         beta_out, beta_win);
+}
+
+const char *xs_last_error(void) { return g_last_error.c_str(); }
+
+int32_t xs_version(void) { return 100; }
+
+xs_status xs_shutdown(void) {
+    release_all_scratch();
+    return XS_OK;
+}
+
+xs_status xs_get_tile_shape(int32_t kind, xs_tile_shape *out) {
+    if ((kind != 0 && kind != 1) || !out) return set_error(XS_EINVAL, "kind must be 0 or 1, out non-NULL");
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    *out = g_shape[kind];
+    return XS_OK;
+}
+
+xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
+    if ((kind != 0 && kind != 1) || !shape) return set_error(XS_EINVAL, "kind must be 0 or 1, shape non-NULL");
+    const int ql = shape->q_per_lane;
+    if (shape->atoms_per_tile != 64)
+        return set_error(XS_ENOTSUP, "atoms_per_tile: only 64 is built (got %d)", shape->atoms_per_tile);
+    if (ql != 1 && ql != 2 && ql != 4 && ql != 8)
+        return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8 (got %d)", ql);
+    if (kind == 0 && shape->atom_split < 1) return set_error(XS_EINVAL, "atom_split must be >= 1");
+    if (kind == 1 && (shape->pixel_split < 64 || shape->pixel_split % 64))
+        return set_error(XS_EINVAL, "pixel_split must be a positive multiple of 64");
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shape[kind] = *shape;
+    return XS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations of the xs library (host side and kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "xs.h"
+
+namespace xs {
+
+// ---------------------------------------------------------------- errors
+xs_status set_error(xs_status st, const char *fmt, ...);
+xs_status hip_error(hipError_t e, const char *what);
+#define XS_HIP(call)                                           \
+    do {                                                       \
+        hipError_t xs_e_ = (call);                             \
+        if (xs_e_ != hipSuccess) return ::xs::hip_error(xs_e_, #call); \
+    } while (0)
+#define XS_TRY(expr)                                           \
+    do {                                                       \
+        xs_status xs_s_ = (expr);                              \
+        if (xs_s_ != XS_OK) return xs_s_;                      \
+    } while (0)
+
+// ---------------------------------------------------------------- scratch
+// Grow-only device buffers cached per (device, stream).  A slot is reused by
+// every call on the same stream; calls on one stream are ordered, so reuse is
+// safe.  Growth synchronises the stream first (refused during graph capture).
+enum Slot {
+    SLOT_SEGS = 0,      // segment / item tables
+    SLOT_ITEMS,
+    SLOT_COUNTER,       // work-queue counters
+    SLOT_KEYS,          // binning: cell key per atom
+    SLOT_HIST,          // binning: per-cell counts / cursors
+    SLOT_SORTED,        // binning: sorted atom index
+    SLOT_TILES,         // FP32C tile atoms (float4)
+    SLOT_ORIGINS,       // FP32C tile origins (double4)
+    SLOT_PARTIAL,       // partial sums
+    SLOT_PIXEL,         // per-pixel prologue data
+    SLOT_PIXEL2,
+    SLOT_RING_KEY,      // reductions: per-pixel ring key
+    SLOT_RING_CNT,      // reductions: per-block ring counts / offsets
+    SLOT_RING_LIST,     // reductions: ring-ordered pixel list
+    SLOT_G,             // g2 per-pixel values
+    SLOT_LEVEL_A,       // XSVS window sums (ping)
+    SLOT_LEVEL_B,       // XSVS window sums (pong)
+    SLOT_BWIN,          // XSVS per-window contrast
+    SLOT_COUNT
+};
+xs_status scratch(hipStream_t stream, Slot slot, size_t bytes, void **ptr);
+// Stage a host table into the stream's scratch slot (async copy from a
+// library-owned pinned staging buffer).
+xs_status upload(hipStream_t stream, Slot slot, const void *host, size_t bytes, void **dev);
+void release_all_scratch();
+
+// ---------------------------------------------------------------- segments
+// One (system, frame) pair of a batch.
+struct Segment {
+    int64_t pos;       // atom offset of the frame in pos (units of atoms)
+    int64_t f;         // offset into f
+    int64_t q;         // pixel offset into q
+    int64_t out;       // pixel offset into outputs
+    int32_t n_atoms;
+    int32_t n_q;
+    int32_t sys;
+    int32_t frame;
+};
+
+// ---------------------------------------------------------------- launchers
+xs_status fp64_forward(hipStream_t s, const Segment *segs_host, int n_segs, int max_q,
+                       const double *pos, const double *f, const double *q, double *I,
+                       double *amp);
+xs_status fp64_grad(hipStream_t s, const Segment *segs_host, int n_segs, int max_atoms,
+                    const double *pos, const double *f, const double *q, const double *amp,
+                    const double *dL_dI, float *dL_dr, double *dL_dr64);
+
+xs_status fp32c_forward(hipStream_t s, const Segment *segs_host, int n_segs, const double *box,
+                        const double *pos, const double *f, const double *q, double *I,
+                        double *amp, const xs_tile_shape &shape);
+xs_status fp32c_grad(hipStream_t s, const Segment *segs_host, int n_segs, const double *box,
+                     const double *pos, const double *f, const double *q, const double *amp,
+                     const double *dL_dI, float *dL_dr, double *dL_dr64,
+                     const xs_tile_shape &shape);
+
+constexpr int kMaxRings = 256;
+struct RingEdges {
+    double e[kMaxRings + 1];
+    int32_t n_rings;
+};
+xs_status g2_rings(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
+                   const double *q, const RingEdges &edges, int32_t n_tau, double *g2_out,
+                   int32_t *ring_count);
+xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
+                        const double *q, const RingEdges &edges, int32_t n_levels,
+                        double *beta_out, double *beta_win);
+
+}  // namespace xs

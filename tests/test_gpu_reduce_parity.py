@@ -1,0 +1,67 @@
+"""g2 and XSVS reductions on the GPU against the oracle: bit-for-bit (Sec. 2.3)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2204_13241_amd import api
+    return api
+
+
+def _speckle_like(rng, F, Q, corr=0.9):
+    """Exponentially distributed, time-correlated synthetic intensities [F, Q]."""
+    z = rng.standard_normal((Q, 2))
+    out = np.empty((F, Q))
+    for t in range(F):
+        z = corr * z + np.sqrt(1 - corr ** 2) * rng.standard_normal((Q, 2))
+        out[t] = 0.5 * (z ** 2).sum(axis=1)
+    return out
+
+
+@pytest.mark.parametrize("F,n_det,n_tau,n_rings,seed", [
+    (1, 8, 1, 3, 1), (20, 33, 10, 7, 2), (200, 64, 100, 32, 3), (9000, 5, 3, 2, 4)])
+def test_g2_bitwise(api, F, n_det, n_tau, n_rings, seed):
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(seed)
+    q = X.ewald_detector(n_det, 1.5)
+    I = _speckle_like(rng, F, q.shape[0])
+    I[:, 3 % q.shape[0]] = 0.0           # a dark pixel is left out
+    edges = X.ring_edges(n_rings, 1.5)
+    print("g2 F=%d Q=%d tau=%d rings=%d" % (F, q.shape[0], n_tau, n_rings), flush=True)
+    g2, cnt = api.g2_rings(dev(I), dev(q), edges, n_tau)
+    g2r, cntr = oracle.g2_rings(I, q, edges, n_tau)
+    assert np.array_equal(host(cnt), cntr)
+    assert bitwise_equal(host(g2), g2r)
+
+
+@pytest.mark.parametrize("F,n_det,n_levels,n_rings,seed", [
+    (1, 8, 1, 2, 1), (7, 21, 3, 5, 2), (64, 48, 7, 16, 3), (1024, 16, 9, 4, 4)])
+def test_xsvs_bitwise(api, F, n_det, n_levels, n_rings, seed):
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(seed)
+    q = X.ewald_detector(n_det, 2.0)
+    I = _speckle_like(rng, F, q.shape[0])
+    edges = X.ring_edges(n_rings, 2.0)
+    print("xsvs F=%d Q=%d levels=%d rings=%d" % (F, q.shape[0], n_levels, n_rings), flush=True)
+    beta, win = api.xsvs_contrast(dev(I), dev(q), edges, n_levels, return_windows=True)
+    br, wr = oracle.xsvs_contrast(I, q, edges, n_levels, want_windows=True)
+    assert bitwise_equal(host(beta), br)
+    assert bitwise_equal(host(win), wr)
+
+
+def test_ring_edges_on_pixel_norms(api):
+    """Pixels exactly on a ring edge go to the upper ring on both sides."""
+    from _gpu import dev, host, bitwise_equal
+    q = np.array([[0.5, 0, 0], [1.0, 0, 0], [0, 0, 1.5], [0.6, 0.8, 0.0], [0, 0, 0.0], [0, 3, 4.0]])
+    I = np.arange(1.0, 1.0 + 4 * 6).reshape(4, 6)
+    edges = [0.0, 1.0, 1.5]
+    g2, cnt = api.g2_rings(dev(I), dev(q), edges, 2)
+    g2r, cntr = oracle.g2_rings(I, q, edges, 2)
+    assert np.array_equal(host(cnt), cntr)
+    assert bitwise_equal(host(g2), g2r)
