@@ -1,0 +1,293 @@
+"""Benchmark of the direct speckle-intensity path on one MI355X.
+
+Default workload (differentiation): N = 65,536 atoms uniform in a cube at
+0.021 atoms per cubic Angstrom, f = 1, 512 x 512 planar pixels with
+q_x, q_y in [-3, 3] 1/Angstrom, target intensities from the positions displaced
+by Gaussian noise (sigma 0.2 Angstrom).  One step = FP32C forward (amplitude
+and intensity of every pixel), speckle-matching loss and dL/dI, FP32C adjoint
+dL/dr, and a gradient-descent position update; 2 N Q atom-pixel pair
+evaluations per step.  Inputs are resident in GPU memory before timing starts.
+
+Prints one JSON line (metric, value in G atom-q pair evals/s, roofline of the
+dominant kernel from HIP-event kernel timings, CPU-oracle baseline, accuracy of
+the FP32C results against the exact FP64 form, FP64-form speedup).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("G atom-q pair evals/s (fwd+adjoint) vs FP64 form at 1e-5 rel err; % VALU roofline")
+UNIT = "G atom-q pair evals/s"
+# MI355X: 256 CUs at 2.4 GHz; FP32 vector FMA 128 lanes/clk/CU (157.3 TFLOP/s);
+# v_sin_f32 / v_cos_f32 issue at a quarter of that, 32 lanes/clk/CU.
+CUS, CLOCK = 256, 2.4e9
+TRANS_LANES = 32
+PEAK_TRANS = CUS * CLOCK * TRANS_LANES          # transcendental lane-ops/s
+PEAK_SINCOS_PAIRS = PEAK_TRANS / 2.0           # pairs/s with one sin + one cos each
+PEAK_SIN_PAIRS = PEAK_TRANS                    # pairs/s with one sin each (adjoint form)
+PEAK_HBM = 8.0e12                              # bytes/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per launch of the forward pair kernel from the committed PMC summary,
+    or None if the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "fwd_fp32c_pmc_grad65536.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != source_hash(kernel_src):
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(pos, f, q, amp, w, budget_s=15.0):
+    """The oracle (FP64 form, OpenMP) on a bounded sample of the same workload."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    N, Q = pos.shape[0], q.shape[0]
+    # calibrate on a small forward piece
+    t = time.perf_counter()
+    oracle.intensity(pos, f, q[:1024], threads=threads)
+    per_pair = (time.perf_counter() - t) / (N * 1024)
+    n_pix = int(max(64, min(Q, (0.6 * budget_s) / (per_pair * N))))
+    n_atoms = int(max(16, min(N, (0.4 * budget_s) / (per_pair * Q))))
+    rng = np.random.default_rng(7)
+    pix = np.sort(rng.choice(Q, n_pix, replace=False))
+    atoms = np.sort(rng.choice(N, n_atoms, replace=False))
+    t0 = time.perf_counter()
+    oracle.intensity(pos, f, q[pix], threads=threads)
+    t1 = time.perf_counter()
+    oracle.intensity_grad(pos[atoms], f[atoms], q, amp, w, threads=threads)
+    t2 = time.perf_counter()
+    pairs = N * n_pix + n_atoms * Q
+    return {
+        "value": pairs / (t2 - t0) / 1e9,
+        "unit": UNIT,
+        "cores": threads,
+        "kind": "oracle",
+        "sample": ("FP64-form forward over all %d atoms x %d random pixels (%.1f s) + FP64-form "
+                   "gradient of %d random atoms over all %d pixels (%.1f s)"
+                   % (N, n_pix, t1 - t0, n_atoms, Q, t2 - t1)),
+    }
+
+
+def rel_grad_err(g, g_ref):
+    g = g.reshape(-1, 3)
+    g_ref = g_ref.reshape(-1, 3)
+    rms = math.sqrt(float(np.mean(np.sum(g_ref * g_ref, axis=1))))
+    return float(np.max(np.linalg.norm(g - g_ref, axis=1)) / rms)
+
+
+def run_grad(args):
+    import torch
+    from paper_2204_13241_amd import api, inputs
+
+    dev = "cuda:0"
+    w = inputs.workload_grad()
+    r0, f_np, q_np, L = w.positions[0][0], w.f[0], w.q[0], w.box[0]
+    N, Q = r0.shape[0], q_np.shape[0]
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    pos, f, q = T(r0), T(f_np), T(q_np)
+    It = api.intensity(T(w.extra["r_target"]), f, q, "fp64")
+    torch.cuda.synchronize()
+    log("inputs ready: N=%d Q=%d" % (N, Q))
+
+    # one plan for the whole run: work lists, buffers and pixel order built once
+    plan = api.Plan.single(N, 1, q, L)
+    I = torch.empty(Q, dtype=torch.float64, device=dev)
+    amp = torch.empty((Q, 2), dtype=torch.float64, device=dev)
+    g = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    state = {"step": None}
+
+    def step():
+        plan.intensity(pos, f, I, amp)
+        loss, dLdI = api.speckle_loss(I, It)
+        plan.grad(pos, f, amp, dLdI, retile=False, g32=g)
+        api.position_step(pos, g, state["step"])
+        return loss
+
+    # fixed step size from the first gradient: 0.05 Angstrom / max |g|
+    plan.intensity(pos, f, I, amp)
+    _, dLdI = api.speckle_loss(I, It)
+    plan.grad(pos, f, amp, dLdI, retile=False, g32=g)
+    state["step"] = 0.05 / float(g.abs().max())
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    graph = None
+    if args.graph:
+        s_cap = torch.cuda.Stream()
+        s_cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_cap):
+            step()
+        torch.cuda.current_stream().wait_stream(s_cap)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            loss_g = step()
+        graph.replay()
+        torch.cuda.synchronize()
+    log("warmup done")
+    api.timing_enable(not args.graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        if graph is not None:
+            graph.replay()
+            loss = loss_g
+        else:
+            loss = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fwd = api.timing_read("fwd32")
+    grd = api.timing_read("grad32")
+    binr = api.timing_read("bin")
+    api.timing_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    pairs_step = 2.0 * N * Q
+    value = pairs_step / (ms_step * 1e-3) / 1e9
+    log("timed %d steps: %.3f ms/step, %.1f G pairs/s, loss %.6g" % (args.steps, ms_step, value,
+                                                                      float(loss[0])))
+
+    plan.close()
+    kern = {}
+    for name, rec, peak in (("forward_fp32c", fwd, PEAK_SINCOS_PAIRS), ("adjoint_fp32c", grd, PEAK_SIN_PAIRS)):
+        avg_ms = rec["ms"] / max(rec["launches"], 1)
+        work = rec["work"] / max(rec["launches"], 1)
+        ach = work / (avg_ms * 1e-3) / 1e9
+        kern[name] = {"avg_ms": avg_ms, "launches": rec["launches"], "pairs_per_launch": work,
+                      "achieved_Gpair_s": ach, "peak_Gpair_s": peak / 1e9, "frac": ach / (peak / 1e9)}
+    kern["binning"] = {"avg_ms": binr["ms"] / max(binr["launches"], 1), "launches": binr["launches"]}
+    dom = max(("forward_fp32c", "adjoint_fp32c"), key=lambda k: kern[k]["avg_ms"])
+    src = os.path.join(ROOT, "paper_2204_13241_amd", "csrc", "k_fp32c.hip")
+    roofline = {
+        "bound": "alu",
+        "kernel": dom,
+        "achieved": kern[dom]["achieved_Gpair_s"],
+        "peak": kern[dom]["peak_Gpair_s"],
+        "unit": "Gpair/s",
+        "frac": kern[dom]["frac"],
+        "traffic": traffic_from_profile(src) if dom == "forward_fp32c" else None,
+    }
+
+    # accuracy against the exact FP64 form at the final positions, and FP64 timing
+    extra = {}
+    if not args.no_fp64:
+        api.timing_enable(True)
+        I64, amp64 = api.intensity(pos, f, q, "fp64", return_amp=True)
+        _, w64 = api.speckle_loss(I64, It)
+        g64 = api.intensity_grad(pos, f, q, amp64, w64, "fp64", out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        t64f = api.timing_read("fwd64")["ms"]
+        t64g = api.timing_read("grad64")["ms"]
+        api.timing_enable(False)
+        I32, amp32 = api.intensity(pos, f, q, "fp32c", box=L, return_amp=True)
+        _, w32 = api.speckle_loss(I32, It)
+        g32 = api.intensity_grad(pos, f, q, amp32, w32, "fp32c", box=L, out_dtype=torch.float64)
+        g32k = api.intensity_grad(pos, f, q, amp64, w64, "fp32c", box=L, out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        I64h, I32h = I64.cpu().numpy(), I32.cpu().numpy()
+        inc = float(np.sum(f_np ** 2))
+        e_I = float(np.max(np.abs(I32h - I64h) / np.maximum(I64h, inc)))
+        g64h = g64.cpu().numpy()
+        extra["accuracy_vs_fp64_form"] = {
+            "e_I_scaled": e_I,
+            "e_I_l2": float(np.linalg.norm(I32h - I64h) / np.linalg.norm(I64h)),
+            "e_grad_chain": rel_grad_err(g32.cpu().numpy(), g64h),
+            "e_grad_kernel": rel_grad_err(g32k.cpu().numpy(), g64h),
+            "tolerance": 1e-5,
+        }
+        fp64_ms = t64f + t64g
+        extra["fp64_form"] = {"fwd_ms": t64f, "grad_ms": t64g,
+                              "pairs_per_s": pairs_step / (fp64_ms * 1e-3),
+                              "speedup_fp32c_kernels": fp64_ms / (kern["forward_fp32c"]["avg_ms"] + kern["adjoint_fp32c"]["avg_ms"]),
+                              "speedup_fp32c_step": fp64_ms / ms_step}
+        log("accuracy", extra["accuracy_vs_fp64_form"], "fp64", extra["fp64_form"])
+        cpu_amp, cpu_w = amp64.cpu().numpy(), w64.cpu().numpy()
+    else:
+        cpu_amp = np.zeros((Q, 2))
+        cpu_w = np.zeros(Q)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "differentiation: N=65536 uniform atoms (rho 0.021/A^3), f=1, 512x512 "
+                               "planar q in [-3,3]/A, FP32C forward + loss + FP32C adjoint + GD update",
+                   "graph": bool(args.graph),
+                   "n_atoms": N, "n_q": Q, "pairs_per_step": pairs_step, "precision": "fp32c",
+                   "tile_shape_fwd": api.get_tile_shape(0), "tile_shape_grad": api.get_tile_shape(1)},
+        "roofline": roofline,
+        "valu_roofline_frac": value / (PEAK_SINCOS_PAIRS / 1e9),
+        "kernels": kern,
+    }
+    result.update(extra)
+    if not args.no_probe:
+        result["measured_peaks"] = {
+            "sincos_lane_ops_per_s": api.roofline_probe(0),
+            "fma32_lane_ops_per_s": api.roofline_probe(1),
+            "fma64_lane_ops_per_s": api.roofline_probe(2),
+            "copy_bytes_per_s": api.roofline_probe(3, 1 << 30),
+        }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(r0, f_np, q_np, cpu_amp, cpu_w, budget_s=args.cpu_budget)
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--graph", action="store_true", help="time HIP-graph replays of the step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    res = run_grad(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

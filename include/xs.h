@@ -204,6 +204,78 @@ typedef struct xs_tile_shape {
 xs_status xs_get_tile_shape(int32_t kind, xs_tile_shape *out);
 xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape);
 
+/*
+ * Batch plans (FP32C only): the one persistent, graph-capturable form of the
+ * pair sums for a fixed batch layout and fixed pixels.
+ *
+ * xs_plan_create builds the work lists of the batch (every system and frame
+ * of uneven atom count in one work queue, largest items first), allocates all
+ * device memory the calls need, and orders the pixels along a Hilbert curve in
+ * q (enqueued on `stream`).  The q array must stay at the same address and
+ * unchanged for the life of the plan.  Tile shapes are those set by
+ * xs_set_tile_shape when the plan is created.
+ *
+ * xs_plan_intensity and xs_plan_grad then only launch kernels on `stream`
+ * (no allocation, copy or memset), so a caller may capture them in a HIP
+ * graph and replay it; positions, form factors and outputs may change between
+ * replays in place.  Arguments as for xs_intensity_direct / xs_intensity_grad
+ * with the plan's batch layout.  xs_plan_grad re-tiles the atoms when
+ * `retile` is non-zero; with retile = 0 it reuses the tiles of the last
+ * xs_plan_intensity (the positions must not have changed since).  Calls on
+ * one plan must be ordered (one stream); plans are not thread-safe.
+ */
+typedef struct xs_plan xs_plan;
+xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **plan, void *stream);
+xs_status xs_plan_intensity(xs_plan *plan, const double *pos, const double *f, double *I_out,
+                            double *amp_out, void *stream);
+xs_status xs_plan_grad(xs_plan *plan, const double *pos, const double *f, const double *amp,
+                       const double *dL_dI, int32_t retile, float *dL_dr, double *dL_dr64,
+                       void *stream);
+/* Waits for the device, then frees the plan's memory.  NULL is accepted. */
+xs_status xs_plan_destroy(xs_plan *plan);
+
+/*
+ * Speckle-matching loss of the differentiation workload and its gradient with
+ * respect to the intensities (deterministic two-pass reduction, FP64):
+ *     L = sum_p (I_p - It_p)^2 / sum_p It_p^2,   dL/dI_p = 2 (I_p - It_p) / sum_p It_p^2.
+ *   I, I_target  device double [n]
+ *   loss_out     device double [2]: (L, sum It^2)
+ *   dL_dI        device double [n], or NULL
+ */
+xs_status xs_speckle_loss(const double *I, const double *I_target, int64_t n, double *loss_out,
+                          double *dL_dI, void *stream);
+
+/*
+ * Gradient-descent update of positions, pos -= step * dL/dr (FP64 fused
+ * multiply-add), from either gradient buffer (dL_dr64 preferred when both are
+ * given).  pos, dL_dr, dL_dr64: device arrays of n values.
+ */
+xs_status xs_position_step(double *pos, const float *dL_dr, const double *dL_dr64, int64_t n,
+                           double step, void *stream);
+
+/*
+ * Kernel timing with HIP events recorded on the stream each kernel runs on.
+ * xs_timing_enable(1) clears the counters and starts recording; (0) stops.
+ * xs_timing_read(kind) waits for the recorded events and returns the summed
+ * duration (ms), number of launches and work (atom-pixel pairs for kinds 0-3,
+ * atoms for 4, intensity bytes read for 5-6) since enabling.
+ *   kind 0: FP32C forward pair kernel   1: FP32C gradient pair kernel
+ *        2: FP64 forward kernel         3: FP64 gradient kernel
+ *        4: FP32C binning               5: g2 call     6: XSVS call
+ */
+xs_status xs_timing_enable(int32_t on);
+xs_status xs_timing_read(int32_t kind, double *total_ms, int64_t *launches, double *work);
+
+/*
+ * Roofline microbenchmarks (throughput of the units the kernels are bound by):
+ *   kind 0: v_sin_f32 + v_cos_f32 lane operations per second
+ *   kind 1: FP32 fused multiply-add lane operations per second (not packed)
+ *   kind 2: FP64 fused multiply-add lane operations per second
+ *   kind 3: HBM bytes per second (read + write) of a plain copy of `bytes`
+ * `rate` is a host double.  Uses the library's scratch memory.
+ */
+xs_status xs_roofline_probe(int32_t kind, int64_t bytes, double *rate, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,6 +9,7 @@ include/xs.h; this package is the thin Python binding.
 __all__ = [
     "intensity", "intensity_systems", "intensity_grad", "g2_rings", "xsvs_contrast",
     "IntensityFn", "make_batch", "get_tile_shape", "set_tile_shape", "shutdown", "inputs",
+    "speckle_loss", "position_step", "timing_enable", "timing_read", "roofline_probe", "Plan",
 ]
 
 

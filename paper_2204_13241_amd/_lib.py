@@ -18,6 +18,8 @@ STATUS_NAMES = {0: "XS_OK", 1: "XS_EINVAL", 2: "XS_ENOMEM", 3: "XS_EDEVICE", 4: 
 EXPORTS = [
     "xs_intensity_direct", "xs_intensity_grad", "xs_g2_rings", "xs_xsvs_contrast",
     "xs_last_error", "xs_version", "xs_shutdown", "xs_get_tile_shape", "xs_set_tile_shape",
+    "xs_speckle_loss", "xs_position_step", "xs_timing_enable", "xs_timing_read",
+    "xs_roofline_probe", "xs_plan_create", "xs_plan_intensity", "xs_plan_grad", "xs_plan_destroy",
 ]
 
 _P = ctypes.c_void_p
@@ -82,6 +84,15 @@ def load():
         "xs_shutdown": (i32, []),
         "xs_get_tile_shape": (i32, [i32, sp]),
         "xs_set_tile_shape": (i32, [i32, sp]),
+        "xs_speckle_loss": (i32, [_P, _P, i64, _P, _P, _P]),
+        "xs_position_step": (i32, [_P, _P, _P, i64, ctypes.c_double, _P]),
+        "xs_timing_enable": (i32, [i32]),
+        "xs_timing_read": (i32, [i32, _dp, _i64p, _dp]),
+        "xs_roofline_probe": (i32, [i32, i64, _dp, _P]),
+        "xs_plan_create": (i32, [bp, _P, ctypes.POINTER(_P), _P]),
+        "xs_plan_intensity": (i32, [_P, _P, _P, _P, _P, _P]),
+        "xs_plan_grad": (i32, [_P, _P, _P, _P, _P, i32, _P, _P, _P]),
+        "xs_plan_destroy": (i32, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -264,3 +264,122 @@ class IntensityFn(torch.autograd.Function):
 
 def shutdown():
     _lib.check(_lib.load().xs_shutdown())
+
+
+def speckle_loss(I: torch.Tensor, I_target: torch.Tensor, want_grad: bool = True):
+    """L = sum (I - I_t)^2 / sum I_t^2 and dL/dI (device); returns (loss_buf[2], dL_dI)."""
+    _need(I, "I"), _need(I_target, "I_target")
+    if I.numel() != I_target.numel():
+        raise ValueError("I and I_target differ in size")
+    out = torch.empty(2, dtype=torch.float64, device=I.device)
+    w = torch.empty_like(I) if want_grad else None
+    _lib.check(_lib.load().xs_speckle_loss(_ptr(I), _ptr(I_target), I.numel(), _ptr(out), _ptr(w),
+                                           _stream()))
+    return out, w
+
+
+def position_step(pos: torch.Tensor, grad: torch.Tensor, step: float):
+    """pos -= step * grad, in place (grad float32 or float64, same shape)."""
+    _need(pos, "pos")
+    if grad.shape != pos.shape or not grad.is_cuda or not grad.is_contiguous():
+        raise ValueError("grad must be a contiguous GPU tensor shaped like pos")
+    g32 = grad if grad.dtype == torch.float32 else None
+    g64 = grad if grad.dtype == torch.float64 else None
+    if g32 is None and g64 is None:
+        raise ValueError("grad must be float32 or float64")
+    _lib.check(_lib.load().xs_position_step(_ptr(pos), _ptr(g32), _ptr(g64), pos.numel(),
+                                            float(step), _stream()))
+
+
+TIMER_KINDS = {"fwd32": 0, "grad32": 1, "fwd64": 2, "grad64": 3, "bin": 4, "g2": 5, "xsvs": 6}
+
+
+def timing_enable(on: bool = True):
+    _lib.check(_lib.load().xs_timing_enable(1 if on else 0))
+
+
+def timing_read(kind) -> dict:
+    k = TIMER_KINDS[kind] if isinstance(kind, str) else int(kind)
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    work = ctypes.c_double(0.0)
+    _lib.check(_lib.load().xs_timing_read(k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(work)))
+    return {"ms": ms.value, "launches": n.value, "work": work.value}
+
+
+def roofline_probe(kind: int, nbytes: int = 1 << 30) -> float:
+    """0: sin+cos lane-ops/s, 1: FP32 FMA lane-ops/s, 2: FP64 FMA lane-ops/s, 3: copy bytes/s."""
+    r = ctypes.c_double(0.0)
+    _lib.check(_lib.load().xs_roofline_probe(int(kind), int(nbytes), ctypes.byref(r), _stream()))
+    return r.value
+
+
+class Plan:
+    """FP32C batch plan over the C ABI (xs_plan_*): fixed batch layout and pixels.
+
+    systems: list of (n_atoms, n_frames, q [Q_s, 3] float64 GPU tensor, box).
+    Positions, form factors and outputs use the packed layout of make_batch:
+    pos [sum_s F_s N_s, 3], f [sum_s N_s], I [sum_s F_s Q_s], amp [.., 2].
+    After construction, intensity() and grad() only launch kernels, so they
+    can be captured in a torch.cuda.CUDAGraph and replayed.
+    """
+
+    def __init__(self, systems):
+        if not systems:
+            raise ValueError("a plan needs at least one system")
+        for i, (_, _, q, _) in enumerate(systems):
+            _need(q, "q[%d]" % i)
+        self.n_atoms = [int(n) for n, _, _, _ in systems]
+        self.n_frames = [int(t) for _, t, _, _ in systems]
+        self.n_q = [int(q.shape[0]) for _, _, q, _ in systems]
+        boxes = np.stack([_box3(bx, None) for _, _, _, bx in systems])
+        self.batch = make_batch(self.n_atoms, self.n_q, self.n_frames, boxes)
+        self.q = torch.cat([q for _, _, q, _ in systems]).contiguous()
+        self.total_out = self.batch.total_out
+        self.total_pos = int(np.sum(np.asarray(self.n_atoms) * np.asarray(self.n_frames)))
+        self.total_f = int(np.sum(self.n_atoms))
+        self._st = self.batch.struct()
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().xs_plan_create(ctypes.byref(self._st), _ptr(self.q), ctypes.byref(h),
+                                              _stream()))
+        self._h = h
+
+    @classmethod
+    def single(cls, n_atoms: int, n_frames: int, q: torch.Tensor, box):
+        return cls([(n_atoms, n_frames, q, box)])
+
+    def _check(self, pos, f):
+        _need(pos, "pos"), _need(f, "f")
+        if pos.numel() != 3 * self.total_pos or f.numel() != self.total_f:
+            raise ValueError("pos / f do not match the plan's batch layout")
+
+    def intensity(self, pos, f, I=None, amp=None, want_amp=True):
+        self._check(pos, f)
+        dev = pos.device
+        if I is None:
+            I = torch.empty(self.total_out, dtype=torch.float64, device=dev)
+        if amp is None and want_amp:
+            amp = torch.empty((self.total_out, 2), dtype=torch.float64, device=dev)
+        _lib.check(_lib.load().xs_plan_intensity(self._h, _ptr(pos), _ptr(f), _ptr(I), _ptr(amp),
+                                                 _stream()))
+        return I, amp
+
+    def grad(self, pos, f, amp, dL_dI, retile=True, g32=None, g64=None):
+        self._check(pos, f)
+        _need(amp, "amp"), _need(dL_dI, "dL_dI")
+        if g32 is None and g64 is None:
+            g32 = torch.empty((self.total_pos, 3), dtype=torch.float32, device=pos.device)
+        _lib.check(_lib.load().xs_plan_grad(self._h, _ptr(pos), _ptr(f), _ptr(amp), _ptr(dL_dI),
+                                            1 if retile else 0, _ptr(g32), _ptr(g64), _stream()))
+        return g32 if g32 is not None else g64
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().xs_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -3,26 +3,34 @@
 //
 // Sec. 3.1 (Algorithm 1): every pixel's amplitude is an independent sum over
 // atoms, p^e(q) = sum_j f_j exp(-i q.r_j) (Eq. (pe_ri)), I = |p^e|^2 (Eq. (Iq_pq)).
-// The GPU form keeps the phase accurate in large boxes by splitting it:
-//   q.r_j / (2 pi) = q_rev . o_k  +  q_rev . d_j,        d_j = r_j - o_k,
-// where o_k is the centre of a compact spatial tile of atoms.  The first term
-// is reduced modulo one revolution in FP64 once per (pixel, tile); the second
-// is small (|d_j| <~ 10 Angstrom) and runs in FP32 together with the hardware
-// sine and cosine (v_sin_f32 / v_cos_f32 take revolutions) and the tile
-// partial sums, which are folded into FP64 after every tile.
+// FP32 cannot hold the phase q.r/(2 pi) of a large box (hundreds of
+// revolutions) to 1e-7 revolution, so the phase is split.  Atoms are sorted
+// along a Hilbert curve and cut into tiles of 64 with FP64 origin o_k; pixels
+// are sorted the same way in q-space and cut into compact groups with FP64
+// centre q_c.  With d_j = r_j - o_k and dq_p = q_p - q_c (revolutions per
+// Angstrom):
+//   q_p.r_j = q_p.o_k + q_c.d_j + dq_p.d_j
+//   theta(p,k) = frac(q_p.o_k)  FP64, once per (pixel, tile)
+//   beta(j)    = frac(q_c.d_j)  FP64 from the exact offset, once per (atom, group)
+//   dq_p.d_j   FP32, |.| < ~0.6 revolution
+// so the FP32 part of every phase stays below ~2 revolutions and rounds at
+// ~1e-7 revolution.  v_sin_f32 / v_cos_f32 take revolutions.  Tile partial
+// sums run in FP32 and fold into FP64; chunk partials combine in fixed order.
 //
-// Pipeline per call:
-//   binning   (per segment = system x frame)  Morton cell key -> counting sort
-//             -> per-cell index sort (deterministic) -> tiles of 64 atoms with
-//             FP64 origin and FP32 (d, f), zero-padded;
-//   pair sum  persistent work queue over (segment, pixel tile, atom chunk),
-//             largest items first; partial amplitudes in FP64 per chunk;
-//   combine   chunks summed in fixed order -> amplitude and intensity.
-// The gradient uses the same tiles; see k_grad_fp32c.
+// Pipeline of a call:
+//   sort      atoms of every segment (system x frame) and pixels of every
+//             system by 30-bit Hilbert index (deterministic radix sort);
+//   tiles     64 consecutive sorted atoms, bounding-box centre as FP64
+//             origin, FP32 offsets split hi + lo, FP32 form factor;
+//   pair sum  persistent work queue over items, largest first;
+//   combine   chunk partials summed in order, written in input pixel order.
 #include <hip/hip_runtime.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -34,28 +42,36 @@ namespace {
 constexpr int kTile = 64;        // atoms per spatial tile (one wavefront)
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kWaves = kBlock / 64;
+constexpr int kHilbertBits = 10;  // per dimension
 constexpr double kInvTwoPi = 0x1.45f306dc9c883p-3;  // RN(1/(2 pi))
 
 // ---------------------------------------------------------------- tables
 
-struct BinSeg {            // binning view of one segment
+struct BinSeg {            // tiling view of one segment (system x frame)
     int64_t pos;           // atom offset of the frame in pos
     int64_t f;             // offset into f
-    int64_t atom0;         // offset of this segment's atoms in key / sorted arrays
-    int64_t key0;          // offset of this segment's cells in the histogram
+    int64_t atom0;         // offset of this segment's atoms in the key / index arrays
+    int64_t cell0;         // offset of this segment's cells in the cell histogram
     int64_t tile0;         // first tile of this segment
-    double lo[3];          // binning box origin (0)
-    double inv_cell[3];    // cells per Angstrom
-    int32_t ncell[3];      // cells per dimension (power of two)
-    int32_t bits;          // Morton bits per dimension
+    double scale[3];       // cells per Angstrom along each box edge
+    int32_t bits;          // Hilbert bits per dimension (2^bits cells per edge)
     int32_t n_atoms;
     int32_t n_tiles;
+    int32_t pad;
+};
+
+struct PixSet {            // one distinct pixel set (a system's q)
+    int64_t q;             // pixel offset into q
+    int64_t slot0;         // offset of its pixels in the sorted order
+    int32_t n_q;
+    int32_t pad;
 };
 
 struct FwdSeg {            // pair-sum view of one segment
     int64_t q;             // pixel offset into q
+    int64_t slot0;         // offset of the segment's pixel set in the sorted order
     int64_t out;           // pixel offset into outputs
-    int64_t part;          // offset (pixels) of this segment's partials: chunk c at part + c*n_q
+    int64_t part;          // offset (pixels) of partials: chunk c at part + c*n_q
     int64_t tile0;
     int32_t n_q;
     int32_t n_tiles;
@@ -65,20 +81,22 @@ struct FwdSeg {            // pair-sum view of one segment
 
 struct FwdItem {
     int32_t seg;
-    int32_t p0;            // first pixel
-    int32_t t0;            // first tile
+    int32_t p0;            // first sorted pixel slot of the item
+    int32_t t0;            // first tile (relative to the segment)
     int32_t nt;            // tiles in this chunk
     int32_t chunk;
     int32_t pad;
 };
 
 struct GradSeg {
-    int64_t q;             // pixel offset into q / prepared pixel data
+    int64_t q;             // pixel offset into q
+    int64_t slot0;         // offset of the pixel set in the sorted order / prepared data
     int64_t out;           // pixel offset into amp / dL_dI
     int64_t pos;           // atom offset in pos (for outputs)
     int64_t f;             // offset into f
     int64_t tile0;
     int64_t part;          // offset (atom slots) of partials: chunk c at part + c*n_tiles*64
+    int64_t grp0;          // first 64-pixel group of the pixel set in the centre table
     int32_t n_q;
     int32_t n_tiles;
     int32_t n_chunks;
@@ -89,118 +107,242 @@ struct GradItem {
     int32_t seg;
     int32_t t0;            // first tile of this group
     int32_t nt;            // tiles in the group (<= kWaves * AL)
-    int32_t p0;            // first pixel of the chunk
+    int32_t p0;            // first sorted pixel slot of the chunk (multiple of 64)
     int32_t np;            // pixels in the chunk
     int32_t chunk;
 };
 
-// Morton interleave of three 10-bit coordinates.
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000ffu;
-    v = (v | (v << 8)) & 0x0300f00fu;
-    v = (v | (v << 4)) & 0x030c30c3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
+// ---------------------------------------------------------------- Hilbert index
+// Skilling's transpose form of the Hilbert curve (J. Skilling, "Programming the
+// Hilbert curve", AIP Conf. Proc. 707, 2004): undo excess work on the axes,
+// Gray-encode, then interleave the transposed bits.  Consecutive indices are
+// always face-adjacent cells, so a run of consecutive points is compact.
+// bits in [1, 10].
+__device__ __forceinline__ uint32_t hilbert3(uint32_t x0, uint32_t x1, uint32_t x2, int bits) {
+    uint32_t X[3] = {x0, x1, x2};
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    X[0] ^= t;
+    X[1] ^= t;
+    X[2] ^= t;
+    uint32_t h = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        h = (h << 3) | (((X[0] >> b) & 1u) << 2) | (((X[1] >> b) & 1u) << 1) | ((X[2] >> b) & 1u);
+    return h;
 }
 
-// ---------------------------------------------------------------- binning
+__device__ __forceinline__ uint32_t cell_of(double x, double scale, int bits) {
+    const double top = double((1 << bits) - 1);
+    double c = __builtin_floor(x * scale);
+    c = c < 0.0 ? 0.0 : (c > top ? top : c);
+    if (!(c == c)) c = 0.0;  // NaN positions land in cell 0
+    return static_cast<uint32_t>(c);
+}
 
-__global__ __launch_bounds__(kBlock) void k_bin_key(const BinSeg *__restrict__ segs,
-                                                    const double *__restrict__ pos,
-                                                    uint32_t *__restrict__ keys,
-                                                    int32_t *__restrict__ hist) {
+// ---------------------------------------------------------------- atom tiling
+// Deterministic counting sort of every segment's atoms by Hilbert cell, built
+// from plain kernels only (no memset or copy), so a captured graph can replay
+// it: zero -> cell key + histogram -> exclusive scan (3 phases) -> scatter ->
+// per-cell ascending index order -> tiles.
+
+__global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *__restrict__ p, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock)
+        p[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_keys(const BinSeg *__restrict__ segs,
+                                                      const double *__restrict__ pos,
+                                                      uint32_t *__restrict__ keys,
+                                                      int32_t *__restrict__ hist) {
     const BinSeg sg = segs[blockIdx.y];
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= sg.n_atoms) return;
     const double *r = pos + (sg.pos + j) * 3;
-    uint32_t c[3];
-    for (int d = 0; d < 3; ++d) {
-        double x = (r[d] - sg.lo[d]) * sg.inv_cell[d];
-        int ci = static_cast<int>(__builtin_floor(x));
-        ci = ci < 0 ? 0 : (ci >= sg.ncell[d] ? sg.ncell[d] - 1 : ci);
-        if (!(x == x)) ci = 0;  // NaN positions land in cell 0
-        c[d] = static_cast<uint32_t>(ci);
-    }
-    const uint32_t key = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
-    keys[sg.atom0 + j] = key;
-    atomicAdd(&hist[sg.key0 + key], 1);
+    const uint32_t h = hilbert3(cell_of(r[0], sg.scale[0], sg.bits), cell_of(r[1], sg.scale[1], sg.bits),
+                                cell_of(r[2], sg.scale[2], sg.bits), sg.bits);
+    keys[sg.atom0 + j] = h;
+    atomicAdd(&hist[sg.cell0 + h], 1);
 }
 
-// Exclusive scan of each segment's cell histogram; start[] keeps the cell
-// starts, hist[] becomes the scatter cursor.  One block per segment.
-__global__ __launch_bounds__(1024) void k_bin_scan(const BinSeg *__restrict__ segs,
-                                                   int32_t *__restrict__ hist,
-                                                   int32_t *__restrict__ start) {
-    const BinSeg sg = segs[blockIdx.x];
-    const int64_t nk = int64_t(1) << (3 * sg.bits);
-    __shared__ int32_t part[1024];
-    const int64_t per = (nk + 1023) / 1024;
-    const int64_t a = threadIdx.x * per, b = (a + per < nk) ? a + per : nk;
-    int32_t s = 0;
-    for (int64_t i = a; i < b; ++i) s += hist[sg.key0 + i];
-    part[threadIdx.x] = s;
+constexpr int kScanBlock = 1024;  // elements per scan block (256 threads x 4)
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ v, int64_t n,
+                                                        int32_t *__restrict__ sums) {
+    __shared__ int32_t s[kBlock];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock;
+    int32_t a = 0;
+    for (int i = threadIdx.x; i < kScanBlock; i += kBlock)
+        if (base + i < n) a += v[base + i];
+    s[threadIdx.x] = a;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            const int32_t v = part[i];
-            part[i] = run;
-            run += v;
-        }
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) sums[blockIdx.x] = s[0];
+}
+
+// Exclusive scan of the block sums in place (one block).
+__global__ __launch_bounds__(1024) void k_scan_top(int32_t *__restrict__ sums, int64_t nb) {
+    __shared__ int32_t s[1024];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t a = threadIdx.x * per, b = a + per < nb ? a + per : nb;
+    int32_t t = 0;
+    for (int64_t i = a; i < b; ++i) t += sums[i];
+    s[threadIdx.x] = t;
     __syncthreads();
-    int32_t run = part[threadIdx.x];
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele
+        const int32_t x = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += x;
+        __syncthreads();
+    }
+    int32_t run = threadIdx.x > 0 ? s[threadIdx.x - 1] : 0;
     for (int64_t i = a; i < b; ++i) {
-        const int32_t v = hist[sg.key0 + i];
-        start[sg.key0 + i] = run;
-        hist[sg.key0 + i] = run;
-        run += v;
+        const int32_t x = sums[i];
+        sums[i] = run;
+        run += x;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(const BinSeg *__restrict__ segs,
-                                                        const uint32_t *__restrict__ keys,
-                                                        int32_t *__restrict__ cursor,
-                                                        int32_t *__restrict__ sorted) {
+// start[i] = exclusive prefix of v; cursor[i] = start[i].
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *__restrict__ v, int64_t n,
+                                                      const int32_t *__restrict__ sums,
+                                                      int32_t *__restrict__ start,
+                                                      int32_t *__restrict__ cursor) {
+    __shared__ int32_t s[kBlock];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanBlock + threadIdx.x * 4;
+    int32_t x[4], t = 0;
+    for (int k = 0; k < 4; ++k) {
+        x[k] = base + k < n ? v[base + k] : 0;
+        t += x[k];
+    }
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int32_t y = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += y;
+        __syncthreads();
+    }
+    int32_t run = sums[blockIdx.x] + (threadIdx.x > 0 ? s[threadIdx.x - 1] : 0);
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) {
+            start[base + k] = run;
+            cursor[base + k] = run;
+            run += x[k];
+        }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_scatter(const BinSeg *__restrict__ segs,
+                                                         const uint32_t *__restrict__ keys,
+                                                         int32_t *__restrict__ cursor,
+                                                         int32_t *__restrict__ sorted) {
     const BinSeg sg = segs[blockIdx.y];
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= sg.n_atoms) return;
-    const int32_t slot = atomicAdd(&cursor[sg.key0 + keys[sg.atom0 + j]], 1);
-    sorted[sg.atom0 + slot] = j;
+    const int32_t slot = atomicAdd(&cursor[sg.cell0 + keys[sg.atom0 + j]], 1);
+    sorted[slot] = j;
 }
 
-// Restore a deterministic order: each cell's atoms ascending by index.
-// After the scatter, cursor[c] is the end of cell c and start[c] its start.
-__global__ __launch_bounds__(kBlock) void k_bin_sort_cells(const BinSeg *__restrict__ segs,
-                                                           const int32_t *__restrict__ start,
-                                                           const int32_t *__restrict__ end,
-                                                           int32_t *__restrict__ sorted) {
-    const BinSeg sg = segs[blockIdx.y];
+// Each cell's atoms in ascending index order (after the scatter, cursor[c]
+// is the end of cell c).
+__global__ __launch_bounds__(kBlock) void k_cell_order(const int32_t *__restrict__ start,
+                                                       const int32_t *__restrict__ end, int64_t n,
+                                                       int32_t *__restrict__ sorted) {
     const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (c >= (int64_t(1) << (3 * sg.bits))) return;
-    int32_t *v = sorted + sg.atom0;
-    const int32_t a = start[sg.key0 + c], b = end[sg.key0 + c];
+    if (c >= n) return;
+    const int32_t a = start[c], b = end[c];
     for (int32_t i = a + 1; i < b; ++i) {
-        const int32_t x = v[i];
+        const int32_t x = sorted[i];
         int32_t k = i - 1;
-        while (k >= a && v[k] > x) {
-            v[k + 1] = v[k];
+        while (k >= a && sorted[k] > x) {
+            sorted[k + 1] = sorted[k];
             --k;
         }
-        v[k + 1] = x;
+        sorted[k + 1] = x;
     }
 }
 
-// One wavefront per tile: bounding-box centre as origin (FP64), offsets and
-// form factors in FP32, zero padding past the segment's last atom.
-__global__ __launch_bounds__(kBlock) void k_bin_tiles(const BinSeg *__restrict__ segs,
-                                                      const double *__restrict__ pos,
-                                                      const double *__restrict__ f,
-                                                      const int32_t *__restrict__ sorted,
-                                                      float4 *__restrict__ tiles,
-                                                      double4 *__restrict__ origins,
-                                                      int32_t *__restrict__ tile_atom) {
+// Pixel sets: bounding box (one block per set), then 64-bit keys
+// (set << 30 | Hilbert index of the q cell) for a radix sort.
+__global__ __launch_bounds__(1024) void k_pix_bbox(const PixSet *__restrict__ sets,
+                                                   const double *__restrict__ q,
+                                                   double *__restrict__ bbox) {
+    const PixSet ps = sets[blockIdx.x];
+    __shared__ double s_lo[3][1024], s_hi[3][1024];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int p = threadIdx.x; p < ps.n_q; p += 1024)
+        for (int c = 0; c < 3; ++c) {
+            const double v = q[(ps.q + p) * 3 + c];
+            lo[c] = fmin(lo[c], v);
+            hi[c] = fmax(hi[c], v);
+        }
+    for (int c = 0; c < 3; ++c) {
+        s_lo[c][threadIdx.x] = lo[c];
+        s_hi[c][threadIdx.x] = hi[c];
+    }
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int c = 0; c < 3; ++c) {
+                s_lo[c][threadIdx.x] = fmin(s_lo[c][threadIdx.x], s_lo[c][threadIdx.x + off]);
+                s_hi[c][threadIdx.x] = fmax(s_hi[c][threadIdx.x], s_hi[c][threadIdx.x + off]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        bbox[6 * blockIdx.x + threadIdx.x] = s_lo[threadIdx.x][0];
+        bbox[6 * blockIdx.x + 3 + threadIdx.x] = s_hi[threadIdx.x][0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pix_keys(const PixSet *__restrict__ sets,
+                                                     const double *__restrict__ q,
+                                                     const double *__restrict__ bbox,
+                                                     uint64_t *__restrict__ keys,
+                                                     int32_t *__restrict__ vals) {
+    const PixSet ps = sets[blockIdx.y];
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= ps.n_q) return;
+    uint32_t c[3];
+    for (int d = 0; d < 3; ++d) {
+        const double lo = bbox[6 * blockIdx.y + d], hi = bbox[6 * blockIdx.y + 3 + d];
+        const double span = hi - lo;
+        const double scale = span > 0.0 ? 1024.0 / (span * 1.000001) : 0.0;
+        c[d] = cell_of(q[(ps.q + p) * 3 + d] - lo, scale, 10);
+    }
+    keys[ps.slot0 + p] = (static_cast<uint64_t>(blockIdx.y) << 30) | hilbert3(c[0], c[1], c[2], 10);
+    vals[ps.slot0 + p] = p;
+}
+
+// One wavefront per tile: bounding-box centre as FP64 origin; offsets in FP32
+// as hi + lo (lo = residual of the FP64 offset); FP32 form factor; zero padding.
+__global__ __launch_bounds__(kBlock) void k_make_tiles(const BinSeg *__restrict__ segs,
+                                                       const double *__restrict__ pos,
+                                                       const double *__restrict__ f,
+                                                       const int32_t *__restrict__ sorted,
+                                                       float4 *__restrict__ t_hi,
+                                                       float4 *__restrict__ t_lo,
+                                                       double4 *__restrict__ origins,
+                                                       int32_t *__restrict__ tile_atom) {
     const BinSeg sg = segs[blockIdx.y];
     const int t = blockIdx.x * kWaves + threadIdx.x / 64;
     const int lane = threadIdx.x & 63;
@@ -212,7 +354,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_tiles(const BinSeg *__restrict__
     if (real) {
         j = sorted[sg.atom0 + slot];
         const double *rp = pos + (sg.pos + j) * 3;
-        r[0] = rp[0]; r[1] = rp[1]; r[2] = rp[2];
+        r[0] = rp[0];
+        r[1] = rp[1];
+        r[2] = rp[2];
     }
     double o[3];
     for (int d = 0; d < 3; ++d) {
@@ -224,42 +368,71 @@ __global__ __launch_bounds__(kBlock) void k_bin_tiles(const BinSeg *__restrict__
         o[d] = 0.5 * (lo + hi);
     }
     const int64_t ti = sg.tile0 + t;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (real)
-        v = make_float4(static_cast<float>(r[0] - o[0]), static_cast<float>(r[1] - o[1]),
-                        static_cast<float>(r[2] - o[2]), static_cast<float>(f[sg.f + j]));
-    tiles[ti * kTile + lane] = v;
+    float4 vh = make_float4(0.f, 0.f, 0.f, 0.f), vl = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (real) {
+        const double d0 = r[0] - o[0], d1 = r[1] - o[1], d2 = r[2] - o[2];
+        const float h0 = static_cast<float>(d0), h1 = static_cast<float>(d1), h2 = static_cast<float>(d2);
+        vh = make_float4(h0, h1, h2, static_cast<float>(f[sg.f + j]));
+        vl = make_float4(static_cast<float>(d0 - h0), static_cast<float>(d1 - h1),
+                         static_cast<float>(d2 - h2), 0.f);
+    }
+    t_hi[ti * kTile + lane] = vh;
+    t_lo[ti * kTile + lane] = vl;
     tile_atom[ti * kTile + lane] = j;
     if (lane == 0) origins[ti] = make_double4(o[0], o[1], o[2], 0.0);
 }
 
-__global__ void k_reset_counter(int32_t *counter, int n) {
-    if (threadIdx.x < n) counter[threadIdx.x] = 0;
+__global__ void k_reset_counters(int32_t *counter, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) counter[i] = 0;
 }
 
-// Zero fill (used instead of hipMemsetAsync so the sequence stays capturable).
-__global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *__restrict__ p, int64_t n) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
+__device__ __forceinline__ float frac_f32(double t) { return static_cast<float>(t - __builtin_rint(t)); }
 
 // ---------------------------------------------------------------- forward pair sum
 //
-// Workgroup = 4 wavefronts x 64 lanes; lane owns QL pixels (p0 + k*256 + tid).
-// Atom tiles of the item's chunk are staged 4 at a time into LDS (double
-// buffered) and read back as broadcasts.  Per (pixel, tile): FP64 base phase
-// theta = frac(q_rev . o).  Per pair: phi = theta + q_rev . d (3 FMA, FP32),
-// v_sin/v_cos, 2 FMA.  Tile partials fold into FP64.
+// Workgroup = 4 wavefronts; the item's 256*QL pixels (consecutive in Hilbert
+// order, so compact in q) share one centre q_c.  Lane owns QL pixels.  Atom
+// tiles of the item's chunk are staged 4 at a time into LDS (double buffered)
+// with their beta(j) = frac(q_c.d_j), and read back as broadcasts.
+// Per pair the in-tile phase xi = beta + dq.d (2 FMA, or 3 when the item has
+// dq_z != 0) feeds v_sin/v_cos and 2 FMA into the tile sums
+// (C, S) = sum_j f_j (cos, sin)(2 pi xi).  The tile's base phase
+// theta = frac(q_p.o_k) (FP64) enters once per (pixel, tile) as a rotation,
+// sum_j f_j e^{2 pi i (theta + xi)} = e^{2 pi i theta} (C + i S), whose result
+// folds into FP64.
+template <int QL, bool PLANAR>
+__device__ __forceinline__ void tile_pairs(const float4 *__restrict__ at, const float *__restrict__ bt,
+                                           const float (&dqx)[QL], const float (&dqy)[QL],
+                                           const float (&dqz)[QL], float (&cs)[QL], float (&sn)[QL]) {
+#pragma unroll 4
+    for (int j = 0; j < kTile; ++j) {
+        const float4 a = at[j];
+        const float b = bt[j];
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            float ph = __builtin_fmaf(dqx[k], a.x, b);
+            ph = __builtin_fmaf(dqy[k], a.y, ph);
+            if (!PLANAR) ph = __builtin_fmaf(dqz[k], a.z, ph);
+            cs[k] = __builtin_fmaf(a.w, __builtin_amdgcn_cosf(ph), cs[k]);
+            sn[k] = __builtin_fmaf(a.w, __builtin_amdgcn_sinf(ph), sn[k]);
+        }
+    }
+}
+
 template <int QL>
 __global__ __launch_bounds__(kBlock) void k_forward_fp32c(
     const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
     const FwdSeg *__restrict__ segs, const double *__restrict__ q,
-    const float4 *__restrict__ tiles, const double4 *__restrict__ origins,
+    const int32_t *__restrict__ pix_order, const float4 *__restrict__ t_hi,
+    const float4 *__restrict__ t_lo, const double4 *__restrict__ origins,
     double2 *__restrict__ partial) {
     __shared__ float4 s_atoms[2][kWaves * kTile];
+    __shared__ float s_beta[2][kWaves * kTile];
     __shared__ double4 s_orig[2][kWaves];
+    __shared__ double s_q[3][QL][kBlock];  // item pixels, revolutions per Angstrom (FP64)
+    __shared__ double s_red[6][kWaves];
     __shared__ int32_t s_item;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
@@ -268,89 +441,131 @@ __global__ __launch_bounds__(kBlock) void k_forward_fp32c(
         if (it >= n_items) break;
         const FwdItem item = items[it];
         const FwdSeg sg = segs[item.seg];
-        // lane pixels
-        float qx[QL], qy[QL], qz[QL];
-        double dx[QL], dy[QL], dz[QL];
+        // lane pixels: sorted slots p0 + k*256 + tid
+        int32_t orig[QL];
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            const int sp = item.p0 + k * kBlock + tid;
+            const bool real = sp < sg.n_q;
+            const int p = pix_order[sg.slot0 + (real ? sp : sg.n_q - 1)];
+            orig[k] = real ? p : -1;
+            const double *qp = q + (sg.q + p) * 3;
+            for (int c = 0; c < 3; ++c) {
+                const double v = qp[c] * kInvTwoPi;
+                s_q[c][k][tid] = v;
+                if (real) {
+                    lo[c] = fmin(lo[c], v);
+                    hi[c] = fmax(hi[c], v);
+                }
+            }
+        }
+        // item centre q_c: bounding-box centre (wavefront then block reduction)
+        for (int c = 0; c < 3; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+                hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+            }
+        if (lane == 0)
+            for (int c = 0; c < 3; ++c) {
+                s_red[c][wave] = lo[c];
+                s_red[3 + c][wave] = hi[c];
+            }
+        __syncthreads();
+        double cen[3];
+        bool planar;
+        {
+            double l3[3], h3[3];
+            for (int c = 0; c < 3; ++c) {
+                l3[c] = s_red[c][0];
+                h3[c] = s_red[3 + c][0];
+                for (int w = 1; w < kWaves; ++w) {
+                    l3[c] = fmin(l3[c], s_red[c][w]);
+                    h3[c] = fmax(h3[c], s_red[3 + c][w]);
+                }
+                cen[c] = 0.5 * (l3[c] + h3[c]);
+            }
+            planar = l3[2] == h3[2];  // dq_z = 0 for every pixel of the item
+        }
+        float dqx[QL], dqy[QL], dqz[QL];
         double re64[QL], im64[QL];
 #pragma unroll
         for (int k = 0; k < QL; ++k) {
-            int p = item.p0 + k * kBlock + tid;
-            p = p < sg.n_q ? p : sg.n_q - 1;
-            const double *qp = q + (sg.q + p) * 3;
-            dx[k] = qp[0] * kInvTwoPi;
-            dy[k] = qp[1] * kInvTwoPi;
-            dz[k] = qp[2] * kInvTwoPi;
-            qx[k] = static_cast<float>(dx[k]);
-            qy[k] = static_cast<float>(dy[k]);
-            qz[k] = static_cast<float>(dz[k]);
+            dqx[k] = static_cast<float>(s_q[0][k][tid] - cen[0]);
+            dqy[k] = static_cast<float>(s_q[1][k][tid] - cen[1]);
+            dqz[k] = static_cast<float>(s_q[2][k][tid] - cen[2]);
             re64[k] = 0.0;
             im64[k] = 0.0;
         }
         const int64_t tbase = sg.tile0 + item.t0;
-        // stage group 0
         const int n_groups = (item.nt + kWaves - 1) / kWaves;
+        // stage group 0
         {
             const int tt = tid / kTile;
-            if (tt < item.nt) s_atoms[0][tid] = tiles[(tbase + tt) * kTile + (tid & (kTile - 1))];
+            if (tt < item.nt) {
+                const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
+                const float4 h = t_hi[ai], l = t_lo[ai];
+                const double b = __builtin_fma(cen[2], double(h.z) + double(l.z),
+                                 __builtin_fma(cen[1], double(h.y) + double(l.y), cen[0] * (double(h.x) + double(l.x))));
+                s_atoms[0][tid] = h;
+                s_beta[0][tid] = frac_f32(b);
+            }
             if (tid < kWaves && tid < item.nt) s_orig[0][tid] = origins[tbase + tid];
         }
         __syncthreads();
         for (int g = 0; g < n_groups; ++g) {
             const int buf = g & 1;
-            // prefetch the next group into registers, store after computing
-            float4 nxt = make_float4(0.f, 0.f, 0.f, 0.f);
-            double4 nxo = make_double4(0.0, 0.0, 0.0, 0.0);
+            // fetch the next group into registers; stored after this group's work
+            float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nl = nh;
+            double4 no = make_double4(0.0, 0.0, 0.0, 0.0);
             const int ng = g + 1;
             const bool have_next = ng < n_groups;
+            bool next_real = false;
             if (have_next) {
                 const int tt = ng * kWaves + tid / kTile;
-                if (tt < item.nt) nxt = tiles[(tbase + tt) * kTile + (tid & (kTile - 1))];
-                if (tid < kWaves && ng * kWaves + tid < item.nt) nxo = origins[tbase + ng * kWaves + tid];
+                next_real = tt < item.nt;
+                if (next_real) {
+                    const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
+                    nh = t_hi[ai];
+                    nl = t_lo[ai];
+                }
+                if (tid < kWaves && ng * kWaves + tid < item.nt) no = origins[tbase + ng * kWaves + tid];
             }
             const int tiles_here = min(kWaves, item.nt - g * kWaves);
             for (int w = 0; w < tiles_here; ++w) {
-                const double4 o = s_orig[buf][w];
-                float th[QL], re[QL], im[QL];
+                float cs[QL], sn[QL];
 #pragma unroll
-                for (int k = 0; k < QL; ++k) {
-                    const double t = __builtin_fma(dz[k], o.z, __builtin_fma(dy[k], o.y, dx[k] * o.x));
-                    th[k] = static_cast<float>(t - __builtin_rint(t));
-                    re[k] = 0.f;
-                    im[k] = 0.f;
-                }
+                for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
                 const float4 *at = &s_atoms[buf][w * kTile];
-#pragma unroll 4
-                for (int j = 0; j < kTile; ++j) {
-                    const float4 a = at[j];
-#pragma unroll
-                    for (int k = 0; k < QL; ++k) {
-                        const float ph = __builtin_fmaf(qz[k], a.z, __builtin_fmaf(qy[k], a.y,
-                                                        __builtin_fmaf(qx[k], a.x, th[k])));
-                        const float sn = __builtin_amdgcn_sinf(ph);
-                        const float cs = __builtin_amdgcn_cosf(ph);
-                        re[k] = __builtin_fmaf(a.w, cs, re[k]);
-                        im[k] = __builtin_fmaf(a.w, sn, im[k]);
-                    }
-                }
+                const float *bt = &s_beta[buf][w * kTile];
+                if (planar) tile_pairs<QL, true>(at, bt, dqx, dqy, dqz, cs, sn);
+                else tile_pairs<QL, false>(at, bt, dqx, dqy, dqz, cs, sn);
+                const double4 o = s_orig[buf][w];
 #pragma unroll
                 for (int k = 0; k < QL; ++k) {
-                    re64[k] += static_cast<double>(re[k]);
-                    im64[k] += static_cast<double>(im[k]);
+                    const float th = frac_f32(__builtin_fma(s_q[2][k][tid], o.z,
+                                              __builtin_fma(s_q[1][k][tid], o.y, s_q[0][k][tid] * o.x)));
+                    const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
+                    re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
+                    im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
                 }
             }
             if (have_next) {
-                s_atoms[buf ^ 1][tid] = nxt;
-                if (tid < kWaves) s_orig[buf ^ 1][tid] = nxo;
+                if (next_real) {
+                    const double b = __builtin_fma(cen[2], double(nh.z) + double(nl.z),
+                                     __builtin_fma(cen[1], double(nh.y) + double(nl.y), cen[0] * (double(nh.x) + double(nl.x))));
+                    s_atoms[buf ^ 1][tid] = nh;
+                    s_beta[buf ^ 1][tid] = frac_f32(b);
+                }
+                if (tid < kWaves) s_orig[buf ^ 1][tid] = no;
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            const int p = item.p0 + k * kBlock + tid;
-            if (p < sg.n_q)
-                partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + p] =
+        for (int k = 0; k < QL; ++k)
+            if (orig[k] >= 0)
+                partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + orig[k]] =
                     make_double2(re64[k], im64[k]);
-        }
     }
 }
 
@@ -384,46 +599,91 @@ __global__ __launch_bounds__(kBlock) void k_forward_combine(const FwdSeg *__rest
 //         =    f_j sum_p W_p sin(phi_pj + psi_p),
 // with W_p = -2 w_p |A_p| q_p and psi_p = arg(A_p) / (2 pi) (revolutions), since
 // a sin(phi) + b cos(phi) = |A| sin(phi + arg A) for A = a + ib.
-// Pixel prologue: FP32 (q_rev, W) and FP64 (q_rev, psi).
+// Pixel prologue, in sorted order, groups of 64 consecutive sorted pixels
+// sharing a centre q_c: FP32 (dq, 0), FP32 (W, 0), FP64 (q_rev, psi) and the
+// group centre (FP64; w = 1 if every dq_z of the group is zero).
+constexpr int kPixStage = 64;
 __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict__ segs,
                                                       const double *__restrict__ q,
+                                                      const int32_t *__restrict__ pix_order,
                                                       const double *__restrict__ amp,
                                                       const double *__restrict__ w,
-                                                      float4 *__restrict__ pq32,
-                                                      float4 *__restrict__ pw32,
-                                                      double4 *__restrict__ pq64) {
+                                                      float4 *__restrict__ pdq,
+                                                      float4 *__restrict__ pw,
+                                                      double4 *__restrict__ pq64,
+                                                      double4 *__restrict__ centre) {
     const GradSeg sg = segs[blockIdx.y];
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= sg.n_q) return;
+    const int sp = blockIdx.x * kBlock + threadIdx.x;  // sorted slot
+    if (blockIdx.x * kBlock >= sg.n_q) return;          // block-uniform exit
+    const bool real = sp < sg.n_q;
+    const int p = pix_order[sg.slot0 + (real ? sp : sg.n_q - 1)];
     const double *qp = q + (sg.q + p) * 3;
+    const double rx = qp[0] * kInvTwoPi, ry = qp[1] * kInvTwoPi, rz = qp[2] * kInvTwoPi;
+    double lo[3] = {real ? rx : INFINITY, real ? ry : INFINITY, real ? rz : INFINITY};
+    double hi[3] = {real ? rx : -INFINITY, real ? ry : -INFINITY, real ? rz : -INFINITY};
+    for (int c = 0; c < 3; ++c)
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+            hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+        }
+    const double cx = 0.5 * (lo[0] + hi[0]), cy = 0.5 * (lo[1] + hi[1]), cz = 0.5 * (lo[2] + hi[2]);
+    if (!real) return;
     const double a = amp[2 * (sg.out + p)], b = amp[2 * (sg.out + p) + 1];
     const double mag = __builtin_sqrt(a * a + b * b);
     const double psi = atan2(b, a) * kInvTwoPi;
     const double c = -2.0 * w[sg.out + p] * mag;
-    const double rx = qp[0] * kInvTwoPi, ry = qp[1] * kInvTwoPi, rz = qp[2] * kInvTwoPi;
-    const int64_t i = sg.q + p;
-    pq32[i] = make_float4(static_cast<float>(rx), static_cast<float>(ry), static_cast<float>(rz), 0.f);
-    pw32[i] = make_float4(static_cast<float>(c * qp[0]), static_cast<float>(c * qp[1]),
-                          static_cast<float>(c * qp[2]), 0.f);
+    const int64_t i = sg.slot0 + sp;
+    pdq[i] = make_float4(static_cast<float>(rx - cx), static_cast<float>(ry - cy),
+                         static_cast<float>(rz - cz), 0.f);
+    pw[i] = make_float4(static_cast<float>(c * qp[0]), static_cast<float>(c * qp[1]),
+                        static_cast<float>(c * qp[2]), 0.f);
     pq64[i] = make_double4(rx, ry, rz, psi);
+    if ((threadIdx.x & 63) == 0)
+        centre[sg.grp0 + sp / kPixStage] = make_double4(cx, cy, cz, lo[2] == hi[2] ? 1.0 : 0.0);
 }
 
 // Workgroup = 4 wavefronts; wavefront w owns tiles t0 + w*AL + a (a < AL),
-// lane l owns atom l of each.  Pixels of the item's chunk are staged 64 at a
-// time into LDS; each wavefront also stages its base phases
-// theta'(p, tile) = frac(q_rev.o + psi) (FP64 -> FP32).  Per pair: 3 FMA phase,
-// one v_sin, 3 FMA accumulate.  Pixel sub-chunk partials fold into FP64.
-constexpr int kPixStage = 64;
+// lane l owns atom l of each.  The item's sorted pixels are staged 64 at a
+// time (one centre q_c per 64): per staged group each lane forms
+// beta = frac(q_c.d) for its atoms (FP64, from the exact offset) and each
+// wavefront the base phases theta'(p, tile) = frac(q_p.o + psi_p).  Per pair:
+// add + 3 FMA (2 when the group has dq_z = 0), one v_sin, 3 FMA.  Group
+// partials fold into FP64.
+template <int AL, bool PLANAR>
+__device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const float4 *__restrict__ sw,
+                                            const float (*__restrict__ sth)[kPixStage],
+                                            const float (&dx)[AL], const float (&dy)[AL],
+                                            const float (&dz)[AL], const float (&beta)[AL],
+                                            float (&gx)[AL], float (&gy)[AL], float (&gz)[AL]) {
+#pragma unroll 2
+    for (int m = 0; m < kPixStage; ++m) {
+        const float4 qv = sq[m];
+        const float4 wv = sw[m];
+#pragma unroll
+        for (int a = 0; a < AL; ++a) {
+            float ph = __builtin_fmaf(qv.x, dx[a], sth[a][m] + beta[a]);
+            ph = __builtin_fmaf(qv.y, dy[a], ph);
+            if (!PLANAR) ph = __builtin_fmaf(qv.z, dz[a], ph);
+            const float sn = __builtin_amdgcn_sinf(ph);
+            gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
+            gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
+            gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
+        }
+    }
+}
+
 template <int AL>
 __global__ __launch_bounds__(kBlock) void k_grad_fp32c(
     const GradItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
-    const GradSeg *__restrict__ segs, const float4 *__restrict__ tiles,
-    const double4 *__restrict__ origins, const float4 *__restrict__ pq32,
-    const float4 *__restrict__ pw32, const double4 *__restrict__ pq64,
+    const GradSeg *__restrict__ segs, const float4 *__restrict__ t_hi,
+    const float4 *__restrict__ t_lo, const double4 *__restrict__ origins,
+    const float4 *__restrict__ pdq, const float4 *__restrict__ pw,
+    const double4 *__restrict__ pq64, const double4 *__restrict__ centre,
     double *__restrict__ gpart) {
     __shared__ float4 s_q[kPixStage];
     __shared__ float4 s_w[kPixStage];
     __shared__ float s_th[kWaves][AL][kPixStage];
+    __shared__ double4 s_c;
     __shared__ int32_t s_item;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (;;) {
@@ -435,57 +695,49 @@ __global__ __launch_bounds__(kBlock) void k_grad_fp32c(
         const GradItem item = items[it];
         const GradSeg sg = segs[item.seg];
         float dx[AL], dy[AL], dz[AL];
+        float lx[AL], ly[AL], lz[AL];
         double ox[AL], oy[AL], oz[AL];
         double gx64[AL], gy64[AL], gz64[AL];
 #pragma unroll
         for (int a = 0; a < AL; ++a) {
             int t = wave * AL + a;
-            const bool real = t < item.nt;
-            t = real ? t : 0;
+            t = t < item.nt ? t : 0;
             const int64_t ti = sg.tile0 + item.t0 + t;
-            const float4 v = tiles[ti * kTile + lane];
+            const float4 h = t_hi[ti * kTile + lane], l = t_lo[ti * kTile + lane];
             const double4 o = origins[ti];
-            dx[a] = v.x; dy[a] = v.y; dz[a] = v.z;
+            dx[a] = h.x; dy[a] = h.y; dz[a] = h.z;
+            lx[a] = l.x; ly[a] = l.y; lz[a] = l.z;
             ox[a] = o.x; oy[a] = o.y; oz[a] = o.z;
             gx64[a] = gy64[a] = gz64[a] = 0.0;
         }
         for (int s0 = 0; s0 < item.np; s0 += kPixStage) {
             const int n_here = min(kPixStage, item.np - s0);
-            // stage pixel data (wave 0) and each wave's base phases
             {
-                int p = item.p0 + s0 + lane;
-                const bool real = lane < n_here;
-                p = real ? p : item.p0;
-                const int64_t i = sg.q + p;
+                const int sp = item.p0 + s0 + (lane < n_here ? lane : 0);
+                const int64_t i = sg.slot0 + sp;
                 if (wave == 0) {
-                    s_q[lane] = pq32[i];
-                    s_w[lane] = real ? pw32[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    s_q[lane] = pdq[i];
+                    s_w[lane] = lane < n_here ? pw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (lane == 0) s_c = centre[sg.grp0 + (item.p0 + s0) / kPixStage];
                 }
                 const double4 d = pq64[i];
 #pragma unroll
-                for (int a = 0; a < AL; ++a) {
-                    const double t = __builtin_fma(d.z, oz[a], __builtin_fma(d.y, oy[a], d.x * ox[a])) + d.w;
-                    s_th[wave][a][lane] = static_cast<float>(t - __builtin_rint(t));
-                }
+                for (int a = 0; a < AL; ++a)
+                    s_th[wave][a][lane] = frac_f32(__builtin_fma(d.z, oz[a], __builtin_fma(d.y, oy[a], d.x * ox[a])) + d.w);
             }
             __syncthreads();
+            const double4 c = s_c;
+            float beta[AL];
+#pragma unroll
+            for (int a = 0; a < AL; ++a)
+                beta[a] = frac_f32(__builtin_fma(c.z, double(dz[a]) + double(lz[a]),
+                                   __builtin_fma(c.y, double(dy[a]) + double(ly[a]),
+                                                 c.x * (double(dx[a]) + double(lx[a])))));
             float gx[AL], gy[AL], gz[AL];
 #pragma unroll
             for (int a = 0; a < AL; ++a) gx[a] = gy[a] = gz[a] = 0.f;
-#pragma unroll 2
-            for (int m = 0; m < kPixStage; ++m) {
-                const float4 qv = s_q[m];
-                const float4 wv = s_w[m];
-#pragma unroll
-                for (int a = 0; a < AL; ++a) {
-                    const float ph = __builtin_fmaf(qv.z, dz[a], __builtin_fmaf(qv.y, dy[a],
-                                                    __builtin_fmaf(qv.x, dx[a], s_th[wave][a][m])));
-                    const float sn = __builtin_amdgcn_sinf(ph);
-                    gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
-                    gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
-                    gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
-                }
-            }
+            if (c.w != 0.0) pixel_pairs<AL, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            else pixel_pairs<AL, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
 #pragma unroll
             for (int a = 0; a < AL; ++a) {
                 gx64[a] += static_cast<double>(gx[a]);
@@ -556,141 +808,152 @@ int device_slots(const void *kernel) {
     return n;
 }
 
-struct Binned {
+int bits_for(int64_t n) {
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+template <typename T>
+std::vector<T> largest_first(const std::vector<T> &items, const std::vector<int64_t> &cost) {
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<T> out(items.size());
+    for (size_t i = 0; i < order.size(); ++i) out[i] = items[order[i]];
+    return out;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// Host tables of one batch layout: segments, pixel sets, work lists.
+struct Plan::Tables {
     std::vector<BinSeg> bsegs;
-    int64_t total_tiles = 0;
-    float4 *tiles = nullptr;
-    double4 *origins = nullptr;
-    int32_t *tile_atom = nullptr;
+    std::vector<PixSet> psets;
+    std::vector<int> seg_set;
+    std::vector<FwdSeg> fsegs;
+    std::vector<FwdItem> fitems;
+    std::vector<GradSeg> gsegs;
+    std::vector<GradItem> gitems;         // concatenated over sub-batches
+    std::vector<int> gsub_seg0, gsub_seg1; // segment range of each sub-batch
+    std::vector<int> gsub_item0, gsub_nitem;
+    std::vector<double> gsub_work;
+    std::vector<int> gsub_maxq;
+    int64_t atoms = 0, cells = 0, tiles = 0, slots = 0, groups = 0, fpart = 0, gpart = 0;
+    int max_atoms = 0, max_tiles = 0, max_q = 0, max_set_q = 0, max_slots_seg = 0;
+    double fwork = 0.0;
+    size_t sort_tmp = 0;
 };
 
-// Bin every segment into tiles (see k_bin_*).  Cells target kTile/8 atoms so a
-// tile of 64 Morton-consecutive atoms spans about 2x2x2 cells.
-xs_status bin_segments(hipStream_t s, const Segment *segs, int n_segs, const double *box,
-                       const double *pos, const double *f, Binned &out) {
-    out.bsegs.resize(n_segs);
-    int64_t atom0 = 0, key0 = 0, tile0 = 0;
-    int max_atoms = 0, max_tiles = 0;
-    int64_t max_keys = 0;
+struct Plan::Buffers {
+    BinSeg *bsegs = nullptr;
+    PixSet *psets = nullptr;
+    FwdSeg *fsegs = nullptr;
+    FwdItem *fitems = nullptr;
+    GradSeg *gsegs = nullptr;
+    GradItem *gitems = nullptr;
+    int32_t *counters = nullptr;
+    int32_t *hist = nullptr, *start = nullptr, *cursor = nullptr, *scan_sums = nullptr;
+    uint32_t *keys = nullptr;
+    int32_t *sorted = nullptr;
+    float4 *t_hi = nullptr, *t_lo = nullptr;
+    int32_t *tile_atom = nullptr;
+    double4 *origins = nullptr;
+    uint64_t *pk = nullptr, *pk2 = nullptr;
+    int32_t *pv = nullptr, *pix_order = nullptr;
+    double *pbbox = nullptr;
+    void *sort_tmp = nullptr;
+    double2 *fpart = nullptr;
+    double *gpart = nullptr;
+    float4 *pdq = nullptr, *pw = nullptr;
+    double4 *pq64 = nullptr, *centre = nullptr;
+    size_t table_bytes = 0;
+};
+
+Plan::Plan() : T(new Tables()), B(new Buffers()) {}
+Plan::~Plan() {
+    if (owned_block) (void)hipFree(owned_block);
+    delete T;
+    delete B;
+}
+
+// Build every host table of the batch (no device work).
+xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const xs_tile_shape &fsh,
+                      const xs_tile_shape &gsh) {
+    Tables &t = *T;
+    fshape = fsh;
+    gshape = gsh;
+    n_seg = n_segs;
+    t.bsegs.resize(n_segs);
+    t.seg_set.resize(n_segs);
     for (int i = 0; i < n_segs; ++i) {
         const Segment &sg = segs[i];
-        BinSeg &b = out.bsegs[i];
+        BinSeg &b = t.bsegs[i];
         b.pos = sg.pos;
         b.f = sg.f;
         b.n_atoms = sg.n_atoms;
         b.n_tiles = (sg.n_atoms + kTile - 1) / kTile;
-        b.atom0 = atom0;
-        b.key0 = key0;
-        b.tile0 = tile0;
-        const double *L = box + 3 * sg.sys;
-        const double vol = std::max(L[0] * L[1] * L[2], 1e-300);
-        const double rho = sg.n_atoms / vol;
-        const double edge = std::cbrt((kTile / 8.0) / std::max(rho, 1e-300));
-        int bits = 0;
-        for (int d = 0; d < 3; ++d) {
-            int nc = static_cast<int>(std::lround(L[d] / edge));
-            nc = std::max(1, std::min(nc, 1024));
-            int bb = 0;
-            while ((1 << bb) < nc) ++bb;
-            bits = std::max(bits, bb);
-        }
-        bits = std::min(bits, 7);  // at most 2^21 cells per segment
-        for (int d = 0; d < 3; ++d) {
-            b.lo[d] = 0.0;
-            b.ncell[d] = 1 << bits;
-            b.inv_cell[d] = L[d] > 0 ? (1 << bits) / L[d] : 0.0;
-        }
+        b.atom0 = t.atoms;
+        b.tile0 = t.tiles;
+        b.cell0 = t.cells;
+        b.pad = 0;
+        // cells: largest 2^bits per edge with about >= 2 atoms per cell (bits 1..10)
+        int bits = 1;
+        while (bits < 10 && (int64_t(1) << (3 * (bits + 1))) * 2 <= sg.n_atoms) ++bits;
         b.bits = bits;
-        atom0 += sg.n_atoms;
-        key0 += int64_t(1) << (3 * bits);
-        tile0 += b.n_tiles;
-        max_atoms = std::max(max_atoms, sg.n_atoms);
-        max_tiles = std::max(max_tiles, b.n_tiles);
-        max_keys = std::max<int64_t>(max_keys, int64_t(1) << (3 * bits));
+        const double *L = box + 3 * sg.sys;
+        for (int d = 0; d < 3; ++d) b.scale[d] = double(1 << bits) / L[d];
+        t.atoms += sg.n_atoms;
+        t.tiles += b.n_tiles;
+        t.cells += int64_t(1) << (3 * bits);
+        t.max_atoms = std::max(t.max_atoms, sg.n_atoms);
+        t.max_tiles = std::max(t.max_tiles, b.n_tiles);
+        t.max_q = std::max(t.max_q, sg.n_q);
+        t.max_slots_seg = std::max(t.max_slots_seg, b.n_tiles * kTile);
+        int set = -1;
+        for (size_t k = 0; k < t.psets.size(); ++k)
+            if (t.psets[k].q == sg.q && t.psets[k].n_q == sg.n_q) { set = static_cast<int>(k); break; }
+        if (set < 0) {
+            PixSet ps;
+            ps.q = sg.q;
+            ps.n_q = sg.n_q;
+            ps.slot0 = t.slots;
+            ps.pad = 0;
+            t.slots += sg.n_q;
+            t.psets.push_back(ps);
+            set = static_cast<int>(t.psets.size()) - 1;
+            t.max_set_q = std::max(t.max_set_q, sg.n_q);
+        }
+        t.seg_set[i] = set;
     }
-    out.total_tiles = tile0;
-    void *d_b = nullptr, *keys = nullptr, *hist = nullptr, *sorted = nullptr, *tiles = nullptr,
-         *orig = nullptr;
-    XS_TRY(upload(s, SLOT_ITEMS, out.bsegs.data(), sizeof(BinSeg) * n_segs, &d_b));
-    XS_TRY(scratch(s, SLOT_KEYS, sizeof(uint32_t) * std::max<int64_t>(atom0, 1), &keys));
-    XS_TRY(scratch(s, SLOT_HIST, sizeof(int32_t) * 2 * std::max<int64_t>(key0, 1), &hist));
-    XS_TRY(scratch(s, SLOT_SORTED, sizeof(int32_t) * std::max<int64_t>(atom0, 1), &sorted));
-    XS_TRY(scratch(s, SLOT_TILES, (sizeof(float4) + sizeof(int32_t)) * kTile * std::max<int64_t>(tile0, 1), &tiles));
-    XS_TRY(scratch(s, SLOT_ORIGINS, sizeof(double4) * std::max<int64_t>(tile0, 1), &orig));
-    int32_t *h = static_cast<int32_t *>(hist);
-    int32_t *start = h + key0;
-    if (key0 > 0)
-        hipLaunchKernelGGL(k_zero_i32, dim3(static_cast<unsigned>((key0 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                           h, key0);
-    const BinSeg *db = static_cast<const BinSeg *>(d_b);
-    if (max_atoms > 0) {
-        dim3 ga((max_atoms + kBlock - 1) / kBlock, n_segs);
-        hipLaunchKernelGGL(k_bin_key, ga, dim3(kBlock), 0, s, db, pos, static_cast<uint32_t *>(keys), h);
-        hipLaunchKernelGGL(k_bin_scan, dim3(n_segs), dim3(1024), 0, s, db, h, start);
-        hipLaunchKernelGGL(k_bin_scatter, ga, dim3(kBlock), 0, s, db,
-                           static_cast<const uint32_t *>(keys), h, static_cast<int32_t *>(sorted));
-        dim3 gc(static_cast<unsigned>((max_keys + kBlock - 1) / kBlock), n_segs);
-        hipLaunchKernelGGL(k_bin_sort_cells, gc, dim3(kBlock), 0, s, db, start, h,
-                           static_cast<int32_t *>(sorted));
-        dim3 gt((max_tiles + kWaves - 1) / kWaves, n_segs);
-        out.tiles = static_cast<float4 *>(tiles);
-        out.tile_atom = reinterpret_cast<int32_t *>(static_cast<float4 *>(tiles) + kTile * std::max<int64_t>(tile0, 1));
-        out.origins = static_cast<double4 *>(orig);
-        hipLaunchKernelGGL(k_bin_tiles, gt, dim3(kBlock), 0, s, db, pos, f,
-                           static_cast<const int32_t *>(sorted), out.tiles, out.origins, out.tile_atom);
-        XS_HIP(hipGetLastError());
-    } else {
-        out.tiles = static_cast<float4 *>(tiles);
-        out.tile_atom = reinterpret_cast<int32_t *>(static_cast<float4 *>(tiles) + kTile);
-        out.origins = static_cast<double4 *>(orig);
+    if (t.cells >= (int64_t(1) << 31) || t.atoms >= (int64_t(1) << 31))
+        return set_error(XS_ENOTSUP, "batch too large for one FP32C call (%lld atoms, %lld cells)",
+                         (long long)t.atoms, (long long)t.cells);
+    std::vector<int64_t> set_grp0(t.psets.size());
+    for (size_t k = 0; k < t.psets.size(); ++k) {
+        set_grp0[k] = t.groups;
+        t.groups += (t.psets[k].n_q + kPixStage - 1) / kPixStage;
     }
-    return XS_OK;
-}
-
-template <int QL>
-void launch_forward(hipStream_t s, int slots, const FwdItem *items, int n_items, int32_t *counter,
-                    const FwdSeg *segs, const double *q, const Binned &b, double2 *partial) {
-    hipLaunchKernelGGL(k_forward_fp32c<QL>, dim3(slots), dim3(kBlock), 0, s, items, n_items, counter,
-                       segs, q, b.tiles, b.origins, partial);
-}
-
-template <int AL>
-void launch_grad(hipStream_t s, int slots, const GradItem *items, int n_items, int32_t *counter,
-                 const GradSeg *segs, const Binned &b, const float4 *pq32, const float4 *pw32,
-                 const double4 *pq64, double *gpart) {
-    hipLaunchKernelGGL(k_grad_fp32c<AL>, dim3(slots), dim3(kBlock), 0, s, items, n_items, counter,
-                       segs, b.tiles, b.origins, pq32, pw32, pq64, gpart);
-}
-
-}  // namespace
-
-xs_status fp32c_forward(hipStream_t s, const Segment *segs, int n_segs, const double *box,
-                        const double *pos, const double *f, const double *q, double *I,
-                        double *amp, const xs_tile_shape &shape) {
-    if (n_segs <= 0) return XS_OK;
-    Binned b;
-    XS_TRY(bin_segments(s, segs, n_segs, box, pos, f, b));
-    const int QL = shape.q_per_lane;
-    const int split = std::max(1, shape.atom_split);
-    const int pix_per_item = kBlock * QL;
-    std::vector<FwdSeg> fs(n_segs);
+    // forward work list
+    const int QL = fsh.q_per_lane, split = std::max(1, fsh.atom_split), ppi = kBlock * QL;
+    t.fsegs.resize(n_segs);
     std::vector<FwdItem> items;
     std::vector<int64_t> cost;
-    int64_t part = 0;
-    int max_q = 0;
     for (int i = 0; i < n_segs; ++i) {
-        FwdSeg &g = fs[i];
+        FwdSeg &g = t.fsegs[i];
         g.q = segs[i].q;
+        g.slot0 = t.psets[t.seg_set[i]].slot0;
         g.out = segs[i].out;
-        g.tile0 = b.bsegs[i].tile0;
+        g.tile0 = t.bsegs[i].tile0;
         g.n_q = segs[i].n_q;
-        g.n_tiles = b.bsegs[i].n_tiles;
+        g.n_tiles = t.bsegs[i].n_tiles;
         g.n_chunks = g.n_tiles > 0 ? (g.n_tiles + split - 1) / split : 0;
-        g.part = part;
+        g.part = t.fpart;
         g.pad = 0;
-        part += static_cast<int64_t>(g.n_chunks) * g.n_q;
-        max_q = std::max(max_q, g.n_q);
-        for (int p0 = 0; p0 < g.n_q; p0 += pix_per_item)
+        t.fpart += static_cast<int64_t>(g.n_chunks) * g.n_q;
+        for (int p0 = 0; p0 < g.n_q; p0 += ppi)
             for (int c = 0; c < g.n_chunks; ++c) {
                 FwdItem it;
                 it.seg = i;
@@ -700,154 +963,317 @@ xs_status fp32c_forward(hipStream_t s, const Segment *segs, int n_segs, const do
                 it.chunk = c;
                 it.pad = 0;
                 items.push_back(it);
+                const int64_t np = std::min(ppi, g.n_q - p0);
+                cost.push_back(np * it.nt);
+                t.fwork += static_cast<double>(np) * it.nt * kTile;
             }
     }
-    // largest work first (pixels x tiles), stable for equal cost
-    std::vector<int> order(items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        const int64_t cx = static_cast<int64_t>(std::min(pix_per_item, fs[items[x].seg].n_q - items[x].p0)) * items[x].nt;
-        const int64_t cy = static_cast<int64_t>(std::min(pix_per_item, fs[items[y].seg].n_q - items[y].p0)) * items[y].nt;
-        return cx > cy;
-    });
-    std::vector<FwdItem> sorted_items(items.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted_items[i] = items[order[i]];
-    void *d_fs = nullptr, *d_items = nullptr, *d_part = nullptr, *d_cnt = nullptr;
-    XS_TRY(upload(s, SLOT_SEGS, fs.data(), sizeof(FwdSeg) * n_segs, &d_fs));
-    XS_TRY(scratch(s, SLOT_PARTIAL, sizeof(double2) * std::max<int64_t>(part, 1), &d_part));
-    XS_TRY(scratch(s, SLOT_COUNTER, 256, &d_cnt));
-    if (!sorted_items.empty()) {
-        XS_TRY(upload(s, SLOT_PIXEL, sorted_items.data(), sizeof(FwdItem) * sorted_items.size(), &d_items));
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, static_cast<int32_t *>(d_cnt), 1);
-        const FwdItem *it = static_cast<const FwdItem *>(d_items);
-        const FwdSeg *sg = static_cast<const FwdSeg *>(d_fs);
-        int32_t *cnt = static_cast<int32_t *>(d_cnt);
-        double2 *pp = static_cast<double2 *>(d_part);
-        const int n = static_cast<int>(sorted_items.size());
-        switch (QL) {
-        case 1: launch_forward<1>(s, std::min(n, device_slots((const void *)k_forward_fp32c<1>)), it, n, cnt, sg, q, b, pp); break;
-        case 2: launch_forward<2>(s, std::min(n, device_slots((const void *)k_forward_fp32c<2>)), it, n, cnt, sg, q, b, pp); break;
-        case 4: launch_forward<4>(s, std::min(n, device_slots((const void *)k_forward_fp32c<4>)), it, n, cnt, sg, q, b, pp); break;
-        case 8: launch_forward<8>(s, std::min(n, device_slots((const void *)k_forward_fp32c<8>)), it, n, cnt, sg, q, b, pp); break;
-        default: return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8 (got %d)", QL);
+    t.fitems = largest_first(items, cost);
+    // gradient work lists: segments sharing a pixel set go to different sub-batches
+    const int AL = gsh.q_per_lane, group = kWaves * AL;
+    const int pchunk = std::max(kPixStage, (gsh.pixel_split / kPixStage) * kPixStage);
+    t.gsegs.resize(n_segs);
+    for (int i = 0; i < n_segs; ++i) {
+        GradSeg &g = t.gsegs[i];
+        g.q = segs[i].q;
+        g.slot0 = t.psets[t.seg_set[i]].slot0;
+        g.grp0 = set_grp0[t.seg_set[i]];
+        g.out = segs[i].out;
+        g.pos = segs[i].pos;
+        g.f = segs[i].f;
+        g.tile0 = t.bsegs[i].tile0;
+        g.n_q = segs[i].n_q;
+        g.n_tiles = t.bsegs[i].n_tiles;
+        g.n_chunks = (g.n_q > 0 && g.n_tiles > 0) ? (g.n_q + pchunk - 1) / pchunk : 0;
+        g.part = t.gpart;
+        g.pad = 0;
+        t.gpart += static_cast<int64_t>(g.n_chunks) * g.n_tiles * kTile;
+    }
+    int i0 = 0;
+    while (i0 < n_segs) {
+        int i1 = i0 + 1;
+        for (; i1 < n_segs; ++i1) {
+            bool clash = false;
+            for (int k = i0; k < i1 && !clash; ++k) clash = t.seg_set[k] == t.seg_set[i1];
+            if (clash) break;
         }
+        std::vector<GradItem> sub;
+        std::vector<int64_t> sc;
+        double work = 0.0;
+        int mq = 0;
+        for (int i = i0; i < i1; ++i) {
+            const GradSeg &g = t.gsegs[i];
+            mq = std::max(mq, g.n_q);
+            for (int t0 = 0; t0 < g.n_tiles; t0 += group)
+                for (int c = 0; c < g.n_chunks; ++c) {
+                    GradItem it;
+                    it.seg = i;
+                    it.t0 = t0;
+                    it.nt = std::min(group, g.n_tiles - t0);
+                    it.p0 = c * pchunk;
+                    it.np = std::min(pchunk, g.n_q - c * pchunk);
+                    it.chunk = c;
+                    sub.push_back(it);
+                    sc.push_back(static_cast<int64_t>(it.nt) * it.np);
+                    work += static_cast<double>(it.np) * it.nt * kTile;
+                }
+        }
+        sub = largest_first(sub, sc);
+        t.gsub_seg0.push_back(i0);
+        t.gsub_seg1.push_back(i1);
+        t.gsub_item0.push_back(static_cast<int>(t.gitems.size()));
+        t.gsub_nitem.push_back(static_cast<int>(sub.size()));
+        t.gsub_work.push_back(work);
+        t.gsub_maxq.push_back(mq);
+        t.gitems.insert(t.gitems.end(), sub.begin(), sub.end());
+        i0 = i1;
+    }
+    // radix-sort workspace for the pixel order
+    if (t.slots > 0) {
+        size_t bytes = 0;
+        XS_HIP(rocprim::radix_sort_pairs(nullptr, bytes, static_cast<const uint64_t *>(nullptr),
+                                         static_cast<uint64_t *>(nullptr), static_cast<const int32_t *>(nullptr),
+                                         static_cast<int32_t *>(nullptr), static_cast<unsigned int>(t.slots), 0,
+                                         30 + bits_for(static_cast<int64_t>(t.psets.size())), nullptr));
+        t.sort_tmp = bytes;
+    }
+    return XS_OK;
+}
+
+// Carve every device buffer out of one block (plan-owned or stream scratch).
+size_t Plan::layout(char *base) {
+    Tables &t = *T;
+    Buffers &b = *B;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(std::max<size_t>(bytes, 1));
+        return p;
+    };
+    const size_t tb0 = off;
+    b.bsegs = reinterpret_cast<BinSeg *>(take(sizeof(BinSeg) * t.bsegs.size()));
+    b.psets = reinterpret_cast<PixSet *>(take(sizeof(PixSet) * t.psets.size()));
+    b.fsegs = reinterpret_cast<FwdSeg *>(take(sizeof(FwdSeg) * t.fsegs.size()));
+    b.fitems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.fitems.size()));
+    b.gsegs = reinterpret_cast<GradSeg *>(take(sizeof(GradSeg) * t.gsegs.size()));
+    b.gitems = reinterpret_cast<GradItem *>(take(sizeof(GradItem) * t.gitems.size()));
+    b.table_bytes = off - tb0;
+    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 1)));
+    const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
+    b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
+    b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
+    b.cursor = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
+    b.scan_sums = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nsb));
+    b.keys = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * t.atoms));
+    b.sorted = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.atoms));
+    b.t_hi = reinterpret_cast<float4 *>(take(sizeof(float4) * kTile * t.tiles));
+    b.t_lo = reinterpret_cast<float4 *>(take(sizeof(float4) * kTile * t.tiles));
+    b.tile_atom = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * kTile * t.tiles));
+    b.origins = reinterpret_cast<double4 *>(take(sizeof(double4) * t.tiles));
+    b.pk = reinterpret_cast<uint64_t *>(take(sizeof(uint64_t) * t.slots));
+    b.pk2 = reinterpret_cast<uint64_t *>(take(sizeof(uint64_t) * t.slots));
+    b.pv = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.slots));
+    b.pix_order = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.slots));
+    b.pbbox = reinterpret_cast<double *>(take(sizeof(double) * 6 * t.psets.size()));
+    b.sort_tmp = take(t.sort_tmp);
+    b.fpart = reinterpret_cast<double2 *>(take(sizeof(double2) * t.fpart));
+    b.gpart = reinterpret_cast<double *>(take(sizeof(double) * 3 * t.gpart));
+    b.pdq = reinterpret_cast<float4 *>(take(sizeof(float4) * t.slots));
+    b.pw = reinterpret_cast<float4 *>(take(sizeof(float4) * t.slots));
+    b.pq64 = reinterpret_cast<double4 *>(take(sizeof(double4) * t.slots));
+    b.centre = reinterpret_cast<double4 *>(take(sizeof(double4) * t.groups));
+    return off;
+}
+
+// Host blob of all tables in the order and alignment of layout().
+std::vector<char> Plan::table_blob() const {
+    const Tables &t = *T;
+    std::vector<char> blob(B->table_bytes, 0);
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes) {
+        if (bytes) std::memcpy(blob.data() + off, src, bytes);
+        off += align256(std::max<size_t>(bytes, 1));
+    };
+    put(t.bsegs.data(), sizeof(BinSeg) * t.bsegs.size());
+    put(t.psets.data(), sizeof(PixSet) * t.psets.size());
+    put(t.fsegs.data(), sizeof(FwdSeg) * t.fsegs.size());
+    put(t.fitems.data(), sizeof(FwdItem) * t.fitems.size());
+    put(t.gsegs.data(), sizeof(GradSeg) * t.gsegs.size());
+    put(t.gitems.data(), sizeof(GradItem) * t.gitems.size());
+    return blob;
+}
+
+// Device memory: owned (persistent plans) or the stream's scratch (one-shot).
+xs_status Plan::allocate(hipStream_t s, bool owned) {
+    const size_t bytes = layout(nullptr);
+    char *base = nullptr;
+    if (owned) {
+        hipError_t e = hipMalloc(&owned_block, bytes);
+        if (e != hipSuccess) {
+            owned_block = nullptr;
+            (void)hipGetLastError();
+            return set_error(XS_ENOMEM, "plan: cannot allocate %zu bytes", bytes);
+        }
+        base = static_cast<char *>(owned_block);
+    } else {
+        void *p = nullptr;
+        XS_TRY(scratch(s, SLOT_PLAN, bytes, &p));
+        base = static_cast<char *>(p);
+    }
+    layout(base);
+    device_bytes = bytes;
+    const std::vector<char> blob = table_blob();
+    if (owned) {
+        XS_HIP(hipMemcpy(B->bsegs, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    } else {
+        XS_TRY(stage_copy(s, SLOT_TABLES, blob.data(), blob.size(), B->bsegs));
+    }
+    return XS_OK;
+}
+
+// Pixel order of every pixel set along the Hilbert curve in q (radix sort).
+xs_status Plan::sort_pixels(hipStream_t s, const double *q) {
+    Tables &t = *T;
+    Buffers &b = *B;
+    if (t.slots == 0) return XS_OK;
+    const int n_sets = static_cast<int>(t.psets.size());
+    hipLaunchKernelGGL(k_pix_bbox, dim3(n_sets), dim3(1024), 0, s, b.psets, q, b.pbbox);
+    hipLaunchKernelGGL(k_pix_keys, dim3((t.max_set_q + kBlock - 1) / kBlock, n_sets), dim3(kBlock), 0, s,
+                       b.psets, q, b.pbbox, b.pk, b.pv);
+    size_t bytes = t.sort_tmp;
+    XS_HIP(rocprim::radix_sort_pairs(b.sort_tmp, bytes, b.pk, b.pk2, b.pv, b.pix_order,
+                                     static_cast<unsigned int>(t.slots), 0, 30 + bits_for(n_sets), s));
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+// Atom tiles of every segment (kernels only: capturable in a graph).
+xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
+    Tables &t = *T;
+    Buffers &b = *B;
+    if (t.max_atoms == 0) return XS_OK;
+    void *tok = nullptr;
+    timer_begin(s, TIMER_BIN, &tok);
+    const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
+    const unsigned zb = static_cast<unsigned>(std::min<int64_t>((t.cells + kBlock - 1) / kBlock, 4096));
+    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(kBlock), 0, s, b.hist, t.cells);
+    const dim3 ga((t.max_atoms + kBlock - 1) / kBlock, n_seg);
+    hipLaunchKernelGGL(k_cell_keys, ga, dim3(kBlock), 0, s, b.bsegs, pos, b.keys, b.hist);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kBlock), 0, s, b.hist, t.cells, b.scan_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, b.scan_sums, nsb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kBlock), 0, s, b.hist, t.cells, b.scan_sums, b.start,
+                       b.cursor);
+    hipLaunchKernelGGL(k_cell_scatter, ga, dim3(kBlock), 0, s, b.bsegs, b.keys, b.cursor, b.sorted);
+    hipLaunchKernelGGL(k_cell_order, dim3((t.cells + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b.start,
+                       b.cursor, t.cells, b.sorted);
+    hipLaunchKernelGGL(k_make_tiles, dim3((t.max_tiles + kWaves - 1) / kWaves, n_seg), dim3(kBlock), 0, s,
+                       b.bsegs, pos, f, b.sorted, b.t_hi, b.t_lo, b.origins, b.tile_atom);
+    timer_end(s, TIMER_BIN, tok, static_cast<double>(t.atoms));
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+namespace {
+template <int QL>
+void launch_forward(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q) {
+    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_forward_fp32c<QL>)));
+    hipLaunchKernelGGL(k_forward_fp32c<QL>, dim3(slots), dim3(kBlock), 0, s, b.fitems, n, counter, b.fsegs,
+                       q, b.pix_order, b.t_hi, b.t_lo, b.origins, b.fpart);
+}
+
+template <int AL>
+void launch_grad(hipStream_t s, const GradItem *items, int n, int32_t *counter, const Plan::Buffers &b) {
+    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_grad_fp32c<AL>)));
+    hipLaunchKernelGGL(k_grad_fp32c<AL>, dim3(slots), dim3(kBlock), 0, s, items, n, counter, b.gsegs, b.t_hi,
+                       b.t_lo, b.origins, b.pdq, b.pw, b.pq64, b.centre, b.gpart);
+}
+}  // namespace
+
+xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) {
+    Tables &t = *T;
+    Buffers &b = *B;
+    const int n = static_cast<int>(t.fitems.size());
+    if (n > 0) {
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, 1);
+        void *tok = nullptr;
+        timer_begin(s, TIMER_FWD32, &tok);
+        switch (fshape.q_per_lane) {
+        case 1: launch_forward<1>(s, n, b.counters, b, q); break;
+        case 2: launch_forward<2>(s, n, b.counters, b, q); break;
+        case 4: launch_forward<4>(s, n, b.counters, b, q); break;
+        case 8: launch_forward<8>(s, n, b.counters, b, q); break;
+        default: return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
+        }
+        timer_end(s, TIMER_FWD32, tok, t.fwork);
         XS_HIP(hipGetLastError());
     }
-    if (max_q > 0) {
-        hipLaunchKernelGGL(k_forward_combine, dim3((max_q + kBlock - 1) / kBlock, n_segs), dim3(kBlock), 0,
-                           s, static_cast<const FwdSeg *>(d_fs), static_cast<const double2 *>(d_part), I,
-                           amp);
+    if (t.max_q > 0) {
+        hipLaunchKernelGGL(k_forward_combine, dim3((t.max_q + kBlock - 1) / kBlock, n_seg), dim3(kBlock), 0, s,
+                           b.fsegs, b.fpart, I, amp);
         XS_HIP(hipGetLastError());
     }
     return XS_OK;
 }
 
-xs_status fp32c_grad(hipStream_t s, const Segment *segs, int n_segs, const double *box,
-                     const double *pos, const double *f, const double *q, const double *amp,
-                     const double *dL_dI, float *dL_dr, double *dL_dr64,
-                     const xs_tile_shape &shape) {
-    if (n_segs <= 0) return XS_OK;
-    Binned b;
-    XS_TRY(bin_segments(s, segs, n_segs, box, pos, f, b));
-    const int AL = shape.q_per_lane;
-    const int group = kWaves * AL;  // tiles per workgroup item
-    int pchunk = std::max(kPixStage, (shape.pixel_split / kPixStage) * kPixStage);
-    std::vector<GradSeg> gs(n_segs);
-    std::vector<GradItem> items;
-    int64_t part = 0, pix = 0;
-    int max_q = 0, max_slots = 0;
-    // the prepared pixel arrays are indexed by the segment's q offset; frames of
-    // one system share q, so allocate over the largest q offset used
-    for (int i = 0; i < n_segs; ++i) pix = std::max<int64_t>(pix, segs[i].q + segs[i].n_q);
-    for (int i = 0; i < n_segs; ++i) {
-        GradSeg &g = gs[i];
-        g.q = segs[i].q;
-        g.out = segs[i].out;
-        g.pos = segs[i].pos;
-        g.f = segs[i].f;
-        g.tile0 = b.bsegs[i].tile0;
-        g.n_q = segs[i].n_q;
-        g.n_tiles = b.bsegs[i].n_tiles;
-        g.n_chunks = g.n_q > 0 ? (g.n_q + pchunk - 1) / pchunk : 0;
-        g.part = part;
-        g.pad = 0;
-        part += static_cast<int64_t>(g.n_chunks) * g.n_tiles * kTile;
-        max_q = std::max(max_q, g.n_q);
-        max_slots = std::max(max_slots, g.n_tiles * kTile);
-        for (int t0 = 0; t0 < g.n_tiles; t0 += group)
-            for (int c = 0; c < g.n_chunks; ++c) {
-                GradItem it;
-                it.seg = i;
-                it.t0 = t0;
-                it.nt = std::min(group, g.n_tiles - t0);
-                it.p0 = c * pchunk;
-                it.np = std::min(pchunk, g.n_q - c * pchunk);
-                it.chunk = c;
-                items.push_back(it);
-            }
+xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const double *amp,
+                     const double *dL_dI, float *g32, double *g64) {
+    Tables &t = *T;
+    Buffers &b = *B;
+    for (size_t k = 0; k < t.gsub_seg0.size(); ++k) {
+        const int i0 = t.gsub_seg0[k], i1 = t.gsub_seg1[k];
+        if (t.gsub_maxq[k] > 0)
+            hipLaunchKernelGGL(k_grad_prep, dim3((t.gsub_maxq[k] + kBlock - 1) / kBlock, i1 - i0), dim3(kBlock), 0,
+                               s, b.gsegs + i0, q, b.pix_order, amp, dL_dI, b.pdq, b.pw, b.pq64, b.centre);
+        const int n = t.gsub_nitem[k];
+        if (n == 0) continue;
+        int32_t *cnt = b.counters + 1 + k;
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 1);
+        const GradItem *items = b.gitems + t.gsub_item0[k];
+        void *tok = nullptr;
+        timer_begin(s, TIMER_GRAD32, &tok);
+        switch (gshape.q_per_lane) {
+        case 1: launch_grad<1>(s, items, n, cnt, b); break;
+        case 2: launch_grad<2>(s, items, n, cnt, b); break;
+        case 4: launch_grad<4>(s, items, n, cnt, b); break;
+        case 8: launch_grad<8>(s, items, n, cnt, b); break;
+        default: return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
+        }
+        timer_end(s, TIMER_GRAD32, tok, t.gsub_work[k]);
+        XS_HIP(hipGetLastError());
     }
-    std::vector<int> order(items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-        return static_cast<int64_t>(items[x].nt) * items[x].np > static_cast<int64_t>(items[y].nt) * items[y].np;
-    });
-    std::vector<GradItem> sorted_items(items.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted_items[i] = items[order[i]];
-    void *d_gs = nullptr, *d_items = nullptr, *d_part = nullptr, *d_cnt = nullptr, *d_pix = nullptr;
-    XS_TRY(upload(s, SLOT_SEGS, gs.data(), sizeof(GradSeg) * n_segs, &d_gs));
-    XS_TRY(scratch(s, SLOT_PARTIAL, sizeof(double) * 3 * std::max<int64_t>(part, 1), &d_part));
-    XS_TRY(scratch(s, SLOT_COUNTER, 256, &d_cnt));
-    XS_TRY(scratch(s, SLOT_PIXEL2, (2 * sizeof(float4) + sizeof(double4)) * std::max<int64_t>(pix, 1), &d_pix));
-    float4 *pq32 = static_cast<float4 *>(d_pix);
-    float4 *pw32 = pq32 + std::max<int64_t>(pix, 1);
-    double4 *pq64 = reinterpret_cast<double4 *>(pw32 + std::max<int64_t>(pix, 1));
-    const GradSeg *dgs = static_cast<const GradSeg *>(d_gs);
-    double *gp = static_cast<double *>(d_part);
-    // The pixel prologue depends on the frame (amp, dL/dI), so segments run
-    // one prologue + pair sum at a time when frames share pixel offsets.
-    // Group segments whose q ranges do not overlap into one launch.
-    int i0 = 0;
-    while (i0 < n_segs) {
-        int i1 = i0 + 1;
-        // extend while the q range is new
-        for (; i1 < n_segs; ++i1) {
-            bool clash = false;
-            for (int k = i0; k < i1 && !clash; ++k)
-                clash = !(segs[i1].q + segs[i1].n_q <= segs[k].q || segs[k].q + segs[k].n_q <= segs[i1].q);
-            if (clash) break;
-        }
-        int mq = 0;
-        for (int k = i0; k < i1; ++k) mq = std::max(mq, segs[k].n_q);
-        if (mq > 0) {
-            hipLaunchKernelGGL(k_grad_prep, dim3((mq + kBlock - 1) / kBlock, i1 - i0), dim3(kBlock), 0, s,
-                               dgs + i0, q, amp, dL_dI, pq32, pw32, pq64);
-        }
-        std::vector<GradItem> sub;
-        for (auto &it : sorted_items)
-            if (it.seg >= i0 && it.seg < i1) sub.push_back(it);
-        if (!sub.empty()) {
-            XS_TRY(upload(s, SLOT_ITEMS, sub.data(), sizeof(GradItem) * sub.size(), &d_items));
-            hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, static_cast<int32_t *>(d_cnt), 1);
-            const GradItem *it = static_cast<const GradItem *>(d_items);
-            int32_t *cnt = static_cast<int32_t *>(d_cnt);
-            const int n = static_cast<int>(sub.size());
-            switch (AL) {
-            case 1: launch_grad<1>(s, std::min(n, device_slots((const void *)k_grad_fp32c<1>)), it, n, cnt, dgs, b, pq32, pw32, pq64, gp); break;
-            case 2: launch_grad<2>(s, std::min(n, device_slots((const void *)k_grad_fp32c<2>)), it, n, cnt, dgs, b, pq32, pw32, pq64, gp); break;
-            case 4: launch_grad<4>(s, std::min(n, device_slots((const void *)k_grad_fp32c<4>)), it, n, cnt, dgs, b, pq32, pw32, pq64, gp); break;
-            case 8: launch_grad<8>(s, std::min(n, device_slots((const void *)k_grad_fp32c<8>)), it, n, cnt, dgs, b, pq32, pw32, pq64, gp); break;
-            default: return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8 (got %d)", AL);
-            }
-            XS_HIP(hipGetLastError());
-        }
-        i0 = i1;
-    }
-    if (max_slots > 0) {
-        hipLaunchKernelGGL(k_grad_combine, dim3((max_slots + kBlock - 1) / kBlock, n_segs), dim3(kBlock), 0, s,
-                           dgs, static_cast<const double *>(d_part), b.tile_atom, f, dL_dr, dL_dr64);
+    if (t.max_slots_seg > 0) {
+        hipLaunchKernelGGL(k_grad_combine, dim3((t.max_slots_seg + kBlock - 1) / kBlock, n_seg), dim3(kBlock), 0,
+                           s, b.gsegs, b.gpart, b.tile_atom, f, g32, g64);
         XS_HIP(hipGetLastError());
     }
     return XS_OK;
+}
+
+// ---------------------------------------------------------------- one-shot calls
+
+xs_status fp32c_forward(hipStream_t s, const Segment *segs, int n_segs, const double *box,
+                        const double *pos, const double *f, const double *q, double *I,
+                        double *amp, const xs_tile_shape &fsh, const xs_tile_shape &gsh) {
+    if (n_segs <= 0) return XS_OK;
+    Plan p;
+    XS_TRY(p.build(segs, n_segs, box, fsh, gsh));
+    XS_TRY(p.allocate(s, false));
+    XS_TRY(p.sort_pixels(s, q));
+    XS_TRY(p.tile_atoms(s, pos, f));
+    return p.forward(s, q, I, amp);
+}
+
+xs_status fp32c_grad(hipStream_t s, const Segment *segs, int n_segs, const double *box,
+                     const double *pos, const double *f, const double *q, const double *amp,
+                     const double *dL_dI, float *dL_dr, double *dL_dr64, const xs_tile_shape &fsh,
+                     const xs_tile_shape &gsh) {
+    if (n_segs <= 0) return XS_OK;
+    Plan p;
+    XS_TRY(p.build(segs, n_segs, box, fsh, gsh));
+    XS_TRY(p.allocate(s, false));
+    XS_TRY(p.sort_pixels(s, q));
+    XS_TRY(p.tile_atoms(s, pos, f));
+    return p.grad(s, q, f, amp, dL_dI, dL_dr, dL_dr64);
 }
 
 }  // namespace xs

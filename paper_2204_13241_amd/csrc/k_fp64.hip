@@ -153,8 +153,13 @@ xs_status fp64_forward(hipStream_t s, const Segment *segs_host, int n_segs, int 
     void *d_segs = nullptr;
     XS_TRY(upload(s, SLOT_SEGS, segs_host, sizeof(Segment) * n_segs, &d_segs));
     dim3 grid((max_q + kBlock - 1) / kBlock, n_segs);
+    double work = 0.0;
+    for (int i = 0; i < n_segs; ++i) work += static_cast<double>(segs_host[i].n_atoms) * segs_host[i].n_q;
+    void *tok = nullptr;
+    timer_begin(s, TIMER_FWD64, &tok);
     hipLaunchKernelGGL(k_forward_fp64, grid, dim3(kBlock), 0, s,
                        static_cast<const Segment *>(d_segs), pos, f, q, I, amp);
+    timer_end(s, TIMER_FWD64, tok, work);
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -166,9 +171,14 @@ xs_status fp64_grad(hipStream_t s, const Segment *segs_host, int n_segs, int max
     void *d_segs = nullptr;
     XS_TRY(upload(s, SLOT_SEGS, segs_host, sizeof(Segment) * n_segs, &d_segs));
     dim3 grid((max_atoms + kBlock - 1) / kBlock, n_segs);
+    double work = 0.0;
+    for (int i = 0; i < n_segs; ++i) work += static_cast<double>(segs_host[i].n_atoms) * segs_host[i].n_q;
+    void *tok = nullptr;
+    timer_begin(s, TIMER_GRAD64, &tok);
     hipLaunchKernelGGL(k_grad_fp64, grid, dim3(kBlock), 0, s,
                        static_cast<const Segment *>(d_segs), pos, f, q, amp, dL_dI, dL_dr,
                        dL_dr64);
+    timer_end(s, TIMER_GRAD64, tok, work);
     XS_HIP(hipGetLastError());
     return XS_OK;
 }

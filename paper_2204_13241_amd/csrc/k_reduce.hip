@@ -271,6 +271,8 @@ xs_status partition(hipStream_t s, int32_t *key, int64_t n_q, int32_t R, int32_t
 xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,
                    const RingEdges &edges, int32_t n_tau, double *g2_out, int32_t *ring_count) {
     const int32_t R = edges.n_rings;
+    void *tok = nullptr;
+    timer_begin(s, TIMER_G2, &tok);
     void *key = nullptr, *G = nullptr, *used = nullptr;
     XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
     XS_TRY(scratch(s, SLOT_PIXEL2, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &used));
@@ -299,6 +301,7 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
     XS_TRY(partition(s, k, n_q, R, &list, &start));
     hipLaunchKernelGGL(k_g2_ring, dim3(blocks_for(static_cast<int64_t>(R) * n_tau)), dim3(kBlock), 0, s,
                        static_cast<const double *>(G), n_tau, R, list, start, g2_out, ring_count);
+    timer_end(s, TIMER_G2, tok, static_cast<double>(F) * n_q * sizeof(double));
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -307,6 +310,8 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
                         const RingEdges &edges, int32_t n_levels, double *beta_out,
                         double *beta_win) {
     const int32_t R = edges.n_rings;
+    void *tok = nullptr;
+    timer_begin(s, TIMER_XSVS, &tok);
     void *key = nullptr, *bwin = nullptr, *la = nullptr, *lb = nullptr;
     XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
     XS_TRY(scratch(s, SLOT_BWIN, sizeof(double) * F * R, &bwin));
@@ -340,6 +345,7 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
                            beta_win ? beta_win + static_cast<int64_t>(l) * F * R : nullptr);
         XS_HIP(hipGetLastError());
     }
+    timer_end(s, TIMER_XSVS, tok, static_cast<double>(F) * n_q * sizeof(double));
     return XS_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -123,6 +124,26 @@ xs_status upload(hipStream_t s, Slot slot, const void *host, size_t bytes, void 
     else XS_HIP(hipEventSynchronize(b.copied));  // previous copy out of `pinned` finished
     std::memcpy(b.pinned, host, bytes);
     XS_HIP(hipMemcpyAsync(*dev, b.pinned, bytes, hipMemcpyHostToDevice, s));
+    XS_HIP(hipEventRecord(b.copied, s));
+    return XS_OK;
+}
+
+xs_status stage_copy(hipStream_t s, Slot slot, const void *host, size_t bytes, void *dst) {
+    StreamScratch *ss = scratch_for(s);
+    Buffer &b = ss->slot[slot];
+    if (b.pinned_bytes < bytes) {
+        XS_TRY(refuse_if_capturing(s));
+        if (b.copied) XS_HIP(hipEventSynchronize(b.copied));
+        if (b.pinned) XS_HIP(hipHostFree(b.pinned));
+        b.pinned = nullptr;
+        b.pinned_bytes = 0;
+        XS_HIP(hipHostMalloc(&b.pinned, bytes + bytes / 4, hipHostMallocDefault));
+        b.pinned_bytes = bytes + bytes / 4;
+    }
+    if (!b.copied) XS_HIP(hipEventCreateWithFlags(&b.copied, hipEventDisableTiming));
+    else XS_HIP(hipEventSynchronize(b.copied));
+    std::memcpy(b.pinned, host, bytes);
+    XS_HIP(hipMemcpyAsync(dst, b.pinned, bytes, hipMemcpyHostToDevice, s));
     XS_HIP(hipEventRecord(b.copied, s));
     return XS_OK;
 }
@@ -249,13 +270,14 @@ xs_status xs_intensity_direct(const xs_batch *b, const double *pos, const double
                             amp_out);
     if (precision == XS_FP32C) {
         XS_TRY(check_box(b));
-        xs_tile_shape sh;
+        xs_tile_shape fsh, gsh;
         {
             std::lock_guard<std::mutex> lk(g_shape_mu);
-            sh = g_shape[0];
+            fsh = g_shape[0];
+            gsh = g_shape[1];
         }
         return fp32c_forward(s, segs.data(), static_cast<int>(segs.size()), b->box, pos, f, q, I_out,
-                             amp_out, sh);
+                             amp_out, fsh, gsh);
     }
     return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
 }
@@ -276,13 +298,14 @@ xs_status xs_intensity_grad(const xs_batch *b, const double *pos, const double *
                          dL_dI, dL_dr, dL_dr64);
     if (precision == XS_FP32C) {
         XS_TRY(check_box(b));
-        xs_tile_shape sh;
+        xs_tile_shape fsh, gsh;
         {
             std::lock_guard<std::mutex> lk(g_shape_mu);
-            sh = g_shape[1];
+            fsh = g_shape[0];
+            gsh = g_shape[1];
         }
         return fp32c_grad(s, segs.data(), static_cast<int>(segs.size()), b->box, pos, f, q, amp,
-                          dL_dI, dL_dr, dL_dr64, sh);
+                          dL_dI, dL_dr, dL_dr64, fsh, gsh);
     }
     return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
 }
@@ -324,6 +347,108 @@ int32_t xs_version(void) { return 100; }
 
 xs_status xs_shutdown(void) {
     release_all_scratch();
+    return XS_OK;
+}
+
+xs_status xs_speckle_loss(const double *I, const double *I_target, int64_t n, double *loss_out,
+                          double *dL_dI, void *stream) {
+    XS_TRY(begin(stream));
+    if (n < 0) return set_error(XS_EINVAL, "n must be >= 0");
+    if (!loss_out) return set_error(XS_EINVAL, "loss_out is NULL");
+    if (n > 0 && (!I || !I_target)) return set_error(XS_EINVAL, "I / I_target is NULL");
+    return speckle_loss(static_cast<hipStream_t>(stream), I, I_target, n, loss_out, dL_dI);
+}
+
+xs_status xs_position_step(double *pos, const float *dL_dr, const double *dL_dr64, int64_t n,
+                           double step, void *stream) {
+    XS_TRY(begin(stream));
+    if (n < 0) return set_error(XS_EINVAL, "n must be >= 0");
+    if (!std::isfinite(step)) return set_error(XS_EINVAL, "step must be finite");
+    if (n > 0 && (!pos || (!dL_dr && !dL_dr64))) return set_error(XS_EINVAL, "pos / gradient is NULL");
+    return position_step(static_cast<hipStream_t>(stream), pos, dL_dr, dL_dr64, n, step);
+}
+
+xs_status xs_timing_enable(int32_t on) { return timing_enable(on); }
+
+xs_status xs_timing_read(int32_t kind, double *total_ms, int64_t *launches, double *work) {
+    return timing_read(kind, total_ms, launches, work);
+}
+
+xs_status xs_roofline_probe(int32_t kind, int64_t bytes, double *rate, void *stream) {
+    XS_TRY(begin(stream));
+    if (!rate) return set_error(XS_EINVAL, "rate is NULL");
+    return roofline_probe(static_cast<hipStream_t>(stream), kind, bytes, rate);
+}
+
+struct xs_plan {
+    xs::Plan plan;
+    int device = 0;
+    const double *q = nullptr;
+    int64_t total_out = 0;
+    int64_t total_pos = 0;
+};
+
+xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void *stream) {
+    XS_TRY(begin(stream));
+    if (!out) return set_error(XS_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    std::vector<Segment> segs;
+    int max_atoms = 0, max_q = 0;
+    XS_TRY(expand_batch(b, segs, max_atoms, max_q));
+    XS_TRY(check_box(b));
+    if (max_q > 0 && !q) return set_error(XS_EINVAL, "q is NULL");
+    xs_tile_shape fsh, gsh;
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        fsh = g_shape[0];
+        gsh = g_shape[1];
+    }
+    auto *p = new (std::nothrow) xs_plan();
+    if (!p) return set_error(XS_ENOMEM, "plan: host allocation failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    xs_status st = p->plan.build(segs.data(), static_cast<int>(segs.size()), b->box, fsh, gsh);
+    if (st == XS_OK) st = p->plan.allocate(s, true);
+    if (st == XS_OK) st = p->plan.sort_pixels(s, q);
+    if (st != XS_OK) {
+        delete p;
+        return st;
+    }
+    (void)hipGetDevice(&p->device);
+    p->q = q;
+    *out = p;
+    return XS_OK;
+}
+
+xs_status xs_plan_intensity(xs_plan *p, const double *pos, const double *f, double *I_out,
+                            double *amp_out, void *stream) {
+    XS_TRY(begin(stream));
+    if (!p) return set_error(XS_EINVAL, "plan is NULL");
+    if (!I_out) return set_error(XS_EINVAL, "I_out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    XS_TRY(p->plan.tile_atoms(s, pos, f));
+    return p->plan.forward(s, p->q, I_out, amp_out);
+}
+
+xs_status xs_plan_grad(xs_plan *p, const double *pos, const double *f, const double *amp,
+                       const double *dL_dI, int32_t retile, float *dL_dr, double *dL_dr64,
+                       void *stream) {
+    XS_TRY(begin(stream));
+    if (!p) return set_error(XS_EINVAL, "plan is NULL");
+    if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
+    if (!amp || !dL_dI) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (retile) XS_TRY(p->plan.tile_atoms(s, pos, f));
+    return p->plan.grad(s, p->q, f, amp, dL_dI, dL_dr, dL_dr64);
+}
+
+xs_status xs_plan_destroy(xs_plan *p) {
+    if (!p) return XS_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    delete p;
+    (void)hipSetDevice(cur);
     return XS_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "xs.h"
 
@@ -47,9 +48,17 @@ enum Slot {
     SLOT_LEVEL_A,       // XSVS window sums (ping)
     SLOT_LEVEL_B,       // XSVS window sums (pong)
     SLOT_BWIN,          // XSVS per-window contrast
+    SLOT_PSETS,         // FP32C pixel-set table
+    SLOT_PIXKEYS,       // FP32C pixel sort keys / order
+    SLOT_SORT_TMP,      // radix-sort temporary storage
+    SLOT_GITEMS,        // FP32C gradient work items
+    SLOT_PLAN,          // one-shot FP32C plan buffers
+    SLOT_TABLES,        // one-shot FP32C plan tables (staging)
     SLOT_COUNT
 };
 xs_status scratch(hipStream_t stream, Slot slot, size_t bytes, void **ptr);
+// Copy a host table to a device address through the slot's pinned staging buffer.
+xs_status stage_copy(hipStream_t stream, Slot slot, const void *host, size_t bytes, void *dst);
 // Stage a host table into the stream's scratch slot (async copy from a
 // library-owned pinned staging buffer).
 xs_status upload(hipStream_t stream, Slot slot, const void *host, size_t bytes, void **dev);
@@ -76,13 +85,45 @@ xs_status fp64_grad(hipStream_t s, const Segment *segs_host, int n_segs, int max
                     const double *pos, const double *f, const double *q, const double *amp,
                     const double *dL_dI, float *dL_dr, double *dL_dr64);
 
+// FP32C batch plan: host tables and work lists of one batch layout, device
+// buffers carved from one block, and the steps of a call.  The pixel order
+// depends on q only; atom tiles depend on the positions.  Every step after
+// allocate() is kernel launches only (capturable in a HIP graph), except
+// sort_pixels, which uses a library radix sort.
+class Plan {
+public:
+    struct Tables;
+    struct Buffers;
+    Plan();
+    ~Plan();
+    Plan(const Plan &) = delete;
+    Plan &operator=(const Plan &) = delete;
+    xs_status build(const Segment *segs, int n_segs, const double *box, const xs_tile_shape &fsh,
+                    const xs_tile_shape &gsh);
+    xs_status allocate(hipStream_t s, bool owned);
+    xs_status sort_pixels(hipStream_t s, const double *q);
+    xs_status tile_atoms(hipStream_t s, const double *pos, const double *f);
+    xs_status forward(hipStream_t s, const double *q, double *I, double *amp);
+    xs_status grad(hipStream_t s, const double *q, const double *f, const double *amp,
+                   const double *dL_dI, float *g32, double *g64);
+    size_t layout(char *base);
+    std::vector<char> table_blob() const;
+
+    Tables *T;
+    Buffers *B;
+    void *owned_block = nullptr;
+    size_t device_bytes = 0;
+    int n_seg = 0;
+    xs_tile_shape fshape{}, gshape{};
+};
+
 xs_status fp32c_forward(hipStream_t s, const Segment *segs_host, int n_segs, const double *box,
                         const double *pos, const double *f, const double *q, double *I,
-                        double *amp, const xs_tile_shape &shape);
+                        double *amp, const xs_tile_shape &fsh, const xs_tile_shape &gsh);
 xs_status fp32c_grad(hipStream_t s, const Segment *segs_host, int n_segs, const double *box,
                      const double *pos, const double *f, const double *q, const double *amp,
                      const double *dL_dI, float *dL_dr, double *dL_dr64,
-                     const xs_tile_shape &shape);
+                     const xs_tile_shape &fsh, const xs_tile_shape &gsh);
 
 constexpr int kMaxRings = 256;
 struct RingEdges {
@@ -95,5 +136,29 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q
 xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
                         const double *q, const RingEdges &edges, int32_t n_levels,
                         double *beta_out, double *beta_win);
+
+// ---------------------------------------------------------------- timing
+// Optional HIP-event timing of kernel launches on the stream they run on.
+enum TimerKind {
+    TIMER_FWD32 = 0,   // FP32C forward pair kernel
+    TIMER_GRAD32 = 1,  // FP32C gradient pair kernel
+    TIMER_FWD64 = 2,   // FP64 forward kernel
+    TIMER_GRAD64 = 3,  // FP64 gradient kernel
+    TIMER_BIN = 4,     // FP32C binning (all binning kernels of a call)
+    TIMER_G2 = 5,      // g2 reduction (whole call)
+    TIMER_XSVS = 6,    // XSVS reduction (whole call)
+};
+#define XS_TIMER_KINDS 7
+bool timing_on();
+void timer_begin(hipStream_t s, int kind, void **token);
+void timer_end(hipStream_t s, int kind, void *token, double work);
+xs_status timing_enable(int on);
+xs_status timing_read(int kind, double *ms, int64_t *launches, double *work);
+
+xs_status speckle_loss(hipStream_t s, const double *I, const double *It, int64_t n, double *out,
+                       double *dL_dI);
+xs_status position_step(hipStream_t s, double *pos, const float *g32, const double *g64, int64_t n,
+                        double step);
+xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate);
 
 }  // namespace xs
