@@ -114,6 +114,11 @@ def run_grad(args):
     torch.cuda.synchronize()
     log("inputs ready: N=%d Q=%d" % (N, Q))
 
+    tuned = None
+    if not args.no_tune:
+        from paper_2204_13241_amd import tune
+        tuned = tune.tune([(N, 1, q, L)], pos, f, use_cache=not args.retune)
+        log("tile shapes (%s): fwd %s  grad %s" % (tuned["source"], tuned["forward"], tuned["gradient"]))
     # one plan for the whole run: work lists, buffers and pixel order built once
     plan = api.Plan.single(N, 1, q, L)
     I = torch.empty(Q, dtype=torch.float64, device=dev)
@@ -252,6 +257,8 @@ def run_grad(args):
         "valu_roofline_frac": value / (PEAK_SINCOS_PAIRS / 1e9),
         "kernels": kern,
     }
+    if tuned is not None:
+        result["autotune"] = {k: tuned[k] for k in ("source", "key", "forward_ms", "gradient_ms") if k in tuned}
     result.update(extra)
     if not args.no_probe:
         result["measured_peaks"] = {
@@ -276,7 +283,16 @@ def main():
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--graph", action="store_true", help="time HIP-graph replays of the step")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run the library's plain copy kernel on BYTES (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        from paper_2204_13241_amd import api
+        rate = api.roofline_probe(3, args.copy_probe)
+        print(json.dumps({"copy_bytes": args.copy_probe, "launches": 6, "bytes_per_s": rate}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

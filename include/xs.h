@@ -188,16 +188,21 @@ xs_status xs_shutdown(void);
 
 /*
  * Tile shape of the FP32C pair kernels (the autotuner's search space):
- *   atoms_per_tile  atoms in one spatial tile (32, 64 or 128)
+ *   atoms_per_tile  atoms in one spatial tile (64: one wavefront)
  *   q_per_lane      pixels (forward) or atoms (gradient) per lane (1, 2, 4, 8)
  *   atom_split      atom tiles per forward work item (>= 1)
  *   pixel_split     pixels per gradient work item (multiple of 64)
+ *   waves_per_simd  0: compiler's register allocation; 4: variant bounded to
+ *                   128 VGPRs (4 wavefronts per SIMD), built for forward
+ *                   q_per_lane 2 and 4 and gradient q_per_lane 4
+ * Shapes apply to calls and plans created after they are set.
  */
 typedef struct xs_tile_shape {
     int32_t atoms_per_tile;
     int32_t q_per_lane;
     int32_t atom_split;
     int32_t pixel_split;
+    int32_t waves_per_simd;
 } xs_tile_shape;
 
 /* kind: 0 = forward pair kernel, 1 = gradient pair kernel. */

@@ -48,6 +48,7 @@ class XsTileShape(ctypes.Structure):
         ("q_per_lane", ctypes.c_int32),
         ("atom_split", ctypes.c_int32),
         ("pixel_split", ctypes.c_int32),
+        ("waves_per_simd", ctypes.c_int32),
     ]
 
 

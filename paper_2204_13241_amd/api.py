@@ -231,11 +231,14 @@ def get_tile_shape(kind: int) -> dict:
     s = _lib.XsTileShape()
     _lib.check(_lib.load().xs_get_tile_shape(int(kind), ctypes.byref(s)))
     return {"atoms_per_tile": s.atoms_per_tile, "q_per_lane": s.q_per_lane,
-            "atom_split": s.atom_split, "pixel_split": s.pixel_split}
+            "atom_split": s.atom_split, "pixel_split": s.pixel_split,
+            "waves_per_simd": s.waves_per_simd}
 
 
-def set_tile_shape(kind: int, atoms_per_tile=64, q_per_lane=4, atom_split=64, pixel_split=8192):
-    s = _lib.XsTileShape(int(atoms_per_tile), int(q_per_lane), int(atom_split), int(pixel_split))
+def set_tile_shape(kind: int, atoms_per_tile=64, q_per_lane=4, atom_split=64, pixel_split=8192,
+                   waves_per_simd=0):
+    s = _lib.XsTileShape(int(atoms_per_tile), int(q_per_lane), int(atom_split), int(pixel_split),
+                         int(waves_per_simd))
     _lib.check(_lib.load().xs_set_tile_shape(int(kind), ctypes.byref(s)))
 
 

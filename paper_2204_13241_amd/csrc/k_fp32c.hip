@@ -419,8 +419,8 @@ __device__ __forceinline__ void tile_pairs(const float4 *__restrict__ at, const 
     }
 }
 
-template <int QL>
-__global__ __launch_bounds__(kBlock) void k_forward_fp32c(
+template <int QL, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
     const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
     const FwdSeg *__restrict__ segs, const double *__restrict__ q,
     const int32_t *__restrict__ pix_order, const float4 *__restrict__ t_hi,
@@ -672,8 +672,8 @@ __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const
     }
 }
 
-template <int AL>
-__global__ __launch_bounds__(kBlock) void k_grad_fp32c(
+template <int AL, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
     const GradItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
     const GradSeg *__restrict__ segs, const float4 *__restrict__ t_hi,
     const float4 *__restrict__ t_lo, const double4 *__restrict__ origins,
@@ -1174,18 +1174,44 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
 }
 
 namespace {
-template <int QL>
+template <int QL, int OCC>
 void launch_forward(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q) {
-    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_forward_fp32c<QL>)));
-    hipLaunchKernelGGL(k_forward_fp32c<QL>, dim3(slots), dim3(kBlock), 0, s, b.fitems, n, counter, b.fsegs,
-                       q, b.pix_order, b.t_hi, b.t_lo, b.origins, b.fpart);
+    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_forward_fp32c<QL, OCC>)));
+    hipLaunchKernelGGL((k_forward_fp32c<QL, OCC>), dim3(slots), dim3(kBlock), 0, s, b.fitems, n, counter,
+                       b.fsegs, q, b.pix_order, b.t_hi, b.t_lo, b.origins, b.fpart);
 }
 
-template <int AL>
+template <int AL, int OCC>
 void launch_grad(hipStream_t s, const GradItem *items, int n, int32_t *counter, const Plan::Buffers &b) {
-    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_grad_fp32c<AL>)));
-    hipLaunchKernelGGL(k_grad_fp32c<AL>, dim3(slots), dim3(kBlock), 0, s, items, n, counter, b.gsegs, b.t_hi,
-                       b.t_lo, b.origins, b.pdq, b.pw, b.pq64, b.centre, b.gpart);
+    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_grad_fp32c<AL, OCC>)));
+    hipLaunchKernelGGL((k_grad_fp32c<AL, OCC>), dim3(slots), dim3(kBlock), 0, s, items, n, counter, b.gsegs,
+                       b.t_hi, b.t_lo, b.origins, b.pdq, b.pw, b.pq64, b.centre, b.gpart);
+}
+
+// Built variants: pixels (forward) or atoms (gradient) per lane, and an
+// optional bound of 4 wavefronts per SIMD (at most 128 VGPRs).
+bool launch_forward_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, const Plan::Buffers &b,
+                            const double *q) {
+    const bool o4 = occ == 4;
+    switch (ql) {
+    case 1: launch_forward<1, 1>(s, n, cnt, b, q); return true;
+    case 2: o4 ? launch_forward<2, 4>(s, n, cnt, b, q) : launch_forward<2, 1>(s, n, cnt, b, q); return true;
+    case 4: o4 ? launch_forward<4, 4>(s, n, cnt, b, q) : launch_forward<4, 1>(s, n, cnt, b, q); return true;
+    case 8: launch_forward<8, 1>(s, n, cnt, b, q); return true;
+    default: return false;
+    }
+}
+
+bool launch_grad_variant(hipStream_t s, int al, int occ, const GradItem *items, int n, int32_t *cnt,
+                         const Plan::Buffers &b) {
+    const bool o4 = occ == 4;
+    switch (al) {
+    case 1: launch_grad<1, 1>(s, items, n, cnt, b); return true;
+    case 2: launch_grad<2, 1>(s, items, n, cnt, b); return true;
+    case 4: o4 ? launch_grad<4, 4>(s, items, n, cnt, b) : launch_grad<4, 1>(s, items, n, cnt, b); return true;
+    case 8: launch_grad<8, 1>(s, items, n, cnt, b); return true;
+    default: return false;
+    }
 }
 }  // namespace
 
@@ -1197,13 +1223,8 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, 1);
         void *tok = nullptr;
         timer_begin(s, TIMER_FWD32, &tok);
-        switch (fshape.q_per_lane) {
-        case 1: launch_forward<1>(s, n, b.counters, b, q); break;
-        case 2: launch_forward<2>(s, n, b.counters, b, q); break;
-        case 4: launch_forward<4>(s, n, b.counters, b, q); break;
-        case 8: launch_forward<8>(s, n, b.counters, b, q); break;
-        default: return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
-        }
+        if (!launch_forward_variant(s, fshape.q_per_lane, fshape.waves_per_simd, n, b.counters, b, q))
+            return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
         timer_end(s, TIMER_FWD32, tok, t.fwork);
         XS_HIP(hipGetLastError());
     }
@@ -1231,13 +1252,8 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
         const GradItem *items = b.gitems + t.gsub_item0[k];
         void *tok = nullptr;
         timer_begin(s, TIMER_GRAD32, &tok);
-        switch (gshape.q_per_lane) {
-        case 1: launch_grad<1>(s, items, n, cnt, b); break;
-        case 2: launch_grad<2>(s, items, n, cnt, b); break;
-        case 4: launch_grad<4>(s, items, n, cnt, b); break;
-        case 8: launch_grad<8>(s, items, n, cnt, b); break;
-        default: return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
-        }
+        if (!launch_grad_variant(s, gshape.q_per_lane, gshape.waves_per_simd, items, n, cnt, b))
+            return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
         timer_end(s, TIMER_GRAD32, tok, t.gsub_work[k]);
         XS_HIP(hipGetLastError());
     }

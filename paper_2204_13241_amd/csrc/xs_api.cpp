@@ -171,7 +171,8 @@ void release_all_scratch() {
 
 namespace {
 
-xs_tile_shape g_shape[2] = {{64, 4, 64, 0}, {64, 4, 0, 8192}};
+// Defaults: the autotuner's choice on a 65,536-atom, 512x512-pixel single frame.
+xs_tile_shape g_shape[2] = {{64, 2, 64, 0, 4}, {64, 4, 0, 4096, 4}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
@@ -469,6 +470,11 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
     if (kind == 0 && shape->atom_split < 1) return set_error(XS_EINVAL, "atom_split must be >= 1");
     if (kind == 1 && (shape->pixel_split < 64 || shape->pixel_split % 64))
         return set_error(XS_EINVAL, "pixel_split must be a positive multiple of 64");
+    if (shape->waves_per_simd != 0 && shape->waves_per_simd != 4)
+        return set_error(XS_EINVAL, "waves_per_simd must be 0 or 4");
+    if (shape->waves_per_simd == 4 && !((kind == 0 && (ql == 2 || ql == 4)) || (kind == 1 && ql == 4)))
+        return set_error(XS_ENOTSUP, "the 4-waves-per-SIMD variant is built for forward q_per_lane 2, 4 "
+                                     "and gradient q_per_lane 4");
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[kind] = *shape;
     return XS_OK;

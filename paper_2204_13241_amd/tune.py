@@ -1,0 +1,152 @@
+"""Autotuner for the FP32C tile shapes.
+
+For a given batch layout it builds a plan per candidate shape, times the pair
+kernel with the library's HIP-event timers (xs_timing_*) and keeps the
+fastest.  Results are cached in a JSON file keyed by the device architecture
+and a workload signature (systems, frames, atom and pixel counts bucketed to
+powers of two, planar or curved detector), so a later run on the same kind of
+workload skips the search.  Cache path: $XS_TUNE_CACHE, else
+~/.cache/paper_2204_13241_amd/tune.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import api
+
+# (pixels per lane, waves-per-SIMD bound) x atom tiles per item
+FWD_CANDIDATES = [(ql, occ, split)
+                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0))
+                  for split in (16, 32, 64, 128)]
+# (atoms per lane, waves-per-SIMD bound) x pixels per item
+GRAD_CANDIDATES = [(al, occ, pc)
+                   for al, occ in ((1, 0), (2, 0), (4, 0), (4, 4), (8, 0))
+                   for pc in (2048, 4096, 8192, 16384)]
+
+
+def _cache_path() -> str:
+    p = os.environ.get("XS_TUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "paper_2204_13241_amd", "tune.json")
+
+
+def _bucket(n: int) -> int:
+    return 0 if n <= 0 else int(round(math.log2(n)))
+
+
+def signature(systems, planar: bool) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    na = sum(int(n) * int(t) for n, t, _, _ in systems)
+    nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
+    return "%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
+        arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
+        "planar" if planar else "curved")
+
+
+def _load_cache(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, data):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def _time_kernel(kind: str, run, reps: int) -> float:
+    run()                                 # warm-up (also builds code objects)
+    torch.cuda.synchronize()
+    api.timing_enable(True)
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    rec = api.timing_read(kind)
+    api.timing_enable(False)
+    return rec["ms"] / max(rec["launches"], 1)
+
+
+def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 3, use_cache: bool = True,
+         fwd_candidates: Optional[List] = None, grad_candidates: Optional[List] = None,
+         apply: bool = True) -> dict:
+    """Pick the fastest forward and gradient tile shapes for this batch.
+
+    systems: as for api.Plan; pos, f: packed positions and form factors.
+    Returns {"forward": shape, "gradient": shape, "source": "cache"|"search",
+    "timings_ms": {...}} and, if apply, installs the shapes (xs_set_tile_shape).
+    """
+    qz = torch.cat([q[:, 2] for _, _, q, _ in systems])
+    planar = bool((qz == qz[0]).all().item()) if qz.numel() else True
+    key = signature(systems, planar)
+    path = _cache_path()
+    cache = _load_cache(path) if use_cache else {}
+    if use_cache and key in cache:
+        best = cache[key]
+        if apply:
+            api.set_tile_shape(0, **best["forward"])
+            api.set_tile_shape(1, **best["gradient"])
+        return dict(best, source="cache", key=key)
+    old_f, old_g = api.get_tile_shape(0), api.get_tile_shape(1)
+    timings = {"forward": {}, "gradient": {}}
+    # forward: candidate shapes with the current gradient shape
+    best_f, best_ft = None, float("inf")
+    for ql, occ, split in (fwd_candidates or FWD_CANDIDATES):
+        shape = dict(atoms_per_tile=64, q_per_lane=ql, atom_split=split, pixel_split=old_f["pixel_split"],
+                     waves_per_simd=occ)
+        api.set_tile_shape(0, **shape)
+        plan = api.Plan(systems)
+        I = torch.empty(plan.total_out, dtype=torch.float64, device=pos.device)
+        amp = torch.empty((plan.total_out, 2), dtype=torch.float64, device=pos.device)
+        t = _time_kernel("fwd32", lambda: plan.intensity(pos, f, I, amp), reps)
+        plan.close()
+        timings["forward"]["ql%d_occ%d_split%d" % (ql, occ, split)] = t
+        if t < best_ft:
+            best_f, best_ft = shape, t
+    api.set_tile_shape(0, **best_f)
+    # gradient: amplitudes of the tuned forward, unit-variance weights
+    plan = api.Plan(systems)
+    I = torch.empty(plan.total_out, dtype=torch.float64, device=pos.device)
+    amp = torch.empty((plan.total_out, 2), dtype=torch.float64, device=pos.device)
+    plan.intensity(pos, f, I, amp)
+    gen = torch.Generator(device=pos.device)
+    gen.manual_seed(1234)
+    w = torch.randn(plan.total_out, dtype=torch.float64, device=pos.device, generator=gen)
+    plan.close()
+    best_g, best_gt = None, float("inf")
+    for al, occ, pc in (grad_candidates or GRAD_CANDIDATES):
+        shape = dict(atoms_per_tile=64, q_per_lane=al, atom_split=old_g["atom_split"], pixel_split=pc,
+                     waves_per_simd=occ)
+        api.set_tile_shape(1, **shape)
+        plan = api.Plan(systems)
+        g = torch.empty((plan.total_pos, 3), dtype=torch.float32, device=pos.device)
+        t = _time_kernel("grad32", lambda: plan.grad(pos, f, amp, w, retile=True, g32=g), reps)
+        plan.close()
+        timings["gradient"]["al%d_occ%d_pix%d" % (al, occ, pc)] = t
+        if t < best_gt:
+            best_g, best_gt = shape, t
+    result = {"forward": best_f, "gradient": best_g, "forward_ms": best_ft, "gradient_ms": best_gt}
+    if use_cache:
+        cache[key] = result
+        _store_cache(path, cache)
+    if apply:
+        api.set_tile_shape(0, **best_f)
+        api.set_tile_shape(1, **best_g)
+    else:
+        api.set_tile_shape(0, **old_f)
+        api.set_tile_shape(1, **old_g)
+    return dict(result, source="search", key=key, timings_ms=timings)

@@ -78,7 +78,7 @@ def test_batch_validation():
 def test_tile_shape_roundtrip_and_limits():
     from paper_2204_13241_amd import api
     old = api.get_tile_shape(0)
-    api.set_tile_shape(0, 64, 2, 16, 8192)
+    api.set_tile_shape(0, 64, 2, 16, 8192, 0)
     assert api.get_tile_shape(0)["q_per_lane"] == 2
     with pytest.raises(_lib.XsError):
         api.set_tile_shape(0, 64, 3, 16, 8192)
