@@ -638,8 +638,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict_
     pw[i] = make_float4(static_cast<float>(c * qp[0]), static_cast<float>(c * qp[1]),
                         static_cast<float>(c * qp[2]), 0.f);
     pq64[i] = make_double4(rx, ry, rz, psi);
+    // group kind: 0 general, 1 all q_z equal (dq_z = 0), 2 all q_z = 0 (also W_z = 0)
     if ((threadIdx.x & 63) == 0)
-        centre[sg.grp0 + sp / kPixStage] = make_double4(cx, cy, cz, lo[2] == hi[2] ? 1.0 : 0.0);
+        centre[sg.grp0 + sp / kPixStage] =
+            make_double4(cx, cy, cz, lo[2] == hi[2] ? (lo[2] == 0.0 ? 2.0 : 1.0) : 0.0);
 }
 
 // Workgroup = 4 wavefronts; wavefront w owns tiles t0 + w*AL + a (a < AL),
@@ -647,9 +649,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict_
 // time (one centre q_c per 64): per staged group each lane forms
 // beta = frac(q_c.d) for its atoms (FP64, from the exact offset) and each
 // wavefront the base phases theta'(p, tile) = frac(q_p.o + psi_p).  Per pair:
-// add + 3 FMA (2 when the group has dq_z = 0), one v_sin, 3 FMA.  Group
-// partials fold into FP64.
-template <int AL, bool PLANAR>
+// add + 3 FMA (2 when the group has dq_z = 0), one v_sin, 3 FMA (2 when every
+// q_z of the group is 0, so W_z = 0).  Group partials fold into FP64.
+template <int AL, bool PLANAR, bool NOZ>
 __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const float4 *__restrict__ sw,
                                             const float (*__restrict__ sth)[kPixStage],
                                             const float (&dx)[AL], const float (&dy)[AL],
@@ -667,7 +669,7 @@ __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const
             const float sn = __builtin_amdgcn_sinf(ph);
             gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
             gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
-            gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
+            if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
         }
     }
 }
@@ -736,8 +738,9 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             float gx[AL], gy[AL], gz[AL];
 #pragma unroll
             for (int a = 0; a < AL; ++a) gx[a] = gy[a] = gz[a] = 0.f;
-            if (c.w != 0.0) pixel_pairs<AL, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
-            else pixel_pairs<AL, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            if (c.w == 2.0) pixel_pairs<AL, true, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            else if (c.w == 1.0) pixel_pairs<AL, true, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            else pixel_pairs<AL, false, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
 #pragma unroll
             for (int a = 0; a < AL; ++a) {
                 gx64[a] += static_cast<double>(gx[a]);

@@ -1,0 +1,191 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times
+(batch plans, default tile shapes), on outputs the oracle computes one by one
+(sampled pixels / frames / atoms) and on reductions fed the same seeded
+intensities on both sides."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2204_13241_amd import api
+    return api
+
+
+def _speckle_like(rng, F, Q, corr=0.95):
+    """Exponentially distributed, time-correlated synthetic intensities [F, Q]."""
+    z = rng.standard_normal((Q, 2))
+    out = np.empty((F, Q))
+    for t in range(F):
+        z = corr * z + math.sqrt(1 - corr ** 2) * rng.standard_normal((Q, 2))
+        out[t] = 0.5 * (z ** 2).sum(axis=1)
+    return out
+
+
+def test_trajectory_full_size(api):
+    """32,000 atoms x 200 frames, 256x256 Ewald detector: I sampled against the oracle,
+    g2 of the FP32C intensities against g2 of the exact FP64 form."""
+    from _gpu import dev, host, scaled_err
+    w = X.workload_trajectory()
+    fr, f, q, L = w.positions[0], w.f[0], w.q[0], w.box[0]
+    F, N = fr.shape[0], fr.shape[1]
+    print("trajectory: %d frames x %d atoms x %d pixels" % (F, N, q.shape[0]), flush=True)
+    qd = dev(q)
+    plan = api.Plan.single(N, F, qd, L)
+    pos = dev(fr.reshape(-1, 3))
+    I32, _ = plan.intensity(pos, dev(f), want_amp=False)
+    I32 = I32.view(F, -1)
+    rng = np.random.default_rng(0)
+    frames = rng.choice(F, 4, replace=False)
+    pix = np.sort(rng.choice(q.shape[0], 128, replace=False))
+    for t in frames:
+        ref = oracle.intensity(fr[t], f, q[pix])[0]
+        assert scaled_err(host(I32[t])[pix], ref, f) < TOL
+    I64 = api.intensity(dev(fr), dev(f), qd, "fp64")
+    g2a, ca = api.g2_rings(I32.contiguous(), qd, w.edges, w.n_tau)
+    g2b, cb = api.g2_rings(I64, qd, w.edges, w.n_tau)
+    a, b = host(g2a), host(g2b)
+    ok = np.isfinite(b)
+    assert np.array_equal(host(ca), host(cb))
+    e_g2 = float(np.max(np.abs(a[ok] - b[ok]) / np.abs(b[ok])))
+    print("e_g2 (FP32C vs FP64 form) =", e_g2)
+    assert e_g2 < TOL
+    plan.close()
+
+
+def test_g2_full_size_bitwise(api):
+    """g2 reduction at 200 frames x 65,536 pixels, 32 rings, 100 lags: bit for bit."""
+    from _gpu import dev, host, bitwise_equal
+    q = X.ewald_detector(256, 1.5)
+    I = _speckle_like(np.random.default_rng(1), 200, q.shape[0])
+    edges = X.ring_edges(32, 1.5)
+    g2, cnt = api.g2_rings(dev(I), dev(q), edges, 100)
+    g2r, cntr = oracle.g2_rings(I, q, edges, 100)
+    assert np.array_equal(host(cnt), cntr)
+    assert bitwise_equal(host(g2), g2r)
+
+
+def test_batch_full_size(api):
+    """64 systems, N log-uniform in [2000, 64000), 512x512 Ewald detector, one plan."""
+    from _gpu import dev, host, scaled_err
+    w = X.workload_batch()
+    systems = [(p.shape[1], 1, dev(q), L) for p, q, L in zip(w.positions, w.q, w.box)]
+    print("batch: %d systems, %d atoms" % (len(systems), sum(w.extra["sizes"])), flush=True)
+    plan = api.Plan(systems)
+    I, _ = plan.intensity(dev(np.concatenate([p.reshape(-1, 3) for p in w.positions])),
+                          dev(np.concatenate(w.f)), want_amp=False)
+    Ih = host(I)
+    rng = np.random.default_rng(2)
+    for s in rng.choice(len(systems), 4, replace=False):
+        pix = np.sort(rng.choice(w.q[s].shape[0], 64, replace=False))
+        ref = oracle.intensity(w.positions[s][0], w.f[s], w.q[s][pix])[0]
+        o = int(plan.batch.out_off[s])
+        assert scaled_err(Ih[o + pix], ref, w.f[s]) < TOL
+    plan.close()
+
+
+def test_xsvs_workload_full_frame_size(api):
+    """256,000 atoms (fcc 40^3 + jitter), 1024x1024 Ewald detector to q = 2: two full
+    frames, intensities sampled against the oracle."""
+    from _gpu import dev, host, scaled_err
+    w = X.workload_xsvs(n_frames=2)
+    fr, f, q, L = w.positions[0], w.f[0], w.q[0], w.box[0]
+    print("xsvs frames: %s atoms x %d pixels" % (fr.shape, q.shape[0]), flush=True)
+    plan = api.Plan.single(fr.shape[1], 2, dev(q), L)
+    I, _ = plan.intensity(dev(fr.reshape(-1, 3)), dev(f), want_amp=False)
+    I = host(I).reshape(2, -1)
+    rng = np.random.default_rng(3)
+    pix = np.sort(rng.choice(q.shape[0], 48, replace=False))
+    for t in range(2):
+        ref = oracle.intensity(fr[t], f, q[pix])[0]
+        assert scaled_err(I[t][pix], ref, f) < TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("F,n_det", [(16, 1024), (1024, 256)])
+def test_xsvs_full_size_bitwise(api, F, n_det):
+    """XSVS reduction at the full pixel count (1024^2, 16 frames) and at the full frame count
+    (1024 frames, 256^2 pixels), 64 rings, windows up to 2^(levels-1): bit for bit."""
+    from _gpu import dev, host, bitwise_equal
+    q = X.ewald_detector(n_det, 2.0)
+    I = _speckle_like(np.random.default_rng(4), F, q.shape[0])
+    edges = X.ring_edges(64, 2.0)
+    levels = int(math.log2(F)) + 1 if F < 256 else 9
+    beta = api.xsvs_contrast(dev(I), dev(q), edges, levels)
+    ref = oracle.xsvs_contrast(I, q, edges, levels)
+    assert bitwise_equal(host(beta), ref)
+
+
+def test_differentiation_full_size(api):
+    """65,536 atoms, 512x512 planar pixels: intensities sampled against the oracle; the
+    adjoint of sum_p w_p I_p with w supported on 512 random pixels against the oracle's
+    gradient and against central differences (h = 1e-4) on 64 atoms."""
+    from _gpu import dev, host, scaled_err, grad_err
+    w = X.workload_grad()
+    r0, f, q, L = w.positions[0][0], w.f[0], w.q[0], w.box[0]
+    N, Q = r0.shape[0], q.shape[0]
+    plan = api.Plan.single(N, 1, dev(q), L)
+    pos = dev(r0)
+    I, amp = plan.intensity(pos, dev(f))
+    rng = np.random.default_rng(5)
+    pix = np.sort(rng.choice(Q, 512, replace=False))
+    Ir, ampr = oracle.intensity(r0, f, q[pix])
+    assert scaled_err(host(I)[pix], Ir, f) < TOL
+    wts = np.zeros(Q)
+    wts[pix] = rng.standard_normal(512)
+    g = plan.grad(pos, dev(f), amp, dev(wts), retile=False)
+    atoms = w.extra["fd_atoms"]
+    g_ref = oracle.intensity_grad(r0[atoms], f[atoms], q[pix], ampr, wts[pix])
+    e = grad_err(host(g)[atoms], g_ref)
+    print("e_grad vs oracle =", e)
+    assert e < TOL
+    fd = oracle.fd_grad(r0, f, q[pix], wts[pix], atoms, h=1e-4)
+    e_fd = grad_err(fd, g_ref)
+    print("oracle gradient vs central differences =", e_fd)
+    assert e_fd < 1e-5
+    plan.close()
+
+
+def test_gradient_descent_20_steps(api):
+    """20 gradient-descent steps on L = sum (I - I_t)^2 / sum I_t^2 (65,536 atoms) with
+    Armijo backtracking: the loss decreases at every step."""
+    from _gpu import dev
+    w = X.workload_grad()
+    r0, f, q, L = w.positions[0][0], w.f[0], w.q[0], w.box[0]
+    N = r0.shape[0]
+    qd, fd_ = dev(q), dev(f)
+    It = api.intensity(dev(w.extra["r_target"]), fd_, qd, "fp64")
+    plan = api.Plan.single(N, 1, qd, L)
+    pos = dev(r0)
+    I, amp = plan.intensity(pos, fd_)
+    loss, dLdI = api.speckle_loss(I, It)
+    losses = [float(loss[0])]
+    for step in range(20):
+        g = plan.grad(pos, fd_, amp, dLdI, retile=False, g64=torch.empty((N, 3), dtype=torch.float64,
+                                                                          device=pos.device))
+        gmax = float(g.abs().max())
+        alpha = 0.05 / gmax
+        gg = float((g * g).sum())
+        base = pos.clone()
+        for _ in range(30):
+            pos.copy_(base)
+            api.position_step(pos, g, alpha)
+            I, amp = plan.intensity(pos, fd_)
+            loss, dLdI = api.speckle_loss(I, It)
+            if float(loss[0]) <= losses[-1] - 1e-4 * alpha * gg:
+                break
+            alpha *= 0.5
+        losses.append(float(loss[0]))
+        assert losses[-1] < losses[-2], (step, losses)
+    print("loss %.6g -> %.6g over 20 steps" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.9 * losses[0]
+    plan.close()
