@@ -273,6 +273,42 @@ def run_grad(args):
     return result
 
 
+def run_reductions(args):
+    """g2 (trajectory shape: 200 frames x 256^2 pixels, 32 rings, 100 lags) and XSVS
+    (XSVS shape: 1024 frames x 1024^2 pixels, 64 rings, W = 1..256) on seeded synthetic
+    exponential intensities already in GPU memory; achieved GB/s = intensity bytes
+    read once / call duration (HIP events)."""
+    import torch
+    from paper_2204_13241_amd import api, inputs
+    out = {}
+    gen = torch.Generator(device="cuda:0")
+    for name, F, n_det, q_max, rings, kw in (("g2", 200, 256, 1.5, 32, {"n_tau": 100}),
+                                            ("xsvs", 1024, 1024, 2.0, 64, {"n_levels": 9})):
+        gen.manual_seed(2024)
+        q = torch.as_tensor(inputs.ewald_detector(n_det, q_max), dtype=torch.float64, device="cuda:0")
+        I = torch.empty((F, q.shape[0]), dtype=torch.float64, device="cuda:0").exponential_(1.0, generator=gen)
+        edges = inputs.ring_edges(rings, q_max)
+        call = (lambda: api.g2_rings(I, q, edges, kw["n_tau"])) if name == "g2" else \
+               (lambda: api.xsvs_contrast(I, q, edges, kw["n_levels"]))
+        call()
+        torch.cuda.synchronize()
+        api.timing_enable(True)
+        for _ in range(args.red_reps):
+            call()
+        torch.cuda.synchronize()
+        rec = api.timing_read(name)
+        api.timing_enable(False)
+        ms = rec["ms"] / max(rec["launches"], 1)
+        nbytes = F * q.shape[0] * 8
+        out[name] = {"frames": F, "pixels": int(q.shape[0]), "rings": rings, **kw, "avg_ms": ms,
+                     "intensity_bytes": nbytes, "achieved_GB_s": nbytes / (ms * 1e-3) / 1e9,
+                     "peak_GB_s": PEAK_HBM / 1e9, "frac": nbytes / (ms * 1e-3) / PEAK_HBM}
+        log("%s: %.3f ms, %.0f GB/s" % (name, ms, out[name]["achieved_GB_s"]))
+        del I
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +321,9 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time HIP-graph replays of the step")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
+    ap.add_argument("--no-reductions", action="store_true", help="skip the g2 / XSVS timings")
+    ap.add_argument("--only-reductions", action="store_true", help="time only g2 / XSVS")
+    ap.add_argument("--red-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the library's plain copy kernel on BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -301,7 +340,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.only_reductions:
+        print(json.dumps({"reductions": run_reductions(args)}), flush=True)
+        return
     res = run_grad(args)
+    if not args.no_reductions:
+        res["reductions"] = run_reductions(args)
     print(json.dumps(res), flush=True)
 
 

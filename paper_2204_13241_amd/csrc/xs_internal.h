@@ -43,8 +43,9 @@ enum Slot {
     SLOT_PIXEL2,
     SLOT_RING_KEY,      // reductions: per-pixel ring key
     SLOT_RING_CNT,      // reductions: per-block ring counts / offsets
-    SLOT_RING_LIST,     // reductions: ring-ordered pixel list
-    SLOT_G,             // g2 per-pixel values
+    SLOT_RING_LIST,     // reductions: rank of each pixel in ring order
+    SLOT_G,             // g2 per-pixel values (rows in ring order)
+    SLOT_LEVEL_0,       // XSVS frames transposed to ring-ordered pixel rows
     SLOT_LEVEL_A,       // XSVS window sums (ping)
     SLOT_LEVEL_B,       // XSVS window sums (pong)
     SLOT_BWIN,          // XSVS per-window contrast

@@ -55,6 +55,26 @@ def test_xsvs_bitwise(api, F, n_det, n_levels, n_rings, seed):
     assert bitwise_equal(host(win), wr)
 
 
+def test_empty_rings_and_ragged_columns(api):
+    """Rings past the detector's largest |q| stay empty (NaN, count 0); column counts
+    (150, 75, 37 windows; 70 lags) that are not multiples of the 64-column tile."""
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(6)
+    q = X.ewald_detector(40, 2.0)
+    I = _speckle_like(rng, 150, q.shape[0])
+    edges = X.ring_edges(12, 4.0)
+    beta, win = api.xsvs_contrast(dev(I), dev(q), edges, 3, return_windows=True)
+    br, wr = oracle.xsvs_contrast(I, q, edges, 3, want_windows=True)
+    assert np.isnan(br[:, -1]).all()
+    assert bitwise_equal(host(beta), br)
+    assert bitwise_equal(host(win), wr)
+    g2, cnt = api.g2_rings(dev(I), dev(q), edges, 70)
+    g2r, cntr = oracle.g2_rings(I, q, edges, 70)
+    assert cntr[-1] == 0
+    assert np.array_equal(host(cnt), cntr)
+    assert bitwise_equal(host(g2), g2r)
+
+
 def test_ring_edges_on_pixel_norms(api):
     """Pixels exactly on a ring edge go to the upper ring on both sides."""
     from _gpu import dev, host, bitwise_equal
