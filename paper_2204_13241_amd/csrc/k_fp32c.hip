@@ -795,22 +795,6 @@ __global__ __launch_bounds__(kBlock) void k_grad_combine(const GradSeg *__restri
 
 // ---------------------------------------------------------------- host side
 
-int device_slots(const void *kernel) {
-    static std::mutex mu;
-    static std::vector<std::pair<std::pair<const void *, int>, int>> cache;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    std::lock_guard<std::mutex> lk(mu);
-    for (auto &e : cache)
-        if (e.first.first == kernel && e.first.second == dev) return e.second;
-    int cus = 0, per = 1;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0);
-    const int n = std::max(1, cus) * std::max(1, per);
-    cache.emplace_back(std::make_pair(kernel, dev), n);
-    return n;
-}
-
 int bits_for(int64_t n) {
     int b = 0;
     while ((int64_t(1) << b) < n) ++b;
@@ -1179,14 +1163,14 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
 namespace {
 template <int QL, int OCC>
 void launch_forward(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q) {
-    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_forward_fp32c<QL, OCC>)));
+    const int slots = std::min(n, resident_blocks(reinterpret_cast<const void *>(k_forward_fp32c<QL, OCC>), kBlock));
     hipLaunchKernelGGL((k_forward_fp32c<QL, OCC>), dim3(slots), dim3(kBlock), 0, s, b.fitems, n, counter,
                        b.fsegs, q, b.pix_order, b.t_hi, b.t_lo, b.origins, b.fpart);
 }
 
 template <int AL, int OCC>
 void launch_grad(hipStream_t s, const GradItem *items, int n, int32_t *counter, const Plan::Buffers &b) {
-    const int slots = std::min(n, device_slots(reinterpret_cast<const void *>(k_grad_fp32c<AL, OCC>)));
+    const int slots = std::min(n, resident_blocks(reinterpret_cast<const void *>(k_grad_fp32c<AL, OCC>), kBlock));
     hipLaunchKernelGGL((k_grad_fp32c<AL, OCC>), dim3(slots), dim3(kBlock), 0, s, items, n, counter, b.gsegs,
                        b.t_hi, b.t_lo, b.origins, b.pdq, b.pw, b.pq64, b.centre, b.gpart);
 }

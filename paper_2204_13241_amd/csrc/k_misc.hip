@@ -2,6 +2,7 @@
 // workload), per-kernel event timing, and the roofline microbenchmarks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -297,6 +298,22 @@ xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate) {
     (void)hipEventDestroy(e1);
     *rate = ops / (static_cast<double>(ms) * 1e-3);
     return XS_OK;
+}
+
+int resident_blocks(const void *kernel, int block) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<const void *, int>, int>> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &e : cache)
+        if (e.first.first == kernel && e.first.second == dev) return e.second;
+    int cus = 0, per = 1;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0);
+    const int n = std::max(1, cus) * std::max(1, per);
+    cache.emplace_back(std::make_pair(kernel, dev), n);
+    return n;
 }
 
 }  // namespace xs

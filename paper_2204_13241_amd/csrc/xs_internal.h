@@ -43,10 +43,9 @@ enum Slot {
     SLOT_PIXEL2,
     SLOT_RING_KEY,      // reductions: per-pixel ring key
     SLOT_RING_CNT,      // reductions: per-block ring counts / offsets
-    SLOT_RING_LIST,     // reductions: rank of each pixel in ring order
+    SLOT_RING_LIST,     // reductions: ring-order rank of each pixel, ring-ordered pixel list
     SLOT_G,             // g2 per-pixel values (rows in ring order)
-    SLOT_LEVEL_0,       // XSVS frames transposed to ring-ordered pixel rows
-    SLOT_LEVEL_A,       // XSVS window sums (ping)
+    SLOT_LEVEL_A,       // XSVS coarser-level window sums (ping)
     SLOT_LEVEL_B,       // XSVS window sums (pong)
     SLOT_BWIN,          // XSVS per-window contrast
     SLOT_PSETS,         // FP32C pixel-set table
@@ -161,5 +160,9 @@ xs_status speckle_loss(hipStream_t s, const double *I, const double *It, int64_t
 xs_status position_step(hipStream_t s, double *pos, const float *g32, const double *g64, int64_t n,
                         double step);
 xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate);
+
+// Blocks of `block` threads of `kernel` that the current device holds at once
+// (occupancy x compute units), cached per kernel and device.
+int resident_blocks(const void *kernel, int block);
 
 }  // namespace xs

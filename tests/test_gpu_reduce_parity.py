@@ -41,7 +41,8 @@ def test_g2_bitwise(api, F, n_det, n_tau, n_rings, seed):
 
 
 @pytest.mark.parametrize("F,n_det,n_levels,n_rings,seed", [
-    (1, 8, 1, 2, 1), (7, 21, 3, 5, 2), (64, 48, 7, 16, 3), (1024, 16, 9, 4, 4)])
+    (1, 8, 1, 2, 1), (7, 21, 3, 5, 2), (64, 48, 7, 16, 3), (1024, 16, 9, 4, 4),
+    (1000, 12, 10, 3, 6), (4096, 4, 13, 2, 7)])
 def test_xsvs_bitwise(api, F, n_det, n_levels, n_rings, seed):
     from _gpu import dev, host, bitwise_equal
     rng = np.random.default_rng(seed)
