@@ -20,6 +20,7 @@ EXPORTS = [
     "xs_last_error", "xs_version", "xs_shutdown", "xs_get_tile_shape", "xs_set_tile_shape",
     "xs_speckle_loss", "xs_position_step", "xs_timing_enable", "xs_timing_read",
     "xs_roofline_probe", "xs_plan_create", "xs_plan_intensity", "xs_plan_grad", "xs_plan_destroy",
+    "xs_plan_describe",
 ]
 
 _P = ctypes.c_void_p
@@ -49,6 +50,17 @@ class XsTileShape(ctypes.Structure):
         ("atom_split", ctypes.c_int32),
         ("pixel_split", ctypes.c_int32),
         ("waves_per_simd", ctypes.c_int32),
+        ("lattice", ctypes.c_int32),
+    ]
+
+
+class XsPlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_segments", ctypes.c_int32),
+        ("n_lattice_segments", ctypes.c_int32),
+        ("n_forward_items", ctypes.c_int32),
+        ("n_gradient_items", ctypes.c_int32),
+        ("device_bytes", ctypes.c_int64),
     ]
 
 
@@ -94,6 +106,7 @@ def load():
         "xs_plan_intensity": (i32, [_P, _P, _P, _P, _P, _P]),
         "xs_plan_grad": (i32, [_P, _P, _P, _P, _P, i32, _P, _P, _P]),
         "xs_plan_destroy": (i32, [_P]),
+        "xs_plan_describe": (i32, [_P, ctypes.POINTER(XsPlanInfo)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -232,13 +232,17 @@ def get_tile_shape(kind: int) -> dict:
     _lib.check(_lib.load().xs_get_tile_shape(int(kind), ctypes.byref(s)))
     return {"atoms_per_tile": s.atoms_per_tile, "q_per_lane": s.q_per_lane,
             "atom_split": s.atom_split, "pixel_split": s.pixel_split,
-            "waves_per_simd": s.waves_per_simd}
+            "waves_per_simd": s.waves_per_simd, "lattice": s.lattice}
 
 
 def set_tile_shape(kind: int, atoms_per_tile=64, q_per_lane=4, atom_split=64, pixel_split=8192,
-                   waves_per_simd=0):
+                   waves_per_simd=0, lattice=None):
+    """Set the forward (kind 0) or gradient (kind 1) tile shape (xs_set_tile_shape).
+    lattice: forward only; None keeps 1 for the forward shape and 0 for the gradient."""
+    if lattice is None:
+        lattice = 1 if int(kind) == 0 else 0
     s = _lib.XsTileShape(int(atoms_per_tile), int(q_per_lane), int(atom_split), int(pixel_split),
-                         int(waves_per_simd))
+                         int(waves_per_simd), int(lattice))
     _lib.check(_lib.load().xs_set_tile_shape(int(kind), ctypes.byref(s)))
 
 
@@ -375,6 +379,12 @@ class Plan:
         _lib.check(_lib.load().xs_plan_grad(self._h, _ptr(pos), _ptr(f), _ptr(amp), _ptr(dL_dI),
                                             1 if retile else 0, _ptr(g32), _ptr(g64), _stream()))
         return g32 if g32 is not None else g64
+
+    def describe(self) -> dict:
+        """Segments, segments on the lattice form, work items and device bytes (xs_plan_describe)."""
+        info = _lib.XsPlanInfo()
+        _lib.check(_lib.load().xs_plan_describe(self._h, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in _lib.XsPlanInfo._fields_}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -44,6 +44,9 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kWaves = kBlock / 64;
 constexpr int kHilbertBits = 10;  // per dimension
 constexpr double kInvTwoPi = 0x1.45f306dc9c883p-3;  // RN(1/(2 pi))
+constexpr int kLatRuns = 8;                         // lattice item: runs across a row per lane row
+constexpr int kLatRows = kBlock / kLatRuns;         // lattice item: rows (32)
+constexpr double kLatTol = 1e-11;                   // lattice test: |q_p - model| bound, 1 / Angstrom
 
 // ---------------------------------------------------------------- tables
 
@@ -76,7 +79,17 @@ struct FwdSeg {            // pair-sum view of one segment
     int32_t n_q;
     int32_t n_tiles;
     int32_t n_chunks;
+    int32_t n2;            // lattice form: pixels per row (0: general form)
+    double a[3];           // lattice form: step between neighbours of a row (revolutions / A)
+    int32_t n_jb;          // lattice form: item rectangles across a row
     int32_t pad;
+};
+
+struct LatSet {            // a pixel set that passed the row-lattice test
+    int64_t q;
+    int32_t n_q;
+    int32_t n2;
+    double a[3];           // row step, 1 / Angstrom
 };
 
 struct FwdItem {
@@ -569,6 +582,239 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
     }
 }
 
+// ---------------------------------------------------------------- forward, lattice form
+//
+// Pixels of the segment come in rows of n2 consecutive q-vectors stepping by a
+// common vector a.  An item is a rectangle of kLatRows rows x kLatRuns runs;
+// lane (row, run) owns the QL pixels p0 + k (k < QL) of its run, with
+// q_{p0+k} = q_{p0} + k a.  The in-tile phase of pixel k is
+// beta_j + dq_0.d_j + k a.d_j, so
+//   sum_j f_j e^{2 pi i (beta_j + dq_0.d_j + k a.d_j)} = sum_j z_j g_jk,
+//   z_j = e^{2 pi i (beta_j + dq_0.d_j)}  (one v_sin + v_cos per lane and atom),
+//   g_jk = f_j e^{2 pi i k a.d_j}          (per atom, formed once per staged tile).
+// Per pair (k >= 1) that is 4 FMA of a complex multiply-add instead of a
+// v_sin/v_cos pair; every g_jk comes from its own sincos, so the error does not
+// grow with k.  Base phases theta_k = frac(q_{p0}.o + k a.o) (FP64) rotate the
+// tile sums as in the general form.
+// LDS per staged atom: float4 (d, f) and QL/2 float4 holding g_1 .. g_{QL-1}
+// (re, im) and beta in the last slot.
+template <int QL>
+__device__ __forceinline__ void lattice_atom_factors(const float4 &h, float e, float beta, float4 *dst) {
+    float g[2 * QL];
+#pragma unroll
+    for (int k = 1; k < QL; ++k) {
+        const float ang = static_cast<float>(k) * e;
+        g[2 * k] = h.w * __builtin_amdgcn_cosf(ang);
+        g[2 * k + 1] = h.w * __builtin_amdgcn_sinf(ang);
+    }
+    g[0] = beta;
+    g[1] = 0.f;
+#pragma unroll
+    for (int v = 0; v < QL / 2; ++v) {
+        // slot v: g_{2v+1}, g_{2v+2}; the last slot: g_{QL-1}, beta, 0
+        const int k1 = 2 * v + 1, k2 = 2 * v + 2;
+        if (k2 < QL) dst[v] = make_float4(g[2 * k1], g[2 * k1 + 1], g[2 * k2], g[2 * k2 + 1]);
+        else dst[v] = make_float4(g[2 * k1], g[2 * k1 + 1], g[0], 0.f);
+    }
+}
+
+template <int QL, bool PLANAR>
+__device__ __forceinline__ void lattice_tile(const float4 *__restrict__ at, const float4 *__restrict__ gt,
+                                             float dqx, float dqy, float dqz, float (&cs)[QL], float (&sn)[QL]) {
+    constexpr int NV = QL / 2;
+#pragma unroll 2
+    for (int j = 0; j < kTile; ++j) {
+        const float4 a = at[j];
+        float4 g[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) g[v] = gt[j * NV + v];
+        const float beta = g[NV - 1].z;
+        float ph = __builtin_fmaf(dqx, a.x, beta);
+        ph = __builtin_fmaf(dqy, a.y, ph);
+        if (!PLANAR) ph = __builtin_fmaf(dqz, a.z, ph);
+        const float zc = __builtin_amdgcn_cosf(ph), zs = __builtin_amdgcn_sinf(ph);
+        cs[0] = __builtin_fmaf(a.w, zc, cs[0]);
+        sn[0] = __builtin_fmaf(a.w, zs, sn[0]);
+#pragma unroll
+        for (int k = 1; k < QL; ++k) {
+            const float4 &gv = g[(k - 1) / 2];
+            const float gr = ((k - 1) & 1) ? gv.z : gv.x;
+            const float gi = ((k - 1) & 1) ? gv.w : gv.y;
+            cs[k] = __builtin_fmaf(zc, gr, cs[k]);
+            cs[k] = __builtin_fmaf(-zs, gi, cs[k]);
+            sn[k] = __builtin_fmaf(zc, gi, sn[k]);
+            sn[k] = __builtin_fmaf(zs, gr, sn[k]);
+        }
+    }
+}
+
+template <int QL, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice(
+    const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
+    const FwdSeg *__restrict__ segs, const double *__restrict__ q, const float4 *__restrict__ t_hi,
+    const float4 *__restrict__ t_lo, const double4 *__restrict__ origins, double2 *__restrict__ partial) {
+    static_assert(QL % 2 == 0, "runs of an even number of pixels");
+    constexpr int NV = QL / 2;
+    __shared__ float4 s_atoms[2][kWaves * kTile];
+    __shared__ float4 s_g[2][kWaves * kTile * NV];
+    __shared__ double4 s_orig[2][kWaves];
+    __shared__ double s_red[6][kWaves];
+    __shared__ int32_t s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const FwdItem item = items[it];
+        const FwdSeg sg = segs[item.seg];
+        const int n1 = sg.n_q / sg.n2;
+        const int ib = item.p0 / sg.n_jb, jb = item.p0 - ib * sg.n_jb;
+        const int row = ib * kLatRows + tid / kLatRuns;
+        const int col0 = jb * kLatRuns * QL + (tid % kLatRuns) * QL;
+        const bool active = row < n1 && col0 < sg.n2;
+        const int nk = active ? min(QL, sg.n2 - col0) : 0;
+        const int p0 = active ? row * sg.n2 + col0 : 0;
+        const double ax = sg.a[0], ay = sg.a[1], az = sg.a[2];
+        double q0[3];
+        for (int c = 0; c < 3; ++c) q0[c] = q[(sg.q + p0) * 3 + c] * kInvTwoPi;
+        // item centre: bounding box of the run ends (wavefront then block reduction)
+        double lo[3], hi[3];
+        {
+            const double e[3] = {ax, ay, az};
+            for (int c = 0; c < 3; ++c) {
+                const double v0 = q0[c], v1 = __builtin_fma(static_cast<double>(nk > 0 ? nk - 1 : 0), e[c], q0[c]);
+                lo[c] = active ? fmin(v0, v1) : INFINITY;
+                hi[c] = active ? fmax(v0, v1) : -INFINITY;
+            }
+        }
+        for (int c = 0; c < 3; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+                hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+            }
+        if (lane == 0)
+            for (int c = 0; c < 3; ++c) {
+                s_red[c][wave] = lo[c];
+                s_red[3 + c][wave] = hi[c];
+            }
+        __syncthreads();
+        double cen[3];
+        bool planar;
+        {
+            double l3[3], h3[3];
+            for (int c = 0; c < 3; ++c) {
+                l3[c] = s_red[c][0];
+                h3[c] = s_red[3 + c][0];
+                for (int w = 1; w < kWaves; ++w) {
+                    l3[c] = fmin(l3[c], s_red[c][w]);
+                    h3[c] = fmax(h3[c], s_red[3 + c][w]);
+                }
+                cen[c] = 0.5 * (l3[c] + h3[c]);
+            }
+            planar = l3[2] == h3[2];
+        }
+        const float dqx = static_cast<float>(q0[0] - cen[0]);
+        const float dqy = static_cast<float>(q0[1] - cen[1]);
+        const float dqz = static_cast<float>(q0[2] - cen[2]);
+        const float afx = static_cast<float>(ax), afy = static_cast<float>(ay), afz = static_cast<float>(az);
+        double re64[QL], im64[QL];
+#pragma unroll
+        for (int k = 0; k < QL; ++k) re64[k] = im64[k] = 0.0;
+        const int64_t tbase = sg.tile0 + item.t0;
+        const int n_groups = (item.nt + kWaves - 1) / kWaves;
+        auto stage = [&](int buf, const float4 &h, const float4 &l) {
+            const double b = __builtin_fma(cen[2], double(h.z) + double(l.z),
+                             __builtin_fma(cen[1], double(h.y) + double(l.y), cen[0] * (double(h.x) + double(l.x))));
+            const float e = __builtin_fmaf(afz, h.z, __builtin_fmaf(afy, h.y, afx * h.x));
+            s_atoms[buf][tid] = h;
+            lattice_atom_factors<QL>(h, e, frac_f32(b), &s_g[buf][tid * NV]);
+        };
+        {
+            const int tt = tid / kTile;
+            if (tt < item.nt) {
+                const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
+                stage(0, t_hi[ai], t_lo[ai]);
+            }
+            if (tid < kWaves && tid < item.nt) s_orig[0][tid] = origins[tbase + tid];
+        }
+        __syncthreads();
+        for (int g = 0; g < n_groups; ++g) {
+            const int buf = g & 1;
+            float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nl = nh;
+            double4 no = make_double4(0.0, 0.0, 0.0, 0.0);
+            const int ng = g + 1;
+            const bool have_next = ng < n_groups;
+            bool next_real = false;
+            if (have_next) {
+                const int tt = ng * kWaves + tid / kTile;
+                next_real = tt < item.nt;
+                if (next_real) {
+                    const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
+                    nh = t_hi[ai];
+                    nl = t_lo[ai];
+                }
+                if (tid < kWaves && ng * kWaves + tid < item.nt) no = origins[tbase + ng * kWaves + tid];
+            }
+            const int tiles_here = min(kWaves, item.nt - g * kWaves);
+            for (int w = 0; w < tiles_here; ++w) {
+                float cs[QL], sn[QL];
+#pragma unroll
+                for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
+                const float4 *at = &s_atoms[buf][w * kTile];
+                const float4 *gt = &s_g[buf][w * kTile * NV];
+                if (planar) lattice_tile<QL, true>(at, gt, dqx, dqy, dqz, cs, sn);
+                else lattice_tile<QL, false>(at, gt, dqx, dqy, dqz, cs, sn);
+                const double4 o = s_orig[buf][w];
+                const double s0 = __builtin_fma(q0[2], o.z, __builtin_fma(q0[1], o.y, q0[0] * o.x));
+                const double t1 = __builtin_fma(az, o.z, __builtin_fma(ay, o.y, ax * o.x));
+#pragma unroll
+                for (int k = 0; k < QL; ++k) {
+                    const float th = frac_f32(__builtin_fma(static_cast<double>(k), t1, s0));
+                    const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
+                    re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
+                    im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
+                }
+            }
+            if (have_next) {
+                if (next_real) stage(buf ^ 1, nh, nl);
+                if (tid < kWaves) s_orig[buf ^ 1][tid] = no;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < QL; ++k)
+            if (k < nk)
+                partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + p0 + k] = make_double2(re64[k], im64[k]);
+    }
+}
+
+// Largest deviation of a pixel set from the row lattice q_p = q_{row start} + j a
+// (j = p mod n2), per block; NaN counts as infinite.
+__global__ __launch_bounds__(kBlock) void k_lattice_check(const double *__restrict__ q, int32_t n_q, int32_t n2,
+                                                          double ax, double ay, double az,
+                                                          double *__restrict__ block_max) {
+    __shared__ double red[kBlock];
+    double m = 0.0;
+    const double a[3] = {ax, ay, az};
+    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_q;
+         p += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t j = p % n2, r0 = p - j;
+        for (int c = 0; c < 3; ++c) {
+            const double d = fabs(q[3 * p + c] - __builtin_fma(static_cast<double>(j), a[c], q[3 * r0 + c]));
+            m = d == d ? fmax(m, d) : INFINITY;
+        }
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < static_cast<unsigned>(off)) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
+}
+
 // Sum the chunk partials of every pixel in chunk order; a = sum f cos,
 // b = -sum f sin (the amplitude carries exp(-i q.r)), I = a*a + b*b.
 __global__ __launch_bounds__(kBlock) void k_forward_combine(const FwdSeg *__restrict__ segs,
@@ -820,8 +1066,10 @@ struct Plan::Tables {
     std::vector<BinSeg> bsegs;
     std::vector<PixSet> psets;
     std::vector<int> seg_set;
+    std::vector<LatSet> lat;              // pixel sets found to be row lattices
     std::vector<FwdSeg> fsegs;
-    std::vector<FwdItem> fitems;
+    std::vector<FwdItem> fitems;          // general form
+    std::vector<FwdItem> litems;          // lattice form
     std::vector<GradSeg> gsegs;
     std::vector<GradItem> gitems;         // concatenated over sub-batches
     std::vector<int> gsub_seg0, gsub_seg1; // segment range of each sub-batch
@@ -830,7 +1078,7 @@ struct Plan::Tables {
     std::vector<int> gsub_maxq;
     int64_t atoms = 0, cells = 0, tiles = 0, slots = 0, groups = 0, fpart = 0, gpart = 0;
     int max_atoms = 0, max_tiles = 0, max_q = 0, max_set_q = 0, max_slots_seg = 0;
-    double fwork = 0.0;
+    double fwork = 0.0, lwork = 0.0;
     size_t sort_tmp = 0;
 };
 
@@ -839,6 +1087,7 @@ struct Plan::Buffers {
     PixSet *psets = nullptr;
     FwdSeg *fsegs = nullptr;
     FwdItem *fitems = nullptr;
+    FwdItem *litems = nullptr;
     GradSeg *gsegs = nullptr;
     GradItem *gitems = nullptr;
     int32_t *counters = nullptr;
@@ -864,6 +1113,78 @@ Plan::~Plan() {
     if (owned_block) (void)hipFree(owned_block);
     delete T;
     delete B;
+}
+
+// Row-lattice test of each distinct pixel set: the step a and row length n2
+// come from a prefix of the set read back to the host (n2: the first pixel
+// off the progression q_0 + j (q_1 - q_0); a then refined from the row's
+// ends), and a device pass bounds |q_p - (q_{row start} + j a)| over the set.
+xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, const double *q) {
+    Tables &t = *T;
+    t.lat.clear();
+    std::vector<std::pair<int64_t, int32_t>> seen;
+    double *dmax = nullptr;
+    constexpr int kCheckBlocks = 512;
+    std::vector<double> hmax(kCheckBlocks);
+    xs_status st = XS_OK;
+    for (int i = 0; i < n_segs && st == XS_OK; ++i) {
+        const int64_t qo = segs[i].q;
+        const int32_t n_q = segs[i].n_q;
+        if (n_q < 16) continue;
+        bool done = false;
+        for (auto &e : seen) done = done || (e.first == qo && e.second == n_q);
+        if (done) continue;
+        seen.emplace_back(qo, n_q);
+        const int64_t m = std::min<int64_t>(n_q, 65536);
+        std::vector<double> h(3 * m);
+        if (hipMemcpyAsync(h.data(), q + 3 * qo, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = set_error(XS_EDEVICE, "lattice test: cannot read q");
+            break;
+        }
+        double a[3];
+        for (int c = 0; c < 3; ++c) a[c] = h[3 + c] - h[c];
+        if (a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0) continue;
+        int64_t n2 = m;
+        for (int64_t p = 2; p < m && n2 == m; ++p)
+            for (int c = 0; c < 3; ++c) {
+                const double tol = 1e-6 * (std::fabs(a[c]) + 1e-300) * static_cast<double>(p) + kLatTol;
+                if (!(std::fabs(h[3 * p + c] - std::fma(static_cast<double>(p), a[c], h[c])) <= tol)) {
+                    n2 = p;
+                    break;
+                }
+            }
+        if (n2 == m && m < n_q) continue;  // row longer than the prefix read
+        if (n2 < 8 || n_q % n2 != 0) continue;
+        for (int c = 0; c < 3; ++c) a[c] = (h[3 * (n2 - 1) + c] - h[c]) / static_cast<double>(n2 - 1);
+        if (!dmax) {
+            if (hipMalloc(&dmax, sizeof(double) * kCheckBlocks) != hipSuccess) {
+                (void)hipGetLastError();
+                st = set_error(XS_ENOMEM, "lattice test: cannot allocate");
+                break;
+            }
+        }
+        const int nb = static_cast<int>(std::min<int64_t>(kCheckBlocks, (n_q + kBlock - 1) / kBlock));
+        hipLaunchKernelGGL(k_lattice_check, dim3(nb), dim3(kBlock), 0, s, q + 3 * qo, n_q, static_cast<int32_t>(n2),
+                           a[0], a[1], a[2], dmax);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(hmax.data(), dmax, sizeof(double) * nb, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = set_error(XS_EDEVICE, "lattice test: device check failed");
+            break;
+        }
+        double worst = 0.0;
+        for (int k = 0; k < nb; ++k) worst = std::max(worst, hmax[k]);
+        if (!(worst <= kLatTol)) continue;
+        LatSet ls;
+        ls.q = qo;
+        ls.n_q = n_q;
+        ls.n2 = static_cast<int32_t>(n2);
+        for (int c = 0; c < 3; ++c) ls.a[c] = a[c];
+        t.lat.push_back(ls);
+    }
+    if (dmax) (void)hipFree(dmax);
+    return st;
 }
 
 // Build every host table of the batch (no device work).
@@ -923,13 +1244,15 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         set_grp0[k] = t.groups;
         t.groups += (t.psets[k].n_q + kPixStage - 1) / kPixStage;
     }
-    // forward work list
+    // forward work lists (general and lattice form)
     const int QL = fsh.q_per_lane, split = std::max(1, fsh.atom_split), ppi = kBlock * QL;
+    const int LQ = std::max(2, QL), lcols = kLatRuns * LQ;
     t.fsegs.resize(n_segs);
-    std::vector<FwdItem> items;
-    std::vector<int64_t> cost;
+    std::vector<FwdItem> items, litems;
+    std::vector<int64_t> cost, lcost;
     for (int i = 0; i < n_segs; ++i) {
         FwdSeg &g = t.fsegs[i];
+        std::memset(&g, 0, sizeof(g));
         g.q = segs[i].q;
         g.slot0 = t.psets[t.seg_set[i]].slot0;
         g.out = segs[i].out;
@@ -938,8 +1261,33 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         g.n_tiles = t.bsegs[i].n_tiles;
         g.n_chunks = g.n_tiles > 0 ? (g.n_tiles + split - 1) / split : 0;
         g.part = t.fpart;
-        g.pad = 0;
         t.fpart += static_cast<int64_t>(g.n_chunks) * g.n_q;
+        const LatSet *ls = nullptr;
+        if (fsh.lattice)
+            for (const LatSet &l : t.lat)
+                if (l.q == g.q && l.n_q == g.n_q) ls = &l;
+        if (ls) {
+            g.n2 = ls->n2;
+            for (int c = 0; c < 3; ++c) g.a[c] = ls->a[c] * kInvTwoPi;
+            g.n_jb = (g.n2 + lcols - 1) / lcols;
+            const int n_ib = (g.n_q / g.n2 + kLatRows - 1) / kLatRows;
+            for (int r = 0; r < n_ib * g.n_jb; ++r)
+                for (int c = 0; c < g.n_chunks; ++c) {
+                    FwdItem it;
+                    it.seg = i;
+                    it.p0 = r;
+                    it.t0 = c * split;
+                    it.nt = std::min(split, g.n_tiles - c * split);
+                    it.chunk = c;
+                    it.pad = 0;
+                    litems.push_back(it);
+                    const int64_t rows = std::min(kLatRows, g.n_q / g.n2 - (r / g.n_jb) * kLatRows);
+                    const int64_t cols = std::min(lcols, g.n2 - (r % g.n_jb) * lcols);
+                    lcost.push_back(rows * cols * it.nt);
+                    t.lwork += static_cast<double>(rows * cols) * it.nt * kTile;
+                }
+            continue;
+        }
         for (int p0 = 0; p0 < g.n_q; p0 += ppi)
             for (int c = 0; c < g.n_chunks; ++c) {
                 FwdItem it;
@@ -956,6 +1304,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
             }
     }
     t.fitems = largest_first(items, cost);
+    t.litems = largest_first(litems, lcost);
     // gradient work lists: segments sharing a pixel set go to different sub-batches
     const int AL = gsh.q_per_lane, group = kWaves * AL;
     const int pchunk = std::max(kPixStage, (gsh.pixel_split / kPixStage) * kPixStage);
@@ -1042,10 +1391,12 @@ size_t Plan::layout(char *base) {
     b.psets = reinterpret_cast<PixSet *>(take(sizeof(PixSet) * t.psets.size()));
     b.fsegs = reinterpret_cast<FwdSeg *>(take(sizeof(FwdSeg) * t.fsegs.size()));
     b.fitems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.fitems.size()));
+    b.litems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.litems.size()));
     b.gsegs = reinterpret_cast<GradSeg *>(take(sizeof(GradSeg) * t.gsegs.size()));
     b.gitems = reinterpret_cast<GradItem *>(take(sizeof(GradItem) * t.gitems.size()));
     b.table_bytes = off - tb0;
-    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 1)));
+    // counters: [0] general forward, [1] lattice forward, [2 + k] gradient sub-batch k
+    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 2)));
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
@@ -1072,6 +1423,15 @@ size_t Plan::layout(char *base) {
     return off;
 }
 
+void Plan::describe(int *n_lattice_segs, int *n_fwd_items, int *n_grad_items) const {
+    const Tables &t = *T;
+    int nl = 0;
+    for (const FwdSeg &g : t.fsegs) nl += g.n2 > 0;
+    *n_lattice_segs = nl;
+    *n_fwd_items = static_cast<int>(t.fitems.size() + t.litems.size());
+    *n_grad_items = static_cast<int>(t.gitems.size());
+}
+
 // Host blob of all tables in the order and alignment of layout().
 std::vector<char> Plan::table_blob() const {
     const Tables &t = *T;
@@ -1085,6 +1445,7 @@ std::vector<char> Plan::table_blob() const {
     put(t.psets.data(), sizeof(PixSet) * t.psets.size());
     put(t.fsegs.data(), sizeof(FwdSeg) * t.fsegs.size());
     put(t.fitems.data(), sizeof(FwdItem) * t.fitems.size());
+    put(t.litems.data(), sizeof(FwdItem) * t.litems.size());
     put(t.gsegs.data(), sizeof(GradSeg) * t.gsegs.size());
     put(t.gitems.data(), sizeof(GradItem) * t.gitems.size());
     return blob;
@@ -1175,6 +1536,26 @@ void launch_grad(hipStream_t s, const GradItem *items, int n, int32_t *counter, 
                        b.t_hi, b.t_lo, b.origins, b.pdq, b.pw, b.pq64, b.centre, b.gpart);
 }
 
+template <int QL, int OCC>
+void launch_lattice(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q) {
+    const int slots =
+        std::min(n, resident_blocks(reinterpret_cast<const void *>(k_forward_lattice<QL, OCC>), kBlock));
+    hipLaunchKernelGGL((k_forward_lattice<QL, OCC>), dim3(slots), dim3(kBlock), 0, s, b.litems, n, counter,
+                       b.fsegs, q, b.t_hi, b.t_lo, b.origins, b.fpart);
+}
+
+bool launch_lattice_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, const Plan::Buffers &b,
+                            const double *q) {
+    const bool o4 = occ == 4;
+    switch (ql) {
+    case 1:
+    case 2: o4 ? launch_lattice<2, 4>(s, n, cnt, b, q) : launch_lattice<2, 1>(s, n, cnt, b, q); return true;
+    case 4: o4 ? launch_lattice<4, 4>(s, n, cnt, b, q) : launch_lattice<4, 1>(s, n, cnt, b, q); return true;
+    case 8: launch_lattice<8, 1>(s, n, cnt, b, q); return true;
+    default: return false;
+    }
+}
+
 // Built variants: pixels (forward) or atoms (gradient) per lane, and an
 // optional bound of 4 wavefronts per SIMD (at most 128 VGPRs).
 bool launch_forward_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, const Plan::Buffers &b,
@@ -1205,14 +1586,17 @@ bool launch_grad_variant(hipStream_t s, int al, int occ, const GradItem *items, 
 xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) {
     Tables &t = *T;
     Buffers &b = *B;
-    const int n = static_cast<int>(t.fitems.size());
-    if (n > 0) {
-        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, 1);
+    const int n = static_cast<int>(t.fitems.size()), nl = static_cast<int>(t.litems.size());
+    if (n + nl > 0) {
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, 2);
         void *tok = nullptr;
         timer_begin(s, TIMER_FWD32, &tok);
-        if (!launch_forward_variant(s, fshape.q_per_lane, fshape.waves_per_simd, n, b.counters, b, q))
+        if (n > 0 && !launch_forward_variant(s, fshape.q_per_lane, fshape.waves_per_simd, n, b.counters, b, q))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
-        timer_end(s, TIMER_FWD32, tok, t.fwork);
+        if (nl > 0 &&
+            !launch_lattice_variant(s, fshape.q_per_lane, fshape.waves_per_simd, nl, b.counters + 1, b, q))
+            return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
+        timer_end(s, TIMER_FWD32, tok, t.fwork + t.lwork);
         XS_HIP(hipGetLastError());
     }
     if (t.max_q > 0) {
@@ -1234,7 +1618,7 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
                                s, b.gsegs + i0, q, b.pix_order, amp, dL_dI, b.pdq, b.pw, b.pq64, b.centre);
         const int n = t.gsub_nitem[k];
         if (n == 0) continue;
-        int32_t *cnt = b.counters + 1 + k;
+        int32_t *cnt = b.counters + 2 + k;
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 1);
         const GradItem *items = b.gitems + t.gsub_item0[k];
         void *tok = nullptr;

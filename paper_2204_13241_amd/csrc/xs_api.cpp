@@ -172,7 +172,7 @@ void release_all_scratch() {
 namespace {
 
 // Defaults: the autotuner's choice on a 65,536-atom, 512x512-pixel single frame.
-xs_tile_shape g_shape[2] = {{64, 2, 64, 0, 4}, {64, 4, 0, 4096, 4}};
+xs_tile_shape g_shape[2] = {{64, 2, 64, 0, 4, 1}, {64, 4, 0, 4096, 4, 0}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
@@ -407,7 +407,9 @@ xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void
     auto *p = new (std::nothrow) xs_plan();
     if (!p) return set_error(XS_ENOMEM, "plan: host allocation failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    xs_status st = p->plan.build(segs.data(), static_cast<int>(segs.size()), b->box, fsh, gsh);
+    xs_status st = XS_OK;
+    if (fsh.lattice) st = p->plan.find_lattices(s, segs.data(), static_cast<int>(segs.size()), q);
+    if (st == XS_OK) st = p->plan.build(segs.data(), static_cast<int>(segs.size()), b->box, fsh, gsh);
     if (st == XS_OK) st = p->plan.allocate(s, true);
     if (st == XS_OK) st = p->plan.sort_pixels(s, q);
     if (st != XS_OK) {
@@ -453,6 +455,18 @@ xs_status xs_plan_destroy(xs_plan *p) {
     return XS_OK;
 }
 
+xs_status xs_plan_describe(const xs_plan *p, xs_plan_info *info) {
+    if (!p || !info) return set_error(XS_EINVAL, "plan and info must be non-NULL");
+    int nl = 0, nf = 0, ng = 0;
+    p->plan.describe(&nl, &nf, &ng);
+    info->n_segments = p->plan.n_seg;
+    info->n_lattice_segments = nl;
+    info->n_forward_items = nf;
+    info->n_gradient_items = ng;
+    info->device_bytes = static_cast<int64_t>(p->plan.device_bytes);
+    return XS_OK;
+}
+
 xs_status xs_get_tile_shape(int32_t kind, xs_tile_shape *out) {
     if ((kind != 0 && kind != 1) || !out) return set_error(XS_EINVAL, "kind must be 0 or 1, out non-NULL");
     std::lock_guard<std::mutex> lk(g_shape_mu);
@@ -475,6 +489,8 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
     if (shape->waves_per_simd == 4 && !((kind == 0 && (ql == 2 || ql == 4)) || (kind == 1 && ql == 4)))
         return set_error(XS_ENOTSUP, "the 4-waves-per-SIMD variant is built for forward q_per_lane 2, 4 "
                                      "and gradient q_per_lane 4");
+    if (shape->lattice != 0 && shape->lattice != 1) return set_error(XS_EINVAL, "lattice must be 0 or 1");
+    if (kind == 1 && shape->lattice) return set_error(XS_ENOTSUP, "lattice applies to the forward kernel only");
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[kind] = *shape;
     return XS_OK;

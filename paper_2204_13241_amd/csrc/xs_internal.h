@@ -98,6 +98,9 @@ public:
     ~Plan();
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;
+    // Row-lattice test of every distinct pixel set (device check, synchronizes s);
+    // build() then uses the lattice form for the sets that pass.
+    xs_status find_lattices(hipStream_t s, const Segment *segs, int n_segs, const double *q);
     xs_status build(const Segment *segs, int n_segs, const double *box, const xs_tile_shape &fsh,
                     const xs_tile_shape &gsh);
     xs_status allocate(hipStream_t s, bool owned);
@@ -108,6 +111,7 @@ public:
                    const double *dL_dI, float *g32, double *g64);
     size_t layout(char *base);
     std::vector<char> table_blob() const;
+    void describe(int *n_lattice_segs, int *n_fwd_items, int *n_grad_items) const;
 
     Tables *T;
     Buffers *B;

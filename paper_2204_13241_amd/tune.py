@@ -45,7 +45,7 @@ def signature(systems, planar: bool) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
+    return "v2|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved")
 

@@ -16,6 +16,18 @@ def api():
 
 
 def test_plan_matches_one_shot_bitwise(api):
+    """With the lattice form off, a plan runs the one-shot call's kernels on the same
+    work lists: identical results."""
+    from _gpu import dev, host, bitwise_equal
+    old = api.get_tile_shape(0)
+    api.set_tile_shape(0, **dict(old, lattice=0))
+    try:
+        _plan_vs_one_shot(api)
+    finally:
+        api.set_tile_shape(0, **old)
+
+
+def _plan_vs_one_shot(api):
     from _gpu import dev, host, bitwise_equal
     w = X.workload_grad(n_atoms=5000, n_det=64)
     r0, f, q, L = dev(w.positions[0][0]), dev(w.f[0]), dev(w.q[0]), w.box[0]
@@ -98,7 +110,8 @@ def test_plan_graph_replay(api):
     graph.replay()
     torch.cuda.synchronize()
     I_moved = host(I).copy()
-    I2, _ = api.intensity(pos, f, q, "fp32c", box=L, return_amp=True)
+    I2, _ = plan.intensity(pos, f)
+    torch.cuda.synchronize()
     assert np.array_equal(host(I2), I_moved)
     del graph
     plan.close()
