@@ -195,13 +195,15 @@ xs_status xs_shutdown(void);
  *   waves_per_simd  0: compiler's register allocation; 4: variant bounded to
  *                   128 VGPRs (4 wavefronts per SIMD), built for forward
  *                   q_per_lane 2 and 4 and gradient q_per_lane 4
- *   lattice         forward only, plans only (0 or 1): when a system's pixels
- *                   come in rows of n2 consecutive q-vectors that each step by
- *                   one common vector a (a planar detector grid stored row by
- *                   row), a lane owns a run of q_per_lane (2, 4 or 8; 1 acts as
- *                   2) pixels along a row and forms the in-tile phase factors
- *                   of the run from one v_sin/v_cos and per-atom factors
- *                   f_j exp(2 pi i k a.d_j) (see xs_plan_create)
+ *   lattice         plans only (0 or 1): when a system's pixels come in rows
+ *                   of n2 consecutive q-vectors that each step by one common
+ *                   vector a (a planar detector grid stored row by row; see
+ *                   xs_plan_create).  Forward: a lane owns a run of q_per_lane
+ *                   (2, 4 or 8; 1 acts as 2) pixels along a row and forms the
+ *                   in-tile phase factors of the run from one v_sin/v_cos and
+ *                   per-atom factors f_j exp(2 pi i k a.d_j).  Gradient (rows
+ *                   of a multiple of 64 pixels): pixels stay in row order and
+ *                   the in-group phase offset of pixel m is (m - 31.5) a.d_j.
  * Shapes apply to calls and plans created after they are set.
  */
 typedef struct xs_tile_shape {
@@ -226,11 +228,11 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape);
  * device memory the calls need, and orders the pixels along a Hilbert curve in
  * q (enqueued on `stream`).  The q array must stay at the same address and
  * unchanged for the life of the plan.  Tile shapes are those set by
- * xs_set_tile_shape when the plan is created.  With the forward shape's
+ * xs_set_tile_shape when the plan is created.  With either shape's
  * `lattice` set, it also tests every system's pixels for the row lattice
  * (each q_p within 1e-11 per Angstrom of q_row_start + j a, rows of n2 >= 8
  * pixels) and synchronizes `stream` to read the result; systems that pass use
- * the lattice form of the forward pair sum.
+ * the lattice form of the pair sums whose shape asks for it.
  *
  * xs_plan_intensity and xs_plan_grad then only launch kernels on `stream`
  * (no allocation, copy or memset), so a caller may capture them in a HIP

@@ -237,10 +237,10 @@ def get_tile_shape(kind: int) -> dict:
 
 def set_tile_shape(kind: int, atoms_per_tile=64, q_per_lane=4, atom_split=64, pixel_split=8192,
                    waves_per_simd=0, lattice=None):
-    """Set the forward (kind 0) or gradient (kind 1) tile shape (xs_set_tile_shape).
-    lattice: forward only; None keeps 1 for the forward shape and 0 for the gradient."""
+    """Set the forward (kind 0) or gradient (kind 1) tile shape (xs_set_tile_shape);
+    lattice None means 1 (use the lattice form where a plan finds row lattices)."""
     if lattice is None:
-        lattice = 1 if int(kind) == 0 else 0
+        lattice = 1
     s = _lib.XsTileShape(int(atoms_per_tile), int(q_per_lane), int(atom_split), int(pixel_split),
                          int(waves_per_simd), int(lattice))
     _lib.check(_lib.load().xs_set_tile_shape(int(kind), ctypes.byref(s)))

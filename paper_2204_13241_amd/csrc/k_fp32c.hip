@@ -67,7 +67,7 @@ struct PixSet {            // one distinct pixel set (a system's q)
     int64_t q;             // pixel offset into q
     int64_t slot0;         // offset of its pixels in the sorted order
     int32_t n_q;
-    int32_t pad;
+    int32_t lattice;       // 1: row lattice with rows of whole 64-pixel groups, kept in input order
 };
 
 struct FwdSeg {            // pair-sum view of one segment
@@ -113,7 +113,8 @@ struct GradSeg {
     int32_t n_q;
     int32_t n_tiles;
     int32_t n_chunks;
-    int32_t pad;
+    int32_t lat;           // 1: every 64-pixel group is a run along a lattice row
+    double a[3];           // lattice row step (revolutions / A)
 };
 
 struct GradItem {
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_pix_keys(const PixSet *__restrict__ 
         const double scale = span > 0.0 ? 1024.0 / (span * 1.000001) : 0.0;
         c[d] = cell_of(q[(ps.q + p) * 3 + d] - lo, scale, 10);
     }
-    keys[ps.slot0 + p] = (static_cast<uint64_t>(blockIdx.y) << 30) | hilbert3(c[0], c[1], c[2], 10);
+    const uint64_t h = ps.lattice ? static_cast<uint64_t>(p) : hilbert3(c[0], c[1], c[2], 10);
+    keys[ps.slot0 + p] = (static_cast<uint64_t>(blockIdx.y) << 30) | h;
     vals[ps.slot0 + p] = p;
 }
 
@@ -894,9 +896,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict_
 // lane l owns atom l of each.  The item's sorted pixels are staged 64 at a
 // time (one centre q_c per 64): per staged group each lane forms
 // beta = frac(q_c.d) for its atoms (FP64, from the exact offset) and each
-// wavefront the base phases theta'(p, tile) = frac(q_p.o + psi_p).  Per pair:
-// add + 3 FMA (2 when the group has dq_z = 0), one v_sin, 3 FMA (2 when every
-// q_z of the group is 0, so W_z = 0).  Group partials fold into FP64.
+// wavefront the base phases theta'(p, tile) = frac(q_p.o + psi_p); the next
+// group's pixel data is fetched from memory while this one is summed.  Per
+// pair: add + 3 FMA (2 when the group has dq_z = 0), one v_sin, 3 FMA (2 when
+// every q_z of the group is 0, so W_z = 0).  Group partials fold into FP64.
 template <int AL, bool PLANAR, bool NOZ>
 __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const float4 *__restrict__ sw,
                                             const float (*__restrict__ sth)[kPixStage],
@@ -916,6 +919,38 @@ __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const
             gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
             gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
             if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
+        }
+    }
+}
+
+// Lattice rows: a 64-pixel group is the run q_{c} + (m - 31.5) a, m < 64, of one
+// row (its centre q_c is the run's midpoint), so dq_m.d_j = (m - 31.5) e_j with
+// e_j = a.d_j fixed per atom lane: phase = theta'(m, tile) + (beta_j + (m - 31.5) e_j),
+// formed per block of 8 pixels as base = fma(m0 - 31.5, e, beta) and then
+// fma(k, e, base): one FMA and one add per pair.
+template <int AL, bool NOZ>
+__device__ __forceinline__ void pixel_pairs_lattice(const float4 *__restrict__ sw,
+                                                    const float (*__restrict__ sth)[kPixStage],
+                                                    const float (&e)[AL], const float (&beta)[AL],
+                                                    float (&gx)[AL], float (&gy)[AL], float (&gz)[AL]) {
+    constexpr int kRun = 8;  // pixels per unrolled block: offset (m0 - 31.5 + k) e = base + k e
+#pragma unroll 1
+    for (int m0 = 0; m0 < kPixStage; m0 += kRun) {
+        const float mcb = static_cast<float>(m0) - 0.5f * static_cast<float>(kPixStage - 1);
+        float base[AL];
+#pragma unroll
+        for (int a = 0; a < AL; ++a) base[a] = __builtin_fmaf(mcb, e[a], beta[a]);
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const float4 wv = sw[m0 + k];
+#pragma unroll
+            for (int a = 0; a < AL; ++a) {
+                const float ph = sth[a][m0 + k] + __builtin_fmaf(static_cast<float>(k), e[a], base[a]);
+                const float sn = __builtin_amdgcn_sinf(ph);
+                gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
+                gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
+                if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
+            }
         }
     }
 }
@@ -944,6 +979,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
         const GradSeg sg = segs[item.seg];
         float dx[AL], dy[AL], dz[AL];
         float lx[AL], ly[AL], lz[AL];
+        float e[AL];
         double ox[AL], oy[AL], oz[AL];
         double gx64[AL], gy64[AL], gz64[AL];
 #pragma unroll
@@ -956,24 +992,38 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             dx[a] = h.x; dy[a] = h.y; dz[a] = h.z;
             lx[a] = l.x; ly[a] = l.y; lz[a] = l.z;
             ox[a] = o.x; oy[a] = o.y; oz[a] = o.z;
+            e[a] = static_cast<float>(__builtin_fma(sg.a[2], double(h.z) + double(l.z),
+                                      __builtin_fma(sg.a[1], double(h.y) + double(l.y),
+                                                    sg.a[0] * (double(h.x) + double(l.x)))));
             gx64[a] = gy64[a] = gz64[a] = 0.0;
         }
-        for (int s0 = 0; s0 < item.np; s0 += kPixStage) {
+        // pixel data of a staged group, loaded one group ahead
+        float4 r_q = make_float4(0.f, 0.f, 0.f, 0.f), r_w = r_q;
+        double4 r_d = make_double4(0.0, 0.0, 0.0, 0.0), r_c = r_d;
+        auto fetch = [&](int s0) {
             const int n_here = min(kPixStage, item.np - s0);
-            {
-                const int sp = item.p0 + s0 + (lane < n_here ? lane : 0);
-                const int64_t i = sg.slot0 + sp;
-                if (wave == 0) {
-                    s_q[lane] = pdq[i];
-                    s_w[lane] = lane < n_here ? pw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (lane == 0) s_c = centre[sg.grp0 + (item.p0 + s0) / kPixStage];
-                }
-                const double4 d = pq64[i];
-#pragma unroll
-                for (int a = 0; a < AL; ++a)
-                    s_th[wave][a][lane] = frac_f32(__builtin_fma(d.z, oz[a], __builtin_fma(d.y, oy[a], d.x * ox[a])) + d.w);
+            const int sp = item.p0 + s0 + (lane < n_here ? lane : 0);
+            const int64_t i = sg.slot0 + sp;
+            if (wave == 0) {
+                r_q = pdq[i];
+                r_w = lane < n_here ? pw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (lane == 0) r_c = centre[sg.grp0 + (item.p0 + s0) / kPixStage];
             }
+            r_d = pq64[i];
+        };
+        fetch(0);
+        for (int s0 = 0; s0 < item.np; s0 += kPixStage) {
+            if (wave == 0) {
+                s_q[lane] = r_q;
+                s_w[lane] = r_w;
+                if (lane == 0) s_c = r_c;
+            }
+#pragma unroll
+            for (int a = 0; a < AL; ++a)
+                s_th[wave][a][lane] =
+                    frac_f32(__builtin_fma(r_d.z, oz[a], __builtin_fma(r_d.y, oy[a], r_d.x * ox[a])) + r_d.w);
             __syncthreads();
+            if (s0 + kPixStage < item.np) fetch(s0 + kPixStage);
             const double4 c = s_c;
             float beta[AL];
 #pragma unroll
@@ -984,9 +1034,16 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             float gx[AL], gy[AL], gz[AL];
 #pragma unroll
             for (int a = 0; a < AL; ++a) gx[a] = gy[a] = gz[a] = 0.f;
-            if (c.w == 2.0) pixel_pairs<AL, true, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
-            else if (c.w == 1.0) pixel_pairs<AL, true, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
-            else pixel_pairs<AL, false, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            if (sg.lat) {
+                if (c.w == 2.0) pixel_pairs_lattice<AL, true>(s_w, s_th[wave], e, beta, gx, gy, gz);
+                else pixel_pairs_lattice<AL, false>(s_w, s_th[wave], e, beta, gx, gy, gz);
+            } else if (c.w == 2.0) {
+                pixel_pairs<AL, true, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            } else if (c.w == 1.0) {
+                pixel_pairs<AL, true, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            } else {
+                pixel_pairs<AL, false, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            }
 #pragma unroll
             for (int a = 0; a < AL; ++a) {
                 gx64[a] += static_cast<double>(gx[a]);
@@ -1228,7 +1285,10 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
             ps.q = sg.q;
             ps.n_q = sg.n_q;
             ps.slot0 = t.slots;
-            ps.pad = 0;
+            ps.lattice = 0;
+            if (gsh.lattice)
+                for (const LatSet &l : t.lat)
+                    if (l.q == sg.q && l.n_q == sg.n_q && l.n2 % kPixStage == 0) ps.lattice = 1;
             t.slots += sg.n_q;
             t.psets.push_back(ps);
             set = static_cast<int>(t.psets.size()) - 1;
@@ -1322,7 +1382,12 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         g.n_tiles = t.bsegs[i].n_tiles;
         g.n_chunks = (g.n_q > 0 && g.n_tiles > 0) ? (g.n_q + pchunk - 1) / pchunk : 0;
         g.part = t.gpart;
-        g.pad = 0;
+        g.lat = t.psets[t.seg_set[i]].lattice;
+        for (int c = 0; c < 3; ++c) g.a[c] = 0.0;
+        if (g.lat)
+            for (const LatSet &l : t.lat)
+                if (l.q == g.q && l.n_q == g.n_q)
+                    for (int c = 0; c < 3; ++c) g.a[c] = l.a[c] * kInvTwoPi;
         t.gpart += static_cast<int64_t>(g.n_chunks) * g.n_tiles * kTile;
     }
     int i0 = 0;

@@ -172,7 +172,7 @@ void release_all_scratch() {
 namespace {
 
 // Defaults: the autotuner's choice on a 65,536-atom, 512x512-pixel single frame.
-xs_tile_shape g_shape[2] = {{64, 2, 64, 0, 4, 1}, {64, 4, 0, 4096, 4, 0}};
+xs_tile_shape g_shape[2] = {{64, 8, 32, 0, 0, 1}, {64, 2, 0, 2048, 0, 1}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
@@ -408,7 +408,7 @@ xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void
     if (!p) return set_error(XS_ENOMEM, "plan: host allocation failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
     xs_status st = XS_OK;
-    if (fsh.lattice) st = p->plan.find_lattices(s, segs.data(), static_cast<int>(segs.size()), q);
+    if (fsh.lattice || gsh.lattice) st = p->plan.find_lattices(s, segs.data(), static_cast<int>(segs.size()), q);
     if (st == XS_OK) st = p->plan.build(segs.data(), static_cast<int>(segs.size()), b->box, fsh, gsh);
     if (st == XS_OK) st = p->plan.allocate(s, true);
     if (st == XS_OK) st = p->plan.sort_pixels(s, q);
@@ -490,7 +490,6 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
         return set_error(XS_ENOTSUP, "the 4-waves-per-SIMD variant is built for forward q_per_lane 2, 4 "
                                      "and gradient q_per_lane 4");
     if (shape->lattice != 0 && shape->lattice != 1) return set_error(XS_EINVAL, "lattice must be 0 or 1");
-    if (kind == 1 && shape->lattice) return set_error(XS_ENOTSUP, "lattice applies to the forward kernel only");
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[kind] = *shape;
     return XS_OK;
