@@ -31,13 +31,38 @@ if ROOT not in sys.path:
 METRIC = ("G atom-q pair evals/s (fwd+adjoint) vs FP64 form at 1e-5 rel err; % VALU roofline")
 UNIT = "G atom-q pair evals/s"
 # MI355X: 256 CUs at 2.4 GHz; FP32 vector FMA 128 lanes/clk/CU (157.3 TFLOP/s);
-# v_sin_f32 / v_cos_f32 issue at a quarter of that, 32 lanes/clk/CU.
+# v_sin_f32 / v_cos_f32 issue at a quarter of that, 32 lanes/clk/CU, and (measured)
+# do not overlap with other VALU work of the same CU.
 CUS, CLOCK = 256, 2.4e9
+VALU_LANES = 128
 TRANS_LANES = 32
 PEAK_TRANS = CUS * CLOCK * TRANS_LANES          # transcendental lane-ops/s
 PEAK_SINCOS_PAIRS = PEAK_TRANS / 2.0           # pairs/s with one sin + one cos each
-PEAK_SIN_PAIRS = PEAK_TRANS                    # pairs/s with one sin each (adjoint form)
 PEAK_HBM = 8.0e12                              # bytes/s
+
+
+def alu_peak(n_valu, n_trans):
+    """Pairs/s when every CU issues only the kernel's per-pair VALU and
+    transcendental instructions back to back (no overlap between the two)."""
+    return CUS * CLOCK / (n_valu / VALU_LANES + n_trans / TRANS_LANES)
+
+
+def pair_mix(kernel, lattice, ql, qz_zero):
+    """Per-pair instruction mix (FP32 VALU, transcendental) of the inner loops.
+    forward, general: 2 FMA phase (3 with dq_z), sin + cos, 2 FMA accumulate.
+    forward, lattice run of QL pixels: per atom 2 FMA phase (3 with dq_z) + sin + cos
+    + 2 FMA for pixel 0 + 4 FMA (complex multiply-add) for each further pixel.
+    adjoint, general: add + 2 FMA phase (3 with dq_z), sin, 2 FMA (3 with W_z).
+    adjoint, lattice: FMA + add phase, sin, 2 FMA (3 with W_z)."""
+    if kernel == "forward_fp32c":
+        ph = 2 if qz_zero else 3
+        if lattice:
+            return (ph + 2 + 4 * (ql - 1)) / ql, 2.0 / ql
+        return ph + 2, 2.0
+    acc = 2 if qz_zero else 3
+    if lattice:
+        return 2 + acc, 1.0
+    return 1 + (2 if qz_zero else 3) + acc, 1.0
 
 
 def log(*a):
@@ -49,17 +74,17 @@ def source_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_src):
-    """HBM bytes per launch of the forward pair kernel from the committed PMC summary,
-    or None if the summary is missing or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", "fwd_fp32c_pmc_grad65536.json")
+def traffic_from_profile(kernel_src, kernel):
+    """HBM bytes per launch of a pair kernel from the committed PMC summary, or None
+    if the summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "pair_kernels_pmc_grad65536.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
     if d.get("source_sha256_16") != source_hash(kernel_src):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(pos, f, q, amp, w, budget_s=15.0):
@@ -119,6 +144,7 @@ def run_grad(args):
         from paper_2204_13241_amd import tune
         tuned = tune.tune([(N, 1, q, L)], pos, f, use_cache=not args.retune)
         log("tile shapes (%s): fwd %s  grad %s" % (tuned["source"], tuned["forward"], tuned["gradient"]))
+    shapes = [api.get_tile_shape(0), api.get_tile_shape(1)]
     # one plan for the whole run: work lists, buffers and pixel order built once
     plan = api.Plan.single(N, 1, q, L)
     I = torch.empty(Q, dtype=torch.float64, device=dev)
@@ -176,17 +202,25 @@ def run_grad(args):
     log("timed %d steps: %.3f ms/step, %.1f G pairs/s, loss %.6g" % (args.steps, ms_step, value,
                                                                       float(loss[0])))
 
-    plan.close()
+    info = plan.describe()
+    lattice = info["n_lattice_segments"] == info["n_segments"]
+    qz_zero = bool(np.all(q_np[:, 2] == 0.0))
+    src = os.path.join(ROOT, "paper_2204_13241_amd", "csrc", "k_fp32c.hip")
     kern = {}
-    for name, rec, peak in (("forward_fp32c", fwd, PEAK_SINCOS_PAIRS), ("adjoint_fp32c", grd, PEAK_SIN_PAIRS)):
+    for name, rec, kind in (("forward_fp32c", fwd, 0), ("adjoint_fp32c", grd, 1)):
         avg_ms = rec["ms"] / max(rec["launches"], 1)
         work = rec["work"] / max(rec["launches"], 1)
         ach = work / (avg_ms * 1e-3) / 1e9
+        ql = max(2, shapes[kind]["q_per_lane"]) if lattice else shapes[kind]["q_per_lane"]
+        n_valu, n_trans = pair_mix(name, lattice, ql, qz_zero)
+        peak = alu_peak(n_valu, n_trans) / 1e9
         kern[name] = {"avg_ms": avg_ms, "launches": rec["launches"], "pairs_per_launch": work,
-                      "achieved_Gpair_s": ach, "peak_Gpair_s": peak / 1e9, "frac": ach / (peak / 1e9)}
+                      "form": "lattice" if lattice else "general", "valu_per_pair": n_valu,
+                      "trans_per_pair": n_trans, "achieved_Gpair_s": ach, "peak_Gpair_s": peak,
+                      "frac": ach / peak, "frac_of_sincos_pair_peak": ach / (PEAK_SINCOS_PAIRS / 1e9),
+                      "traffic": traffic_from_profile(src, name)}
     kern["binning"] = {"avg_ms": binr["ms"] / max(binr["launches"], 1), "launches": binr["launches"]}
     dom = max(("forward_fp32c", "adjoint_fp32c"), key=lambda k: kern[k]["avg_ms"])
-    src = os.path.join(ROOT, "paper_2204_13241_amd", "csrc", "k_fp32c.hip")
     roofline = {
         "bound": "alu",
         "kernel": dom,
@@ -194,7 +228,7 @@ def run_grad(args):
         "peak": kern[dom]["peak_Gpair_s"],
         "unit": "Gpair/s",
         "frac": kern[dom]["frac"],
-        "traffic": traffic_from_profile(src) if dom == "forward_fp32c" else None,
+        "traffic": kern[dom]["traffic"],
     }
 
     # accuracy against the exact FP64 form at the final positions, and FP64 timing
@@ -208,10 +242,13 @@ def run_grad(args):
         t64f = api.timing_read("fwd64")["ms"]
         t64g = api.timing_read("grad64")["ms"]
         api.timing_enable(False)
-        I32, amp32 = api.intensity(pos, f, q, "fp32c", box=L, return_amp=True)
+        # the timed plan (same form and tile shapes) at the final positions
+        I32, amp32 = plan.intensity(pos, f)
         _, w32 = api.speckle_loss(I32, It)
-        g32 = api.intensity_grad(pos, f, q, amp32, w32, "fp32c", box=L, out_dtype=torch.float64)
-        g32k = api.intensity_grad(pos, f, q, amp64, w64, "fp32c", box=L, out_dtype=torch.float64)
+        g32 = plan.grad(pos, f, amp32, w32, retile=False,
+                        g64=torch.empty((N, 3), dtype=torch.float64, device=dev))
+        g32k = plan.grad(pos, f, amp64, w64, retile=False,
+                         g64=torch.empty((N, 3), dtype=torch.float64, device=dev))
         torch.cuda.synchronize()
         I64h, I32h = I64.cpu().numpy(), I32.cpu().numpy()
         inc = float(np.sum(f_np ** 2))
@@ -234,6 +271,7 @@ def run_grad(args):
     else:
         cpu_amp = np.zeros((Q, 2))
         cpu_w = np.zeros(Q)
+    plan.close()
 
     result = {
         "metric": METRIC,
@@ -254,6 +292,8 @@ def run_grad(args):
                    "n_atoms": N, "n_q": Q, "pairs_per_step": pairs_step, "precision": "fp32c",
                    "tile_shape_fwd": api.get_tile_shape(0), "tile_shape_grad": api.get_tile_shape(1)},
         "roofline": roofline,
+        # headline fraction: pair evaluations per second over the sincos-pair roofline
+        # (one v_sin + one v_cos per pair at 32 transcendental lanes/clk/CU)
         "valu_roofline_frac": value / (PEAK_SINCOS_PAIRS / 1e9),
         "kernels": kern,
     }
