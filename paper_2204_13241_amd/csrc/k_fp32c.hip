@@ -937,25 +937,35 @@ __device__ __forceinline__ void pixel_pairs_lattice(const float4 *__restrict__ s
 #pragma unroll 1
     for (int m0 = 0; m0 < kPixStage; m0 += kRun) {
         const float mcb = static_cast<float>(m0) - 0.5f * static_cast<float>(kPixStage - 1);
-        float base[AL];
+        // phases of the block first, then the sines, then the sums: independent
+        // transcendentals back to back instead of one sine feeding the next FMA
+        float sn[kRun][AL];
 #pragma unroll
-        for (int a = 0; a < AL; ++a) base[a] = __builtin_fmaf(mcb, e[a], beta[a]);
+        for (int a = 0; a < AL; ++a) {
+            const float base = __builtin_fmaf(mcb, e[a], beta[a]);
+            sn[0][a] = sth[a][m0] + base;
+#pragma unroll
+            for (int k = 1; k < kRun; ++k)
+                sn[k][a] = sth[a][m0 + k] + __builtin_fmaf(static_cast<float>(k), e[a], base);
+        }
+#pragma unroll
+        for (int k = 0; k < kRun; ++k)
+#pragma unroll
+            for (int a = 0; a < AL; ++a) sn[k][a] = __builtin_amdgcn_sinf(sn[k][a]);
 #pragma unroll
         for (int k = 0; k < kRun; ++k) {
             const float4 wv = sw[m0 + k];
 #pragma unroll
             for (int a = 0; a < AL; ++a) {
-                const float ph = sth[a][m0 + k] + __builtin_fmaf(static_cast<float>(k), e[a], base[a]);
-                const float sn = __builtin_amdgcn_sinf(ph);
-                gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
-                gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
-                if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
+                gx[a] = __builtin_fmaf(wv.x, sn[k][a], gx[a]);
+                gy[a] = __builtin_fmaf(wv.y, sn[k][a], gy[a]);
+                if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn[k][a], gz[a]);
             }
         }
     }
 }
 
-template <int AL, int OCC>
+template <int AL, int OCC, bool LAT>
 __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
     const GradItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
     const GradSeg *__restrict__ segs, const float4 *__restrict__ t_hi,
@@ -992,9 +1002,10 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             dx[a] = h.x; dy[a] = h.y; dz[a] = h.z;
             lx[a] = l.x; ly[a] = l.y; lz[a] = l.z;
             ox[a] = o.x; oy[a] = o.y; oz[a] = o.z;
-            e[a] = static_cast<float>(__builtin_fma(sg.a[2], double(h.z) + double(l.z),
-                                      __builtin_fma(sg.a[1], double(h.y) + double(l.y),
-                                                    sg.a[0] * (double(h.x) + double(l.x)))));
+            e[a] = LAT ? static_cast<float>(__builtin_fma(sg.a[2], double(h.z) + double(l.z),
+                                            __builtin_fma(sg.a[1], double(h.y) + double(l.y),
+                                                          sg.a[0] * (double(h.x) + double(l.x)))))
+                       : 0.f;
             gx64[a] = gy64[a] = gz64[a] = 0.0;
         }
         // pixel data of a staged group, loaded one group ahead
@@ -1005,7 +1016,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             const int sp = item.p0 + s0 + (lane < n_here ? lane : 0);
             const int64_t i = sg.slot0 + sp;
             if (wave == 0) {
-                r_q = pdq[i];
+                if (!LAT) r_q = pdq[i];
                 r_w = lane < n_here ? pw[i] : make_float4(0.f, 0.f, 0.f, 0.f);
                 if (lane == 0) r_c = centre[sg.grp0 + (item.p0 + s0) / kPixStage];
             }
@@ -1014,7 +1025,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
         fetch(0);
         for (int s0 = 0; s0 < item.np; s0 += kPixStage) {
             if (wave == 0) {
-                s_q[lane] = r_q;
+                if (!LAT) s_q[lane] = r_q;
                 s_w[lane] = r_w;
                 if (lane == 0) s_c = r_c;
             }
@@ -1034,7 +1045,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             float gx[AL], gy[AL], gz[AL];
 #pragma unroll
             for (int a = 0; a < AL; ++a) gx[a] = gy[a] = gz[a] = 0.f;
-            if (sg.lat) {
+            if (LAT) {
                 if (c.w == 2.0) pixel_pairs_lattice<AL, true>(s_w, s_th[wave], e, beta, gx, gy, gz);
                 else pixel_pairs_lattice<AL, false>(s_w, s_th[wave], e, beta, gx, gy, gz);
             } else if (c.w == 2.0) {
@@ -1133,6 +1144,7 @@ struct Plan::Tables {
     std::vector<int> gsub_item0, gsub_nitem;
     std::vector<double> gsub_work;
     std::vector<int> gsub_maxq;
+    std::vector<int> gsub_lat;            // form of each sub-batch (1: lattice)
     int64_t atoms = 0, cells = 0, tiles = 0, slots = 0, groups = 0, fpart = 0, gpart = 0;
     int max_atoms = 0, max_tiles = 0, max_q = 0, max_set_q = 0, max_slots_seg = 0;
     double fwork = 0.0, lwork = 0.0;
@@ -1394,7 +1406,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
     while (i0 < n_segs) {
         int i1 = i0 + 1;
         for (; i1 < n_segs; ++i1) {
-            bool clash = false;
+            bool clash = t.gsegs[i1].lat != t.gsegs[i0].lat;  // one form per sub-batch
             for (int k = i0; k < i1 && !clash; ++k) clash = t.seg_set[k] == t.seg_set[i1];
             if (clash) break;
         }
@@ -1426,6 +1438,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         t.gsub_nitem.push_back(static_cast<int>(sub.size()));
         t.gsub_work.push_back(work);
         t.gsub_maxq.push_back(mq);
+        t.gsub_lat.push_back(t.gsegs[i0].lat);
         t.gitems.insert(t.gitems.end(), sub.begin(), sub.end());
         i0 = i1;
     }
@@ -1594,11 +1607,20 @@ void launch_forward(hipStream_t s, int n, int32_t *counter, const Plan::Buffers 
                        b.fsegs, q, b.pix_order, b.t_hi, b.t_lo, b.origins, b.fpart);
 }
 
-template <int AL, int OCC>
-void launch_grad(hipStream_t s, const GradItem *items, int n, int32_t *counter, const Plan::Buffers &b) {
-    const int slots = std::min(n, resident_blocks(reinterpret_cast<const void *>(k_grad_fp32c<AL, OCC>), kBlock));
-    hipLaunchKernelGGL((k_grad_fp32c<AL, OCC>), dim3(slots), dim3(kBlock), 0, s, items, n, counter, b.gsegs,
+template <int AL, int OCC, bool LAT>
+void launch_grad_form(hipStream_t s, const GradItem *items, int n, int32_t *counter, const Plan::Buffers &b) {
+    const int slots =
+        std::min(n, resident_blocks(reinterpret_cast<const void *>(k_grad_fp32c<AL, OCC, LAT>), kBlock));
+    hipLaunchKernelGGL((k_grad_fp32c<AL, OCC, LAT>), dim3(slots), dim3(kBlock), 0, s, items, n, counter, b.gsegs,
                        b.t_hi, b.t_lo, b.origins, b.pdq, b.pw, b.pq64, b.centre, b.gpart);
+}
+
+// The items of one gradient sub-batch are all of one form (lattice or general).
+template <int AL, int OCC>
+void launch_grad(hipStream_t s, bool lat, const GradItem *items, int n, int32_t *counter,
+                 const Plan::Buffers &b) {
+    if (lat) launch_grad_form<AL, OCC, true>(s, items, n, counter, b);
+    else launch_grad_form<AL, OCC, false>(s, items, n, counter, b);
 }
 
 template <int QL, int OCC>
@@ -1635,14 +1657,16 @@ bool launch_forward_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt,
     }
 }
 
-bool launch_grad_variant(hipStream_t s, int al, int occ, const GradItem *items, int n, int32_t *cnt,
+bool launch_grad_variant(hipStream_t s, int al, int occ, bool lat, const GradItem *items, int n, int32_t *cnt,
                          const Plan::Buffers &b) {
     const bool o4 = occ == 4;
     switch (al) {
-    case 1: launch_grad<1, 1>(s, items, n, cnt, b); return true;
-    case 2: launch_grad<2, 1>(s, items, n, cnt, b); return true;
-    case 4: o4 ? launch_grad<4, 4>(s, items, n, cnt, b) : launch_grad<4, 1>(s, items, n, cnt, b); return true;
-    case 8: launch_grad<8, 1>(s, items, n, cnt, b); return true;
+    case 1: launch_grad<1, 1>(s, lat, items, n, cnt, b); return true;
+    case 2: launch_grad<2, 1>(s, lat, items, n, cnt, b); return true;
+    case 4:
+        o4 ? launch_grad<4, 4>(s, lat, items, n, cnt, b) : launch_grad<4, 1>(s, lat, items, n, cnt, b);
+        return true;
+    case 8: launch_grad<8, 1>(s, lat, items, n, cnt, b); return true;
     default: return false;
     }
 }
@@ -1688,7 +1712,7 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
         const GradItem *items = b.gitems + t.gsub_item0[k];
         void *tok = nullptr;
         timer_begin(s, TIMER_GRAD32, &tok);
-        if (!launch_grad_variant(s, gshape.q_per_lane, gshape.waves_per_simd, items, n, cnt, b))
+        if (!launch_grad_variant(s, gshape.q_per_lane, gshape.waves_per_simd, t.gsub_lat[k] != 0, items, n, cnt, b))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
         timer_end(s, TIMER_GRAD32, tok, t.gsub_work[k]);
         XS_HIP(hipGetLastError());
