@@ -906,19 +906,34 @@ __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const
                                             const float (&dx)[AL], const float (&dy)[AL],
                                             const float (&dz)[AL], const float (&beta)[AL],
                                             float (&gx)[AL], float (&gy)[AL], float (&gz)[AL]) {
-#pragma unroll 2
-    for (int m = 0; m < kPixStage; ++m) {
-        const float4 qv = sq[m];
-        const float4 wv = sw[m];
+    constexpr int kRun = 4;  // pixels per block: phases, then sines, then sums
+#pragma unroll 1
+    for (int m0 = 0; m0 < kPixStage; m0 += kRun) {
+        float sn[kRun][AL];
 #pragma unroll
-        for (int a = 0; a < AL; ++a) {
-            float ph = __builtin_fmaf(qv.x, dx[a], sth[a][m] + beta[a]);
-            ph = __builtin_fmaf(qv.y, dy[a], ph);
-            if (!PLANAR) ph = __builtin_fmaf(qv.z, dz[a], ph);
-            const float sn = __builtin_amdgcn_sinf(ph);
-            gx[a] = __builtin_fmaf(wv.x, sn, gx[a]);
-            gy[a] = __builtin_fmaf(wv.y, sn, gy[a]);
-            if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn, gz[a]);
+        for (int k = 0; k < kRun; ++k) {
+            const float4 qv = sq[m0 + k];
+#pragma unroll
+            for (int a = 0; a < AL; ++a) {
+                float ph = __builtin_fmaf(qv.x, dx[a], sth[a][m0 + k] + beta[a]);
+                ph = __builtin_fmaf(qv.y, dy[a], ph);
+                if (!PLANAR) ph = __builtin_fmaf(qv.z, dz[a], ph);
+                sn[k][a] = ph;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kRun; ++k)
+#pragma unroll
+            for (int a = 0; a < AL; ++a) sn[k][a] = __builtin_amdgcn_sinf(sn[k][a]);
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const float4 wv = sw[m0 + k];
+#pragma unroll
+            for (int a = 0; a < AL; ++a) {
+                gx[a] = __builtin_fmaf(wv.x, sn[k][a], gx[a]);
+                gy[a] = __builtin_fmaf(wv.y, sn[k][a], gy[a]);
+                if (!NOZ) gz[a] = __builtin_fmaf(wv.z, sn[k][a], gz[a]);
+            }
         }
     }
 }
