@@ -75,6 +75,15 @@ static int or_threads(int n_threads)
 #endif
 }
 
+static int omp_thread_index(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
 int32_t or_max_threads(void) { return or_threads(0); }
 
 void or_constants(double *out)
@@ -356,6 +365,47 @@ int or_ring_index(int64_t n_q, const double *q, int32_t n_rings,
 }
 
 /*
+ * Pairwise sum of x[0..n), n >= 1, in the given order: adjacent pairs are
+ * added level by level, x'[i] = x[2i] + x[2i+1], an odd last element moving up
+ * unchanged, until one value is left.  This is the tree that splits [0, n) at
+ * the largest power of two below n and sums both parts the same way.
+ * Overwrites x.
+ */
+static double or_pairwise(double *x, int64_t n)
+{
+    while (n > 1) {
+        int64_t h = n / 2;
+        for (int64_t i = 0; i < h; ++i) x[i] = x[2 * i] + x[2 * i + 1];
+        if (n & 1) x[h] = x[n - 1];
+        n = h + (n & 1);
+    }
+    return x[0];
+}
+
+/* Members of each ring in ascending pixel index: start[r] .. start[r+1] of
+ * list (start has n_rings + 1 entries).  Pixels with ring < 0 or keep[p] == 0
+ * (keep may be NULL) are left out. */
+static int or_ring_lists(int64_t n_q, const int32_t *ring, const unsigned char *keep,
+                         int32_t n_rings, int64_t **start_out, int64_t **list_out)
+{
+    int64_t *start = calloc((size_t)n_rings + 1, sizeof(int64_t));
+    int64_t *list = malloc(sizeof(int64_t) * (size_t)(n_q > 0 ? n_q : 1));
+    if (!start || !list) { free(start); free(list); return OR_ENOMEM; }
+    for (int64_t p = 0; p < n_q; ++p)
+        if (ring[p] >= 0 && (!keep || keep[p])) start[ring[p] + 1]++;
+    for (int32_t r = 0; r < n_rings; ++r) start[r + 1] += start[r];
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)n_rings);
+    if (!fill) { free(start); free(list); return OR_ENOMEM; }
+    for (int32_t r = 0; r < n_rings; ++r) fill[r] = start[r];
+    for (int64_t p = 0; p < n_q; ++p)
+        if (ring[p] >= 0 && (!keep || keep[p])) list[fill[ring[p]]++] = p;
+    free(fill);
+    *start_out = start;
+    *list_out = list;
+    return OR_OK;
+}
+
+/*
  * Intensity autocorrelation on |q| rings, Sec. 2.3 Eq. (g2_def) with the
  * ring average of Sec. 4.2:
  *   per pixel  G_p(tau) = [ sum_{t < F-tau} I_t I_{t+tau} / (F - tau) ] / <I>_t^2,
@@ -363,8 +413,8 @@ int or_ring_index(int64_t n_q, const double *q, int32_t n_rings,
  *   per ring   g2(r, tau) = mean of G_p(tau) over the ring's pixels.
  * I: [F][Q] (pixel fastest).  Pixels whose <I>_t^2 is zero are left out and
  * not counted.  Fixed order: time sums sequential in t (products by fma),
- * ring sums sequential in ascending pixel index.  Empty rings give NaN.
- * g2: [n_rings][n_tau]; count (may be NULL): [n_rings].
+ * ring sums pairwise over the ring's pixels in ascending index (or_pairwise).
+ * Empty rings give NaN.  g2: [n_rings][n_tau]; count (may be NULL): [n_rings].
  */
 int or_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
                 const double *edges, int32_t n_rings, int32_t n_tau,
@@ -393,18 +443,24 @@ int or_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
             G[p * n_tau + tau] = (acc / (double)(n_frames - tau)) / den;
         }
     }
+    int64_t *start = NULL, *list = NULL;
+    rc = or_ring_lists(n_q, ring, used, n_rings, &start, &list);
+    if (rc != OR_OK) { free(ring); free(G); free(used); return rc; }
+    double *buf = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1));
+    if (!buf) { free(ring); free(G); free(used); free(start); free(list); return OR_ENOMEM; }
     for (int32_t r = 0; r < n_rings; ++r) {
-        int32_t cnt = 0;
-        for (int64_t p = 0; p < n_q; ++p) if (ring[p] == r && used[p]) ++cnt;
-        if (count) count[r] = cnt;
+        const int64_t cnt = start[r + 1] - start[r];
+        if (count) count[r] = (int32_t)cnt;
         for (int32_t tau = 0; tau < n_tau; ++tau) {
-            double sum = 0.0;
-            for (int64_t p = 0; p < n_q; ++p)
-                if (ring[p] == r && used[p]) sum = sum + G[p * n_tau + tau];
-            g2[(int64_t)r * n_tau + tau] = cnt > 0 ? sum / (double)cnt : NAN;
+            double mean = NAN;
+            if (cnt > 0) {
+                for (int64_t m = 0; m < cnt; ++m) buf[m] = G[list[start[r] + m] * n_tau + tau];
+                mean = or_pairwise(buf, cnt) / (double)cnt;
+            }
+            g2[(int64_t)r * n_tau + tau] = mean;
         }
     }
-    free(ring); free(G); free(used);
+    free(ring); free(G); free(used); free(start); free(list); free(buf);
     return OR_OK;
 }
 
@@ -414,7 +470,8 @@ int or_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
  *   frame 0 (trailing partial window dropped), built pairwise:
  *       J_0[k] = I_k,   J_{l+1}[k] = J_l[2k] + J_l[2k+1],  K_l = floor(F / 2^l);
  *   per (level l, window k, ring r) over the ring's pixels in ascending order:
- *       mu = sum J / n,  var = sum (J - mu)^2 / n  (two-pass; fma),
+ *       mu = sum J / n,  var = sum (J - mu)^2 / n  (two-pass; both sums
+ *       pairwise, or_pairwise, over the rounded values J and (J - mu)*(J - mu)),
  *       beta = var / mu^2;
  *   beta_out[l][r] = sum_k beta / K_l  (sequential in k).
  * I: [F][Q].  beta_out: [n_levels][n_rings].  beta_win (may be NULL):
@@ -433,9 +490,15 @@ int or_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const doubl
     int rc = or_ring_index(n_q, q, n_rings, edges, ring);
     if (rc != OR_OK) { free(ring); free(J); return rc; }
     memcpy(J, I, sizeof(double) * (size_t)n_frames * (size_t)n_q);
+    int64_t *start = NULL, *list = NULL;
+    rc = or_ring_lists(n_q, ring, NULL, n_rings, &start, &list);
+    if (rc != OR_OK) { free(ring); free(J); return rc; }
     int32_t *cnt = calloc((size_t)n_rings, sizeof(int32_t));
-    if (!cnt) { free(ring); free(J); return OR_ENOMEM; }
-    for (int64_t p = 0; p < n_q; ++p) if (ring[p] >= 0) cnt[ring[p]]++;
+    if (!cnt) { free(ring); free(J); free(start); free(list); return OR_ENOMEM; }
+    for (int32_t r = 0; r < n_rings; ++r) cnt[r] = (int32_t)(start[r + 1] - start[r]);
+    const int nth = or_threads(n_threads);
+    double *bufs = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1) * (size_t)nth);
+    if (!bufs) { free(ring); free(J); free(start); free(list); free(cnt); return OR_ENOMEM; }
     if (beta_win)
         for (int64_t i = 0; i < (int64_t)n_levels * n_frames * n_rings; ++i) beta_win[i] = NAN;
     int64_t K = n_frames;
@@ -448,20 +511,22 @@ int or_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const doubl
             K = Kn;
         }
         double *bw = malloc(sizeof(double) * (size_t)K * (size_t)n_rings);
-        if (!bw) { free(ring); free(J); free(cnt); return OR_ENOMEM; }
-#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+        if (!bw) { free(ring); free(J); free(cnt); free(start); free(list); free(bufs); return OR_ENOMEM; }
+#pragma omp parallel for schedule(static) num_threads(nth)
         for (int64_t k = 0; k < K; ++k) {
+            double *buf = bufs + (size_t)omp_thread_index() * (size_t)(n_q > 0 ? n_q : 1);
             for (int32_t r = 0; r < n_rings; ++r) {
                 double b = NAN;
-                if (cnt[r] > 0) {
-                    double s = 0.0;
-                    for (int64_t p = 0; p < n_q; ++p)
-                        if (ring[p] == r) s = s + J[k * n_q + p];
-                    double mu = s / (double)cnt[r];
-                    double v = 0.0;
-                    for (int64_t p = 0; p < n_q; ++p)
-                        if (ring[p] == r) { double d = J[k * n_q + p] - mu; v = fma(d, d, v); }
-                    double var = v / (double)cnt[r];
+                const int64_t n = cnt[r];
+                if (n > 0) {
+                    const int64_t *mem = list + start[r];
+                    for (int64_t m = 0; m < n; ++m) buf[m] = J[k * n_q + mem[m]];
+                    double mu = or_pairwise(buf, n) / (double)n;
+                    for (int64_t m = 0; m < n; ++m) {
+                        double d = J[k * n_q + mem[m]] - mu;
+                        buf[m] = d * d;
+                    }
+                    double var = or_pairwise(buf, n) / (double)n;
                     b = var / (mu * mu);
                 }
                 bw[k * n_rings + r] = b;
@@ -477,6 +542,6 @@ int or_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const doubl
         }
         free(bw);
     }
-    free(ring); free(J); free(cnt);
+    free(ring); free(J); free(cnt); free(start); free(list); free(bufs);
     return OR_OK;
 }

@@ -1,15 +1,16 @@
 // Reductions of the speckle intensities (Sec. 2.3):
 //   g2 on |q| rings, Eq. (g2_def) with the ring mean of Sec. 4.2;
 //   XSVS contrast versus exposure, Eqs. (inte_Iq), (bq_Iq).
-// Every floating-point sum has a fixed order (time sums sequential in t, ring
-// sums sequential in ascending pixel index, window sums pairwise), so results
-// are bit-for-bit reproducible.  The sequential ring chains are kept fast by
-// the data layout: pixels are renumbered in ring order (ascending index within
-// a ring: `rank`, and its inverse `list`), and a block stages a chunk of one
-// ring's rows in LDS with all its threads while the owning lanes walk the
-// previous chunk in order.  g2 writes its per-pixel lag values as rank-ordered
-// rows; XSVS gathers a ring's frames through `list` and forms six exposure
-// levels per pass over them.
+// Every floating-point sum has a fixed order, so results are bit-for-bit
+// reproducible: time sums sequential in t, window sums pairwise (dyadic), the
+// mean over windows sequential in k, and ring sums pairwise over the ring's
+// pixels in ascending index — adjacent pairs added level by level, an odd last
+// element carried up unchanged.  That ring tree is computed in parallel:
+// aligned groups of 32 consecutive elements form exact subtrees (a partial
+// last group is the fold from the right of the complete subtrees of its binary
+// decomposition), and the group values are reduced the same way, level after
+// level, until one value per ring is left.  Pixels are renumbered in ring
+// order (`rank`, inverse `list`) so each level reads contiguous rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,19 +23,88 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kPartChunk = 1024;  // pixels per partition block
 constexpr int kLagBlock = 8;      // lags per thread in the g2 lag kernel
-constexpr int kColTile = 64;      // columns (lags / windows) per ring-sum block
-constexpr int kColChunk = 4096;   // doubles staged per chunk (32 KiB of LDS)
-constexpr int kColLoads = kColChunk / kBlock;
-constexpr int kSumBatch = 8;      // LDS reads in flight per ring-sum lane
+constexpr int kGroup = 32;        // elements per pairwise-tree group
 constexpr int kLvTile = 64;       // XSVS: base windows per block
 constexpr int kLvDepth = 6;       // XSVS: levels per launch (base and 5 coarser)
-constexpr int kLvRows = 32;       // XSVS: ring rows per staged chunk
+constexpr int kLvRows = kGroup;   // XSVS: ring rows per staged chunk (one tree group)
 constexpr int kLvStride = 2 * kLvTile + 1;  // LDS row: 127 windows of 7 levels, odd stride
+constexpr int kLvCols = 2 * kLvTile;        // chunk-sum columns per tile (126 used)
 constexpr int kLvLoads = kLvRows * kLvTile / kBlock;
+constexpr int kLvChunksPerBlock = 4;        // consecutive chunks of one ring per block
 static_assert(kLvRows * 8 == kBlock && kLvTile == 64 && (1 << kLvDepth) == kLvTile,
               "XSVS level kernel: thread (row, group of 8 windows) covers one chunk");
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------- pairwise tree
+
+// Complete tree over 2^K values v(st), v(st + 1), ...
+template <int K, typename Load>
+__device__ __forceinline__ double complete_tree(int st, const Load &v) {
+    double x[1 << K];
+#pragma unroll
+    for (int i = 0; i < (1 << K); ++i) x[i] = v(st + i);
+#pragma unroll
+    for (int w = (1 << K) / 2; w >= 1; w >>= 1)
+#pragma unroll
+        for (int i = 0; i < w; ++i) x[i] = x[2 * i] + x[2 * i + 1];
+    return x[0];
+}
+
+// Pairwise tree of v(0) .. v(n - 1), 1 <= n <= 32: the complete subtrees of the
+// binary decomposition of n, left to right by decreasing size, folded from the
+// right (the bottom-up tree with the odd element carried up).
+template <typename Load>
+__device__ __forceinline__ double tree_upto32(int n, const Load &v) {
+    double s = 0.0;
+    int end = n;
+    bool have = false;
+    auto part = [&](double t, int size) {
+        s = have ? t + s : t;
+        have = true;
+        end -= size;
+    };
+    if (n & 1) part(complete_tree<0>(end - 1, v), 1);
+    if (n & 2) part(complete_tree<1>(end - 2, v), 2);
+    if (n & 4) part(complete_tree<2>(end - 4, v), 4);
+    if (n & 8) part(complete_tree<3>(end - 8, v), 8);
+    if (n & 16) part(complete_tree<4>(end - 16, v), 16);
+    if (n & 32) part(complete_tree<5>(end - 32, v), 32);
+    return s;
+}
+
+// Ring of element e from the offsets off[0..R] (off non-decreasing, e < off[R]).
+__device__ __forceinline__ int ring_of(const int32_t *off, int R, int64_t e) {
+    int lo = 0, hi = R;  // off[lo] <= e < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// One tree level: out[e][c] = tree over in's elements [s, s + cnt) of the
+// element's ring, s = in_off[r] + (e - out_off[r]) * 32.  Rows of ncol columns.
+__global__ __launch_bounds__(kBlock) void k_group_tree(const double *__restrict__ in,
+                                                       double *__restrict__ out, int64_t ncol,
+                                                       const int32_t *__restrict__ in_off,
+                                                       const int32_t *__restrict__ out_off, int32_t R) {
+    __shared__ int32_t o_s[kMaxRings + 1], i_s[kMaxRings + 1];
+    for (int r = threadIdx.x; r <= R; r += kBlock) {
+        o_s[r] = out_off[r];
+        i_s[r] = in_off[r];
+    }
+    __syncthreads();
+    const int64_t gid = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t e = gid / ncol, c = gid - (gid / ncol) * ncol;
+    if (e >= o_s[R]) return;
+    const int r = ring_of(o_s, R, e);
+    const int64_t s = i_s[r] + (e - o_s[r]) * kGroup;
+    const int cnt = static_cast<int>(std::min<int64_t>(kGroup, i_s[r + 1] - s));
+    out[e * ncol + c] = tree_upto32(cnt, [&](int i) { return in[(s + i) * ncol + c]; });
+}
+
+// ---------------------------------------------------------------- partition
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -105,20 +175,36 @@ __global__ __launch_bounds__(kBlock) void k_part_scan_ring(int32_t *__restrict__
     if (threadIdx.x == 0) tot[r] = carry;
 }
 
-// ring_start[r] = sum_{r' < r} tot[r'], r = 0..R.  One block.
-__global__ __launch_bounds__(kBlock) void k_part_start(const int32_t *__restrict__ tot, int32_t R,
-                                                       int32_t *__restrict__ ring_start) {
-    __shared__ int32_t t_s[kMaxRings];
-    for (int r = threadIdx.x; r < R; r += kBlock) t_s[r] = tot[r];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (int r = 0; r < R; ++r) {
-            ring_start[r] = run;
-            run += t_s[r];
-        }
-        ring_start[R] = run;
+// Offsets of the ring tree, one thread:
+//   lev[l][r], l = 0..levels, r = 0..R: first element of ring r at tree level l
+//   (level 0: the ring's pixels, the ring starts; level l + 1 has ceil(n / 32)
+//   of level l's n elements per ring);
+//   grp[r], r = 0..R: first block group (chunk_groups level-1 chunks) of ring r.
+__global__ void k_tree_offsets(const int32_t *__restrict__ tot, int32_t R, int32_t levels,
+                               int32_t chunk_groups, int32_t *__restrict__ lev, int32_t *__restrict__ grp) {
+    if (threadIdx.x != 0) return;
+    int32_t run = 0;
+    for (int r = 0; r < R; ++r) {
+        lev[r] = run;
+        run += tot[r];
     }
+    lev[R] = run;
+    for (int l = 1; l <= levels; ++l) {
+        int32_t acc = 0;
+        for (int r = 0; r < R; ++r) {
+            const int32_t n = lev[(l - 1) * (R + 1) + r + 1] - lev[(l - 1) * (R + 1) + r];
+            lev[l * (R + 1) + r] = acc;
+            acc += (n + kGroup - 1) / kGroup;
+        }
+        lev[l * (R + 1) + R] = acc;
+    }
+    int32_t g = 0;
+    for (int r = 0; r < R; ++r) {
+        grp[r] = g;
+        const int32_t n1 = lev[(R + 1) + r + 1] - lev[(R + 1) + r];
+        g += (n1 + chunk_groups - 1) / chunk_groups;
+    }
+    grp[R] = g;
 }
 
 // Stable ranks: the pixels of ring r get ranks ring_start[r], ring_start[r] + 1, ...
@@ -145,82 +231,6 @@ __global__ __launch_bounds__(kBlock) void k_part_rank(const int32_t *__restrict_
                 ++o;
             }
     }
-}
-
-// One chunk of a ring's rows: val[j] = X[m0 + row][k0 + col] for the flat
-// index i = tid + j * kBlock = row * W + col, rows < `rows`.  The thread's
-// first element is (q0, c0); each step advances by kBlock = dq rows + dc columns.
-__device__ inline void stage_rows(double (&val)[kColLoads], const double *__restrict__ X, int64_t K,
-                                  int32_t m0, int rows, int64_t k0, int W, int q0, int c0, int dq, int dc) {
-    int qq = q0, cc = c0;
-#pragma unroll
-    for (int j = 0; j < kColLoads; ++j) {
-        val[j] = qq < rows ? X[static_cast<int64_t>(m0 + qq) * K + k0 + cc] : 0.0;
-        qq += dq;
-        cc += dc;
-        if (cc >= W) {
-            cc -= W;
-            ++qq;
-        }
-    }
-}
-
-// Ring mean of each column of a ring-ordered row table X[m][k] (row m = rank):
-// out[r * K + k] = (sum over the ring's rows in order) / n (NaN for an empty
-// ring), count[r] = n.  Block (column tile of width Wt, ring): all threads
-// stage chunks of rows into LDS, loading chunk c + 1 into registers while lanes
-// 0..W-1 of the first wave, one per column, add the rows of chunk c in order.
-__global__ __launch_bounds__(kBlock) void k_ring_mean(const double *__restrict__ X, int64_t K, int32_t Wt,
-                                                      const int32_t *__restrict__ ring_start,
-                                                      double *__restrict__ out, int32_t *__restrict__ count) {
-    __shared__ double tile[kColChunk];
-    const int r = blockIdx.y;
-    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * Wt;
-    const int W = static_cast<int>(std::min<int64_t>(Wt, K - k0));
-    const int C = kColChunk / W;  // rows per chunk
-    const int32_t a = ring_start[r], b = ring_start[r + 1];
-    const int32_t n = b - a;
-    const int q0 = threadIdx.x / W, c0 = threadIdx.x - (threadIdx.x / W) * W;
-    const int dq = kBlock / W, dc = kBlock - (kBlock / W) * W;
-    const int lane = threadIdx.x;
-    const bool owner = lane < W;
-
-    double s = 0.0;
-    double val[kColLoads];
-    int32_t m0 = a;
-    int rows = std::min<int32_t>(C, b - a);
-    stage_rows(val, X, K, m0, rows, k0, W, q0, c0, dq, dc);
-    while (m0 < b) {
-        __syncthreads();  // previous chunk consumed
-#pragma unroll
-        for (int j = 0; j < kColLoads; ++j) {
-            const int i = threadIdx.x + j * kBlock;
-            if (i < rows * W) tile[i] = val[j];
-        }
-        __syncthreads();
-        const int32_t m1 = m0 + rows;
-        const int rows1 = std::min<int32_t>(C, b - m1);
-        if (rows1 > 0) stage_rows(val, X, K, m1, rows1, k0, W, q0, c0, dq, dc);
-        if (owner) {
-            // LDS reads in batches of kSumBatch issued ahead of the dependent adds
-            const double *col = tile + lane;
-            int q = 0;
-            for (; q + kSumBatch <= rows; q += kSumBatch) {
-                double x[kSumBatch];
-#pragma unroll
-                for (int j = 0; j < kSumBatch; ++j) x[j] = col[(q + j) * W];
-#pragma unroll
-                for (int j = 0; j < kSumBatch; ++j) s = s + x[j];
-            }
-            for (; q < rows; ++q) s = s + col[q * W];
-        }
-        m0 = m1;
-        rows = rows1;
-    }
-    if (!owner) return;
-    const int64_t k = k0 + lane;
-    out[static_cast<int64_t>(r) * K + k] = n > 0 ? s / static_cast<double>(n) : __builtin_nan("");
-    if (count && k == 0) count[r] = n;
 }
 
 // ---------------------------------------------------------------- g2
@@ -339,52 +349,63 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags_global(const double *__restr
     }
 }
 
+// g2 ring mean from the tree's top level: g2[r][tau] = total / n (NaN for an
+// empty ring), count[r] = n.
+__global__ __launch_bounds__(kBlock) void k_g2_finish(const double *__restrict__ top, int32_t n_tau,
+                                                      int32_t R, const int32_t *__restrict__ ring_start,
+                                                      const int32_t *__restrict__ top_off,
+                                                      double *__restrict__ g2, int32_t *__restrict__ count) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= static_cast<int64_t>(R) * n_tau) return;
+    const int r = static_cast<int>(i / n_tau), tau = static_cast<int>(i - static_cast<int64_t>(r) * n_tau);
+    const int32_t n = ring_start[r + 1] - ring_start[r];
+    g2[i] = n > 0 ? top[static_cast<int64_t>(top_off[r]) * n_tau + tau] / static_cast<double>(n)
+                  : __builtin_nan("");
+    if (count && tau == 0) count[r] = n;
+}
+
 // ---------------------------------------------------------------- XSVS
 
-// Exposure levels handled by one k_xsvs_levels launch: level base + d for
-// d < depths, with bwin[d] = [R][K_d] per-window contrast, K_d = K_base >> d.
-struct LevelOut {
-    double *bwin[kLvDepth];
-    int64_t K[kLvDepth];
-};
-
-// Windows of base level L (K per row) and the next kLvDepth - 1 levels, per ring.
-// Block (64-window tile k0.., ring r).  A chunk of kLvRows ring rows of the
-// tile's 64 base windows is staged in LDS (row stride kLvStride):
+// Windows of base level L (K per row) and the next kLvDepth - 1 levels.
+// Block (block group of kLvChunksPerBlock consecutive 32-row chunks of one
+// ring, 64-window tile k0..).  Each chunk of the ring's rows of the tile's 64
+// base windows is staged in LDS (row stride kLvStride):
 //   columns [0, 64)    level L windows,
 //   [64, 96) L+1,  [96, 112) L+2,  [112, 120) L+3,  [120, 124) L+4,
 //   [124, 126) L+5, [126] L+6,
-// the coarser levels formed by pairwise sums J_{l+1}[j] = J_l[2j] + J_l[2j+1].  Thread t < 126 owns column t (one window of one level) and runs its
-// two-pass mean / variance over the ring's rows in order: the levels of a tile
-// advance together instead of one launch (and one walk of the ring) per level.
-// Level L+6 (one window per full tile) is written to `next` [rank][K >> 6] for
-// the launch that continues from it.
-// kGather: base rows gathered from the frames I[k][list[m]] (ld = pixels);
+// the coarser levels formed by pairwise sums J_{l+1}[j] = J_l[2j] + J_l[2j+1].
+// Thread t < 126 owns column t (one window of one level) and writes the
+// chunk's pairwise tree of its values (pass 1: J; pass 2: (J - mu)^2 with the
+// column's ring mean mu) to csum[chunk][tile * 128 + t].  Pass 1 also writes
+// level L+6 (one window per full tile) to `next` [rank][K >> 6] for the
+// launch that continues from it.
+// kGather: rows gathered from the frames I[k][list[m]] (ld = pixels);
 // otherwise read from a ring-ordered table X[m][k] (ld = K).
-template <bool kGather>
-__global__ __launch_bounds__(kBlock) void k_xsvs_levels(const double *__restrict__ X, int64_t K, int64_t ld,
-                                                        const int32_t *__restrict__ list,
-                                                        const int32_t *__restrict__ ring_start, int32_t depths,
-                                                        LevelOut lo, double *__restrict__ next) {
+template <bool kGather, bool kPass2>
+__global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
+                                                        const int32_t *__restrict__ list, int32_t R,
+                                                        const int32_t *__restrict__ ring_start,
+                                                        const int32_t *__restrict__ chunk_off,
+                                                        const int32_t *__restrict__ grp_off,
+                                                        const double *__restrict__ mu, int64_t ncol,
+                                                        double *__restrict__ csum, double *__restrict__ next) {
     __shared__ double tile[kLvRows * kLvStride];
-    const int r = blockIdx.y;
-    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * kLvTile;
+    __shared__ int32_t g_s[kMaxRings + 1];
+    for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
+    __syncthreads();
+    const int64_t gb = blockIdx.x;
+    if (gb >= g_s[R]) return;  // block-uniform
+    const int r = ring_of(g_s, R, gb);
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kLvTile;
     const int W = static_cast<int>(std::min<int64_t>(kLvTile, K - k0));
     const int32_t a = ring_start[r], b = ring_start[r + 1];
-    const int32_t n = b - a;
+    const int32_t c_first = static_cast<int32_t>((gb - g_s[r]) * kLvChunksPerBlock);
+    const int32_t n_chunks_ring = (b - a + kLvRows - 1) / kLvRows;
     const int t = threadIdx.x;
-    // the window this thread owns: level depth d, local index j, column t
-    int d = -1, j = 0;
-#pragma unroll
-    for (int dd = 0; dd < kLvDepth; ++dd) {
-        const int o = 2 * kLvTile - ((2 * kLvTile) >> dd), w = kLvTile >> dd;
-        if (dd < depths && t >= o && t < o + w) {
-            d = dd;
-            j = t - o;
-        }
-    }
-    const bool owner = d >= 0 && k0 + (static_cast<int64_t>(j) + 1) * (int64_t(1) << d) <= K;
-    const bool want_next = next != nullptr && k0 + kLvTile <= K;
+    const int64_t col = static_cast<int64_t>(blockIdx.y) * kLvCols + t;
+    const bool owner = t < kLvCols - 2;
+    const double m = (kPass2 && owner) ? mu[static_cast<int64_t>(r) * ncol + col] : 0.0;
+    const bool want_next = !kPass2 && next != nullptr && k0 + kLvTile <= K;
     const int64_t K_next = K >> kLvDepth;
 
     // staging map: element i of thread t is (row q_t + i * dqi, column c_t + i * dci)
@@ -413,98 +434,119 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_levels(const double *__restrict
         }
     };
 
-    double mu = 0.0, v = 0.0;
-#pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-        double s = 0.0;
-        // the next chunk is loaded into registers while the current one is summed
-        double buf[kLvLoads];
-        int32_t mc = a, rc = std::min<int32_t>(kLvRows, b - a);
-        load_chunk(buf, mc, rc);
-        int32_t m = a + rc;
-        while (rc > 0) {
-            const int32_t mrow = mc;
-            const int rows = rc;
-            __syncthreads();  // previous chunk consumed
+    const int32_t c_end = std::min<int32_t>(n_chunks_ring, c_first + kLvChunksPerBlock);
+    double buf[kLvLoads];
+    int32_t mc = a + c_first * kLvRows;
+    int rows = std::min<int32_t>(kLvRows, b - mc);
+    load_chunk(buf, mc, rows);
+    for (int32_t ch = c_first; ch < c_end; ++ch) {
+        const int32_t mrow = mc;
+        const int crow = rows;
+        __syncthreads();  // previous chunk consumed
 #pragma unroll
-            for (int i = 0; i < kLvLoads; ++i) tile[(q_t + i * dqi) * kLvStride + c_t + i * dci] = buf[i];
-            __syncthreads();
-            // coarser levels of the chunk: thread (row q, group g of 8 level-L windows)
-            // forms levels L+1..L+3 of its group; the 8 lanes of a row (one wave)
-            // then pair up their level-L+3 sums for L+4..L+6 by lane exchange
-            {
-                const int q = t >> 3, g = t & 7;
-                double *row = tile + q * kLvStride;
-                double x[8], y1[4], y2[2];
+        for (int i = 0; i < kLvLoads; ++i) tile[(q_t + i * dqi) * kLvStride + c_t + i * dci] = buf[i];
+        __syncthreads();
+        // coarser levels of the chunk: thread (row q, group g of 8 level-L windows)
+        // forms levels L+1..L+3 of its group; the 8 lanes of a row (one wave)
+        // then pair up their level-L+3 sums for L+4..L+6 by lane exchange
+        {
+            const int q = t >> 3, g = t & 7;
+            double *row = tile + q * kLvStride;
+            double x[8], y1[4], y2[2];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) x[i] = row[8 * g + i];
+            for (int i = 0; i < 8; ++i) x[i] = row[8 * g + i];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    y1[i] = x[2 * i] + x[2 * i + 1];
-                    row[64 + 4 * g + i] = y1[i];
-                }
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    y2[i] = y1[2 * i] + y1[2 * i + 1];
-                    row[96 + 2 * g + i] = y2[i];
-                }
-                const double y3 = y2[0] + y2[1];
-                row[112 + g] = y3;
-                const double y4 = y3 + __shfl_xor(y3, 1);  // lanes g = 0, 2, 4, 6
-                if (!(g & 1)) row[120 + (g >> 1)] = y4;
-                const double y5 = y4 + __shfl_xor(y4, 2);  // lanes g = 0, 4
-                if (!(g & 3)) row[124 + (g >> 2)] = y5;
-                const double y6 = y5 + __shfl_xor(y5, 4);  // lane g = 0
-                if (g == 0) {
-                    row[126] = y6;
-                    if (pass == 0 && want_next && q < rows)
-                        next[static_cast<int64_t>(mrow + q) * K_next + (k0 >> kLvDepth)] = y6;
-                }
+            for (int i = 0; i < 4; ++i) {
+                y1[i] = x[2 * i] + x[2 * i + 1];
+                row[64 + 4 * g + i] = y1[i];
             }
-            __syncthreads();
-            mc = m;
-            rc = std::min<int32_t>(kLvRows, b - m);
-            if (rc > 0) load_chunk(buf, mc, rc);
-            m += rc;
-            if (owner) {
-                const double *col = tile + t;
-                int q = 0;
-                if (pass == 0) {
-                    for (; q + kSumBatch <= rows; q += kSumBatch) {
-                        double x[kSumBatch];
 #pragma unroll
-                        for (int i = 0; i < kSumBatch; ++i) x[i] = col[(q + i) * kLvStride];
-#pragma unroll
-                        for (int i = 0; i < kSumBatch; ++i) s = s + x[i];
-                    }
-                    for (; q < rows; ++q) s = s + col[q * kLvStride];
-                } else {
-                    for (; q + kSumBatch <= rows; q += kSumBatch) {
-                        double x[kSumBatch];
-#pragma unroll
-                        for (int i = 0; i < kSumBatch; ++i) x[i] = col[(q + i) * kLvStride];
-#pragma unroll
-                        for (int i = 0; i < kSumBatch; ++i) {
-                            const double e = x[i] - mu;
-                            v = __builtin_fma(e, e, v);
-                        }
-                    }
-                    for (; q < rows; ++q) {
-                        const double e = col[q * kLvStride] - mu;
-                        v = __builtin_fma(e, e, v);
-                    }
-                }
+            for (int i = 0; i < 2; ++i) {
+                y2[i] = y1[2 * i] + y1[2 * i + 1];
+                row[96 + 2 * g + i] = y2[i];
+            }
+            const double y3 = y2[0] + y2[1];
+            row[112 + g] = y3;
+            const double y4 = y3 + __shfl_xor(y3, 1);  // lanes g = 0, 2, 4, 6
+            if (!(g & 1)) row[120 + (g >> 1)] = y4;
+            const double y5 = y4 + __shfl_xor(y4, 2);  // lanes g = 0, 4
+            if (!(g & 3)) row[124 + (g >> 2)] = y5;
+            const double y6 = y5 + __shfl_xor(y5, 4);  // lane g = 0
+            if (g == 0) {
+                row[126] = y6;
+                if (want_next && q < crow)
+                    next[static_cast<int64_t>(mrow + q) * K_next + (k0 >> kLvDepth)] = y6;
             }
         }
-        if (pass == 0) mu = s / static_cast<double>(n);
+        __syncthreads();
+        mc += crow;
+        rows = std::min<int32_t>(kLvRows, b - mc);
+        if (ch + 1 < c_end) load_chunk(buf, mc, rows);
+        if (owner) {
+            const double *colp = tile + t;
+            const double tr = tree_upto32(crow, [&](int i) {
+                const double x = colp[i * kLvStride];
+                if (!kPass2) return x;
+                const double d = x - m;
+                return d * d;
+            });
+            csum[static_cast<int64_t>(chunk_off[r] + ch) * ncol + col] = tr;
+        }
     }
-    if (!owner) return;
-    const int64_t Kd = lo.K[d];
-    const int64_t k = (k0 >> d) + j;
-    lo.bwin[d][static_cast<int64_t>(r) * Kd + k] =
-        n > 0 ? (v / static_cast<double>(n)) / (mu * mu) : __builtin_nan("");
 }
 
+// Ring means of the pass-1 tree top: mu[r][c] = total / n (0 for an empty ring:
+// pass 2 has no chunks there).
+__global__ __launch_bounds__(kBlock) void k_xsvs_mu(const double *__restrict__ top, int64_t ncol, int32_t R,
+                                                    const int32_t *__restrict__ ring_start,
+                                                    const int32_t *__restrict__ top_off,
+                                                    double *__restrict__ mu) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= static_cast<int64_t>(R) * ncol) return;
+    const int r = static_cast<int>(i / ncol);
+    const int64_t c = i - static_cast<int64_t>(r) * ncol;
+    const int32_t n = ring_start[r + 1] - ring_start[r];
+    mu[i] = n > 0 ? top[static_cast<int64_t>(top_off[r]) * ncol + c] / static_cast<double>(n) : 0.0;
+}
+
+// Exposure levels handled by one launch group: level base + d for d < depths,
+// bwin[d] = [R][K_d] per-window contrast, K_d = K_base >> d.
+struct LevelOut {
+    double *bwin[kLvDepth];
+    int64_t K[kLvDepth];
+};
+
+// beta per (ring, column) from the pass-2 tree top and mu: var = total / n,
+// beta = var / mu^2 (NaN for an empty ring), to the column's level and window.
+__global__ __launch_bounds__(kBlock) void k_xsvs_beta(const double *__restrict__ top, const double *__restrict__ mu,
+                                                      int64_t ncol, int64_t K, int32_t depths, int32_t R,
+                                                      const int32_t *__restrict__ ring_start,
+                                                      const int32_t *__restrict__ top_off, LevelOut lo) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= static_cast<int64_t>(R) * ncol) return;
+    const int r = static_cast<int>(i / ncol);
+    const int64_t c = i - static_cast<int64_t>(r) * ncol;
+    const int64_t k0 = (c / kLvCols) * kLvTile;
+    const int t = static_cast<int>(c % kLvCols);
+    int d = -1, j = 0;
+#pragma unroll
+    for (int dd = 0; dd < kLvDepth; ++dd) {
+        const int o = 2 * kLvTile - ((2 * kLvTile) >> dd), w = kLvTile >> dd;
+        if (dd < depths && t >= o && t < o + w) {
+            d = dd;
+            j = t - o;
+        }
+    }
+    if (d < 0 || k0 + (static_cast<int64_t>(j) + 1) * (int64_t(1) << d) > K) return;
+    const int32_t n = ring_start[r + 1] - ring_start[r];
+    double beta = __builtin_nan("");
+    if (n > 0) {
+        const double m = mu[i];
+        const double var = top[static_cast<int64_t>(top_off[r]) * ncol + c] / static_cast<double>(n);
+        beta = var / (m * m);
+    }
+    lo.bwin[d][static_cast<int64_t>(r) * lo.K[d] + (k0 >> d) + j] = beta;
+}
 
 // Mean over windows, block per ring r: beta_out[r] = (sum_k bwin[r][k] in order) / K;
 // optional per-window output beta_win_level[k][r] (rows k >= K filled with NaN).
@@ -533,48 +575,80 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_mean(const double *__restrict__
     if (threadIdx.x == 0) beta_out[r] = acc / static_cast<double>(K);
 }
 
-// Ring starts and ring-order ranks (-1 for pixels with key -1) from the keys.
-xs_status partition(hipStream_t s, const int32_t *key, int64_t n_q, int32_t R, int32_t **start_out,
-                    int32_t **rank_out, int32_t **list_out) {
+// ---------------------------------------------------------------- host side
+
+// Tree levels above the leaves so that every ring of up to n_q leaves ends with one value.
+int tree_levels(int64_t n_q) {
+    int levels = 0;
+    int64_t e = std::max<int64_t>(n_q, 1);
+    while (e > 1) {
+        e = (e + kGroup - 1) / kGroup;
+        ++levels;
+    }
+    return std::max(levels, 1);
+}
+
+// Elements of tree level l over all R rings, at most (level 0: n_q).
+int64_t level_bound(int64_t n_q, int32_t R, int l) {
+    int64_t e = std::max<int64_t>(n_q, 1);
+    for (int i = 0; i < l; ++i) e = (e + kGroup - 1) / kGroup + R;
+    return e;
+}
+
+struct Partition {
+    int32_t *start = nullptr;  // ring starts [R + 1] = tree level 0 offsets
+    int32_t *rank = nullptr;
+    int32_t *list = nullptr;
+    int32_t *lev = nullptr;    // [(levels + 1)][R + 1]
+    int32_t *grp = nullptr;    // [R + 1] block groups of level-1 chunks
+    int levels = 0;
+};
+
+// Ring starts, ring-order ranks (-1 for pixels with key -1), the inverse list
+// and the tree offsets.
+xs_status partition(hipStream_t s, const int32_t *key, int64_t n_q, int32_t R, Partition *P) {
     const int64_t nb = (n_q + kPartChunk - 1) / kPartChunk;
+    const int levels = tree_levels(n_q);
     void *cnt = nullptr, *rk = nullptr;
-    XS_TRY(scratch(s, SLOT_RING_CNT, sizeof(int32_t) * (nb * R + 2 * R + 1), &cnt));
+    XS_TRY(scratch(s, SLOT_RING_CNT,
+                   sizeof(int32_t) * (nb * R + R + (levels + 1) * (R + 1) + (R + 1)), &cnt));
     XS_TRY(scratch(s, SLOT_RING_LIST, sizeof(int32_t) * 2 * std::max<int64_t>(n_q, 1), &rk));
     int32_t *c = static_cast<int32_t *>(cnt);
     int32_t *tot = c + nb * R;
-    int32_t *start = tot + R;
-    int32_t *rank = static_cast<int32_t *>(rk);
-    int32_t *list = rank + std::max<int64_t>(n_q, 1);
+    P->lev = tot + R;
+    P->grp = P->lev + (levels + 1) * (R + 1);
+    P->start = P->lev;
+    P->rank = static_cast<int32_t *>(rk);
+    P->list = P->rank + std::max<int64_t>(n_q, 1);
+    P->levels = levels;
     if (n_q > 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(blocks_for(n_q), 4096u)), dim3(kBlock), 0, s,
-                           rank, n_q, -1);
+                           P->rank, n_q, -1);
         hipLaunchKernelGGL(k_part_count, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, key, n_q, R, c);
     }
     hipLaunchKernelGGL(k_part_scan_ring, dim3(static_cast<unsigned>(R)), dim3(kBlock), 0, s, c, nb, R, tot);
-    hipLaunchKernelGGL(k_part_start, dim3(1), dim3(kBlock), 0, s, tot, R, start);
+    hipLaunchKernelGGL(k_tree_offsets, dim3(1), dim3(64), 0, s, tot, R, levels, kLvChunksPerBlock, P->lev,
+                       P->grp);
     if (n_q > 0)
         hipLaunchKernelGGL(k_part_rank, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, key, n_q, R, c,
-                           start, rank, list);
+                           P->start, P->rank, P->list);
     XS_HIP(hipGetLastError());
-    *start_out = start;
-    *rank_out = rank;
-    *list_out = list;
     return XS_OK;
 }
 
-// Column tile width for k_ring_columns: 64, halved while the grid stays within
-// the blocks the device holds at once, so short tables still spread their
-// (long, sequential) ring chains over the whole chip.
-int column_tile(const void *kernel, int64_t K, int32_t R, int min_width) {
-    const int64_t slots = resident_blocks(kernel, kBlock);
-    auto blocks = [&](int w) { return static_cast<int64_t>(R) * ((K + w - 1) / w); };
-    int W = kColTile;
-    while (W / 2 >= min_width && blocks(W) < slots && blocks(W / 2) <= slots) W /= 2;
-    return W;
-}
-
-dim3 column_grid(int64_t K, int32_t R, int W) {
-    return dim3(static_cast<unsigned>((K + W - 1) / W), static_cast<unsigned>(R));
+// Reduce tree level `from` (rows of ncol in `a`) to the top level (one row per
+// ring); `a` and `b` alternate as input and output.  Returns the top's buffer.
+double *reduce_tree(hipStream_t s, const Partition &P, int32_t R, int from, int64_t n_q, int64_t ncol, double *a,
+                    double *b) {
+    double *in = a, *out = b;
+    for (int l = from; l < P.levels; ++l) {
+        const int64_t n_out = level_bound(n_q, R, l + 1);
+        hipLaunchKernelGGL(k_group_tree, dim3(blocks_for(n_out * ncol)), dim3(kBlock), 0, s, in, out, ncol,
+                           P.lev + static_cast<int64_t>(l) * (R + 1), P.lev + static_cast<int64_t>(l + 1) * (R + 1),
+                           R);
+        std::swap(in, out);
+    }
+    return in;
 }
 
 }  // namespace
@@ -584,10 +658,11 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
     const int32_t R = edges.n_rings;
     void *tok = nullptr;
     timer_begin(s, TIMER_G2, &tok);
-    void *key = nullptr, *G = nullptr, *den = nullptr;
+    void *key = nullptr, *G = nullptr, *G2 = nullptr, *den = nullptr;
     XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
     XS_TRY(scratch(s, SLOT_PIXEL2, sizeof(double) * std::max<int64_t>(n_q, 1), &den));
     XS_TRY(scratch(s, SLOT_G, sizeof(double) * std::max<int64_t>(n_q * n_tau, 1), &G));
+    XS_TRY(scratch(s, SLOT_LEVEL_B, sizeof(double) * level_bound(n_q, R, 1) * n_tau, &G2));
     int32_t *k = static_cast<int32_t *>(key);
     double *dn = static_cast<double *>(den);
     if (n_q > 0) {
@@ -595,8 +670,8 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
         hipLaunchKernelGGL(k_pixel_mean, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, I, F, n_q, k, dn);
         XS_HIP(hipGetLastError());
     }
-    int32_t *start = nullptr, *rank = nullptr, *list = nullptr;
-    XS_TRY(partition(s, k, n_q, R, &start, &rank, &list));
+    Partition P;
+    XS_TRY(partition(s, k, n_q, R, &P));
     if (n_q > 0) {
         // pixels per block for the LDS path: largest power of two <= 64 with the
         // series in at most 64 KiB
@@ -606,19 +681,19 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
             const size_t lds = sizeof(double) * (F << lpw);
             const int64_t pw = int64_t(1) << lpw;
             hipLaunchKernelGGL(k_g2_lags, dim3(static_cast<unsigned>((n_q + pw - 1) / pw)), dim3(kBlock), lds, s,
-                               I, static_cast<int32_t>(F), n_q, n_tau, static_cast<int32_t>(lpw), rank, dn,
+                               I, static_cast<int32_t>(F), n_q, n_tau, static_cast<int32_t>(lpw), P.rank, dn,
                                static_cast<double *>(G));
         } else {
             const int64_t n_lb = (n_tau + kLagBlock - 1) / kLagBlock;
             hipLaunchKernelGGL(k_g2_lags_global, dim3(blocks_for(n_q * n_lb)), dim3(kBlock), 0, s, I, F, n_q,
-                               n_tau, rank, dn, static_cast<double *>(G));
+                               n_tau, P.rank, dn, static_cast<double *>(G));
         }
         XS_HIP(hipGetLastError());
     }
-    const int W = column_tile(reinterpret_cast<const void *>(k_ring_mean), n_tau, R, 1);
-    hipLaunchKernelGGL(k_ring_mean, column_grid(n_tau, R, W), dim3(kBlock), 0, s,
-                       static_cast<const double *>(G), static_cast<int64_t>(n_tau), W, start, g2_out,
-                       ring_count);
+    // ring sums: pairwise tree over the rank-ordered rows of G
+    const double *top = reduce_tree(s, P, R, 0, n_q, n_tau, static_cast<double *>(G), static_cast<double *>(G2));
+    hipLaunchKernelGGL(k_g2_finish, dim3(blocks_for(static_cast<int64_t>(R) * n_tau)), dim3(kBlock), 0, s, top,
+                       n_tau, R, P.start, P.lev + static_cast<int64_t>(P.levels) * (R + 1), g2_out, ring_count);
     timer_end(s, TIMER_G2, tok, static_cast<double>(F) * n_q * sizeof(double));
     XS_HIP(hipGetLastError());
     return XS_OK;
@@ -643,11 +718,12 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
     int32_t *k = static_cast<int32_t *>(key);
     if (n_q > 0)
         hipLaunchKernelGGL(k_ring_key, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, q, n_q, edges, k);
-    int32_t *start = nullptr, *rank = nullptr, *list = nullptr;
-    XS_TRY(partition(s, k, n_q, R, &start, &rank, &list));
+    Partition P;
+    XS_TRY(partition(s, k, n_q, R, &P));
     const int64_t rows = std::max<int64_t>(n_q, 1);  // bounds the pixels in rings
+    const int64_t groups_bound = level_bound(n_q, R, 1) / kLvChunksPerBlock + R + 1;
     const double *src = nullptr;
-    // launches of kLvDepth levels each; a launch that does not reach the last
+    // launch groups of kLvDepth levels; a group that does not reach the last
     // level writes the level after its own into a ring-ordered table
     int64_t K = F;
     int pong = 0;
@@ -661,18 +737,51 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
             dst = static_cast<double *>(nx);
             pong ^= 1;
         }
+        const int64_t tiles = (K + kLvTile - 1) / kLvTile;
+        const int64_t ncol = tiles * kLvCols;
+        void *t1 = nullptr, *t2 = nullptr, *mu = nullptr;
+        XS_TRY(scratch(s, SLOT_G, sizeof(double) * level_bound(n_q, R, 1) * ncol, &t1));
+        XS_TRY(scratch(s, SLOT_PIXEL2, sizeof(double) * level_bound(n_q, R, 2) * ncol, &t2));
+        XS_TRY(scratch(s, SLOT_PSETS, sizeof(double) * static_cast<int64_t>(R) * ncol, &mu));
+        double *c1 = static_cast<double *>(t1), *c2 = static_cast<double *>(t2), *m = static_cast<double *>(mu);
         LevelOut lo{};
         for (int32_t d = 0; d < depths; ++d) {
             lo.bwin[d] = bw + off[L + d];
             lo.K[d] = K >> d;
         }
-        const dim3 grid(static_cast<unsigned>((K + kLvTile - 1) / kLvTile), static_cast<unsigned>(R));
-        if (L == 0)
-            hipLaunchKernelGGL(k_xsvs_levels<true>, grid, dim3(kBlock), 0, s, I, K, n_q,
-                               static_cast<const int32_t *>(list), start, depths, lo, dst);
-        else
-            hipLaunchKernelGGL(k_xsvs_levels<false>, grid, dim3(kBlock), 0, s, src, K, K,
-                               static_cast<const int32_t *>(nullptr), start, depths, lo, dst);
+        const dim3 grid(static_cast<unsigned>(groups_bound), static_cast<unsigned>(tiles));
+        const int32_t *lev1 = P.lev + (R + 1);
+        const int32_t *top_off = P.lev + static_cast<int64_t>(P.levels) * (R + 1);
+        for (int pass = 0; pass < 2; ++pass) {
+            if (L == 0) {
+                if (pass == 0)
+                    hipLaunchKernelGGL((k_xsvs_chunks<true, false>), grid, dim3(kBlock), 0, s, I, K, n_q,
+                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp, m, ncol, c1,
+                                       dst);
+                else
+                    hipLaunchKernelGGL((k_xsvs_chunks<true, true>), grid, dim3(kBlock), 0, s, I, K, n_q,
+                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp, m, ncol, c1,
+                                       static_cast<double *>(nullptr));
+            } else {
+                if (pass == 0)
+                    hipLaunchKernelGGL((k_xsvs_chunks<false, false>), grid, dim3(kBlock), 0, s, src, K, K,
+                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp, m, ncol,
+                                       c1, dst);
+                else
+                    hipLaunchKernelGGL((k_xsvs_chunks<false, true>), grid, dim3(kBlock), 0, s, src, K, K,
+                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp, m, ncol,
+                                       c1, static_cast<double *>(nullptr));
+            }
+            XS_HIP(hipGetLastError());
+            const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);
+            if (pass == 0)
+                hipLaunchKernelGGL(k_xsvs_mu, dim3(blocks_for(static_cast<int64_t>(R) * ncol)), dim3(kBlock), 0, s,
+                                   top, ncol, R, P.start, top_off, m);
+            else
+                hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * ncol)), dim3(kBlock), 0,
+                                   s, top, static_cast<const double *>(m), ncol, K, depths, R, P.start, top_off, lo);
+            XS_HIP(hipGetLastError());
+        }
         for (int32_t d = 0; d < depths; ++d)
             hipLaunchKernelGGL(k_xsvs_mean, dim3(static_cast<unsigned>(R)), dim3(kBlock), 0, s,
                                static_cast<const double *>(lo.bwin[d]), K >> d, F, R,

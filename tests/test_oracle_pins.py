@@ -343,3 +343,55 @@ def test_xsvs_erlang_contrast_one_over_w():
         W = 2 ** lvl
         assert abs(beta[lvl, 0] * W - 1.0) < 0.03, (W, beta[lvl, 0])
     assert np.all(oracle.xsvs_contrast(np.full((4, 3), 3.0), q[:3], [0.0, 1.0], 3) == 0.0)
+
+
+def _fma(a, b, c):
+    """a * b + c rounded once (exact rational arithmetic, then one rounding)."""
+    from fractions import Fraction
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def _pairwise_recursive(x):
+    """Sum of x split at the largest power of two below len(x), both parts alike."""
+    n = len(x)
+    if n == 1:
+        return x[0]
+    h = 1 << ((n - 1).bit_length() - 1)
+    return _pairwise_recursive(x[:h]) + _pairwise_recursive(x[h:])
+
+
+def test_ring_sums_follow_the_pairwise_tree():
+    """The ring mean and variance of the XSVS contrast (and the ring mean of g2) are
+    pairwise sums over the ring's pixels in ascending index: one frame of 13 values
+    spanning 16 decades, against the recursive definition bit for bit; a sequential
+    sum gives a different result, so the order is what is tested."""
+    rng = np.random.default_rng(8)
+    vals = [float(v) for v in 10.0 ** rng.uniform(-8, 8, 13)]
+    q = np.array([[0.5, 0.0, 0.0]] * 13 + [[5.0, 0.0, 0.0]])      # last pixel outside the ring
+    I = np.array([vals + [123.0]])
+    n = 13
+    mu = _pairwise_recursive(vals) / n
+    var = _pairwise_recursive([(v - mu) * (v - mu) for v in vals]) / n
+    want = var / (mu * mu)
+    got = oracle.xsvs_contrast(I, q, [0.0, 1.0], 1)[0, 0]
+    assert got == want
+    seq_mu = 0.0
+    for v in vals:
+        seq_mu = seq_mu + v
+    seq_mu /= n
+    assert seq_mu != mu
+    # g2: two frames, lag 0 and 1, G_p from the per-pixel time sums, ring mean pairwise
+    I2 = np.stack([np.array(vals), np.array(vals[::-1]) * 0.5])
+    q2 = q[:13]
+    g2, cnt = oracle.g2_rings(I2, q2, [0.0, 1.0], 2)
+    for tau in range(2):
+        G = []
+        for p in range(13):
+            a, b = I2[0, p], I2[1, p]
+            mean = (a + b) / 2.0
+            if tau == 0:
+                acc = _fma(b, b, _fma(a, a, 0.0))
+                G.append((acc / 2.0) / (mean * mean))
+            else:
+                G.append((_fma(a, b, 0.0) / 1.0) / (mean * mean))
+        assert g2[0, tau] == _pairwise_recursive(G) / 13
