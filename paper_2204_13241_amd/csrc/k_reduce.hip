@@ -175,61 +175,86 @@ __global__ __launch_bounds__(kBlock) void k_part_scan_ring(int32_t *__restrict__
     if (threadIdx.x == 0) tot[r] = carry;
 }
 
-// Offsets of the ring tree, one thread:
+// Offsets of the ring tree, one block (counts in LDS, one thread per ring for
+// the per-ring counts, thread 0 for the running sums):
 //   lev[l][r], l = 0..levels, r = 0..R: first element of ring r at tree level l
 //   (level 0: the ring's pixels, the ring starts; level l + 1 has ceil(n / 32)
 //   of level l's n elements per ring);
 //   grp[r], r = 0..R: first block group (chunk_groups level-1 chunks) of ring r.
-__global__ void k_tree_offsets(const int32_t *__restrict__ tot, int32_t R, int32_t levels,
-                               int32_t chunk_groups, int32_t *__restrict__ lev, int32_t *__restrict__ grp) {
-    if (threadIdx.x != 0) return;
-    int32_t run = 0;
-    for (int r = 0; r < R; ++r) {
-        lev[r] = run;
-        run += tot[r];
-    }
-    lev[R] = run;
-    for (int l = 1; l <= levels; ++l) {
-        int32_t acc = 0;
-        for (int r = 0; r < R; ++r) {
-            const int32_t n = lev[(l - 1) * (R + 1) + r + 1] - lev[(l - 1) * (R + 1) + r];
-            lev[l * (R + 1) + r] = acc;
-            acc += (n + kGroup - 1) / kGroup;
+__global__ __launch_bounds__(kBlock) void k_tree_offsets(const int32_t *__restrict__ tot, int32_t R,
+                                                         int32_t levels, int32_t chunk_groups,
+                                                         int32_t *__restrict__ lev, int32_t *__restrict__ grp) {
+    __shared__ int32_t n_s[kMaxRings], c1_s[kMaxRings], o_s[kMaxRings + 1];
+    for (int r = threadIdx.x; r < R; r += kBlock) n_s[r] = tot[r];
+    // step l <= levels: tree level l; step levels + 1: block groups of level 1
+    for (int l = 0; l <= levels + 1; ++l) {
+        __syncthreads();
+        if (l > 0)
+            for (int r = threadIdx.x; r < R; r += kBlock) {
+                if (l <= levels) {
+                    n_s[r] = (n_s[r] + kGroup - 1) / kGroup;
+                    if (l == 1) c1_s[r] = n_s[r];
+                } else {
+                    n_s[r] = (c1_s[r] + chunk_groups - 1) / chunk_groups;
+                }
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t acc = 0;
+            for (int r = 0; r < R; ++r) {
+                o_s[r] = acc;
+                acc += n_s[r];
+            }
+            o_s[R] = acc;
         }
-        lev[l * (R + 1) + R] = acc;
+        __syncthreads();
+        int32_t *dst = l <= levels ? lev + static_cast<int64_t>(l) * (R + 1) : grp;
+        for (int r = threadIdx.x; r <= R; r += kBlock) dst[r] = o_s[r];
     }
-    int32_t g = 0;
-    for (int r = 0; r < R; ++r) {
-        grp[r] = g;
-        const int32_t n1 = lev[(R + 1) + r + 1] - lev[(R + 1) + r];
-        g += (n1 + chunk_groups - 1) / chunk_groups;
-    }
-    grp[R] = g;
 }
 
 // Stable ranks: the pixels of ring r get ranks ring_start[r], ring_start[r] + 1, ...
-// in ascending pixel index, and list[rank[p]] = p.  Thread r walks the block's
-// keys in order.
+// in ascending pixel index, and list[rank[p]] = p.  Wave w of the block takes
+// pixels [256 w, 256 w + 256) of the block's 1024 in four steps of 64: lanes of
+// one key are found with a ballot per distinct key, ranked by their position
+// in the ballot, and the wave's per-ring running counts kept in LDS; the
+// counts of the earlier waves then give each wave's starting offsets.
 __global__ __launch_bounds__(kBlock) void k_part_rank(const int32_t *__restrict__ key, int64_t n_q,
                                                       int32_t R, const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ ring_start,
                                                       int32_t *__restrict__ rank, int32_t *__restrict__ list) {
-    __shared__ int32_t k_s[kPartChunk];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kPartChunk;
-    for (int i = threadIdx.x; i < kPartChunk; i += kBlock) {
-        const int64_t p = base + i;
-        k_s[i] = p < n_q ? key[p] : -1;
+    constexpr int kWaves = kBlock / 64, kSteps = kPartChunk / kBlock;
+    __shared__ int32_t run[kWaves][kMaxRings];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = lane; r < R; r += 64) run[wave][r] = 0;
+    __syncthreads();
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kPartChunk + static_cast<int64_t>(wave) * (64 * kSteps);
+    int32_t k[kSteps], within[kSteps];
+    for (int st = 0; st < kSteps; ++st) {
+        const int64_t p = base + st * 64 + lane;
+        k[st] = p < n_q ? key[p] : -1;
+        within[st] = 0;
+        uint64_t todo = __ballot(k[st] >= 0);
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const int kk = __shfl(k[st], leader);
+            const uint64_t same = __ballot(k[st] == kk);
+            if (k[st] == kk)
+                within[st] = run[wave][kk] + __builtin_popcountll(same & ((uint64_t(1) << lane) - 1));
+            __builtin_amdgcn_wave_barrier();
+            if (lane == leader) run[wave][kk] += __builtin_popcountll(same);
+            __builtin_amdgcn_wave_barrier();
+            todo &= ~same;
+        }
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < R; r += kBlock) {
-        int32_t o = ring_start[r] + off[static_cast<int64_t>(blockIdx.x) * R + r];
-#pragma unroll 8
-        for (int i = 0; i < kPartChunk; ++i)
-            if (k_s[i] == r) {
-                rank[base + i] = o;
-                list[o] = static_cast<int32_t>(base + i);
-                ++o;
-            }
+    for (int st = 0; st < kSteps; ++st) {
+        const int64_t p = base + st * 64 + lane;
+        if (k[st] < 0) continue;
+        int32_t o = ring_start[k[st]] + off[static_cast<int64_t>(blockIdx.x) * R + k[st]] + within[st];
+        for (int w = 0; w < wave; ++w) o += run[w][k[st]];
+        rank[p] = o;
+        list[o] = static_cast<int32_t>(p);
     }
 }
 
@@ -627,7 +652,7 @@ xs_status partition(hipStream_t s, const int32_t *key, int64_t n_q, int32_t R, P
         hipLaunchKernelGGL(k_part_count, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, key, n_q, R, c);
     }
     hipLaunchKernelGGL(k_part_scan_ring, dim3(static_cast<unsigned>(R)), dim3(kBlock), 0, s, c, nb, R, tot);
-    hipLaunchKernelGGL(k_tree_offsets, dim3(1), dim3(64), 0, s, tot, R, levels, kLvChunksPerBlock, P->lev,
+    hipLaunchKernelGGL(k_tree_offsets, dim3(1), dim3(kBlock), 0, s, tot, R, levels, kLvChunksPerBlock, P->lev,
                        P->grp);
     if (n_q > 0)
         hipLaunchKernelGGL(k_part_rank, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, key, n_q, R, c,
