@@ -39,6 +39,7 @@ TRANS_LANES = 32
 PEAK_TRANS = CUS * CLOCK * TRANS_LANES          # transcendental lane-ops/s
 PEAK_SINCOS_PAIRS = PEAK_TRANS / 2.0           # pairs/s with one sin + one cos each
 PEAK_HBM = 8.0e12                              # bytes/s
+PEAK_FMA64 = CUS * CLOCK * 64                  # FP64 FMA lane-ops/s (78.6 TFLOP/s)
 
 
 def alu_peak(n_valu, n_trans):
@@ -316,8 +317,11 @@ def run_grad(args):
 def run_reductions(args):
     """g2 (trajectory shape: 200 frames x 256^2 pixels, 32 rings, 100 lags) and XSVS
     (XSVS shape: 1024 frames x 1024^2 pixels, 64 rings, W = 1..256) on seeded synthetic
-    exponential intensities already in GPU memory; achieved GB/s = intensity bytes
-    read once / call duration (HIP events)."""
+    exponential intensities already in GPU memory, whole calls timed with HIP events.
+    g2 is FP64-FMA work (over the pixels inside the rings and lags tau < n_tau, F - tau
+    products each) on 105 MB of intensities: its roofline is the FP64 FMA rate.  XSVS
+    reads the in-ring intensities twice (mean, then variance, as the two-pass
+    definition prescribes): its roofline is HBM."""
     import torch
     from paper_2204_13241_amd import api, inputs
     out = {}
@@ -331,6 +335,7 @@ def run_reductions(args):
         call = (lambda: api.g2_rings(I, q, edges, kw["n_tau"])) if name == "g2" else \
                (lambda: api.xsvs_contrast(I, q, edges, kw["n_levels"]))
         call()
+        used = int(api.g2_rings(I[:2], q, edges, 1)[1].sum())   # pixels inside the rings
         torch.cuda.synchronize()
         api.timing_enable(True)
         for _ in range(args.red_reps):
@@ -339,11 +344,25 @@ def run_reductions(args):
         rec = api.timing_read(name)
         api.timing_enable(False)
         ms = rec["ms"] / max(rec["launches"], 1)
-        nbytes = F * q.shape[0] * 8
-        out[name] = {"frames": F, "pixels": int(q.shape[0]), "rings": rings, **kw, "avg_ms": ms,
-                     "intensity_bytes": nbytes, "achieved_GB_s": nbytes / (ms * 1e-3) / 1e9,
-                     "peak_GB_s": PEAK_HBM / 1e9, "frac": nbytes / (ms * 1e-3) / PEAK_HBM}
-        log("%s: %.3f ms, %.0f GB/s" % (name, ms, out[name]["achieved_GB_s"]))
+        Qn = int(q.shape[0])
+        nbytes = F * used * 8
+        rec = {"frames": F, "pixels": Qn, "pixels_in_rings": used, "rings": rings, **kw,
+               "avg_ms": ms, "intensity_bytes": nbytes}
+        if name == "g2":
+            nt = kw["n_tau"]
+            fma = used * (nt * F - nt * (nt - 1) // 2)
+            ach = fma / (ms * 1e-3)
+            rec.update({"bound": "fp64", "fma_per_call": fma, "achieved_TFMA_s": ach / 1e12,
+                        "peak_TFMA_s": PEAK_FMA64 / 1e12, "frac": ach / PEAK_FMA64,
+                        "intensity_GB_s": nbytes / (ms * 1e-3) / 1e9})
+            log("g2: %.3f ms, %.2f TFMA/s (%.1f%% of FP64 FMA)" % (ms, ach / 1e12, 100 * ach / PEAK_FMA64))
+        else:
+            alg = 2 * nbytes
+            rec.update({"bound": "hbm", "algorithmic_bytes": alg, "achieved_GB_s": alg / (ms * 1e-3) / 1e9,
+                        "peak_GB_s": PEAK_HBM / 1e9, "frac": alg / (ms * 1e-3) / PEAK_HBM})
+            log("xsvs: %.3f ms, %.0f GB/s of two intensity reads (%.1f%% of HBM)"
+                % (ms, rec["achieved_GB_s"], 100 * rec["frac"]))
+        out[name] = rec
         del I
         torch.cuda.empty_cache()
     return out
