@@ -16,6 +16,8 @@ Functions (each cites the passage it follows in ``xs_oracle.c``):
 - ``ring_index``         |q| shells of Sec. 2.3 Eq. (bq_Iq)
 - ``g2_rings``           Sec. 2.3 Eq. (g2_def), ring mean of Sec. 4.2
 - ``xsvs_contrast``      Sec. 2.3 Eqs. (inte_Iq), (bq_Iq), dyadic exposure windows
+- ``isf_rings``          Sec. 2.3 Eq. (Fq_pq), ring mean of Sec. 4.2
+- ``siegert``            Sec. 2.3 Eqs. (bq_g2), (norm_Fq), (g2_from_fq), (beta_alt_int)
 """
 from __future__ import annotations
 
@@ -65,6 +67,8 @@ def _load():
         "or_ring_index": (c_int, [i64, P, i32, P, P]),
         "or_g2_rings": (c_int, [P, i64, i64, P, P, i32, i32, P, P, c_int]),
         "or_xsvs_contrast": (c_int, [P, i64, i64, P, P, i32, i32, P, P, c_int]),
+        "or_isf_rings": (c_int, [P, i64, i64, P, P, i32, i32, d, P, P, c_int]),
+        "or_siegert": (c_int, [P, P, i32, i32, i32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -212,3 +216,36 @@ def xsvs_contrast(I, q, edges, n_levels: int, threads: int = 0, want_windows: bo
                                     int(n_levels), _ptr(beta), _ptr(win), int(threads)),
            "xsvs_contrast")
     return (beta, win) if want_windows else beta
+
+
+def isf_rings(amp, q, edges, n_tau: int, f2_sum: float, threads: int = 0):
+    """F(q, tau) per ring [n_rings, n_tau, 2] (re, im) and pixel counts [n_rings]
+    from amplitudes amp [F, Q, 2]."""
+    amp = _f64(amp, 2)
+    if amp.ndim != 3:
+        raise ValueError("amp must be [frames, pixels, 2]")
+    q = _f64(q, 3).reshape(-1, 3)
+    edges = _f64(edges).reshape(-1)
+    nr = edges.shape[0] - 1
+    F = np.empty((nr, n_tau, 2))
+    cnt = np.empty(nr, dtype=np.int32)
+    _check(_load().or_isf_rings(_ptr(amp), amp.shape[0], amp.shape[1], _ptr(q), _ptr(edges), nr,
+                                int(n_tau), float(f2_sum), _ptr(F), _ptr(cnt), int(threads)),
+           "isf_rings")
+    return F, cnt
+
+
+def siegert(g2, F, n_levels: int):
+    """(lhs, fhat2, beta_pred): (g2 - 1) / beta0 and |F-hat|^2 [n_rings, n_tau], and the
+    contrast predicted from F-hat for W = 1, 2, ..., 2^(n_levels-1) [n_levels, n_rings]."""
+    g2 = _f64(g2)
+    F = _f64(F, 2)
+    nr, nt = g2.shape
+    if F.shape != (nr, nt, 2):
+        raise ValueError("F must be [n_rings, n_tau, 2] matching g2")
+    lhs = np.empty((nr, nt))
+    fh = np.empty((nr, nt))
+    beta = np.empty((n_levels, nr))
+    _check(_load().or_siegert(_ptr(g2), _ptr(F), nr, nt, int(n_levels), _ptr(lhs), _ptr(fh),
+                              _ptr(beta)), "siegert")
+    return lhs, fh, beta

@@ -545,3 +545,116 @@ int or_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const doubl
     free(ring); free(J); free(cnt); free(start); free(list); free(bufs);
     return OR_OK;
 }
+
+/*
+ * Intermediate scattering function on |q| rings, Sec. 2.3 Eq. (Fq_pq) with the
+ * ring average of Sec. 4.2:
+ *   per pixel  F_p(tau) = [ sum_{t < F-tau} p_t conj(p_{t+tau}) / (F - tau) ] / sum_j f_j^2,
+ *              p_t = a_t + i b_t, the amplitude of Eq. (pe_ri) in frame t, so
+ *              p_t conj(p_{t+tau}) = (a_t a_{t+tau} + b_t b_{t+tau})
+ *                                  + i (b_t a_{t+tau} - a_t b_{t+tau});
+ *   per ring   F(r, tau) = mean of F_p(tau) over every pixel of the ring (real
+ *              and imaginary parts separately).
+ * amp: [F][Q][2] (a, b).  f2_sum = sum_j f_j^2 > 0.  Fixed order: for each t
+ * ascending, re = fma(a_t, a_{t+tau}, re), re = fma(b_t, b_{t+tau}, re),
+ * im = fma(b_t, a_{t+tau}, im), im = fma(-a_t, b_{t+tau}, im), from +0.0;
+ * F_p = (sum / (F - tau)) / f2_sum; ring sums pairwise (or_pairwise) in
+ * ascending pixel index, then / n.  Empty rings give NaN.
+ * F_out: [n_rings][n_tau][2]; count (may be NULL): [n_rings].
+ */
+int or_isf_rings(const double *amp, int64_t n_frames, int64_t n_q, const double *q,
+                 const double *edges, int32_t n_rings, int32_t n_tau, double f2_sum,
+                 double *F_out, int32_t *count, int n_threads)
+{
+    if (n_frames <= 0 || n_q < 0 || n_rings <= 0 || n_tau <= 0 || n_tau > n_frames ||
+        !(f2_sum > 0.0) || !isfinite(f2_sum) || !F_out)
+        return OR_EINVAL;
+    int32_t *ring = malloc(sizeof(int32_t) * (size_t)(n_q > 0 ? n_q : 1));
+    double *Fp = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1) * (size_t)n_tau * 2);
+    if (!ring || !Fp) { free(ring); free(Fp); return OR_ENOMEM; }
+    int rc = or_ring_index(n_q, q, n_rings, edges, ring);
+    if (rc != OR_OK) { free(ring); free(Fp); return rc; }
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t p = 0; p < n_q; ++p) {
+        for (int32_t tau = 0; tau < n_tau; ++tau) {
+            double re = 0.0, im = 0.0;
+            for (int64_t t = 0; t + tau < n_frames; ++t) {
+                const double a0 = amp[2 * (t * n_q + p)], b0 = amp[2 * (t * n_q + p) + 1];
+                const double a1 = amp[2 * ((t + tau) * n_q + p)], b1 = amp[2 * ((t + tau) * n_q + p) + 1];
+                re = fma(a0, a1, re);
+                re = fma(b0, b1, re);
+                im = fma(b0, a1, im);
+                im = fma(-a0, b1, im);
+            }
+            const double nt = (double)(n_frames - tau);
+            Fp[(p * n_tau + tau) * 2] = (re / nt) / f2_sum;
+            Fp[(p * n_tau + tau) * 2 + 1] = (im / nt) / f2_sum;
+        }
+    }
+    int64_t *start = NULL, *list = NULL;
+    rc = or_ring_lists(n_q, ring, NULL, n_rings, &start, &list);
+    if (rc != OR_OK) { free(ring); free(Fp); return rc; }
+    double *buf = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1));
+    if (!buf) { free(ring); free(Fp); free(start); free(list); return OR_ENOMEM; }
+    for (int32_t r = 0; r < n_rings; ++r) {
+        const int64_t cnt = start[r + 1] - start[r];
+        if (count) count[r] = (int32_t)cnt;
+        for (int32_t tau = 0; tau < n_tau; ++tau)
+            for (int c = 0; c < 2; ++c) {
+                double mean = NAN;
+                if (cnt > 0) {
+                    for (int64_t m = 0; m < cnt; ++m) buf[m] = Fp[(list[start[r] + m] * n_tau + tau) * 2 + c];
+                    mean = or_pairwise(buf, cnt) / (double)cnt;
+                }
+                F_out[((int64_t)r * n_tau + tau) * 2 + c] = mean;
+            }
+    }
+    free(ring); free(Fp); free(start); free(list); free(buf);
+    return OR_OK;
+}
+
+/*
+ * Siegert relation and the exposure contrast it predicts, Sec. 2.3
+ * Eqs. (bq_g2), (norm_Fq), (g2_from_fq), (beta_alt_int), per ring r:
+ *   beta0(r)      = g2(r, 0) - 1                          Eq. (bq_g2)
+ *   lhs(r, tau)   = (g2(r, tau) - 1) / beta0(r)           measured side of Eq. (g2_from_fq)
+ *   fhat2(r, tau) = |F(r, tau)|^2 / |F(r, 0)|^2           |F-hat|^2, Eq. (norm_Fq)
+ *   beta(l, r)    = beta0(r) * (1 + 2 s) / W,  W = 2^l,
+ *                   s = sum_{k=1}^{W-1} (1 - k/W) fhat2(r, k)
+ * The last line is Eq. (beta_alt_int) for an exposure that is the sum of W
+ * consecutive frames (the rectangle rule of Eq. (inte_Iq)): the variance of
+ * the window sum is the double sum of the frame covariances, and the Siegert
+ * relation gives each as <I>^2 beta0 |F-hat(k)|^2 at lag k.
+ * |z|^2 = fma(re, re, im*im); s by fma over k = 1, 2, ..., from +0.0, with
+ * the exact weight 1 - k/W; 1 + 2 s as fma(2, s, 1).
+ * g2: [R][n_tau]; F: [R][n_tau][2]; lhs, fhat2: [R][n_tau]; beta_pred:
+ * [n_levels][R]; needs 2^(n_levels-1) <= n_tau.
+ */
+int or_siegert(const double *g2, const double *F, int32_t n_rings, int32_t n_tau,
+               int32_t n_levels, double *lhs, double *fhat2, double *beta_pred)
+{
+    if (n_rings <= 0 || n_tau <= 0 || n_levels < 0 || n_levels > 30 ||
+        (n_levels > 0 && ((int64_t)1 << (n_levels - 1)) > n_tau) || !g2 || !F)
+        return OR_EINVAL;
+    for (int32_t r = 0; r < n_rings; ++r) {
+        const double beta0 = g2[(int64_t)r * n_tau] - 1.0;
+        const double *Fr = F + (int64_t)r * n_tau * 2;
+        const double f0 = fma(Fr[0], Fr[0], Fr[1] * Fr[1]);
+        for (int32_t tau = 0; tau < n_tau; ++tau) {
+            if (lhs) lhs[(int64_t)r * n_tau + tau] = (g2[(int64_t)r * n_tau + tau] - 1.0) / beta0;
+            if (fhat2)
+                fhat2[(int64_t)r * n_tau + tau] =
+                    fma(Fr[2 * tau], Fr[2 * tau], Fr[2 * tau + 1] * Fr[2 * tau + 1]) / f0;
+        }
+        for (int32_t l = 0; l < n_levels && beta_pred; ++l) {
+            const int64_t W = (int64_t)1 << l;
+            double s = 0.0;
+            for (int64_t k = 1; k < W; ++k) {
+                const double fh = fma(Fr[2 * k], Fr[2 * k], Fr[2 * k + 1] * Fr[2 * k + 1]) / f0;
+                s = fma(1.0 - (double)k / (double)W, fh, s);
+            }
+            beta_pred[(int64_t)l * n_rings + r] = beta0 * fma(2.0, s, 1.0) / (double)W;
+        }
+    }
+    return OR_OK;
+}

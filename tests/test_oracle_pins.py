@@ -395,3 +395,173 @@ def test_ring_sums_follow_the_pairwise_tree():
             else:
                 G.append((_fma(a, b, 0.0) / 1.0) / (mean * mean))
         assert g2[0, tau] == _pairwise_recursive(G) / 13
+
+
+# ---------------------------------------------------------------- intermediate scattering function
+
+def test_isf_constant_velocity_closed_form():
+    """One atom moving at constant velocity: p_t = f exp(-i q.(r0 + v t)), so
+    p_t conj(p_{t+tau}) / f^2 = exp(+i q.v tau) for every t (Eq. (Fq_pq)); the ring
+    value is the mean of that over the ring's pixels.  Checks the conjugated factor
+    (the sign of Im F) and the lag index."""
+    rng = np.random.default_rng(31)
+    F, Q, f = 9, 7, 2.5
+    q = rng.uniform(-1.0, 1.0, (Q, 3))
+    r0, v = rng.uniform(-5, 5, 3), rng.uniform(-0.3, 0.3, 3)
+    amp = np.empty((F, Q, 2))
+    for t in range(F):
+        for p in range(Q):
+            z = f * mp.expj(-mp.fdot([mp.mpf(float(c)) for c in q[p]],
+                                     [mp.mpf(float(c)) for c in r0 + v * t]))
+            amp[t, p] = float(z.real), float(z.imag)
+    Fr, cnt = oracle.isf_rings(amp, q, [0.0, 10.0], 6, f * f)
+    assert cnt[0] == Q
+    for tau in range(6):
+        want = sum(mp.expj(mp.fdot([mp.mpf(float(c)) for c in q[p]],
+                                   [mp.mpf(float(c)) for c in v * tau])) for p in range(Q)) / Q
+        assert abs(Fr[0, tau, 0] - float(want.real)) < 1e-14
+        assert abs(Fr[0, tau, 1] - float(want.imag)) < 1e-14
+
+
+def test_isf_matches_the_double_sum_over_atom_positions():
+    """Eq. (Fq_pq) from the oracle's amplitudes against Eq. (fq_def_pos) summed
+    directly over atom pairs i, j and frames (long-double numpy), several f_j."""
+    rng = np.random.default_rng(32)
+    N, F, Q = 5, 6, 4
+    f = np.array([1.0, 2.5, 0.5, 1.5, 3.0])
+    traj = rng.uniform(0, 12, (F, N, 3))
+    q = rng.normal(size=(Q, 3)) * 0.6
+    amp = np.stack([oracle.intensity(traj[t], f, q)[1] for t in range(F)])
+    f2 = float(np.sum(f * f))
+    Fr, _ = oracle.isf_rings(amp, q, [0.0, 100.0], 4, f2)
+    for tau in range(4):
+        tot = 0j
+        for p in range(Q):
+            acc = 0j
+            for t in range(F - tau):
+                d = traj[t][:, None, :] - traj[t + tau][None, :, :]        # r_i(t) - r_j(t+tau)
+                acc += np.sum(f[:, None] * f[None, :] * np.exp(-1j * (d @ q[p])))
+            tot += acc / (F - tau) / f2
+        want = tot / Q
+        assert abs(Fr[0, tau, 0] - want.real) < 1e-12 * max(1.0, abs(want))
+        assert abs(Fr[0, tau, 1] - want.imag) < 1e-12 * max(1.0, abs(want))
+
+
+def test_isf_at_zero_lag_is_the_mean_intensity_over_sum_f2():
+    """F(q, 0) = <I>_t / sum f^2 (Eq. (Fq_pq) with tau = 0, Eq. (Iq_pq)); Im F(q, 0) is
+    only the rounding residue of b a - a b."""
+    rng = np.random.default_rng(33)
+    amp = rng.normal(size=(20, 30, 2)) * 3.0
+    q = np.tile([[0.3, 0, 0]], (30, 1))
+    Fr, _ = oracle.isf_rings(amp, q, [0.0, 1.0], 3, 7.0)
+    I = amp[..., 0] ** 2 + amp[..., 1] ** 2
+    assert abs(Fr[0, 0, 0] - I.mean(axis=0).mean() / 7.0) < 1e-14 * Fr[0, 0, 0]
+    assert abs(Fr[0, 0, 1]) < 1e-15 * Fr[0, 0, 0]
+
+
+def test_isf_fixed_summation_order():
+    """Per pixel: for t ascending, re = fma(a, a', re), fma(b, b', re); im = fma(b, a', im),
+    fma(-a, b', im); then / (F - tau) / sum f^2; ring: pairwise in pixel order.  Bit for bit
+    against the same sequence with fma emulated exactly."""
+    rng = np.random.default_rng(34)
+    F, Q = 5, 3
+    amp = rng.normal(size=(F, Q, 2)) * 10.0 ** rng.uniform(-3, 3, (F, Q, 1))
+    q = np.tile([[0.2, 0, 0]], (Q, 1))
+    Fr, _ = oracle.isf_rings(amp, q, [0.0, 1.0], 3, 3.0)
+    for tau in range(3):
+        vals = [[], []]
+        for p in range(Q):
+            re = im = 0.0
+            for t in range(F - tau):
+                a0, b0 = amp[t, p]
+                a1, b1 = amp[t + tau, p]
+                re = _fma(a0, a1, re)
+                re = _fma(b0, b1, re)
+                im = _fma(b0, a1, im)
+                im = _fma(-a0, b1, im)
+            vals[0].append((re / (F - tau)) / 3.0)
+            vals[1].append((im / (F - tau)) / 3.0)
+        assert Fr[0, tau, 0] == _pairwise_recursive(vals[0]) / Q
+        assert Fr[0, tau, 1] == _pairwise_recursive(vals[1]) / Q
+
+
+def test_isf_brownian_ideal_gas_decays_as_exp_minus_d_q2_tau():
+    """Non-interacting atoms with Gaussian steps (variance 2 D dt per component and
+    frame, unwrapped): F-hat(q, tau) = exp(-D q^2 tau dt) (Eq. (fq_exp)); statistical,
+    200 pixels on the |q| = 1 sphere, 400 frames."""
+    rng = np.random.default_rng(21)
+    N, L, F, Q, Ddt = 200, 30.0, 400, 200, 0.05
+    r = rng.uniform(0, L, (N, 3))
+    q = rng.normal(size=(Q, 3))
+    q /= np.linalg.norm(q, axis=1)[:, None]
+    f = np.ones(N)
+    amp = np.empty((F, Q, 2))
+    for t in range(F):
+        amp[t] = oracle.intensity(r, f, q)[1]
+        r = r + np.sqrt(2 * Ddt) * rng.normal(size=(N, 3))
+    Fr, cnt = oracle.isf_rings(amp, q, [0.5, 1.5], 12, float(N))
+    assert cnt[0] == Q
+    tau = np.arange(12)
+    fhat = Fr[0, :, 0] / Fr[0, 0, 0]
+    assert np.all(np.abs(fhat - np.exp(-Ddt * tau)) < 0.02)
+    assert np.all(np.abs(Fr[0, :, 1] / Fr[0, 0, 0]) < 0.01)
+
+
+def test_siegert_closed_forms():
+    """Eq. (beta_alt_int) in its window-sum form: a frozen sample (|F-hat| = 1) keeps
+    beta_W = beta0 exactly; a sample with no memory beyond one frame (F-hat(k) = 0,
+    k >= 1) gives beta0 / W exactly; F-hat(k) = c^k gives the geometric sum (mpmath);
+    (g2 - 1) / beta0 and |F-hat|^2 are 1 at tau = 0."""
+    R, nt, nl = 3, 16, 5
+    g2 = np.array([np.linspace(1.9, 1.0, nt), np.linspace(1.7, 1.1, nt), np.full(nt, 1.25)])
+    frozen = np.zeros((R, nt, 2))
+    frozen[..., 0] = 2.5
+    lhs, fh, bp = oracle.siegert(g2, frozen, nl)
+    beta0 = g2[:, 0] - 1.0
+    assert np.all(bp == beta0[None, :])
+    assert np.all(fh == 1.0) and np.all(lhs[:, 0] == 1.0)
+    white = np.zeros((R, nt, 2))
+    white[:, 0, 0] = 4.0
+    _, fh, bp = oracle.siegert(g2, white, nl)
+    assert np.all(fh[:, 1:] == 0.0)
+    for lvl in range(nl):
+        assert np.all(bp[lvl] == beta0 / 2 ** lvl)
+    c = 0.83
+    geo = np.zeros((R, nt, 2))
+    geo[..., 0] = c ** np.arange(nt)
+    geo[..., 1] = 0.0
+    _, fh, bp = oracle.siegert(g2, geo, nl)
+    for lvl in range(nl):
+        W = 2 ** lvl
+        s = sum((1 - mp.mpf(k) / W) * mp.mpf(c) ** (2 * k) for k in range(1, W))
+        want = (1 + 2 * s) / W
+        assert np.allclose(bp[lvl] / beta0, float(want), rtol=1e-14)
+
+
+def test_siegert_holds_for_a_gaussian_field():
+    """A circular complex Gaussian amplitude, AR(1) in time with coefficient rho, is the
+    case the Siegert relation Eq. (g2_from_fq) is derived for: (g2 - 1) / beta0 and
+    |F-hat|^2 both follow rho^(2 tau), and the contrast of W-frame windows (Eqs. (inte_Iq),
+    (bq_Iq)) matches the prediction of Eq. (beta_alt_int).  Statistical, 4000 pixels x
+    512 frames; the finite-series bias of g2 (about -var(<I>_t) / <I>^2) is within the bound."""
+    rng = np.random.default_rng(22)
+    F, Q, rho = 512, 4000, 0.8
+    p = np.empty((F, Q), complex)
+    p[0] = (rng.normal(size=Q) + 1j * rng.normal(size=Q)) / np.sqrt(2)
+    for t in range(1, F):
+        p[t] = rho * p[t - 1] + np.sqrt(1 - rho ** 2) * (rng.normal(size=Q) + 1j * rng.normal(size=Q)) / np.sqrt(2)
+    amp = np.stack([p.real, p.imag], -1)
+    I = np.abs(p) ** 2
+    q = np.tile([[0.5, 0, 0]], (Q, 1))
+    g2, _ = oracle.g2_rings(I, q, [0.0, 1.0], 16)
+    Fr, _ = oracle.isf_rings(amp, q, [0.0, 1.0], 16, 1.0)
+    lhs, fh, bp = oracle.siegert(g2, Fr, 5)
+    model = rho ** (2 * np.arange(16))
+    assert np.all(np.abs(fh[0] - model) < 0.01)
+    assert np.all(np.abs(lhs[0] - model) < 0.03)
+    beta = oracle.xsvs_contrast(I, q, [0.0, 1.0], 5)
+    for lvl in range(5):
+        W = 2 ** lvl
+        exact = (1 + 2 * sum((1 - k / W) * rho ** (2 * k) for k in range(1, W))) / W
+        assert abs(bp[lvl, 0] / exact - 1) < 0.03
+        assert abs(beta[lvl, 0] / exact - 1) < 0.03
