@@ -319,7 +319,8 @@ def run_reductions(args):
     (XSVS shape: 1024 frames x 1024^2 pixels, 64 rings, W = 1..256) on seeded synthetic
     exponential intensities already in GPU memory, whole calls timed with HIP events.
     g2 is FP64-FMA work (over the pixels inside the rings and lags tau < n_tau, F - tau
-    products each) on 105 MB of intensities: its roofline is the FP64 FMA rate.  XSVS
+    products each) on 105 MB of intensities: its roofline is the FP64 FMA rate; F(q, tau)
+    (same shape, complex amplitudes, 4 FMA per product) likewise.  XSVS
     reads the in-ring intensities twice (mean, then variance, as the two-pass
     definition prescribes): its roofline is HBM."""
     import torch
@@ -327,15 +328,21 @@ def run_reductions(args):
     out = {}
     gen = torch.Generator(device="cuda:0")
     for name, F, n_det, q_max, rings, kw in (("g2", 200, 256, 1.5, 32, {"n_tau": 100}),
+                                            ("isf", 200, 256, 1.5, 32, {"n_tau": 100}),
                                             ("xsvs", 1024, 1024, 2.0, 64, {"n_levels": 9})):
         gen.manual_seed(2024)
         q = torch.as_tensor(inputs.ewald_detector(n_det, q_max), dtype=torch.float64, device="cuda:0")
-        I = torch.empty((F, q.shape[0]), dtype=torch.float64, device="cuda:0").exponential_(1.0, generator=gen)
         edges = inputs.ring_edges(rings, q_max)
-        call = (lambda: api.g2_rings(I, q, edges, kw["n_tau"])) if name == "g2" else \
-               (lambda: api.xsvs_contrast(I, q, edges, kw["n_levels"]))
+        if name == "isf":
+            I = torch.empty((F, q.shape[0], 2), dtype=torch.float64, device="cuda:0").normal_(generator=gen)
+            call = lambda: api.isf_rings(I, q, edges, kw["n_tau"], 1.0)
+        else:
+            I = torch.empty((F, q.shape[0]), dtype=torch.float64, device="cuda:0").exponential_(1.0, generator=gen)
+            call = (lambda: api.g2_rings(I, q, edges, kw["n_tau"])) if name == "g2" else \
+                   (lambda: api.xsvs_contrast(I, q, edges, kw["n_levels"]))
         call()
-        used = int(api.g2_rings(I[:2], q, edges, 1)[1].sum())   # pixels inside the rings
+        used = int(api.isf_rings(I, q, edges, 1, 1.0)[1].sum()) if name == "isf" else \
+            int(api.g2_rings(I[:2], q, edges, 1)[1].sum())   # pixels inside the rings
         torch.cuda.synchronize()
         api.timing_enable(True)
         for _ in range(args.red_reps):
@@ -345,17 +352,17 @@ def run_reductions(args):
         api.timing_enable(False)
         ms = rec["ms"] / max(rec["launches"], 1)
         Qn = int(q.shape[0])
-        nbytes = F * used * 8
+        nbytes = F * used * (16 if name == "isf" else 8)
         rec = {"frames": F, "pixels": Qn, "pixels_in_rings": used, "rings": rings, **kw,
                "avg_ms": ms, "intensity_bytes": nbytes}
-        if name == "g2":
+        if name in ("g2", "isf"):
             nt = kw["n_tau"]
-            fma = used * (nt * F - nt * (nt - 1) // 2)
+            fma = used * (nt * F - nt * (nt - 1) // 2) * (4 if name == "isf" else 1)
             ach = fma / (ms * 1e-3)
             rec.update({"bound": "fp64", "fma_per_call": fma, "achieved_TFMA_s": ach / 1e12,
                         "peak_TFMA_s": PEAK_FMA64 / 1e12, "frac": ach / PEAK_FMA64,
-                        "intensity_GB_s": nbytes / (ms * 1e-3) / 1e9})
-            log("g2: %.3f ms, %.2f TFMA/s (%.1f%% of FP64 FMA)" % (ms, ach / 1e12, 100 * ach / PEAK_FMA64))
+                        "input_GB_s": nbytes / (ms * 1e-3) / 1e9})
+            log("%s: %.3f ms, %.2f TFMA/s (%.1f%% of FP64 FMA)" % (name, ms, ach / 1e12, 100 * ach / PEAK_FMA64))
         else:
             alg = 2 * nbytes
             rec.update({"bound": "hbm", "algorithmic_bytes": alg, "achieved_GB_s": alg / (ms * 1e-3) / 1e9,

@@ -149,8 +149,10 @@ xs_status xs_intensity_grad(const xs_batch *b, const double *pos, const double *
  *   g2_out     device double [n_rings][n_tau]; NaN for rings with no pixel
  *   ring_count device int32 [n_rings] pixels used per ring, or NULL
  * Pixels whose <I>_t^2 is zero are left out.  Every sum has a fixed order
- * (time sums sequential in t; ring sums sequential in ascending pixel index),
- * so the result is bit-for-bit reproducible and equal to the oracle's.
+ * (time sums sequential in t; ring sums pairwise over the ring's pixels in
+ * ascending index: adjacent pairs added level by level, an odd last element
+ * carried up), so the result is bit-for-bit reproducible and equal to the
+ * oracle's.
  */
 xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
                       const double *ring_edges, int32_t n_rings, int32_t n_tau,
@@ -175,6 +177,48 @@ xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const doub
 xs_status xs_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const double *q,
                            const double *ring_edges, int32_t n_rings, int32_t n_levels,
                            double *beta_out, double *beta_win, void *stream);
+
+/*
+ * Intermediate scattering function on |q| rings, Sec. 2.3 Eq. (Fq_pq), with
+ * the per-pixel-then-ring-mean average used for g2 (Sec. 4.2):
+ *     F_p(tau) = [sum_{t < F - tau} p_t,p conj(p_t+tau,p) / (F - tau)] / f2_sum,
+ *     F(r, tau) = mean over every pixel p of ring r of F_p(tau),
+ * with p = a + i b the amplitude of Eq. (pe_ri) as xs_intensity_direct writes
+ * it.  F-hat of Eq. (norm_Fq) is F(r, tau) / F(r, 0).
+ *   amp        device double [n_frames][n_q][2] (a, b), 16-byte aligned
+ *   q, ring_edges, n_rings, n_tau as for xs_g2_rings
+ *   f2_sum     sum_j f_j^2 of the sample (> 0, finite)
+ *   F_out      device double [n_rings][n_tau][2] (re, im); NaN for empty rings
+ *   ring_count device int32 [n_rings] pixels per ring, or NULL
+ * Fixed order: for t ascending, re = fma(a_t, a_t+tau, re), fma(b_t, b_t+tau, re);
+ * im = fma(b_t, a_t+tau, im), fma(-a_t, b_t+tau, im); ring sums pairwise as
+ * for xs_g2_rings.  Bit-for-bit equal to the oracle.
+ */
+xs_status xs_isf_rings(const double *amp, int64_t n_frames, int64_t n_q, const double *q,
+                       const double *ring_edges, int32_t n_rings, int32_t n_tau, double f2_sum,
+                       double *F_out, int32_t *ring_count, void *stream);
+
+/*
+ * Siegert relation and the exposure contrast it predicts, Sec. 2.3
+ * Eqs. (bq_g2), (norm_Fq), (g2_from_fq), (beta_alt_int), per ring r:
+ *     beta0(r)       = g2(r, 0) - 1
+ *     lhs(r, tau)    = (g2(r, tau) - 1) / beta0(r)     (equals |F-hat|^2 when
+ *                                                       the relation holds)
+ *     fhat2(r, tau)  = |F(r, tau)|^2 / |F(r, 0)|^2
+ *     beta(l, r)     = beta0(r) (1 + 2 sum_{k=1}^{W-1} (1 - k/W) fhat2(r, k)) / W,
+ *                      W = 2^l: Eq. (beta_alt_int) for exposures that are sums
+ *                      of W consecutive frames, comparable with
+ *                      xs_xsvs_contrast's beta_out[l].
+ *   g2         device double [n_rings][n_tau] (xs_g2_rings)
+ *   F          device double [n_rings][n_tau][2] (xs_isf_rings)
+ *   n_levels   0 <= n_levels, 2^(n_levels-1) <= n_tau
+ *   lhs_out, fhat2_out  device double [n_rings][n_tau], or NULL
+ *   beta_out   device double [n_levels][n_rings] (may be NULL if n_levels = 0)
+ * |z|^2 = fma(re, re, im * im); the sum over k runs k = 1, 2, ... by fma.
+ * Bit-for-bit equal to the oracle.
+ */
+xs_status xs_siegert(const double *g2, const double *F, int32_t n_rings, int32_t n_tau, int32_t n_levels,
+                     double *lhs_out, double *fhat2_out, double *beta_out, void *stream);
 
 /* Thread-local message for the last non-OK status returned to this thread. */
 const char *xs_last_error(void);
@@ -289,10 +333,11 @@ xs_status xs_position_step(double *pos, const float *dL_dr, const double *dL_dr6
  * xs_timing_enable(1) clears the counters and starts recording; (0) stops.
  * xs_timing_read(kind) waits for the recorded events and returns the summed
  * duration (ms), number of launches and work (atom-pixel pairs for kinds 0-3,
- * atoms for 4, intensity bytes read for 5-6) since enabling.
+ * atoms for 4, input bytes read once for 5-7) since enabling.
  *   kind 0: FP32C forward pair kernel   1: FP32C gradient pair kernel
  *        2: FP64 forward kernel         3: FP64 gradient kernel
  *        4: FP32C binning               5: g2 call     6: XSVS call
+ *        7: xs_isf_rings call
  */
 xs_status xs_timing_enable(int32_t on);
 xs_status xs_timing_read(int32_t kind, double *total_ms, int64_t *launches, double *work);

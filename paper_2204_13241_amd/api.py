@@ -227,6 +227,37 @@ def xsvs_contrast(I: torch.Tensor, q: torch.Tensor, edges, n_levels: int,
     return (beta, win) if return_windows else beta
 
 
+def isf_rings(amp: torch.Tensor, q: torch.Tensor, edges, n_tau: int, f2_sum: float):
+    """F(q, tau) per ring [n_rings, n_tau, 2] (float64: re, im) from amplitudes
+    amp [F, Q, 2], and the pixel count per ring (int32)."""
+    _need(amp, "amp"), _need(q, "q")
+    if amp.dim() != 3 or amp.shape[2] != 2 or q.shape != (amp.shape[1], 3):
+        raise ValueError("amp must be [F, Q, 2] and q [Q, 3]")
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    R = e.shape[0] - 1
+    F = torch.empty((R, n_tau, 2), dtype=torch.float64, device=amp.device)
+    cnt = torch.empty(R, dtype=torch.int32, device=amp.device)
+    _lib.check(_lib.load().xs_isf_rings(_ptr(amp), amp.shape[0], amp.shape[1], _ptr(q),
+                                        e.ctypes.data_as(ctypes.c_void_p), R, int(n_tau), float(f2_sum),
+                                        _ptr(F), _ptr(cnt), _stream()))
+    return F, cnt
+
+
+def siegert(g2: torch.Tensor, F: torch.Tensor, n_levels: int):
+    """(lhs, fhat2, beta): (g2 - 1) / beta0 and |F-hat|^2 [n_rings, n_tau], and the
+    contrast predicted from F-hat for W = 1, 2, ..., 2^(n_levels-1) [n_levels, n_rings]."""
+    _need(g2, "g2"), _need(F, "F")
+    if g2.dim() != 2 or F.shape != (g2.shape[0], g2.shape[1], 2):
+        raise ValueError("g2 must be [R, n_tau] and F [R, n_tau, 2]")
+    R, nt = g2.shape
+    lhs = torch.empty((R, nt), dtype=torch.float64, device=g2.device)
+    fh = torch.empty((R, nt), dtype=torch.float64, device=g2.device)
+    beta = torch.empty((n_levels, R), dtype=torch.float64, device=g2.device)
+    _lib.check(_lib.load().xs_siegert(_ptr(g2), _ptr(F), R, nt, int(n_levels), _ptr(lhs), _ptr(fh),
+                                      _ptr(beta) if n_levels > 0 else None, _stream()))
+    return lhs, fh, beta
+
+
 def get_tile_shape(kind: int) -> dict:
     s = _lib.XsTileShape()
     _lib.check(_lib.load().xs_get_tile_shape(int(kind), ctypes.byref(s)))
@@ -298,7 +329,7 @@ def position_step(pos: torch.Tensor, grad: torch.Tensor, step: float):
                                             float(step), _stream()))
 
 
-TIMER_KINDS = {"fwd32": 0, "grad32": 1, "fwd64": 2, "grad64": 3, "bin": 4, "g2": 5, "xsvs": 6}
+TIMER_KINDS = {"fwd32": 0, "grad32": 1, "fwd64": 2, "grad64": 3, "bin": 4, "g2": 5, "xsvs": 6, "isf": 7}
 
 
 def timing_enable(on: bool = True):

@@ -31,6 +31,7 @@ constexpr int kLvStride = 2 * kLvTile + 1;  // LDS row: 127 windows of 7 levels,
 constexpr int kLvCols = 2 * kLvTile;        // chunk-sum columns per tile (126 used)
 constexpr int kLvLoads = kLvRows * kLvTile / kBlock;
 constexpr int kLvChunksPerBlock = 4;        // consecutive chunks of one ring per block
+constexpr int kXcds = 8;                    // accelerator complex dies (one L2 each)
 static_assert(kLvRows * 8 == kBlock && kLvTile == 64 && (1 << kLvDepth) == kLvTile,
               "XSVS level kernel: thread (row, group of 8 windows) covers one chunk");
 
@@ -38,9 +39,14 @@ unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) /
 
 // ---------------------------------------------------------------- pairwise tree
 
-// Complete tree over 2^K values v(st), v(st + 1), ...
+// Complete tree over 2^K values v(st), v(st + 1), ...  Above 16 values the
+// two halves are summed one after the other (the same tree, half the registers).
 template <int K, typename Load>
 __device__ __forceinline__ double complete_tree(int st, const Load &v) {
+    if constexpr (K > 4) {
+        const double lo = complete_tree<K - 1>(st, v);
+        return lo + complete_tree<K - 1>(st + (1 << (K - 1)), v);
+    }
     double x[1 << K];
 #pragma unroll
     for (int i = 0; i < (1 << K); ++i) x[i] = v(st + i);
@@ -260,6 +266,31 @@ __global__ __launch_bounds__(kBlock) void k_part_rank(const int32_t *__restrict_
 
 // ---------------------------------------------------------------- g2
 
+// Stage the time series of pixels p0 .. p0 + 2^lpw - 1 in LDS:
+// lds[t * 2^lpw + pp] = src[t * n_q + p0 + pp] (zero past n_q).  Each thread
+// issues U loads before it writes, so a block waits for ceil(F 2^lpw / (256 U))
+// memory round trips rather than one per element.
+template <int U, typename T>
+__device__ __forceinline__ void stage_series(T *lds, const T *__restrict__ src, int F, int lpw, int64_t n_q,
+                                             int64_t p0) {
+    const int n = F << lpw, pmask = (1 << lpw) - 1;
+    for (int base = 0; base < n; base += kBlock * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + static_cast<int>(threadIdx.x);
+            const int t = i >> lpw;
+            const int64_t p = p0 + (i & pmask);
+            v[u] = (i < n && p < n_q) ? src[static_cast<int64_t>(t) * n_q + p] : T{};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * kBlock + static_cast<int>(threadIdx.x);
+            if (i < n) lds[i] = v[u];
+        }
+    }
+}
+
 // Per pixel: S = sum_t I_t (sequential), mean = S / F, den = mean^2; pixels
 // with den = 0 leave the ring partition (key -1).
 __global__ __launch_bounds__(kBlock) void k_pixel_mean(const double *__restrict__ I, int64_t F,
@@ -289,11 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags(const double *__restrict__ I
     extern __shared__ double lds[];
     const int pw = 1 << lpw;
     const int64_t p0 = static_cast<int64_t>(blockIdx.x) * pw;
-    for (int i = threadIdx.x; i < F * pw; i += kBlock) {
-        const int t = i >> lpw, pp = i & (pw - 1);
-        const int64_t p = p0 + pp;
-        lds[i] = p < n_q ? I[static_cast<int64_t>(t) * n_q + p] : 0.0;
-    }
+    stage_series<16>(lds, I, F, lpw, n_q, p0);
     __syncthreads();
     const int pp = threadIdx.x & (pw - 1);
     const int slot = threadIdx.x >> lpw, n_slots = kBlock >> lpw;
@@ -374,19 +401,163 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags_global(const double *__restr
     }
 }
 
-// g2 ring mean from the tree's top level: g2[r][tau] = total / n (NaN for an
-// empty ring), count[r] = n.
-__global__ __launch_bounds__(kBlock) void k_g2_finish(const double *__restrict__ top, int32_t n_tau,
-                                                      int32_t R, const int32_t *__restrict__ ring_start,
-                                                      const int32_t *__restrict__ top_off,
-                                                      double *__restrict__ g2, int32_t *__restrict__ count) {
+// Ring means from the tree's top level (rows of ncol columns): out[r][c] =
+// total / n (NaN for an empty ring), count[r] = n.
+__global__ __launch_bounds__(kBlock) void k_ring_mean_finish(const double *__restrict__ top, int64_t ncol,
+                                                             int32_t R, const int32_t *__restrict__ ring_start,
+                                                             const int32_t *__restrict__ top_off,
+                                                             double *__restrict__ out, int32_t *__restrict__ count) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= static_cast<int64_t>(R) * n_tau) return;
-    const int r = static_cast<int>(i / n_tau), tau = static_cast<int>(i - static_cast<int64_t>(r) * n_tau);
+    if (i >= static_cast<int64_t>(R) * ncol) return;
+    const int r = static_cast<int>(i / ncol);
+    const int64_t c = i - static_cast<int64_t>(r) * ncol;
     const int32_t n = ring_start[r + 1] - ring_start[r];
-    g2[i] = n > 0 ? top[static_cast<int64_t>(top_off[r]) * n_tau + tau] / static_cast<double>(n)
-                  : __builtin_nan("");
-    if (count && tau == 0) count[r] = n;
+    out[i] = n > 0 ? top[static_cast<int64_t>(top_off[r]) * ncol + c] / static_cast<double>(n)
+                   : __builtin_nan("");
+    if (count && c == 0) count[r] = n;
+}
+
+// ---------------------------------------------------------------- F(q, tau)
+
+// Rows of the per-pixel intermediate scattering function, Eq. (Fq_pq):
+// G[rank[p]][tau] = (re, im) of [sum_{t < F - tau} p_t conj(p_{t+tau}) / (F - tau)] / f2,
+// p_t = a_t + i b_t, accumulated for t = 0, 1, ... as
+//   re = fma(a_t, a_{t+tau}, re), re = fma(b_t, b_{t+tau}, re),
+//   im = fma(b_t, a_{t+tau}, im), im = fma(-a_t, b_{t+tau}, im).
+// Staging and lag blocking as in k_g2_lags, with the complex series in LDS.
+__device__ __forceinline__ void isf_step(double2 x, double2 y, double &re, double &im) {
+    re = __builtin_fma(x.x, y.x, re);
+    re = __builtin_fma(x.y, y.y, re);
+    im = __builtin_fma(x.y, y.x, im);
+    im = __builtin_fma(-x.x, y.y, im);
+}
+
+__device__ __forceinline__ void isf_store(double *G, int32_t row, int32_t n_tau, int tau, int F, double f2,
+                                          double re, double im) {
+    const double nt = static_cast<double>(F - tau);
+    double *g = G + (static_cast<int64_t>(row) * n_tau + tau) * 2;
+    g[0] = (re / nt) / f2;
+    g[1] = (im / nt) / f2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_isf_lags(const double2 *__restrict__ amp, int32_t F, int64_t n_q,
+                                                     int32_t n_tau, int32_t lpw, const int32_t *__restrict__ rank,
+                                                     double f2, double *__restrict__ G) {
+    extern __shared__ double2 lds2[];
+    const int pw = 1 << lpw;
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * pw;
+    stage_series<8>(lds2, amp, F, lpw, n_q, p0);
+    __syncthreads();
+    const int pp = threadIdx.x & (pw - 1);
+    const int slot = threadIdx.x >> lpw, n_slots = kBlock >> lpw;
+    const int64_t p = p0 + pp;
+    if (p >= n_q) return;
+    const int32_t row = rank[p];
+    if (row < 0) return;
+    const int n_lb = (n_tau + kLagBlock - 1) / kLagBlock;
+    for (int lb = slot; lb < n_lb; lb += n_slots) {
+        const int tau0 = lb * kLagBlock;
+        double re[kLagBlock], im[kLagBlock];
+        double2 y[kLagBlock];
+#pragma unroll
+        for (int j = 0; j < kLagBlock; ++j) {
+            re[j] = 0.0;
+            im[j] = 0.0;
+            y[j] = tau0 + j < F ? lds2[(tau0 + j) * pw + pp] : make_double2(0.0, 0.0);
+        }
+        const int t_main = F - tau0 - kLagBlock;  // t < t_main: lags and the next load in range
+        int t = 0;
+#pragma unroll 4
+        for (; t < t_main; ++t) {
+            const double2 x = lds2[t * pw + pp];
+#pragma unroll
+            for (int j = 0; j < kLagBlock; ++j) isf_step(x, y[j], re[j], im[j]);
+#pragma unroll
+            for (int j = 0; j + 1 < kLagBlock; ++j) y[j] = y[j + 1];
+            y[kLagBlock - 1] = lds2[(t + tau0 + kLagBlock) * pw + pp];
+        }
+        for (; t + tau0 < F; ++t) {
+            const double2 x = lds2[t * pw + pp];
+#pragma unroll
+            for (int j = 0; j < kLagBlock; ++j)
+                if (t + tau0 + j < F) isf_step(x, y[j], re[j], im[j]);
+#pragma unroll
+            for (int j = 0; j + 1 < kLagBlock; ++j) y[j] = y[j + 1];
+            const int nt = t + tau0 + kLagBlock;
+            y[kLagBlock - 1] = nt < F ? lds2[nt * pw + pp] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int j = 0; j < kLagBlock; ++j)
+            if (tau0 + j < n_tau) isf_store(G, row, n_tau, tau0 + j, F, f2, re[j], im[j]);
+    }
+}
+
+// Same lag step reading global memory (series too long for LDS): one thread
+// per (pixel, lag block).
+__global__ __launch_bounds__(kBlock) void k_isf_lags_global(const double2 *__restrict__ amp, int64_t F,
+                                                            int64_t n_q, int32_t n_tau,
+                                                            const int32_t *__restrict__ rank, double f2,
+                                                            double *__restrict__ G) {
+    const int n_lb = (n_tau + kLagBlock - 1) / kLagBlock;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n_q * n_lb) return;
+    const int64_t p = i % n_q;
+    const int lb = static_cast<int>(i / n_q);
+    const int32_t row = rank[p];
+    if (row < 0) return;
+    const int tau0 = lb * kLagBlock;
+    double re[kLagBlock], im[kLagBlock];
+#pragma unroll
+    for (int j = 0; j < kLagBlock; ++j) re[j] = im[j] = 0.0;
+    for (int64_t t = 0; t + tau0 < F; ++t) {
+        const double2 x = amp[t * n_q + p];
+#pragma unroll
+        for (int j = 0; j < kLagBlock; ++j)
+            if (t + tau0 + j < F) isf_step(x, amp[(t + tau0 + j) * n_q + p], re[j], im[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kLagBlock; ++j)
+        if (tau0 + j < n_tau) isf_store(G, row, n_tau, tau0 + j, static_cast<int>(F), f2, re[j], im[j]);
+}
+
+// Siegert relation and the contrast it predicts (Eqs. (bq_g2), (norm_Fq),
+// (g2_from_fq), (beta_alt_int)), per ring r:
+//   beta0 = g2[r][0] - 1,  lhs[r][tau] = (g2[r][tau] - 1) / beta0,
+//   fhat2[r][tau] = |F[r][tau]|^2 / |F[r][0]|^2,  |z|^2 = fma(re, re, im * im),
+//   beta[l][r] = beta0 * fma(2, s, 1) / W,  W = 2^l,
+//   s = sum over k = 1 .. W-1 in order of fma(1 - k / W, fhat2[r][k], s).
+// Threads [0, R n_tau) form lhs and fhat2, the next R n_levels form beta.
+__global__ __launch_bounds__(kBlock) void k_siegert(const double *__restrict__ g2, const double *__restrict__ F,
+                                                    int32_t R, int32_t n_tau, int32_t n_levels,
+                                                    double *__restrict__ lhs, double *__restrict__ fhat2,
+                                                    double *__restrict__ beta) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t n1 = static_cast<int64_t>(R) * n_tau;
+    if (i < n1) {
+        const int r = static_cast<int>(i / n_tau);
+        const double *Fr = F + static_cast<int64_t>(r) * n_tau * 2;
+        const int64_t k = i - static_cast<int64_t>(r) * n_tau;
+        const double beta0 = g2[static_cast<int64_t>(r) * n_tau] - 1.0;
+        if (lhs) lhs[i] = (g2[i] - 1.0) / beta0;
+        if (fhat2) {
+            const double f0 = __builtin_fma(Fr[0], Fr[0], Fr[1] * Fr[1]);
+            fhat2[i] = __builtin_fma(Fr[2 * k], Fr[2 * k], Fr[2 * k + 1] * Fr[2 * k + 1]) / f0;
+        }
+    } else if (beta && i < n1 + static_cast<int64_t>(n_levels) * R) {
+        const int64_t j = i - n1;
+        const int l = static_cast<int>(j / R), r = static_cast<int>(j - static_cast<int64_t>(l) * R);
+        const double *Fr = F + static_cast<int64_t>(r) * n_tau * 2;
+        const double beta0 = g2[static_cast<int64_t>(r) * n_tau] - 1.0;
+        const double f0 = __builtin_fma(Fr[0], Fr[0], Fr[1] * Fr[1]);
+        const int64_t W = int64_t(1) << l;
+        const double w = static_cast<double>(W);
+        double acc = 0.0;
+        for (int64_t k = 1; k < W; ++k) {
+            const double fh = __builtin_fma(Fr[2 * k], Fr[2 * k], Fr[2 * k + 1] * Fr[2 * k + 1]) / f0;
+            acc = __builtin_fma(1.0 - static_cast<double>(k) / w, fh, acc);
+        }
+        beta[static_cast<int64_t>(l) * R + r] = beta0 * __builtin_fma(2.0, acc, 1.0) / w;
+    }
 }
 
 // ---------------------------------------------------------------- XSVS
@@ -405,20 +576,32 @@ __global__ __launch_bounds__(kBlock) void k_g2_finish(const double *__restrict__
 // level L+6 (one window per full tile) to `next` [rank][K >> 6] for the
 // launch that continues from it.
 // kGather: rows gathered from the frames I[k][list[m]] (ld = pixels);
-// otherwise read from a ring-ordered table X[m][k] (ld = K).
+// otherwise read from a ring-ordered table X[m][k] (ld = K).  order (or NULL
+// for block group = blockIdx.x): block groups sorted by their first pixel.
 template <bool kGather, bool kPass2>
 __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
                                                         const int32_t *__restrict__ list, int32_t R,
                                                         const int32_t *__restrict__ ring_start,
                                                         const int32_t *__restrict__ chunk_off,
                                                         const int32_t *__restrict__ grp_off,
+                                                        const int32_t *__restrict__ order,
                                                         const double *__restrict__ mu, int64_t ncol,
                                                         double *__restrict__ csum, double *__restrict__ next) {
     __shared__ double tile[kLvRows * kLvStride];
     __shared__ int32_t g_s[kMaxRings + 1];
     for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
     __syncthreads();
-    const int64_t gb = blockIdx.x;
+    int64_t gb = blockIdx.x;
+    if (order) {
+        // workgroups go to the 8 XCDs round robin (x mod 8 with gridDim.x a
+        // multiple of 8): XCD x takes the x-th eighth of the groups in detector
+        // order, so groups of neighbouring rings that share cache lines run
+        // close together in time on one L2
+        const int64_t G = g_s[R], G8 = (G + kXcds - 1) / kXcds;
+        const int64_t j = blockIdx.x / kXcds, slot = (blockIdx.x % kXcds) * G8 + j;
+        if (j >= G8 || slot >= G) return;  // block-uniform
+        gb = order[slot];
+    }
     if (gb >= g_s[R]) return;  // block-uniform
     const int r = ring_of(g_s, R, gb);
     const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kLvTile;
@@ -460,16 +643,19 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
     };
 
     const int32_t c_end = std::min<int32_t>(n_chunks_ring, c_first + kLvChunksPerBlock);
-    double buf[kLvLoads];
-    int32_t mc = a + c_first * kLvRows;
-    int rows = std::min<int32_t>(kLvRows, b - mc);
-    load_chunk(buf, mc, rows);
-    for (int32_t ch = c_first; ch < c_end; ++ch) {
-        const int32_t mrow = mc;
-        const int crow = rows;
+    auto chunk_rows = [&](int32_t ch) { return std::min<int32_t>(kLvRows, b - (a + ch * kLvRows)); };
+    // two chunks in flight: buffer A carries the even steps, B the odd ones; a
+    // buffer is refilled with the chunk two steps ahead as soon as it is in LDS
+    double bufA[kLvLoads], bufB[kLvLoads];
+    load_chunk(bufA, a + c_first * kLvRows, chunk_rows(c_first));
+    if (c_first + 1 < c_end) load_chunk(bufB, a + (c_first + 1) * kLvRows, chunk_rows(c_first + 1));
+    auto process = [&](double (&buf)[kLvLoads], int32_t ch) {
+        const int32_t mrow = a + ch * kLvRows;
+        const int crow = chunk_rows(ch);
         __syncthreads();  // previous chunk consumed
 #pragma unroll
         for (int i = 0; i < kLvLoads; ++i) tile[(q_t + i * dqi) * kLvStride + c_t + i * dci] = buf[i];
+        if (ch + 2 < c_end) load_chunk(buf, a + (ch + 2) * kLvRows, chunk_rows(ch + 2));
         __syncthreads();
         // coarser levels of the chunk: thread (row q, group g of 8 level-L windows)
         // forms levels L+1..L+3 of its group; the 8 lanes of a row (one wave)
@@ -504,9 +690,6 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
             }
         }
         __syncthreads();
-        mc += crow;
-        rows = std::min<int32_t>(kLvRows, b - mc);
-        if (ch + 1 < c_end) load_chunk(buf, mc, rows);
         if (owner) {
             const double *colp = tile + t;
             const double tr = tree_upto32(crow, [&](int i) {
@@ -517,7 +700,52 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
             });
             csum[static_cast<int64_t>(chunk_off[r] + ch) * ncol + col] = tr;
         }
+    };
+    for (int32_t ch = c_first; ch < c_end; ch += 2) {
+        process(bufA, ch);
+        if (ch + 1 < c_end) process(bufB, ch + 1);
     }
+}
+
+// First pixel of each XSVS block group (group gb of ring r starts at ring
+// element (gb - grp[r]) * kLvChunksPerBlock * kLvRows).
+__global__ __launch_bounds__(kBlock) void k_group_keys(const int32_t *__restrict__ grp_off, int32_t R,
+                                                       const int32_t *__restrict__ ring_start,
+                                                       const int32_t *__restrict__ list, int64_t bound,
+                                                       int32_t *__restrict__ gkey) {
+    __shared__ int32_t g_s[kMaxRings + 1];
+    for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
+    __syncthreads();
+    const int64_t gb = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (gb >= bound || gb >= g_s[R]) return;
+    const int r = ring_of(g_s, R, gb);
+    gkey[gb] = list[ring_start[r] + (gb - g_s[r]) * (kLvChunksPerBlock * kLvRows)];
+}
+
+// Block groups in ascending first pixel: order[rank] = gb, rank = the group's
+// index in its ring plus, for every other ring, its count of groups with a
+// smaller first pixel (each ring's keys ascend; keys are distinct pixels).
+__global__ __launch_bounds__(kBlock) void k_group_order(const int32_t *__restrict__ grp_off, int32_t R,
+                                                        const int32_t *__restrict__ gkey, int64_t bound,
+                                                        int32_t *__restrict__ order) {
+    __shared__ int32_t g_s[kMaxRings + 1];
+    for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
+    __syncthreads();
+    const int64_t gb = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (gb >= bound || gb >= g_s[R]) return;
+    const int r = ring_of(g_s, R, gb);
+    const int32_t key = gkey[gb];
+    int64_t rank = gb - g_s[r];
+    for (int o = 0; o < R; ++o) {
+        if (o == r) continue;
+        int32_t lo = g_s[o], hi = g_s[o + 1];  // first element >= key in [lo, hi)
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (gkey[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        rank += lo - g_s[o];
+    }
+    order[rank] = static_cast<int32_t>(gb);
 }
 
 // Ring means of the pass-1 tree top: mu[r][c] = total / n (0 for an empty ring:
@@ -717,9 +945,63 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
     }
     // ring sums: pairwise tree over the rank-ordered rows of G
     const double *top = reduce_tree(s, P, R, 0, n_q, n_tau, static_cast<double *>(G), static_cast<double *>(G2));
-    hipLaunchKernelGGL(k_g2_finish, dim3(blocks_for(static_cast<int64_t>(R) * n_tau)), dim3(kBlock), 0, s, top,
-                       n_tau, R, P.start, P.lev + static_cast<int64_t>(P.levels) * (R + 1), g2_out, ring_count);
+    hipLaunchKernelGGL(k_ring_mean_finish, dim3(blocks_for(static_cast<int64_t>(R) * n_tau)), dim3(kBlock), 0, s,
+                       top, static_cast<int64_t>(n_tau), R, P.start,
+                       P.lev + static_cast<int64_t>(P.levels) * (R + 1), g2_out, ring_count);
     timer_end(s, TIMER_G2, tok, static_cast<double>(F) * n_q * sizeof(double));
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, const double *q,
+                    const RingEdges &edges, int32_t n_tau, double f2, double *F_out, int32_t *ring_count) {
+    const int32_t R = edges.n_rings;
+    const int64_t ncol = 2 * static_cast<int64_t>(n_tau);
+    void *tok = nullptr;
+    timer_begin(s, TIMER_ISF, &tok);
+    void *key = nullptr, *G = nullptr, *G2 = nullptr;
+    XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
+    XS_TRY(scratch(s, SLOT_G, sizeof(double) * std::max<int64_t>(n_q * ncol, 1), &G));
+    XS_TRY(scratch(s, SLOT_LEVEL_B, sizeof(double) * level_bound(n_q, R, 1) * ncol, &G2));
+    int32_t *k = static_cast<int32_t *>(key);
+    if (n_q > 0) {
+        hipLaunchKernelGGL(k_ring_key, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, q, n_q, edges, k);
+        XS_HIP(hipGetLastError());
+    }
+    Partition P;
+    XS_TRY(partition(s, k, n_q, R, &P));
+    const double2 *a2 = reinterpret_cast<const double2 *>(amp);
+    if (n_q > 0) {
+        // pixels per block for the LDS path: largest power of two <= 64 with the
+        // complex series in at most 64 KiB
+        int lpw = 6;
+        while (lpw > 0 && (F << lpw) * static_cast<int64_t>(sizeof(double2)) > 65536) --lpw;
+        if ((F << lpw) * static_cast<int64_t>(sizeof(double2)) <= 65536) {
+            const size_t lds = sizeof(double2) * (F << lpw);
+            const int64_t pw = int64_t(1) << lpw;
+            hipLaunchKernelGGL(k_isf_lags, dim3(static_cast<unsigned>((n_q + pw - 1) / pw)), dim3(kBlock), lds, s,
+                               a2, static_cast<int32_t>(F), n_q, n_tau, static_cast<int32_t>(lpw), P.rank, f2,
+                               static_cast<double *>(G));
+        } else {
+            const int64_t n_lb = (n_tau + kLagBlock - 1) / kLagBlock;
+            hipLaunchKernelGGL(k_isf_lags_global, dim3(blocks_for(n_q * n_lb)), dim3(kBlock), 0, s, a2, F, n_q,
+                               n_tau, P.rank, f2, static_cast<double *>(G));
+        }
+        XS_HIP(hipGetLastError());
+    }
+    const double *top = reduce_tree(s, P, R, 0, n_q, ncol, static_cast<double *>(G), static_cast<double *>(G2));
+    hipLaunchKernelGGL(k_ring_mean_finish, dim3(blocks_for(static_cast<int64_t>(R) * ncol)), dim3(kBlock), 0, s,
+                       top, ncol, R, P.start, P.lev + static_cast<int64_t>(P.levels) * (R + 1), F_out, ring_count);
+    timer_end(s, TIMER_ISF, tok, static_cast<double>(F) * n_q * sizeof(double2));
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+xs_status siegert(hipStream_t s, const double *g2, const double *F, int32_t R, int32_t n_tau, int32_t n_levels,
+                  double *lhs, double *fhat2, double *beta) {
+    const int64_t n = static_cast<int64_t>(R) * n_tau + static_cast<int64_t>(R) * n_levels;
+    hipLaunchKernelGGL(k_siegert, dim3(blocks_for(n)), dim3(kBlock), 0, s, g2, F, R, n_tau, n_levels, lhs, fhat2,
+                       beta);
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -747,6 +1029,18 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
     XS_TRY(partition(s, k, n_q, R, &P));
     const int64_t rows = std::max<int64_t>(n_q, 1);  // bounds the pixels in rings
     const int64_t groups_bound = level_bound(n_q, R, 1) / kLvChunksPerBlock + R + 1;
+    // block groups in detector order for the launches that gather from the frames
+    void *ord = nullptr;
+    XS_TRY(scratch(s, SLOT_PIXKEYS, sizeof(int32_t) * 2 * groups_bound, &ord));
+    int32_t *gkey = static_cast<int32_t *>(ord), *order = gkey + groups_bound;
+    if (n_q > 0) {
+        hipLaunchKernelGGL(k_group_keys, dim3(blocks_for(groups_bound)), dim3(kBlock), 0, s, P.grp, R, P.start,
+                           static_cast<const int32_t *>(P.list), groups_bound, gkey);
+        hipLaunchKernelGGL(k_group_order, dim3(blocks_for(groups_bound)), dim3(kBlock), 0, s, P.grp, R,
+                           static_cast<const int32_t *>(gkey), groups_bound, order);
+        XS_HIP(hipGetLastError());
+    }
+    const int64_t groups_x = (groups_bound + kXcds - 1) / kXcds * kXcds;
     const double *src = nullptr;
     // launch groups of kLvDepth levels; a group that does not reach the last
     // level writes the level after its own into a ring-ordered table
@@ -774,28 +1068,30 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
             lo.bwin[d] = bw + off[L + d];
             lo.K[d] = K >> d;
         }
-        const dim3 grid(static_cast<unsigned>(groups_bound), static_cast<unsigned>(tiles));
+        const dim3 grid(static_cast<unsigned>(groups_x), static_cast<unsigned>(tiles));
         const int32_t *lev1 = P.lev + (R + 1);
         const int32_t *top_off = P.lev + static_cast<int64_t>(P.levels) * (R + 1);
         for (int pass = 0; pass < 2; ++pass) {
             if (L == 0) {
                 if (pass == 0)
                     hipLaunchKernelGGL((k_xsvs_chunks<true, false>), grid, dim3(kBlock), 0, s, I, K, n_q,
-                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp, m, ncol, c1,
-                                       dst);
+                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
+                                       static_cast<const int32_t *>(order), m, ncol, c1, dst);
                 else
                     hipLaunchKernelGGL((k_xsvs_chunks<true, true>), grid, dim3(kBlock), 0, s, I, K, n_q,
-                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp, m, ncol, c1,
+                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
+                                       static_cast<const int32_t *>(order), m, ncol, c1,
                                        static_cast<double *>(nullptr));
             } else {
                 if (pass == 0)
                     hipLaunchKernelGGL((k_xsvs_chunks<false, false>), grid, dim3(kBlock), 0, s, src, K, K,
-                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp, m, ncol,
-                                       c1, dst);
+                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
+                                       static_cast<const int32_t *>(nullptr), m, ncol, c1, dst);
                 else
                     hipLaunchKernelGGL((k_xsvs_chunks<false, true>), grid, dim3(kBlock), 0, s, src, K, K,
-                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp, m, ncol,
-                                       c1, static_cast<double *>(nullptr));
+                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
+                                       static_cast<const int32_t *>(nullptr), m, ncol, c1,
+                                       static_cast<double *>(nullptr));
             }
             XS_HIP(hipGetLastError());
             const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);

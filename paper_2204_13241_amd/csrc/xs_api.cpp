@@ -342,6 +342,37 @@ xs_status xs_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const
                          beta_out, beta_win);
 }
 
+xs_status xs_isf_rings(const double *amp, int64_t n_frames, int64_t n_q, const double *q,
+                       const double *ring_edges, int32_t n_rings, int32_t n_tau, double f2_sum,
+                       double *F_out, int32_t *ring_count, void *stream) {
+    XS_TRY(begin(stream));
+    if (n_frames < 1) return set_error(XS_EINVAL, "n_frames must be >= 1");
+    if (n_q < 0 || n_q >= (int64_t(1) << 31)) return set_error(XS_EINVAL, "n_q out of range");
+    if (n_tau < 1 || n_tau > n_frames) return set_error(XS_EINVAL, "n_tau must be in [1, n_frames]");
+    if (!(f2_sum > 0.0) || !std::isfinite(f2_sum)) return set_error(XS_EINVAL, "f2_sum must be finite and > 0");
+    if (!F_out) return set_error(XS_EINVAL, "F_out is NULL");
+    if (n_q > 0 && (!amp || !q)) return set_error(XS_EINVAL, "amp / q is NULL");
+    if (n_q > 0 && (reinterpret_cast<uintptr_t>(amp) & 15))
+        return set_error(XS_EINVAL, "amp must be 16-byte aligned");
+    RingEdges e;
+    XS_TRY(read_edges(ring_edges, n_rings, e));
+    return isf_rings(static_cast<hipStream_t>(stream), amp, n_frames, n_q, q, e, n_tau, f2_sum, F_out,
+                     ring_count);
+}
+
+xs_status xs_siegert(const double *g2, const double *F, int32_t n_rings, int32_t n_tau, int32_t n_levels,
+                     double *lhs_out, double *fhat2_out, double *beta_out, void *stream) {
+    XS_TRY(begin(stream));
+    if (n_rings < 1) return set_error(XS_EINVAL, "n_rings must be >= 1");
+    if (n_tau < 1) return set_error(XS_EINVAL, "n_tau must be >= 1");
+    if (n_levels < 0 || n_levels > 30 || (n_levels > 0 && (int64_t(1) << (n_levels - 1)) > n_tau))
+        return set_error(XS_EINVAL, "n_levels must satisfy 0 <= n_levels and 2^(n_levels-1) <= n_tau");
+    if (!g2 || !F) return set_error(XS_EINVAL, "g2 / F is NULL");
+    if (n_levels > 0 && !beta_out) return set_error(XS_EINVAL, "beta_out is NULL with n_levels > 0");
+    return siegert(static_cast<hipStream_t>(stream), g2, F, n_rings, n_tau, n_levels, lhs_out, fhat2_out,
+                   beta_out);
+}
+
 const char *xs_last_error(void) { return g_last_error.c_str(); }
 
 int32_t xs_version(void) { return 100; }

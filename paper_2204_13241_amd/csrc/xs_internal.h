@@ -44,7 +44,7 @@ enum Slot {
     SLOT_RING_KEY,      // reductions: per-pixel ring key
     SLOT_RING_CNT,      // reductions: per-block ring counts / offsets
     SLOT_RING_LIST,     // reductions: ring-order rank of each pixel, ring-ordered pixel list
-    SLOT_G,             // g2 per-pixel values (rows in ring order)
+    SLOT_G,             // g2 / F(q, tau) per-pixel values (rows in ring order)
     SLOT_LEVEL_A,       // XSVS coarser-level window sums (ping)
     SLOT_LEVEL_B,       // XSVS window sums (pong)
     SLOT_BWIN,          // XSVS per-window contrast
@@ -140,6 +140,10 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q
 xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
                         const double *q, const RingEdges &edges, int32_t n_levels,
                         double *beta_out, double *beta_win);
+xs_status isf_rings(hipStream_t s, const double *amp, int64_t n_frames, int64_t n_q, const double *q,
+                    const RingEdges &edges, int32_t n_tau, double f2, double *F_out, int32_t *ring_count);
+xs_status siegert(hipStream_t s, const double *g2, const double *F, int32_t n_rings, int32_t n_tau,
+                  int32_t n_levels, double *lhs, double *fhat2, double *beta);
 
 // ---------------------------------------------------------------- timing
 // Optional HIP-event timing of kernel launches on the stream they run on.
@@ -151,8 +155,9 @@ enum TimerKind {
     TIMER_BIN = 4,     // FP32C binning (all binning kernels of a call)
     TIMER_G2 = 5,      // g2 reduction (whole call)
     TIMER_XSVS = 6,    // XSVS reduction (whole call)
+    TIMER_ISF = 7,     // intermediate scattering function on rings (whole call)
 };
-#define XS_TIMER_KINDS 7
+#define XS_TIMER_KINDS 8
 bool timing_on();
 void timer_begin(hipStream_t s, int kind, void **token);
 void timer_end(hipStream_t s, int kind, void *token, double work);
