@@ -469,10 +469,11 @@ int or_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
  *   exposure integral over W = 2^l frames as non-overlapping windows from
  *   frame 0 (trailing partial window dropped), built pairwise:
  *       J_0[k] = I_k,   J_{l+1}[k] = J_l[2k] + J_l[2k+1],  K_l = floor(F / 2^l);
- *   per (level l, window k, ring r) over the ring's pixels in ascending order:
- *       mu = sum J / n,  var = sum (J - mu)^2 / n  (two-pass; both sums
- *       pairwise, or_pairwise, over the rounded values J and (J - mu)*(J - mu)),
- *       beta = var / mu^2;
+ *   per (level l, window k, ring r) over the ring's pixels in ascending order,
+ *   the moments of Eq. (bq_Iq) as written there:
+ *       m1 = sum J / n,  m2 = sum J^2 / n  (both sums pairwise, or_pairwise,
+ *       over the rounded values J and J*J),
+ *       beta = (m2 - m1^2) / m1^2,  m1^2 rounded once;
  *   beta_out[l][r] = sum_k beta / K_l  (sequential in k).
  * I: [F][Q].  beta_out: [n_levels][n_rings].  beta_win (may be NULL):
  * [n_levels][F][n_rings], entries k >= K_l set to NaN.  Empty rings: NaN.
@@ -521,13 +522,14 @@ int or_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const doubl
                 if (n > 0) {
                     const int64_t *mem = list + start[r];
                     for (int64_t m = 0; m < n; ++m) buf[m] = J[k * n_q + mem[m]];
-                    double mu = or_pairwise(buf, n) / (double)n;
+                    const double m1 = or_pairwise(buf, n) / (double)n;
                     for (int64_t m = 0; m < n; ++m) {
-                        double d = J[k * n_q + mem[m]] - mu;
-                        buf[m] = d * d;
+                        const double x = J[k * n_q + mem[m]];
+                        buf[m] = x * x;
                     }
-                    double var = or_pairwise(buf, n) / (double)n;
-                    b = var / (mu * mu);
+                    const double m2 = or_pairwise(buf, n) / (double)n;
+                    const double sq = m1 * m1;
+                    b = (m2 - sq) / sq;
                 }
                 bw[k * n_rings + r] = b;
             }

@@ -332,6 +332,20 @@ def test_xsvs_hand_example():
     assert np.all(np.isnan(win[1, 2:, 0])) and np.all(np.isnan(win[2, 1:, 0]))
 
 
+def test_xsvs_moments_exact_on_small_integers():
+    """Eq. (bq_Iq) with exactly representable moments: ring values 1, 2, 3, 4 give
+    <I> = 5/2, <I^2> = 15/2, beta = (15/2 - 25/4) / (25/4) = 1/5; the 2-frame windows
+    3, 7, 11, 15 (W = 2) give beta = (101 - 81) / 81."""
+    I = np.array([[1.0, 2.0, 3.0, 4.0], [2.0, 5.0, 8.0, 11.0]])
+    q = np.tile([[0.5, 0, 0]], (4, 1))
+    beta, win = oracle.xsvs_contrast(I, q, [0.0, 1.0], 2, want_windows=True)
+    assert win[0, 0, 0] == 0.2
+    assert win[1, 0, 0] == (101.0 - 81.0) / 81.0
+    # frame 1: values 2, 5, 8, 11: <I> = 13/2, <I^2> = 214/4 = 53.5, beta = (53.5 - 42.25) / 42.25
+    assert win[0, 1, 0] == (53.5 - 42.25) / 42.25
+    assert beta[0, 0] == (0.2 + (53.5 - 42.25) / 42.25) / 2
+
+
 def test_xsvs_erlang_contrast_one_over_w():
     # iid exponential frames: a window of W frames is an Erlang(W) sum, beta = 1/W (Eq. (Erlang))
     rng = np.random.default_rng(14)
@@ -361,7 +375,7 @@ def _pairwise_recursive(x):
 
 
 def test_ring_sums_follow_the_pairwise_tree():
-    """The ring mean and variance of the XSVS contrast (and the ring mean of g2) are
+    """The ring moments of the XSVS contrast (and the ring mean of g2) are
     pairwise sums over the ring's pixels in ascending index: one frame of 13 values
     spanning 16 decades, against the recursive definition bit for bit; a sequential
     sum gives a different result, so the order is what is tested."""
@@ -371,8 +385,8 @@ def test_ring_sums_follow_the_pairwise_tree():
     I = np.array([vals + [123.0]])
     n = 13
     mu = _pairwise_recursive(vals) / n
-    var = _pairwise_recursive([(v - mu) * (v - mu) for v in vals]) / n
-    want = var / (mu * mu)
+    m2 = _pairwise_recursive([v * v for v in vals]) / n
+    want = (m2 - mu * mu) / (mu * mu)
     got = oracle.xsvs_contrast(I, q, [0.0, 1.0], 1)[0, 0]
     assert got == want
     seq_mu = 0.0
