@@ -320,9 +320,9 @@ def run_reductions(args):
     exponential intensities already in GPU memory, whole calls timed with HIP events.
     g2 is FP64-FMA work (over the pixels inside the rings and lags tau < n_tau, F - tau
     products each) on 105 MB of intensities: its roofline is the FP64 FMA rate; F(q, tau)
-    (same shape, complex amplitudes, 4 FMA per product) likewise.  XSVS
-    reads the in-ring intensities twice (mean, then variance, as the two-pass
-    definition prescribes): its roofline is HBM."""
+    (same shape, complex amplitudes, 4 FMA per product) likewise.  XSVS reads the
+    in-ring intensities once (both moments of Eq. (bq_Iq) from one read): its
+    roofline is HBM."""
     import torch
     from paper_2204_13241_amd import api, inputs
     out = {}
@@ -364,10 +364,10 @@ def run_reductions(args):
                         "input_GB_s": nbytes / (ms * 1e-3) / 1e9})
             log("%s: %.3f ms, %.2f TFMA/s (%.1f%% of FP64 FMA)" % (name, ms, ach / 1e12, 100 * ach / PEAK_FMA64))
         else:
-            alg = 2 * nbytes
+            alg = nbytes
             rec.update({"bound": "hbm", "algorithmic_bytes": alg, "achieved_GB_s": alg / (ms * 1e-3) / 1e9,
                         "peak_GB_s": PEAK_HBM / 1e9, "frac": alg / (ms * 1e-3) / PEAK_HBM})
-            log("xsvs: %.3f ms, %.0f GB/s of two intensity reads (%.1f%% of HBM)"
+            log("xsvs: %.3f ms, %.0f GB/s of in-ring intensities read once (%.1f%% of HBM)"
                 % (ms, rec["achieved_GB_s"], 100 * rec["frac"]))
         out[name] = rec
         del I

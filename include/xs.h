@@ -163,8 +163,8 @@ xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const doub
  * exposure windows of W = 2^l frames (l = 0 .. n_levels-1), non-overlapping
  * from frame 0, trailing partial window dropped, window sums built pairwise
  * (J_{l+1}[k] = J_l[2k] + J_l[2k+1]);
- *     beta(l, k, r) = var_r(J_l[k]) / mean_r(J_l[k])^2   (population variance,
- *                                                        two-pass),
+ *     beta(l, k, r) = (m2 - m1^2) / m1^2,  m1 = mean_r(J_l[k]),
+ *                     m2 = mean_r(J_l[k]^2)   (the moments of Eq. (bq_Iq), read once),
  *     beta_out[l][r] = mean over the K_l = floor(F / 2^l) windows.
  *   I          device double [n_frames][n_q]
  *   q, ring_edges, n_rings as for xs_g2_rings

@@ -28,7 +28,8 @@ constexpr int kLvTile = 64;       // XSVS: base windows per block
 constexpr int kLvDepth = 6;       // XSVS: levels per launch (base and 5 coarser)
 constexpr int kLvRows = kGroup;   // XSVS: ring rows per staged chunk (one tree group)
 constexpr int kLvStride = 2 * kLvTile + 1;  // LDS row: 127 windows of 7 levels, odd stride
-constexpr int kLvCols = 2 * kLvTile;        // chunk-sum columns per tile (126 used)
+constexpr int kLvHalf = 2 * kLvTile;        // windows per tile over its 7 levels (126 used)
+constexpr int kLvCols = 2 * kLvHalf;        // chunk-sum columns per tile: sums of J, then of J^2
 constexpr int kLvLoads = kLvRows * kLvTile / kBlock;
 constexpr int kLvChunksPerBlock = 4;        // consecutive chunks of one ring per block
 constexpr int kXcds = 8;                    // accelerator complex dies (one L2 each)
@@ -77,6 +78,55 @@ __device__ __forceinline__ double tree_upto32(int n, const Load &v) {
     if (n & 16) part(complete_tree<4>(end - 16, v), 16);
     if (n & 32) part(complete_tree<5>(end - 32, v), 32);
     return s;
+}
+
+// Complete trees over 2^K values x = v(st + i) and over their rounded squares x * x.
+template <int K, typename Load>
+__device__ __forceinline__ void complete_tree2(int st, const Load &v, double &s1, double &s2) {
+    if constexpr (K > 4) {
+        double a1, a2, b1, b2;
+        complete_tree2<K - 1>(st, v, a1, a2);
+        complete_tree2<K - 1>(st + (1 << (K - 1)), v, b1, b2);
+        s1 = a1 + b1;
+        s2 = a2 + b2;
+    } else {
+        double x[1 << K], y[1 << K];
+#pragma unroll
+        for (int i = 0; i < (1 << K); ++i) {
+            x[i] = v(st + i);
+            y[i] = x[i] * x[i];
+        }
+#pragma unroll
+        for (int w = (1 << K) / 2; w >= 1; w >>= 1)
+#pragma unroll
+            for (int i = 0; i < w; ++i) {
+                x[i] = x[2 * i] + x[2 * i + 1];
+                y[i] = y[2 * i] + y[2 * i + 1];
+            }
+        s1 = x[0];
+        s2 = y[0];
+    }
+}
+
+// tree_upto32 of the values and of their rounded squares, in one read.
+template <typename Load>
+__device__ __forceinline__ void tree2_upto32(int n, const Load &v, double &s1, double &s2) {
+    int end = n;
+    bool have = false;
+    auto part = [&](double t1, double t2, int size) {
+        s1 = have ? t1 + s1 : t1;
+        s2 = have ? t2 + s2 : t2;
+        have = true;
+        end -= size;
+    };
+    double t1, t2;
+    s1 = s2 = 0.0;
+    if (n & 1) { complete_tree2<0>(end - 1, v, t1, t2); part(t1, t2, 1); }
+    if (n & 2) { complete_tree2<1>(end - 2, v, t1, t2); part(t1, t2, 2); }
+    if (n & 4) { complete_tree2<2>(end - 4, v, t1, t2); part(t1, t2, 4); }
+    if (n & 8) { complete_tree2<3>(end - 8, v, t1, t2); part(t1, t2, 8); }
+    if (n & 16) { complete_tree2<4>(end - 16, v, t1, t2); part(t1, t2, 16); }
+    if (n & 32) { complete_tree2<5>(end - 32, v, t1, t2); part(t1, t2, 32); }
 }
 
 // Ring of element e from the offsets off[0..R] (off non-decreasing, e < off[R]).
@@ -571,21 +621,20 @@ __global__ __launch_bounds__(kBlock) void k_siegert(const double *__restrict__ g
 //   [124, 126) L+5, [126] L+6,
 // the coarser levels formed by pairwise sums J_{l+1}[j] = J_l[2j] + J_l[2j+1].
 // Thread t < 126 owns column t (one window of one level) and writes the
-// chunk's pairwise tree of its values (pass 1: J; pass 2: (J - mu)^2 with the
-// column's ring mean mu) to csum[chunk][tile * 128 + t].  Pass 1 also writes
-// level L+6 (one window per full tile) to `next` [rank][K >> 6] for the
-// launch that continues from it.
+// chunk's pairwise trees of its values J and of their squares J*J to
+// csum[chunk][tile * 256 + t] and [tile * 256 + 128 + t] (the two moments of
+// Eq. (bq_Iq)).  Level L+6 (one window per full tile) also goes to `next`
+// [rank][K >> 6] for the launch that continues from it.
 // kGather: rows gathered from the frames I[k][list[m]] (ld = pixels);
 // otherwise read from a ring-ordered table X[m][k] (ld = K).  order (or NULL
 // for block group = blockIdx.x): block groups sorted by their first pixel.
-template <bool kGather, bool kPass2>
+template <bool kGather>
 __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
                                                         const int32_t *__restrict__ list, int32_t R,
                                                         const int32_t *__restrict__ ring_start,
                                                         const int32_t *__restrict__ chunk_off,
                                                         const int32_t *__restrict__ grp_off,
-                                                        const int32_t *__restrict__ order,
-                                                        const double *__restrict__ mu, int64_t ncol,
+                                                        const int32_t *__restrict__ order, int64_t ncol,
                                                         double *__restrict__ csum, double *__restrict__ next) {
     __shared__ double tile[kLvRows * kLvStride];
     __shared__ int32_t g_s[kMaxRings + 1];
@@ -611,9 +660,8 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
     const int32_t n_chunks_ring = (b - a + kLvRows - 1) / kLvRows;
     const int t = threadIdx.x;
     const int64_t col = static_cast<int64_t>(blockIdx.y) * kLvCols + t;
-    const bool owner = t < kLvCols - 2;
-    const double m = (kPass2 && owner) ? mu[static_cast<int64_t>(r) * ncol + col] : 0.0;
-    const bool want_next = !kPass2 && next != nullptr && k0 + kLvTile <= K;
+    const bool owner = t < kLvHalf - 2;
+    const bool want_next = next != nullptr && k0 + kLvTile <= K;
     const int64_t K_next = K >> kLvDepth;
 
     // staging map: element i of thread t is (row q_t + i * dqi, column c_t + i * dci)
@@ -692,13 +740,11 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
         __syncthreads();
         if (owner) {
             const double *colp = tile + t;
-            const double tr = tree_upto32(crow, [&](int i) {
-                const double x = colp[i * kLvStride];
-                if (!kPass2) return x;
-                const double d = x - m;
-                return d * d;
-            });
-            csum[static_cast<int64_t>(chunk_off[r] + ch) * ncol + col] = tr;
+            double s1, s2;
+            tree2_upto32(crow, [&](int i) { return colp[i * kLvStride]; }, s1, s2);
+            double *out = csum + static_cast<int64_t>(chunk_off[r] + ch) * ncol + col;
+            out[0] = s1;
+            out[kLvHalf] = s2;
         }
     };
     for (int32_t ch = c_first; ch < c_end; ch += 2) {
@@ -748,20 +794,6 @@ __global__ __launch_bounds__(kBlock) void k_group_order(const int32_t *__restric
     order[rank] = static_cast<int32_t>(gb);
 }
 
-// Ring means of the pass-1 tree top: mu[r][c] = total / n (0 for an empty ring:
-// pass 2 has no chunks there).
-__global__ __launch_bounds__(kBlock) void k_xsvs_mu(const double *__restrict__ top, int64_t ncol, int32_t R,
-                                                    const int32_t *__restrict__ ring_start,
-                                                    const int32_t *__restrict__ top_off,
-                                                    double *__restrict__ mu) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= static_cast<int64_t>(R) * ncol) return;
-    const int r = static_cast<int>(i / ncol);
-    const int64_t c = i - static_cast<int64_t>(r) * ncol;
-    const int32_t n = ring_start[r + 1] - ring_start[r];
-    mu[i] = n > 0 ? top[static_cast<int64_t>(top_off[r]) * ncol + c] / static_cast<double>(n) : 0.0;
-}
-
 // Exposure levels handled by one launch group: level base + d for d < depths,
 // bwin[d] = [R][K_d] per-window contrast, K_d = K_base >> d.
 struct LevelOut {
@@ -769,18 +801,22 @@ struct LevelOut {
     int64_t K[kLvDepth];
 };
 
-// beta per (ring, column) from the pass-2 tree top and mu: var = total / n,
-// beta = var / mu^2 (NaN for an empty ring), to the column's level and window.
-__global__ __launch_bounds__(kBlock) void k_xsvs_beta(const double *__restrict__ top, const double *__restrict__ mu,
-                                                      int64_t ncol, int64_t K, int32_t depths, int32_t R,
+// beta per (ring, window column) from the tree top of the two moments:
+// m1 = S1 / n, m2 = S2 / n, beta = (m2 - m1^2) / m1^2 (NaN for an empty ring),
+// to the column's level and window.  Threads cover R x (ncol / 2) columns of J sums.
+__global__ __launch_bounds__(kBlock) void k_xsvs_beta(const double *__restrict__ top, int64_t ncol, int64_t K,
+                                                      int32_t depths, int32_t R,
                                                       const int32_t *__restrict__ ring_start,
                                                       const int32_t *__restrict__ top_off, LevelOut lo) {
+    const int64_t half = ncol / 2;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= static_cast<int64_t>(R) * ncol) return;
-    const int r = static_cast<int>(i / ncol);
-    const int64_t c = i - static_cast<int64_t>(r) * ncol;
-    const int64_t k0 = (c / kLvCols) * kLvTile;
-    const int t = static_cast<int>(c % kLvCols);
+    if (i >= static_cast<int64_t>(R) * half) return;
+    const int r = static_cast<int>(i / half);
+    const int64_t h = i - static_cast<int64_t>(r) * half;
+    const int64_t tile = h / kLvHalf;
+    const int t = static_cast<int>(h % kLvHalf);
+    const int64_t k0 = tile * kLvTile;
+    const int64_t c = tile * kLvCols + t;
     int d = -1, j = 0;
 #pragma unroll
     for (int dd = 0; dd < kLvDepth; ++dd) {
@@ -794,9 +830,11 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_beta(const double *__restrict__
     const int32_t n = ring_start[r + 1] - ring_start[r];
     double beta = __builtin_nan("");
     if (n > 0) {
-        const double m = mu[i];
-        const double var = top[static_cast<int64_t>(top_off[r]) * ncol + c] / static_cast<double>(n);
-        beta = var / (m * m);
+        const double *row = top + static_cast<int64_t>(top_off[r]) * ncol;
+        const double m1 = row[c] / static_cast<double>(n);
+        const double m2 = row[c + kLvHalf] / static_cast<double>(n);
+        const double sq = m1 * m1;
+        beta = (m2 - sq) / sq;
     }
     lo.bwin[d][static_cast<int64_t>(r) * lo.K[d] + (k0 >> d) + j] = beta;
 }
@@ -1058,11 +1096,10 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         }
         const int64_t tiles = (K + kLvTile - 1) / kLvTile;
         const int64_t ncol = tiles * kLvCols;
-        void *t1 = nullptr, *t2 = nullptr, *mu = nullptr;
+        void *t1 = nullptr, *t2 = nullptr;
         XS_TRY(scratch(s, SLOT_G, sizeof(double) * level_bound(n_q, R, 1) * ncol, &t1));
         XS_TRY(scratch(s, SLOT_PIXEL2, sizeof(double) * level_bound(n_q, R, 2) * ncol, &t2));
-        XS_TRY(scratch(s, SLOT_PSETS, sizeof(double) * static_cast<int64_t>(R) * ncol, &mu));
-        double *c1 = static_cast<double *>(t1), *c2 = static_cast<double *>(t2), *m = static_cast<double *>(mu);
+        double *c1 = static_cast<double *>(t1), *c2 = static_cast<double *>(t2);
         LevelOut lo{};
         for (int32_t d = 0; d < depths; ++d) {
             lo.bwin[d] = bw + off[L + d];
@@ -1071,38 +1108,20 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         const dim3 grid(static_cast<unsigned>(groups_x), static_cast<unsigned>(tiles));
         const int32_t *lev1 = P.lev + (R + 1);
         const int32_t *top_off = P.lev + static_cast<int64_t>(P.levels) * (R + 1);
-        for (int pass = 0; pass < 2; ++pass) {
-            if (L == 0) {
-                if (pass == 0)
-                    hipLaunchKernelGGL((k_xsvs_chunks<true, false>), grid, dim3(kBlock), 0, s, I, K, n_q,
-                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
-                                       static_cast<const int32_t *>(order), m, ncol, c1, dst);
-                else
-                    hipLaunchKernelGGL((k_xsvs_chunks<true, true>), grid, dim3(kBlock), 0, s, I, K, n_q,
-                                       static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
-                                       static_cast<const int32_t *>(order), m, ncol, c1,
-                                       static_cast<double *>(nullptr));
-            } else {
-                if (pass == 0)
-                    hipLaunchKernelGGL((k_xsvs_chunks<false, false>), grid, dim3(kBlock), 0, s, src, K, K,
-                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
-                                       static_cast<const int32_t *>(nullptr), m, ncol, c1, dst);
-                else
-                    hipLaunchKernelGGL((k_xsvs_chunks<false, true>), grid, dim3(kBlock), 0, s, src, K, K,
-                                       static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
-                                       static_cast<const int32_t *>(nullptr), m, ncol, c1,
-                                       static_cast<double *>(nullptr));
-            }
-            XS_HIP(hipGetLastError());
-            const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);
-            if (pass == 0)
-                hipLaunchKernelGGL(k_xsvs_mu, dim3(blocks_for(static_cast<int64_t>(R) * ncol)), dim3(kBlock), 0, s,
-                                   top, ncol, R, P.start, top_off, m);
-            else
-                hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * ncol)), dim3(kBlock), 0,
-                                   s, top, static_cast<const double *>(m), ncol, K, depths, R, P.start, top_off, lo);
-            XS_HIP(hipGetLastError());
-        }
+        // one read of the windows: chunk trees of J and J*J, then the ring trees
+        if (L == 0)
+            hipLaunchKernelGGL(k_xsvs_chunks<true>, grid, dim3(kBlock), 0, s, I, K, n_q,
+                               static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
+                               static_cast<const int32_t *>(order), ncol, c1, dst);
+        else
+            hipLaunchKernelGGL(k_xsvs_chunks<false>, grid, dim3(kBlock), 0, s, src, K, K,
+                               static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
+                               static_cast<const int32_t *>(nullptr), ncol, c1, dst);
+        XS_HIP(hipGetLastError());
+        const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);
+        hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * (ncol / 2))), dim3(kBlock), 0, s,
+                           top, ncol, K, depths, R, P.start, top_off, lo);
+        XS_HIP(hipGetLastError());
         for (int32_t d = 0; d < depths; ++d)
             hipLaunchKernelGGL(k_xsvs_mean, dim3(static_cast<unsigned>(R)), dim3(kBlock), 0, s,
                                static_cast<const double *>(lo.bwin[d]), K >> d, F, R,
