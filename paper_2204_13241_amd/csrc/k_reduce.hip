@@ -32,7 +32,6 @@ constexpr int kLvHalf = 2 * kLvTile;        // windows per tile over its 7 level
 constexpr int kLvCols = 2 * kLvHalf;        // chunk-sum columns per tile: sums of J, then of J^2
 constexpr int kLvLoads = kLvRows * kLvTile / kBlock;
 constexpr int kLvChunksPerBlock = 4;        // consecutive chunks of one ring per block
-constexpr int kXcds = 8;                    // accelerator complex dies (one L2 each)
 static_assert(kLvRows * 8 == kBlock && kLvTile == 64 && (1 << kLvDepth) == kLvTile,
               "XSVS level kernel: thread (row, group of 8 windows) covers one chunk");
 
@@ -626,31 +625,19 @@ __global__ __launch_bounds__(kBlock) void k_siegert(const double *__restrict__ g
 // Eq. (bq_Iq)).  Level L+6 (one window per full tile) also goes to `next`
 // [rank][K >> 6] for the launch that continues from it.
 // kGather: rows gathered from the frames I[k][list[m]] (ld = pixels);
-// otherwise read from a ring-ordered table X[m][k] (ld = K).  order (or NULL
-// for block group = blockIdx.x): block groups sorted by their first pixel.
+// otherwise read from a ring-ordered table X[m][k] (ld = K).
 template <bool kGather>
 __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
                                                         const int32_t *__restrict__ list, int32_t R,
                                                         const int32_t *__restrict__ ring_start,
                                                         const int32_t *__restrict__ chunk_off,
-                                                        const int32_t *__restrict__ grp_off,
-                                                        const int32_t *__restrict__ order, int64_t ncol,
+                                                        const int32_t *__restrict__ grp_off, int64_t ncol,
                                                         double *__restrict__ csum, double *__restrict__ next) {
     __shared__ double tile[kLvRows * kLvStride];
     __shared__ int32_t g_s[kMaxRings + 1];
     for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
     __syncthreads();
-    int64_t gb = blockIdx.x;
-    if (order) {
-        // workgroups go to the 8 XCDs round robin (x mod 8 with gridDim.x a
-        // multiple of 8): XCD x takes the x-th eighth of the groups in detector
-        // order, so groups of neighbouring rings that share cache lines run
-        // close together in time on one L2
-        const int64_t G = g_s[R], G8 = (G + kXcds - 1) / kXcds;
-        const int64_t j = blockIdx.x / kXcds, slot = (blockIdx.x % kXcds) * G8 + j;
-        if (j >= G8 || slot >= G) return;  // block-uniform
-        gb = order[slot];
-    }
+    const int64_t gb = blockIdx.x;
     if (gb >= g_s[R]) return;  // block-uniform
     const int r = ring_of(g_s, R, gb);
     const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kLvTile;
@@ -751,47 +738,6 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
         process(bufA, ch);
         if (ch + 1 < c_end) process(bufB, ch + 1);
     }
-}
-
-// First pixel of each XSVS block group (group gb of ring r starts at ring
-// element (gb - grp[r]) * kLvChunksPerBlock * kLvRows).
-__global__ __launch_bounds__(kBlock) void k_group_keys(const int32_t *__restrict__ grp_off, int32_t R,
-                                                       const int32_t *__restrict__ ring_start,
-                                                       const int32_t *__restrict__ list, int64_t bound,
-                                                       int32_t *__restrict__ gkey) {
-    __shared__ int32_t g_s[kMaxRings + 1];
-    for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
-    __syncthreads();
-    const int64_t gb = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (gb >= bound || gb >= g_s[R]) return;
-    const int r = ring_of(g_s, R, gb);
-    gkey[gb] = list[ring_start[r] + (gb - g_s[r]) * (kLvChunksPerBlock * kLvRows)];
-}
-
-// Block groups in ascending first pixel: order[rank] = gb, rank = the group's
-// index in its ring plus, for every other ring, its count of groups with a
-// smaller first pixel (each ring's keys ascend; keys are distinct pixels).
-__global__ __launch_bounds__(kBlock) void k_group_order(const int32_t *__restrict__ grp_off, int32_t R,
-                                                        const int32_t *__restrict__ gkey, int64_t bound,
-                                                        int32_t *__restrict__ order) {
-    __shared__ int32_t g_s[kMaxRings + 1];
-    for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
-    __syncthreads();
-    const int64_t gb = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (gb >= bound || gb >= g_s[R]) return;
-    const int r = ring_of(g_s, R, gb);
-    const int32_t key = gkey[gb];
-    int64_t rank = gb - g_s[r];
-    for (int o = 0; o < R; ++o) {
-        if (o == r) continue;
-        int32_t lo = g_s[o], hi = g_s[o + 1];  // first element >= key in [lo, hi)
-        while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (gkey[mid] < key) lo = mid + 1; else hi = mid;
-        }
-        rank += lo - g_s[o];
-    }
-    order[rank] = static_cast<int32_t>(gb);
 }
 
 // Exposure levels handled by one launch group: level base + d for d < depths,
@@ -1067,18 +1013,6 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
     XS_TRY(partition(s, k, n_q, R, &P));
     const int64_t rows = std::max<int64_t>(n_q, 1);  // bounds the pixels in rings
     const int64_t groups_bound = level_bound(n_q, R, 1) / kLvChunksPerBlock + R + 1;
-    // block groups in detector order for the launches that gather from the frames
-    void *ord = nullptr;
-    XS_TRY(scratch(s, SLOT_PIXKEYS, sizeof(int32_t) * 2 * groups_bound, &ord));
-    int32_t *gkey = static_cast<int32_t *>(ord), *order = gkey + groups_bound;
-    if (n_q > 0) {
-        hipLaunchKernelGGL(k_group_keys, dim3(blocks_for(groups_bound)), dim3(kBlock), 0, s, P.grp, R, P.start,
-                           static_cast<const int32_t *>(P.list), groups_bound, gkey);
-        hipLaunchKernelGGL(k_group_order, dim3(blocks_for(groups_bound)), dim3(kBlock), 0, s, P.grp, R,
-                           static_cast<const int32_t *>(gkey), groups_bound, order);
-        XS_HIP(hipGetLastError());
-    }
-    const int64_t groups_x = (groups_bound + kXcds - 1) / kXcds * kXcds;
     const double *src = nullptr;
     // launch groups of kLvDepth levels; a group that does not reach the last
     // level writes the level after its own into a ring-ordered table
@@ -1105,18 +1039,16 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
             lo.bwin[d] = bw + off[L + d];
             lo.K[d] = K >> d;
         }
-        const dim3 grid(static_cast<unsigned>(groups_x), static_cast<unsigned>(tiles));
+        const dim3 grid(static_cast<unsigned>(groups_bound), static_cast<unsigned>(tiles));
         const int32_t *lev1 = P.lev + (R + 1);
         const int32_t *top_off = P.lev + static_cast<int64_t>(P.levels) * (R + 1);
         // one read of the windows: chunk trees of J and J*J, then the ring trees
         if (L == 0)
             hipLaunchKernelGGL(k_xsvs_chunks<true>, grid, dim3(kBlock), 0, s, I, K, n_q,
-                               static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
-                               static_cast<const int32_t *>(order), ncol, c1, dst);
+                               static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp, ncol, c1, dst);
         else
             hipLaunchKernelGGL(k_xsvs_chunks<false>, grid, dim3(kBlock), 0, s, src, K, K,
-                               static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
-                               static_cast<const int32_t *>(nullptr), ncol, c1, dst);
+                               static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp, ncol, c1, dst);
         XS_HIP(hipGetLastError());
         const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);
         hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * (ncol / 2))), dim3(kBlock), 0, s,
