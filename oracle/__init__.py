@@ -18,6 +18,9 @@ Functions (each cites the passage it follows in ``xs_oracle.c``):
 - ``xsvs_contrast``      Sec. 2.3 Eqs. (inte_Iq), (bq_Iq), dyadic exposure windows
 - ``isf_rings``          Sec. 2.3 Eq. (Fq_pq), ring mean of Sec. 4.2
 - ``siegert``            Sec. 2.3 Eqs. (bq_g2), (norm_Fq), (g2_from_fq), (beta_alt_int)
+- ``form_factors``       Sec. 2.1: Gaussian-sum atomic form factors f_s(|q|)
+- ``intensity_species``  Eqs. (Iq_rij), (pe_ri) with f_j(q) of each atom's species
+- ``intensity_species_grad``  chain rule through the same, FP64 form
 """
 from __future__ import annotations
 
@@ -69,6 +72,9 @@ def _load():
         "or_xsvs_contrast": (c_int, [P, i64, i64, P, P, i32, i32, P, P, c_int]),
         "or_isf_rings": (c_int, [P, i64, i64, P, P, i32, i32, d, P, P, c_int]),
         "or_siegert": (c_int, [P, P, i32, i32, i32, P, P, P]),
+        "or_form_factors": (c_int, [i64, P, i32, P, P]),
+        "or_intensity_species": (c_int, [i64, P, P, i32, P, i64, P, P, P, c_int]),
+        "or_intensity_species_grad": (c_int, [i64, P, P, i32, P, i64, P, P, P, P, c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -249,3 +255,48 @@ def siegert(g2, F, n_levels: int):
     _check(_load().or_siegert(_ptr(g2), _ptr(F), nr, nt, int(n_levels), _ptr(lhs), _ptr(fh),
                               _ptr(beta)), "siegert")
     return lhs, fh, beta
+
+
+def _coef(coef):
+    c = _f64(coef, 9).reshape(-1, 9)
+    return c, c.shape[0]
+
+
+def form_factors(q, coef):
+    """f_s(|q|) [Q, n_species] from Gaussian-sum coefficients coef [n_species, 9]
+    (a_1..a_4, b_1..b_4, c; s = |q| / (4 pi))."""
+    q = _f64(q, 3).reshape(-1, 3)
+    c, ns = _coef(coef)
+    out = np.empty((q.shape[0], ns))
+    _check(_load().or_form_factors(q.shape[0], _ptr(q), ns, _ptr(c), _ptr(out)), "form_factors")
+    return out
+
+
+def intensity_species(pos, species, coef, q, threads: int = 0):
+    """FP64 form with q-dependent form factors: (I [Q], amp [Q, 2]) for one frame."""
+    pos = _f64(pos, 3).reshape(-1, 3)
+    sp = np.ascontiguousarray(species, dtype=np.int32).reshape(-1)
+    if sp.shape[0] != pos.shape[0]:
+        raise ValueError("species and pos disagree on the atom count")
+    q = _f64(q, 3).reshape(-1, 3)
+    c, ns = _coef(coef)
+    I = np.empty(q.shape[0])
+    amp = np.empty((q.shape[0], 2))
+    _check(_load().or_intensity_species(pos.shape[0], _ptr(pos), _ptr(sp), ns, _ptr(c), q.shape[0], _ptr(q),
+                                        _ptr(I), _ptr(amp), int(threads)), "intensity_species")
+    return I, amp
+
+
+def intensity_species_grad(pos, species, coef, q, amp, dL_dI, threads: int = 0):
+    """FP64-form dL/dr [N, 3] with q-dependent form factors."""
+    pos = _f64(pos, 3).reshape(-1, 3)
+    sp = np.ascontiguousarray(species, dtype=np.int32).reshape(-1)
+    q = _f64(q, 3).reshape(-1, 3)
+    c, ns = _coef(coef)
+    amp = _f64(amp, 2).reshape(-1, 2)
+    w = _f64(dL_dI).reshape(-1)
+    g = np.empty((pos.shape[0], 3))
+    _check(_load().or_intensity_species_grad(pos.shape[0], _ptr(pos), _ptr(sp), ns, _ptr(c), q.shape[0],
+                                             _ptr(q), _ptr(amp), _ptr(w), _ptr(g), int(threads)),
+           "intensity_species_grad")
+    return g

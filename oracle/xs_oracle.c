@@ -660,3 +660,118 @@ int or_siegert(const double *g2, const double *F, int32_t n_rings, int32_t n_tau
     }
     return OR_OK;
 }
+
+/*
+ * X-ray atomic form factor of a species at wavevector magnitude |q|, as a sum
+ * of Gaussians (Sec. 2.1: the form factor is well parameterized by a sum of
+ * Gaussians, the International Tables form):
+ *     f_s(q) = c + sum_{i=1..4} a_i exp(-b_i s^2),   s = |q| / (4 pi),
+ * coef[s] = {a_1, a_2, a_3, a_4, b_1, b_2, b_3, b_4, c} (b in Angstrom^2).
+ * s^2 = (q.q) / (16 pi^2); the four terms are added to c in order i = 1..4.
+ */
+static double or_form_factor(const double *coef, const double *qv)
+{
+    const double qq = fma(qv[2], qv[2], fma(qv[1], qv[1], qv[0] * qv[0]));
+    const double s2 = qq / (16.0 * M_PI * M_PI);
+    double f = coef[8];
+    for (int i = 0; i < 4; ++i) f = f + coef[i] * exp(-coef[4 + i] * s2);
+    return f;
+}
+
+/* f_s(|q|) for every pixel and species: out[p][s]. */
+int or_form_factors(int64_t n_q, const double *q, int32_t n_species, const double *coef, double *out)
+{
+    if (n_q < 0 || n_species <= 0 || !coef || (n_q > 0 && (!q || !out))) return OR_EINVAL;
+    for (int64_t p = 0; p < n_q; ++p)
+        for (int32_t s = 0; s < n_species; ++s) out[p * n_species + s] = or_form_factor(coef + 9 * s, q + 3 * p);
+    return OR_OK;
+}
+
+/*
+ * Direct method with q-dependent form factors, Eqs. (Iq_rij), (pe_ri) with
+ * f_j(q) = f_{species[j]}(|q|): for every pixel, atoms summed in input order
+ * from +0.0 with the FP64-form sine and cosine,
+ *   ac += f_j(q) cos(q.r_j), as += f_j(q) sin(q.r_j)   (fma),
+ *   a = ac, b = -as, I = a*a + b*b.
+ * species: [N] in 0 .. n_species-1; coef: [n_species][9] as above.
+ */
+int or_intensity_species(int64_t n_atoms, const double *pos, const int32_t *species, int32_t n_species,
+                         const double *coef, int64_t n_q, const double *q, double *I, double *amp,
+                         int n_threads)
+{
+    if (n_atoms < 0 || n_q < 0 || n_species <= 0 || !coef || (n_q > 0 && (!q || !I)) ||
+        (n_atoms > 0 && (!pos || !species)))
+        return OR_EINVAL;
+    for (int64_t j = 0; j < n_atoms; ++j)
+        if (species[j] < 0 || species[j] >= n_species) return OR_EINVAL;
+    int rc = OR_OK;
+#pragma omp parallel num_threads(or_threads(n_threads))
+    {
+        double *fs = malloc(sizeof(double) * (size_t)n_species);
+        if (!fs) {
+#pragma omp atomic write
+            rc = OR_ENOMEM;
+        }
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n_q; ++p) {
+            if (!fs) continue;
+            double qrev[3];
+            for (int k = 0; k < 3; ++k) qrev[k] = q[3 * p + k] * OR_INV2PI;
+            for (int32_t s = 0; s < n_species; ++s) fs[s] = or_form_factor(coef + 9 * s, q + 3 * p);
+            double ac = 0.0, as = 0.0;
+            for (int64_t j = 0; j < n_atoms; ++j) {
+                double sn, cs;
+                or_sincos_rev(or_phase_rev(qrev, pos + 3 * j), &sn, &cs);
+                const double fj = fs[species[j]];
+                ac = fma(fj, cs, ac);
+                as = fma(fj, sn, as);
+            }
+            double a = ac, b = -as;
+            I[p] = fma(a, a, b * b);
+            if (amp) { amp[2 * p] = a; amp[2 * p + 1] = b; }
+        }
+        free(fs);
+    }
+    return rc;
+}
+
+/*
+ * Gradient of L = sum_p w_p I_p with q-dependent form factors (chain rule
+ * through Eqs. (pe_ri), (Iq_pq) with f_j(q)): with the amplitude a_p + i b_p of
+ * the same positions,
+ *   dI_p/dr_j = -2 f_j(q_p) q_p (a_p sin(q_p.r_j) + b_p cos(q_p.r_j)),
+ *   dL/dr_j   = sum_p w_p dI_p/dr_j.
+ * FP64 form: per atom, pixels in input order from +0.0;
+ *   h = fma(a, s, b*c); k = (w * f_j(q)) * h; g += k*q (fma per component);
+ *   dL/dr_j = -2 g.
+ */
+int or_intensity_species_grad(int64_t n_atoms, const double *pos, const int32_t *species, int32_t n_species,
+                              const double *coef, int64_t n_q, const double *q, const double *amp,
+                              const double *dL_dI, double *grad, int n_threads)
+{
+    if (n_atoms < 0 || n_q < 0 || n_species <= 0 || !coef || (n_atoms > 0 && (!pos || !species || !grad)) ||
+        (n_q > 0 && (!q || !amp || !dL_dI)))
+        return OR_EINVAL;
+    for (int64_t j = 0; j < n_atoms; ++j)
+        if (species[j] < 0 || species[j] >= n_species) return OR_EINVAL;
+    double *fq = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1) * (size_t)n_species);
+    if (!fq) return OR_ENOMEM;
+    or_form_factors(n_q, q, n_species, coef, fq);
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t j = 0; j < n_atoms; ++j) {
+        double g[3] = {0.0, 0.0, 0.0};
+        for (int64_t p = 0; p < n_q; ++p) {
+            double qrev[3];
+            for (int k = 0; k < 3; ++k) qrev[k] = q[3 * p + k] * OR_INV2PI;
+            double sn, cs;
+            or_sincos_rev(or_phase_rev(qrev, pos + 3 * j), &sn, &cs);
+            const double a = amp[2 * p], b = amp[2 * p + 1];
+            const double h = fma(a, sn, b * cs);
+            const double k = (dL_dI[p] * fq[p * n_species + species[j]]) * h;
+            for (int c = 0; c < 3; ++c) g[c] = fma(k, q[3 * p + c], g[c]);
+        }
+        for (int c = 0; c < 3; ++c) grad[3 * j + c] = -2.0 * g[c];
+    }
+    free(fq);
+    return OR_OK;
+}

@@ -579,3 +579,91 @@ def test_siegert_holds_for_a_gaussian_field():
         exact = (1 + 2 * sum((1 - k / W) * rho ** (2 * k) for k in range(1, W))) / W
         assert abs(bp[lvl, 0] / exact - 1) < 0.03
         assert abs(beta[lvl, 0] / exact - 1) < 0.03
+
+
+# ---------------------------------------------------------------- q-dependent form factors
+
+_FF = np.array([[1.2, 2.1, 0.6, 0.3, 11.0, 3.2, 0.9, 0.21, 0.25],     # a1..a4, b1..b4, c
+                [0.5, 0.3, 0.12, 0.08, 6.0, 2.0, 0.7, 0.15, 0.02],
+                [2.0, 1.0, 0.5, 0.25, 0.0, 0.0, 0.0, 0.0, 1.0]])       # b = 0: a constant 4.75
+
+
+def test_form_factor_gaussian_sum_against_mpmath():
+    """f_s(q) = c + sum_i a_i exp(-b_i s^2) with s = |q| / (4 pi) (Sec. 2.1, the
+    sum-of-Gaussians form); f(0) = c + sum a_i; at |q| = 4 pi a single Gaussian
+    gives a e^{-b}."""
+    rng = np.random.default_rng(41)
+    q = np.vstack([[0.0, 0.0, 0.0], rng.normal(size=(20, 3)) * 2.0])
+    f = oracle.form_factors(q, _FF)
+    for p in range(q.shape[0]):
+        s2 = sum(mp.mpf(float(c)) ** 2 for c in q[p]) / (16 * mp.pi ** 2)
+        for s in range(3):
+            a, b, c = _FF[s, :4], _FF[s, 4:8], _FF[s, 8]
+            want = mp.mpf(float(c)) + sum(mp.mpf(float(a[i])) * mp.e ** (-mp.mpf(float(b[i])) * s2) for i in range(4))
+            assert abs(f[p, s] - float(want)) <= 4e-16 * float(want)
+    # q = 0: every exponential is 1, the terms added to c in order i = 1..4
+    assert np.array_equal(f[0], np.array([(((0.25 + 1.2) + 2.1) + 0.6) + 0.3,
+                                          (((0.02 + 0.5) + 0.3) + 0.12) + 0.08, 4.75]))
+    one = np.array([[1.0, 0, 0, 0, 0.7, 0, 0, 0, 0]])
+    assert abs(oracle.form_factors([[4 * np.pi, 0, 0]], one)[0, 0] - np.exp(-0.7)) < 1e-15
+
+
+def test_species_constant_form_factor_matches_per_atom_weights_bitwise():
+    """With b = 0 the species form factor is a constant; the species sum is then the
+    FP64-form sum of Eq. (pe_ri) with those per-atom weights, bit for bit."""
+    rng = np.random.default_rng(42)
+    pos = rng.uniform(0, 20, (50, 3))
+    q = rng.normal(size=(30, 3))
+    coef = np.array([_FF[2], [0.5, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.5]])
+    sp = rng.integers(0, 2, 50).astype(np.int32)
+    f = np.where(sp == 0, 4.75, 1.0)
+    I, amp = oracle.intensity_species(pos, sp, coef, q)
+    I0, amp0 = oracle.intensity(pos, f, q)
+    assert np.array_equal(I, I0) and np.array_equal(amp, amp0)
+
+
+def test_single_species_factorizes():
+    """All atoms of one species: p^e(q) = f(|q|) p(q) (Sec. 2.2), so I = f^2 I_unit."""
+    rng = np.random.default_rng(43)
+    pos = rng.uniform(0, 25, (80, 3))
+    q = rng.normal(size=(40, 3)) * 1.5
+    I, _ = oracle.intensity_species(pos, np.zeros(80, np.int32), _FF[:1], q)
+    Iu, _ = oracle.intensity(pos, np.ones(80), q)
+    f = oracle.form_factors(q, _FF[:1])[:, 0]
+    assert np.allclose(I, f * f * Iu, rtol=1e-13, atol=1e-13 * 80 * f.max() ** 2)
+
+
+def test_two_species_two_atoms_closed_form():
+    """I = f1^2 + f2^2 + 2 f1 f2 cos(q.(r1 - r2)) (Eq. (Iq_rij)) with f1, f2 at |q|."""
+    rng = np.random.default_rng(44)
+    pos = rng.uniform(-3, 3, (2, 3))
+    q = rng.normal(size=(25, 3))
+    I, _ = oracle.intensity_species(pos, np.array([0, 1], np.int32), _FF[:2], q)
+    f = oracle.form_factors(q, _FF[:2])
+    for p in range(25):
+        d = mp.fdot([mp.mpf(float(c)) for c in q[p]], [mp.mpf(float(c)) for c in pos[0] - pos[1]])
+        f1, f2 = mp.mpf(float(f[p, 0])), mp.mpf(float(f[p, 1]))
+        want = f1 ** 2 + f2 ** 2 + 2 * f1 * f2 * mp.cos(d)
+        assert abs(I[p] - float(want)) < 1e-13 * (f1 + f2) ** 2
+
+
+def test_species_gradient_against_central_differences():
+    """dL/dr of L = sum_p w_p I_p (chain rule with f_j(q)) against central differences
+    of the species intensity (h = 1e-5 A, long-double accumulation of the difference)."""
+    rng = np.random.default_rng(45)
+    pos = rng.uniform(0, 12, (6, 3))
+    sp = np.array([0, 1, 2, 0, 1, 2], np.int32)
+    q = rng.normal(size=(40, 3))
+    w = rng.normal(size=40)
+    I, amp = oracle.intensity_species(pos, sp, _FF, q)
+    g = oracle.intensity_species_grad(pos, sp, _FF, q, amp, w)
+    h = 1e-5
+    for j in range(6):
+        for c in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[j, c] += h
+            pm[j, c] -= h
+            Ip, _ = oracle.intensity_species(pp, sp, _FF, q)
+            Im, _ = oracle.intensity_species(pm, sp, _FF, q)
+            fd = float(np.sum(np.longdouble(w) * (np.longdouble(Ip) - np.longdouble(Im)))) / (2 * h)
+            assert abs(g[j, c] - fd) < 2e-6 * np.max(np.abs(g)) + 1e-9
