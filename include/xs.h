@@ -137,6 +137,45 @@ xs_status xs_intensity_grad(const xs_batch *b, const double *pos, const double *
                             int32_t precision, float *dL_dr, double *dL_dr64, void *stream);
 
 /*
+ * Intensity with q-dependent atomic form factors, Eqs. (Iq_rij), (pe_ri) with
+ * f_j(q) = f_{species[j]}(|q|), each species' form factor a sum of Gaussians
+ * (Sec. 2.1):
+ *     f_s(q) = c + sum_{i=1..4} a_i exp(-b_i s^2),   s = |q| / (4 pi)  (1/A),
+ * computed on the device per pixel and species.
+ *   b          batch descriptor as for xs_intensity_direct; species[] has the
+ *              layout of f (offset f_off[s] per system, shared by its frames)
+ *   pos, q     as for xs_intensity_direct
+ *   species    device int32 [..] species index of every atom, 0 <= v < n_species
+ *   n_species  1 .. 4096
+ *   ff_coef    host double [n_species][9]: a_1..a_4, b_1..b_4 (A^2), c
+ *   precision  XS_FP64 or XS_FP32C (as for xs_intensity_direct)
+ *   I_out      device double, same layout as for xs_intensity_direct
+ *   amp_out    device double [..][2] (a, b) of p^e = a + i b, or NULL
+ * The atoms of each species form their own pair sum P_s(q) = sum_{j in s}
+ * e^{-i q.r_j} (unit weights, the ordinary batched pair kernels), and
+ * p^e = sum_s f_s(|q|) P_s.  The species array is read back to the host to
+ * build that split: the call waits for the stream's earlier work.  Errors:
+ * XS_EINVAL for a species index out of range, non-finite coefficients, or the
+ * conditions of xs_intensity_direct.
+ */
+xs_status xs_intensity_species(const xs_batch *b, const double *pos, const int32_t *species,
+                               int32_t n_species, const double *ff_coef, const double *q,
+                               int32_t precision, double *I_out, double *amp_out, void *stream);
+
+/*
+ * Gradient of L = sum_p w_p I_p with q-dependent form factors (the chain rule
+ * through Eqs. (pe_ri), (Iq_pq) with f_j(q)):
+ *     dL/dr_j = -2 sum_p w_p f_j(q_p) q_p (a_p sin(q_p.r_j) + b_p cos(q_p.r_j)),
+ * amp the amplitude from xs_intensity_species of the same positions, dL_dI =
+ * w.  Arguments and outputs as for xs_intensity_grad plus species, n_species
+ * and ff_coef as for xs_intensity_species; gradients in the caller's atom order.
+ */
+xs_status xs_intensity_species_grad(const xs_batch *b, const double *pos, const int32_t *species,
+                                    int32_t n_species, const double *ff_coef, const double *q,
+                                    const double *amp, const double *dL_dI, int32_t precision,
+                                    float *dL_dr, double *dL_dr64, void *stream);
+
+/*
  * Intensity autocorrelation on |q| rings, Sec. 2.3 Eq. (g2_def), ring mean of
  * Sec. 4.2:
  *     G_p(tau) = [sum_{t < F - tau} I_t,p I_t+tau,p / (F - tau)] / <I_p>_t^2,

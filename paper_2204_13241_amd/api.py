@@ -196,6 +196,66 @@ def intensity_grad(pos: torch.Tensor, f: torch.Tensor, q: torch.Tensor, amp: tor
     return g[0] if single else g
 
 
+def _species_args(species: torch.Tensor, coef, N: int):
+    if not isinstance(species, torch.Tensor) or not species.is_cuda or species.dtype != torch.int32:
+        raise ValueError("species must be an int32 tensor in GPU memory")
+    if species.shape != (N,) or not species.is_contiguous():
+        raise ValueError("species must be a contiguous [N] tensor")
+    c = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1, 9)
+    return c
+
+
+def intensity_species(pos: torch.Tensor, species: torch.Tensor, coef, q: torch.Tensor, precision="fp32c",
+                      box=None, return_amp: bool = False):
+    """Intensity with q-dependent form factors f_s(|q|) = c + sum_i a_i exp(-b_i (|q|/4pi)^2).
+
+    pos [F, N, 3] or [N, 3] float64, species [N] int32 (GPU), coef [n_species, 9]
+    (a_1..a_4, b_1..b_4, c; host), q [Q, 3] float64.  Returns I [F, Q] (or [Q]) and
+    the amplitude [F, Q, 2] if asked."""
+    _need(pos, "pos"), _need(q, "q")
+    single = pos.dim() == 2
+    p3 = pos.unsqueeze(0) if single else pos
+    F, N, Q = int(p3.shape[0]), int(p3.shape[1]), int(q.shape[0])
+    c = _species_args(species, coef, N)
+    bx = _box3(box, pos) if _prec(precision) == _lib.XS_FP32C else np.ones(3)
+    b = make_batch([N], [Q], [F], bx)
+    I = torch.empty((F, Q), dtype=torch.float64, device=pos.device)
+    amp = torch.empty((F, Q, 2), dtype=torch.float64, device=pos.device) if return_amp else None
+    st = b.struct()
+    _lib.check(_lib.load().xs_intensity_species(ctypes.byref(st), _ptr(p3), _ptr(species), c.shape[0],
+                                                c.ctypes.data_as(ctypes.c_void_p), _ptr(q), _prec(precision),
+                                                _ptr(I), _ptr(amp), _stream()))
+    if single:
+        I = I[0]
+        amp = amp[0] if amp is not None else None
+    return (I, amp) if return_amp else I
+
+
+def intensity_species_grad(pos: torch.Tensor, species: torch.Tensor, coef, q: torch.Tensor, amp: torch.Tensor,
+                           dL_dI: torch.Tensor, precision="fp32c", box=None, out_dtype=torch.float32):
+    """dL/dpos with q-dependent form factors, from the amplitude of intensity_species."""
+    _need(pos, "pos"), _need(q, "q"), _need(amp, "amp"), _need(dL_dI, "dL_dI")
+    single = pos.dim() == 2
+    p3 = pos.unsqueeze(0) if single else pos
+    F, N, Q = int(p3.shape[0]), int(p3.shape[1]), int(q.shape[0])
+    c = _species_args(species, coef, N)
+    if amp.numel() != F * Q * 2 or dL_dI.numel() != F * Q:
+        raise ValueError("amp must be [F, Q, 2] and dL_dI [F, Q]")
+    bx = _box3(box, pos) if _prec(precision) == _lib.XS_FP32C else np.ones(3)
+    b = make_batch([N], [Q], [F], bx)
+    g32 = torch.empty(p3.shape, dtype=torch.float32, device=pos.device) if out_dtype == torch.float32 else None
+    g64 = torch.empty(p3.shape, dtype=torch.float64, device=pos.device) if out_dtype == torch.float64 else None
+    if g32 is None and g64 is None:
+        raise ValueError("out_dtype must be torch.float32 or torch.float64")
+    st = b.struct()
+    _lib.check(_lib.load().xs_intensity_species_grad(ctypes.byref(st), _ptr(p3), _ptr(species), c.shape[0],
+                                                     c.ctypes.data_as(ctypes.c_void_p), _ptr(q), _ptr(amp),
+                                                     _ptr(dL_dI), _prec(precision), _ptr(g32), _ptr(g64),
+                                                     _stream()))
+    g = g32 if g32 is not None else g64
+    return g[0] if single else g
+
+
 def g2_rings(I: torch.Tensor, q: torch.Tensor, edges, n_tau: int):
     """g2 [n_rings, n_tau] (float64) and the pixel count per ring (int32)."""
     _need(I, "I"), _need(q, "q")

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxs.so")
-SOURCES = ["xs_api.cpp", "k_fp64.hip", "k_fp32c.hip", "k_reduce.hip", "k_misc.hip"]
+SOURCES = ["xs_api.cpp", "k_fp64.hip", "k_fp32c.hip", "k_reduce.hip", "k_misc.hip", "k_species.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

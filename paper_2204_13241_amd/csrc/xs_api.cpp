@@ -311,6 +311,62 @@ xs_status xs_intensity_grad(const xs_batch *b, const double *pos, const double *
     return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
 }
 
+static xs_status check_species_args(int32_t n_species, const double *coef) {
+    if (n_species < 1 || n_species > 4096) return set_error(XS_EINVAL, "n_species must be in [1, 4096]");
+    if (!coef) return set_error(XS_EINVAL, "form-factor coefficients are NULL");
+    for (int i = 0; i < 9 * n_species; ++i)
+        if (!std::isfinite(coef[i])) return set_error(XS_EINVAL, "form-factor coefficient %d is not finite", i);
+    return XS_OK;
+}
+
+xs_status xs_intensity_species(const xs_batch *b, const double *pos, const int32_t *species, int32_t n_species,
+                               const double *ff_coef, const double *q, int32_t precision, double *I_out,
+                               double *amp_out, void *stream) {
+    XS_TRY(begin(stream));
+    std::vector<Segment> segs;
+    int max_atoms = 0, max_q = 0;
+    XS_TRY(expand_batch(b, segs, max_atoms, max_q));
+    XS_TRY(check_species_args(n_species, ff_coef));
+    if (max_q > 0 && (!q || !I_out)) return set_error(XS_EINVAL, "q / I_out is NULL");
+    if (max_atoms > 0 && (!pos || !species)) return set_error(XS_EINVAL, "pos / species is NULL");
+    if (precision != XS_FP64 && precision != XS_FP32C)
+        return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
+    if (precision == XS_FP32C) XS_TRY(check_box(b));
+    xs_tile_shape fsh, gsh;
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        fsh = g_shape[0];
+        gsh = g_shape[1];
+    }
+    return species_forward(static_cast<hipStream_t>(stream), segs, b->box, pos, species, n_species, ff_coef, q,
+                           precision, I_out, amp_out, fsh, gsh);
+}
+
+xs_status xs_intensity_species_grad(const xs_batch *b, const double *pos, const int32_t *species,
+                                    int32_t n_species, const double *ff_coef, const double *q, const double *amp,
+                                    const double *dL_dI, int32_t precision, float *dL_dr, double *dL_dr64,
+                                    void *stream) {
+    XS_TRY(begin(stream));
+    std::vector<Segment> segs;
+    int max_atoms = 0, max_q = 0;
+    XS_TRY(expand_batch(b, segs, max_atoms, max_q));
+    XS_TRY(check_species_args(n_species, ff_coef));
+    if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
+    if (max_atoms > 0 && (!pos || !species)) return set_error(XS_EINVAL, "pos / species is NULL");
+    if (max_q > 0 && (!q || !amp || !dL_dI)) return set_error(XS_EINVAL, "q / amp / dL_dI is NULL");
+    if (precision != XS_FP64 && precision != XS_FP32C)
+        return set_error(XS_EINVAL, "precision must be XS_FP64 (0) or XS_FP32C (1), got %d", precision);
+    if (precision == XS_FP32C) XS_TRY(check_box(b));
+    xs_tile_shape fsh, gsh;
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        fsh = g_shape[0];
+        gsh = g_shape[1];
+    }
+    return species_grad(static_cast<hipStream_t>(stream), segs, b->box, pos, species, n_species, ff_coef, q, amp,
+                        dL_dI, precision, dL_dr, dL_dr64, fsh, gsh);
+}
+
 xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const double *q,
                       const double *ring_edges, int32_t n_rings, int32_t n_tau, double *g2_out,
                       int32_t *ring_count, void *stream) {

@@ -54,6 +54,10 @@ enum Slot {
     SLOT_GITEMS,        // FP32C gradient work items
     SLOT_PLAN,          // one-shot FP32C plan buffers
     SLOT_TABLES,        // one-shot FP32C plan tables (staging)
+    SLOT_SPECIES_TAB,   // species split: segment tables, species order, form-factor coefficients
+    SLOT_SPECIES_POS,   // species split: unit weights and positions in species order
+    SLOT_SPECIES_OUT,   // species split: per-species amplitudes / adjoint weights
+    SLOT_SPECIES_GRAD,  // species split: gradients in species order
     SLOT_COUNT
 };
 xs_status scratch(hipStream_t stream, Slot slot, size_t bytes, void **ptr);
@@ -140,6 +144,14 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q
 xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
                         const double *q, const RingEdges &edges, int32_t n_levels,
                         double *beta_out, double *beta_win);
+xs_status species_forward(hipStream_t s, const std::vector<Segment> &segs, const double *box, const double *pos,
+                          const int32_t *species, int32_t n_species, const double *coef_host, const double *q,
+                          int32_t precision, double *I, double *amp, const xs_tile_shape &fsh,
+                          const xs_tile_shape &gsh);
+xs_status species_grad(hipStream_t s, const std::vector<Segment> &segs, const double *box, const double *pos,
+                       const int32_t *species, int32_t n_species, const double *coef_host, const double *q,
+                       const double *amp, const double *dL_dI, int32_t precision, float *dL_dr, double *dL_dr64,
+                       const xs_tile_shape &fsh, const xs_tile_shape &gsh);
 xs_status isf_rings(hipStream_t s, const double *amp, int64_t n_frames, int64_t n_q, const double *q,
                     const RingEdges &edges, int32_t n_tau, double f2, double *F_out, int32_t *ring_count);
 xs_status siegert(hipStream_t s, const double *g2, const double *F, int32_t n_rings, int32_t n_tau,

@@ -1,0 +1,102 @@
+"""q-dependent form factors per species on the GPU against the oracle (Sec. 2.1, Eqs.
+(Iq_rij), (pe_ri) with f_j(q)).  The GPU sums each species' phasors separately and then
+weights them by f_s(|q|), a different rounding order from the oracle's single sum over
+atoms: FP64 parity is tolerance-based (1e-12 on the scaled error), FP32C at 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+pytestmark = pytest.mark.gpu
+
+COEF = np.array([[1.2, 2.1, 0.6, 0.3, 11.0, 3.2, 0.9, 0.21, 0.25],
+                 [0.5, 0.3, 0.12, 0.08, 6.0, 2.0, 0.7, 0.15, 0.02],
+                 [3.0, 2.2, 1.1, 0.4, 9.0, 2.5, 0.6, 0.1, 0.3]])
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2204_13241_amd import api
+    return api
+
+
+def _case(seed, N, F, grid, L=40.0, n_species=3, absent=None):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, L, (F, N, 3))
+    sp = rng.integers(0, n_species, N).astype(np.int32)
+    if absent is not None:
+        sp[sp == absent] = 0
+    q = X.planar_grid(grid, 3.0) if grid > 0 else X.ewald_detector(-grid, 1.5)
+    return pos, sp, q, L
+
+
+def _scaled(I, I_ref, sp, q):
+    """max |I - I_ref| / max(I_ref, sum_j f_j(q)^2) per pixel (the intensity error scale)."""
+    f = oracle.form_factors(q, COEF)[:, sp]            # [Q, N]
+    inc = np.sum(f * f, axis=1)
+    return float(np.max(np.abs(I - I_ref) / np.maximum(I_ref, inc[None, :])))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+@pytest.mark.parametrize("N,F,grid,seed", [(1000, 2, 48, 1), (777, 1, -40, 2), (64, 3, 16, 3)])
+def test_species_intensity(api, prec, tol, N, F, grid, seed):
+    from _gpu import dev, host
+    pos, sp, q, L = _case(seed, N, F, grid)
+    print("species %s N=%d F=%d Q=%d" % (prec, N, F, q.shape[0]), flush=True)
+    I, amp = api.intensity_species(dev(pos), dev(sp, dtype=__import__("torch").int32), COEF, dev(q),
+                                   precision=prec, box=L, return_amp=True)
+    for t in range(F):
+        Ir, ampr = oracle.intensity_species(pos[t], sp, COEF, q)
+        assert _scaled(host(I)[t], Ir, sp, q) < tol
+        # amplitude error on the same scale (sqrt of the incoherent level)
+        f = oracle.form_factors(q, COEF)[:, sp]
+        inc = np.sqrt(np.sum(f * f, axis=1))
+        assert np.max(np.abs(host(amp)[t] - ampr) / np.maximum(np.abs(ampr).max(axis=1), inc)[:, None]) < tol
+
+
+def test_species_absent_and_constant_form_factor(api):
+    """A species with no atoms contributes nothing; b = 0 makes f_s a constant and the
+    result the per-atom-weight intensity of xs_intensity_direct."""
+    import torch
+    from _gpu import dev, host
+    pos, sp, q, L = _case(4, 500, 1, 32, absent=2)
+    print("species absent", flush=True)
+    I = api.intensity_species(dev(pos[0]), dev(sp, dtype=torch.int32), COEF, dev(q), precision="fp64")
+    Ir, _ = oracle.intensity_species(pos[0], sp, COEF, q)
+    assert _scaled(host(I)[None, :], Ir, sp, q) < 1e-12
+    const = np.array([[2.0, 1.0, 0.5, 0.25, 0, 0, 0, 0, 1.0], [0.5, 0, 0, 0, 0, 0, 0, 0, 0.5]])
+    sp2 = (sp % 2).astype(np.int32)
+    I2 = api.intensity_species(dev(pos[0]), dev(sp2, dtype=torch.int32), const, dev(q), precision="fp64")
+    Id = api.intensity(dev(pos[0]), dev(np.where(sp2 == 0, 4.75, 1.0)), dev(q), precision="fp64")
+    assert np.max(np.abs(host(I2) - host(Id)) / np.maximum(host(Id), 500 * 4.75 ** 2)) < 1e-13
+
+
+def test_species_rejects_bad_species(api):
+    import torch
+    from _gpu import dev
+    pos, sp, q, L = _case(5, 50, 1, 8)
+    sp[3] = 7
+    with pytest.raises(RuntimeError):
+        api.intensity_species(dev(pos[0]), dev(sp, dtype=torch.int32), COEF, dev(q), precision="fp64")
+    with pytest.raises(RuntimeError):
+        api.intensity_species(dev(pos[0]), dev(sp * 0, dtype=torch.int32), np.full((3, 9), np.nan), dev(q),
+                              precision="fp64")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 2e-5)])
+def test_species_gradient(api, prec, tol):
+    import torch
+    from _gpu import dev, host, grad_err
+    pos, sp, q, L = _case(6, 300, 2, 24)
+    rng = np.random.default_rng(7)
+    w = rng.normal(size=(2, q.shape[0]))
+    print("species grad %s" % prec, flush=True)
+    I, amp = api.intensity_species(dev(pos), dev(sp, dtype=torch.int32), COEF, dev(q), precision="fp64",
+                                   box=L, return_amp=True)
+    g = api.intensity_species_grad(dev(pos), dev(sp, dtype=torch.int32), COEF, dev(q), amp, dev(w),
+                                   precision=prec, box=L, out_dtype=torch.float64)
+    for t in range(2):
+        _, ampr = oracle.intensity_species(pos[t], sp, COEF, q)
+        gr = oracle.intensity_species_grad(pos[t], sp, COEF, q, ampr, w[t])
+        assert grad_err(host(g)[t], gr) < tol
