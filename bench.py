@@ -375,6 +375,56 @@ def run_reductions(args):
     return out
 
 
+def run_species(args):
+    """q-dependent form factors (two species, Gaussian-sum f_s(|q|)) on the
+    differentiation workload's atoms and pixels: one-shot FP32C calls of the species
+    path against the same calls with per-atom weights, whole calls timed with HIP
+    events (host split of the species and plan building included in both)."""
+    import torch
+    from paper_2204_13241_amd import api, inputs
+    dev = "cuda:0"
+    w = inputs.workload_grad()
+    r0, q_np, L = w.positions[0][0], w.q[0], w.box[0]
+    N, Q = r0.shape[0], q_np.shape[0]
+    rng = np.random.default_rng(2204)
+    sp_np = (rng.random(N) < 2.0 / 3.0).astype(np.int32)            # 1/3 species 0, 2/3 species 1
+    coef = np.array([[3.1, 2.3, 1.5, 0.9, 13.0, 5.5, 0.3, 30.0, 0.2],  # synthetic Gaussian sums
+                     [0.49, 0.32, 0.14, 0.04, 10.5, 26.1, 3.1, 57.8, 0.003]])
+    pos = torch.as_tensor(r0, dtype=torch.float64, device=dev)
+    q = torch.as_tensor(q_np, dtype=torch.float64, device=dev)
+    sp = torch.as_tensor(sp_np, dtype=torch.int32, device=dev)
+    f_eff = torch.ones(N, dtype=torch.float64, device=dev)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    ms_sp = timed(lambda: api.intensity_species(pos, sp, coef, q, precision="fp32c", box=L))
+    ms_plain = timed(lambda: api.intensity(pos, f_eff, q, precision="fp32c", box=L))
+    I64 = api.intensity_species(pos, sp, coef, q, precision="fp64")
+    I32 = api.intensity_species(pos, sp, coef, q, precision="fp32c", box=L)
+    fq = np.zeros((Q, 2))
+    qq = np.sum(q_np * q_np, axis=1) / (16 * np.pi ** 2)
+    for s_ in range(2):
+        a, b, c = coef[s_, :4], coef[s_, 4:8], coef[s_, 8]
+        fq[:, s_] = c + np.sum(a[None, :] * np.exp(-b[None, :] * qq[:, None]), axis=1)
+    inc = (np.sum(sp_np == 0) * fq[:, 0] ** 2 + np.sum(sp_np == 1) * fq[:, 1] ** 2)
+    e = float(np.max(np.abs(I32.cpu().numpy() - I64.cpu().numpy()) / np.maximum(I64.cpu().numpy(), inc)))
+    rec = {"workload": "65,536 atoms (two species), 512x512 planar pixels, one frame, synthetic Gaussian-sum "
+                       "form factors", "pairs": N * Q, "species_ms": ms_sp, "per_atom_weights_ms": ms_plain,
+           "species_Gpair_s": N * Q / (ms_sp * 1e-3) / 1e9, "overhead": ms_sp / ms_plain - 1.0,
+           "e_I_scaled_fp32c_vs_fp64": e}
+    log("species: %.3f ms per call (per-atom weights %.3f ms), %.0f Gpair/s, e_I %.2e"
+        % (ms_sp, ms_plain, rec["species_Gpair_s"], e))
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +438,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--no-reductions", action="store_true", help="skip the g2 / XSVS timings")
+    ap.add_argument("--no-species", action="store_true", help="skip the form-factor (species) timing")
     ap.add_argument("--only-reductions", action="store_true", help="time only g2 / XSVS")
     ap.add_argument("--red-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -412,6 +463,8 @@ def main():
     res = run_grad(args)
     if not args.no_reductions:
         res["reductions"] = run_reductions(args)
+    if not args.no_species:
+        res["species_form_factors"] = run_species(args)
     print(json.dumps(res), flush=True)
 
 
