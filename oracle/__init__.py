@@ -21,6 +21,8 @@ Functions (each cites the passage it follows in ``xs_oracle.c``):
 - ``form_factors``       Sec. 2.1: Gaussian-sum atomic form factors f_s(|q|)
 - ``intensity_species``  Eqs. (Iq_rij), (pe_ri) with f_j(q) of each atom's species
 - ``intensity_species_grad``  chain rule through the same, FP64 form
+- ``frame_sums``         incoherent sums of configurations / exposure integrals (Sec. 4.5, Eq. (inte_Iq))
+- ``ring_histogram``     distribution of I / <I>_ring per frame and ring (Sec. 4.5, Eq. (Erlang))
 """
 from __future__ import annotations
 
@@ -75,6 +77,8 @@ def _load():
         "or_form_factors": (c_int, [i64, P, i32, P, P]),
         "or_intensity_species": (c_int, [i64, P, P, i32, P, i64, P, P, P, c_int]),
         "or_intensity_species_grad": (c_int, [i64, P, P, i32, P, i64, P, P, P, P, c_int]),
+        "or_frame_sums": (c_int, [P, i64, i64, i64, i64, i64, i64, P, c_int]),
+        "or_ring_histogram": (c_int, [P, i64, i64, P, P, i32, i32, d, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -300,3 +304,29 @@ def intensity_species_grad(pos, species, coef, q, amp, dL_dI, threads: int = 0):
                                              _ptr(q), _ptr(amp), _ptr(w), _ptr(g), int(threads)),
            "intensity_species_grad")
     return g
+
+
+def frame_sums(I, n_out: int, s_out: int, n_sum: int, s_sum: int, threads: int = 0):
+    """J [n_out, Q]: J[k] = pairwise sum over i < n_sum of I[k s_out + i s_sum] (I [F, Q])."""
+    I = _f64(I)
+    if I.ndim != 2:
+        raise ValueError("I must be [frames, pixels]")
+    J = np.empty((n_out, I.shape[1]))
+    _check(_load().or_frame_sums(_ptr(I), I.shape[0], I.shape[1], int(n_out), int(s_out), int(n_sum),
+                                 int(s_sum), _ptr(J), int(threads)), "frame_sums")
+    return J
+
+
+def ring_histogram(I, q, edges, n_bins: int, kappa_max: float):
+    """(counts [F, R, n_bins + 1] int64, ring means [F, R]) of kappa = I / <I>_ring."""
+    I = _f64(I)
+    if I.ndim != 2:
+        raise ValueError("I must be [frames, pixels]")
+    q = _f64(q, 3).reshape(-1, 3)
+    edges = _f64(edges).reshape(-1)
+    nr = edges.shape[0] - 1
+    counts = np.empty((I.shape[0], nr, n_bins + 1), dtype=np.int64)
+    mean = np.empty((I.shape[0], nr))
+    _check(_load().or_ring_histogram(_ptr(I), I.shape[0], I.shape[1], _ptr(q), _ptr(edges), nr, int(n_bins),
+                                     float(kappa_max), _ptr(counts), _ptr(mean)), "ring_histogram")
+    return counts, mean

@@ -775,3 +775,82 @@ int or_intensity_species_grad(int64_t n_atoms, const double *pos, const int32_t 
     free(fq);
     return OR_OK;
 }
+
+/*
+ * Sums of frames: incoherent superposition of independent configurations
+ * (Sec. 4.5: the speckle of several scattering volumes is the sum of their
+ * intensities) and exposure integrals over consecutive frames (Eq. (inte_Iq),
+ * rectangle rule), one definition for both:
+ *     J[k][p] = sum_{i < n_sum} I[k * s_out + i * s_sum][p],   k < n_out,
+ * each sum the pairwise tree over i in ascending order (adjacent pairs added
+ * level by level, an odd last element carried up: for n_sum = 2^l and
+ * s_sum = 1 this is the dyadic window sum of or_xsvs_contrast).
+ * I: [n_frames][n_q]; J: [n_out][n_q].
+ */
+int or_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t n_out, int64_t s_out,
+                  int64_t n_sum, int64_t s_sum, double *J, int n_threads)
+{
+    if (n_frames <= 0 || n_q < 0 || n_out <= 0 || n_sum <= 0 || s_out < 0 || s_sum < 0 || !J ||
+        (n_out - 1) * s_out + (n_sum - 1) * s_sum >= n_frames || (n_q > 0 && !I))
+        return OR_EINVAL;
+    const int nth = or_threads(n_threads);
+    double *bufs = malloc(sizeof(double) * (size_t)n_sum * (size_t)nth);
+    if (!bufs) return OR_ENOMEM;
+#pragma omp parallel for schedule(static) num_threads(nth)
+    for (int64_t p = 0; p < n_q; ++p) {
+        double *buf = bufs + (size_t)omp_thread_index() * (size_t)n_sum;
+        for (int64_t k = 0; k < n_out; ++k) {
+            for (int64_t i = 0; i < n_sum; ++i) buf[i] = I[(k * s_out + i * s_sum) * n_q + p];
+            J[k * n_q + p] = or_pairwise(buf, n_sum);
+        }
+    }
+    free(bufs);
+    return OR_OK;
+}
+
+/*
+ * Distribution of the normalized intensity kappa = I / <I>_ring per frame and
+ * ring (Sec. 4.5, Eq. (Erlang): for M superposed configurations kappa follows
+ * the Erlang distribution of order M):
+ *   <I>_ring = (pairwise sum over the ring's pixels, ascending index) / n,
+ *   u = (I / <I>_ring) * (n_bins / kappa_max)   (the factor rounded once),
+ *   bin = u < n_bins ? max(0, floor(u)) : n_bins   (n_bins: the overflow bin,
+ *         also taken by NaN).
+ * counts: [n_frames][n_rings][n_bins + 1]; mean (may be NULL):
+ * [n_frames][n_rings], NaN for an empty ring.
+ */
+int or_ring_histogram(const double *I, int64_t n_frames, int64_t n_q, const double *q, const double *edges,
+                      int32_t n_rings, int32_t n_bins, double kappa_max, int64_t *counts, double *mean)
+{
+    if (n_frames <= 0 || n_q < 0 || n_rings <= 0 || n_bins <= 0 || !(kappa_max > 0.0) || !counts)
+        return OR_EINVAL;
+    int32_t *ring = malloc(sizeof(int32_t) * (size_t)(n_q > 0 ? n_q : 1));
+    double *buf = malloc(sizeof(double) * (size_t)(n_q > 0 ? n_q : 1));
+    if (!ring || !buf) { free(ring); free(buf); return OR_ENOMEM; }
+    int rc = or_ring_index(n_q, q, n_rings, edges, ring);
+    if (rc != OR_OK) { free(ring); free(buf); return rc; }
+    int64_t *start = NULL, *list = NULL;
+    rc = or_ring_lists(n_q, ring, NULL, n_rings, &start, &list);
+    if (rc != OR_OK) { free(ring); free(buf); return rc; }
+    const double scale = (double)n_bins / kappa_max;
+    memset(counts, 0, sizeof(int64_t) * (size_t)n_frames * (size_t)n_rings * (size_t)(n_bins + 1));
+    for (int64_t t = 0; t < n_frames; ++t)
+        for (int32_t r = 0; r < n_rings; ++r) {
+            const int64_t n = start[r + 1] - start[r];
+            double m = NAN;
+            if (n > 0) {
+                for (int64_t i = 0; i < n; ++i) buf[i] = I[t * n_q + list[start[r] + i]];
+                m = or_pairwise(buf, n) / (double)n;
+            }
+            if (mean) mean[t * n_rings + r] = m;
+            int64_t *c = counts + (t * n_rings + r) * (int64_t)(n_bins + 1);
+            for (int64_t i = 0; i < n; ++i) {
+                const double u = (I[t * n_q + list[start[r] + i]] / m) * scale;
+                int64_t b = n_bins;
+                if (u < (double)n_bins) b = u > 0.0 ? (int64_t)floor(u) : 0;
+                c[b]++;
+            }
+        }
+    free(ring); free(buf); free(start); free(list);
+    return OR_OK;
+}

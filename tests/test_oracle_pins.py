@@ -667,3 +667,58 @@ def test_species_gradient_against_central_differences():
             Im, _ = oracle.intensity_species(pm, sp, _FF, q)
             fd = float(np.sum(np.longdouble(w) * (np.longdouble(Ip) - np.longdouble(Im)))) / (2 * h)
             assert abs(g[j, c] - fd) < 2e-6 * np.max(np.abs(g)) + 1e-9
+
+
+# ---------------------------------------------------------------- frame sums, intensity distribution
+
+def test_frame_sums_index_maps_on_integers():
+    """Exposure windows (s_sum = 1) and incoherent sums over configurations stored as
+    blocks of frames (s_sum = F): exact on small integers, so every index is checked."""
+    I = np.arange(60.0).reshape(12, 5)
+    J = oracle.frame_sums(I, 4, 3, 3, 1)                     # windows of 3 frames
+    assert np.array_equal(J, np.stack([I[3 * k:3 * k + 3].sum(axis=0) for k in range(4)]))
+    J = oracle.frame_sums(I, 10, 1, 3, 1)                    # sliding windows
+    assert np.array_equal(J, np.stack([I[k:k + 3].sum(axis=0) for k in range(10)]))
+    J = oracle.frame_sums(I, 4, 1, 3, 4)                     # 3 configurations x 4 frames
+    assert np.array_equal(J, np.stack([I[k] + I[k + 4] + I[k + 8] for k in range(4)]))
+    with pytest.raises(RuntimeError):
+        oracle.frame_sums(I, 4, 3, 4, 1)                     # runs past the last frame
+
+
+def test_frame_sums_follow_the_pairwise_tree():
+    rng = np.random.default_rng(51)
+    vals = [float(v) for v in 10.0 ** rng.uniform(-8, 8, 13)]
+    J = oracle.frame_sums(np.array(vals)[:, None], 1, 0, 13, 1)
+    assert J[0, 0] == _pairwise_recursive(vals)
+
+
+def test_ring_histogram_hand_example():
+    I = np.array([[0.0, 1.0, 5.0], [2.0, 3.0, 7.0]])
+    q = np.array([[0.5, 0, 0], [0.6, 0, 0], [1.5, 0, 0]])
+    c, m = oracle.ring_histogram(I, q, [0.0, 1.0, 2.0, 3.0], 4, 2.0)
+    # ring 0 holds pixels 0, 1; ring 1 pixel 2; ring 2 is empty
+    assert m[0, 0] == 0.5 and m[1, 0] == 2.5 and m[0, 1] == 5.0 and np.isnan(m[0, 2])
+    assert list(c[0, 0]) == [1, 0, 0, 0, 1]                  # kappa 0 -> bin 0; 2 -> overflow
+    assert list(c[1, 0]) == [0, 1, 1, 0, 0]                  # kappa 0.8, 1.2
+    assert list(c[0, 1]) == [0, 0, 1, 0, 0]                  # kappa 1 -> u = 2
+    assert c[:, 2].sum() == 0
+
+
+def test_incoherent_sum_of_m_configurations_follows_erlang():
+    """M independent speckle patterns (exponential intensities) summed: kappa = I/<I>
+    follows Eq. (Erlang) of order M, and the contrast is 1/M (Sec. 4.5); statistical,
+    60,000 pixels."""
+    rng = np.random.default_rng(52)
+    Q, kmax, nb = 60000, 4.0, 40
+    q = np.tile([[0.5, 0, 0]], (Q, 1))
+    for M in (1, 5, 10):
+        I = rng.exponential(1.0, (M, Q))
+        J = oracle.frame_sums(I, 1, 0, M, 1)
+        c, _ = oracle.ring_histogram(J, q, [0.0, 1.0], nb, kmax)
+        edges = np.linspace(0, kmax, nb + 1)
+        mid = 0.5 * (edges[1:] + edges[:-1])
+        pdf = M ** M * mid ** (M - 1) / math.factorial(M - 1) * np.exp(-mid * M)
+        emp = c[0, 0, :nb] / Q / (kmax / nb)
+        assert np.max(np.abs(emp - pdf)) < 0.06 * pdf.max() + 0.02
+        beta = oracle.xsvs_contrast(J, q, [0.0, 1.0], 1)[0, 0]
+        assert abs(beta * M - 1.0) < 0.03
