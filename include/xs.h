@@ -259,6 +259,41 @@ xs_status xs_isf_rings(const double *amp, int64_t n_frames, int64_t n_q, const d
 xs_status xs_siegert(const double *g2, const double *F, int32_t n_rings, int32_t n_tau, int32_t n_levels,
                      double *lhs_out, double *fhat2_out, double *beta_out, void *stream);
 
+/*
+ * Sums of frames, one definition for two uses of Sec. 4.5 and Eq. (inte_Iq):
+ *     J[k][p] = sum_{i < n_sum} I[k * s_out + i * s_sum][p],   k < n_out,
+ * - incoherent superposition of M independent configurations stored as blocks
+ *   of F frames: n_out = F, s_out = 1, n_sum = M, s_sum = F;
+ * - exposure integrals over W frames (rectangle rule): n_sum = W, s_sum = 1,
+ *   s_out = W (non-overlapping) or 1 (sliding); xs_g2_rings of J is then the
+ *   g2 of the exposure-integrated intensity, Eq. (g2_def_pulse).
+ *   I      device double [n_frames][n_q];  J_out device double [n_out][n_q]
+ * Each sum is the pairwise tree over i in ascending order (adjacent pairs added
+ * level by level, an odd last element carried up; for n_sum = 2^l, s_sum = 1 it
+ * is the dyadic window sum of xs_xsvs_contrast), bit-for-bit equal to the
+ * oracle.  Needs (n_out-1) s_out + (n_sum-1) s_sum < n_frames, n_sum <= 2^24.
+ */
+xs_status xs_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t n_out, int64_t s_out,
+                        int64_t n_sum, int64_t s_sum, double *J_out, void *stream);
+
+/*
+ * Distribution of the normalized intensity kappa = I / <I>_ring per frame and
+ * ring (Sec. 4.5, Eq. (Erlang): kappa of M superposed speckle patterns follows
+ * the Erlang law of order M):
+ *     <I>_ring = (pairwise sum over the ring's pixels, ascending index) / n,
+ *     u = (I / <I>_ring) * (n_bins / kappa_max),
+ *     bin = floor(u) for 0 <= u < n_bins (u <= 0: bin 0), else bin n_bins
+ *           (overflow; NaN too).
+ *   I, q, ring_edges, n_rings as for xs_g2_rings; n_frames <= 65535
+ *   counts_out device int64 [n_frames][n_rings][n_bins + 1]
+ *   mean_out   device double [n_frames][n_rings] (NaN for empty rings), or NULL
+ * n_rings * (n_bins + 1) <= 16384.  Counts are exact; bins are decided in FP64
+ * exactly as the oracle decides them.
+ */
+xs_status xs_ring_histogram(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                            const double *ring_edges, int32_t n_rings, int32_t n_bins, double kappa_max,
+                            int64_t *counts_out, double *mean_out, void *stream);
+
 /* Thread-local message for the last non-OK status returned to this thread. */
 const char *xs_last_error(void);
 
@@ -277,7 +312,8 @@ xs_status xs_shutdown(void);
  *   pixel_split     pixels per gradient work item (multiple of 64)
  *   waves_per_simd  0: compiler's register allocation; 4: variant bounded to
  *                   128 VGPRs (4 wavefronts per SIMD), built for forward
- *                   q_per_lane 2 and 4 and gradient q_per_lane 4
+ *                   q_per_lane 2, 4 and (lattice form only; the general form
+ *                   keeps its own allocation) 8, and gradient q_per_lane 4
  *   lattice         plans only (0 or 1): when a system's pixels come in rows
  *                   of n2 consecutive q-vectors that each step by one common
  *                   vector a (a planar detector grid stored row by row; see

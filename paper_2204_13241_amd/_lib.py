@@ -21,6 +21,7 @@ EXPORTS = [
     "xs_speckle_loss", "xs_position_step", "xs_timing_enable", "xs_timing_read",
     "xs_roofline_probe", "xs_plan_create", "xs_plan_intensity", "xs_plan_grad", "xs_plan_destroy",
     "xs_plan_describe", "xs_isf_rings", "xs_siegert", "xs_intensity_species", "xs_intensity_species_grad",
+    "xs_frame_sums", "xs_ring_histogram",
 ]
 
 _P = ctypes.c_void_p
@@ -96,6 +97,8 @@ def load():
         "xs_siegert": (i32, [_P, _P, i32, i32, i32, _P, _P, _P, _P]),
         "xs_intensity_species": (i32, [bp, _P, _P, i32, _P, _P, i32, _P, _P, _P]),
         "xs_intensity_species_grad": (i32, [bp, _P, _P, i32, _P, _P, _P, _P, i32, _P, _P, _P]),
+        "xs_frame_sums": (i32, [_P, i64, i64, i64, i64, i64, i64, _P, _P]),
+        "xs_ring_histogram": (i32, [_P, i64, i64, _P, _P, i32, i32, ctypes.c_double, _P, _P, _P]),
         "xs_last_error": (ctypes.c_char_p, []),
         "xs_version": (i32, []),
         "xs_shutdown": (i32, []),

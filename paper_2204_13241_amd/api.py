@@ -318,6 +318,32 @@ def siegert(g2: torch.Tensor, F: torch.Tensor, n_levels: int):
     return lhs, fh, beta
 
 
+def frame_sums(I: torch.Tensor, n_out: int, s_out: int, n_sum: int, s_sum: int):
+    """J [n_out, Q]: J[k] = pairwise sum over i < n_sum of I[k s_out + i s_sum] (I [F, Q])."""
+    _need(I, "I")
+    if I.dim() != 2:
+        raise ValueError("I must be [F, Q]")
+    J = torch.empty((int(n_out), I.shape[1]), dtype=torch.float64, device=I.device)
+    _lib.check(_lib.load().xs_frame_sums(_ptr(I), I.shape[0], I.shape[1], int(n_out), int(s_out), int(n_sum),
+                                         int(s_sum), _ptr(J), _stream()))
+    return J
+
+
+def ring_histogram(I: torch.Tensor, q: torch.Tensor, edges, n_bins: int, kappa_max: float):
+    """(counts [F, R, n_bins + 1] int64, ring means [F, R]) of kappa = I / <I>_ring."""
+    _need(I, "I"), _need(q, "q")
+    if I.dim() != 2 or q.shape != (I.shape[1], 3):
+        raise ValueError("I must be [F, Q] and q [Q, 3]")
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    R = e.shape[0] - 1
+    counts = torch.empty((I.shape[0], R, int(n_bins) + 1), dtype=torch.int64, device=I.device)
+    mean = torch.empty((I.shape[0], R), dtype=torch.float64, device=I.device)
+    _lib.check(_lib.load().xs_ring_histogram(_ptr(I), I.shape[0], I.shape[1], _ptr(q),
+                                             e.ctypes.data_as(ctypes.c_void_p), R, int(n_bins), float(kappa_max),
+                                             _ptr(counts), _ptr(mean), _stream()))
+    return counts, mean
+
+
 def get_tile_shape(kind: int) -> dict:
     s = _lib.XsTileShape()
     _lib.check(_lib.load().xs_get_tile_shape(int(kind), ctypes.byref(s)))

@@ -598,8 +598,9 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
 // v_sin/v_cos pair; every g_jk comes from its own sincos, so the error does not
 // grow with k.  Base phases theta_k = frac(q_{p0}.o + k a.o) (FP64) rotate the
 // tile sums as in the general form.
-// LDS per staged atom: float4 (d, f) and QL/2 float4 holding g_1 .. g_{QL-1}
-// (re, im) and beta in the last slot.
+// LDS per staged atom: float2 (d_x, d_y), float d_z and QL/2 float4 holding
+// g_1 .. g_{QL-1} (re, im), beta and f in the last slot (40 KB per block at
+// QL = 8 with two buffers, so four blocks share a CU).
 template <int QL>
 __device__ __forceinline__ void lattice_atom_factors(const float4 &h, float e, float beta, float4 *dst) {
     float g[2 * QL];
@@ -613,30 +614,31 @@ __device__ __forceinline__ void lattice_atom_factors(const float4 &h, float e, f
     g[1] = 0.f;
 #pragma unroll
     for (int v = 0; v < QL / 2; ++v) {
-        // slot v: g_{2v+1}, g_{2v+2}; the last slot: g_{QL-1}, beta, 0
+        // slot v: g_{2v+1}, g_{2v+2}; the last slot: g_{QL-1}, beta, f
         const int k1 = 2 * v + 1, k2 = 2 * v + 2;
         if (k2 < QL) dst[v] = make_float4(g[2 * k1], g[2 * k1 + 1], g[2 * k2], g[2 * k2 + 1]);
-        else dst[v] = make_float4(g[2 * k1], g[2 * k1 + 1], g[0], 0.f);
+        else dst[v] = make_float4(g[2 * k1], g[2 * k1 + 1], g[0], h.w);
     }
 }
 
 template <int QL, bool PLANAR>
-__device__ __forceinline__ void lattice_tile(const float4 *__restrict__ at, const float4 *__restrict__ gt,
-                                             float dqx, float dqy, float dqz, float (&cs)[QL], float (&sn)[QL]) {
+__device__ __forceinline__ void lattice_tile(const float2 *__restrict__ axy, const float *__restrict__ az,
+                                             const float4 *__restrict__ gt, float dqx, float dqy, float dqz,
+                                             float (&cs)[QL], float (&sn)[QL]) {
     constexpr int NV = QL / 2;
 #pragma unroll 2
     for (int j = 0; j < kTile; ++j) {
-        const float4 a = at[j];
+        const float2 a = axy[j];
         float4 g[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) g[v] = gt[j * NV + v];
-        const float beta = g[NV - 1].z;
+        const float beta = g[NV - 1].z, fw = g[NV - 1].w;
         float ph = __builtin_fmaf(dqx, a.x, beta);
         ph = __builtin_fmaf(dqy, a.y, ph);
-        if (!PLANAR) ph = __builtin_fmaf(dqz, a.z, ph);
+        if (!PLANAR) ph = __builtin_fmaf(dqz, az[j], ph);
         const float zc = __builtin_amdgcn_cosf(ph), zs = __builtin_amdgcn_sinf(ph);
-        cs[0] = __builtin_fmaf(a.w, zc, cs[0]);
-        sn[0] = __builtin_fmaf(a.w, zs, sn[0]);
+        cs[0] = __builtin_fmaf(fw, zc, cs[0]);
+        sn[0] = __builtin_fmaf(fw, zs, sn[0]);
 #pragma unroll
         for (int k = 1; k < QL; ++k) {
             const float4 &gv = g[(k - 1) / 2];
@@ -657,7 +659,8 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice(
     const float4 *__restrict__ t_lo, const double4 *__restrict__ origins, double2 *__restrict__ partial) {
     static_assert(QL % 2 == 0, "runs of an even number of pixels");
     constexpr int NV = QL / 2;
-    __shared__ float4 s_atoms[2][kWaves * kTile];
+    __shared__ float2 s_xy[2][kWaves * kTile];
+    __shared__ float s_z[2][kWaves * kTile];
     __shared__ float4 s_g[2][kWaves * kTile * NV];
     __shared__ double4 s_orig[2][kWaves];
     __shared__ double s_red[6][kWaves];
@@ -730,7 +733,8 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice(
             const double b = __builtin_fma(cen[2], double(h.z) + double(l.z),
                              __builtin_fma(cen[1], double(h.y) + double(l.y), cen[0] * (double(h.x) + double(l.x))));
             const float e = __builtin_fmaf(afz, h.z, __builtin_fmaf(afy, h.y, afx * h.x));
-            s_atoms[buf][tid] = h;
+            s_xy[buf][tid] = make_float2(h.x, h.y);
+            s_z[buf][tid] = h.z;
             lattice_atom_factors<QL>(h, e, frac_f32(b), &s_g[buf][tid * NV]);
         };
         {
@@ -764,10 +768,11 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice(
                 float cs[QL], sn[QL];
 #pragma unroll
                 for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
-                const float4 *at = &s_atoms[buf][w * kTile];
+                const float2 *axy = &s_xy[buf][w * kTile];
+                const float *azp = &s_z[buf][w * kTile];
                 const float4 *gt = &s_g[buf][w * kTile * NV];
-                if (planar) lattice_tile<QL, true>(at, gt, dqx, dqy, dqz, cs, sn);
-                else lattice_tile<QL, false>(at, gt, dqx, dqy, dqz, cs, sn);
+                if (planar) lattice_tile<QL, true>(axy, azp, gt, dqx, dqy, dqz, cs, sn);
+                else lattice_tile<QL, false>(axy, azp, gt, dqx, dqy, dqz, cs, sn);
                 const double4 o = s_orig[buf][w];
                 const double s0 = __builtin_fma(q0[2], o.z, __builtin_fma(q0[1], o.y, q0[0] * o.x));
                 const double t1 = __builtin_fma(az, o.z, __builtin_fma(ay, o.y, ax * o.x));
@@ -1653,7 +1658,7 @@ bool launch_lattice_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt,
     case 1:
     case 2: o4 ? launch_lattice<2, 4>(s, n, cnt, b, q) : launch_lattice<2, 1>(s, n, cnt, b, q); return true;
     case 4: o4 ? launch_lattice<4, 4>(s, n, cnt, b, q) : launch_lattice<4, 1>(s, n, cnt, b, q); return true;
-    case 8: launch_lattice<8, 1>(s, n, cnt, b, q); return true;
+    case 8: o4 ? launch_lattice<8, 4>(s, n, cnt, b, q) : launch_lattice<8, 1>(s, n, cnt, b, q); return true;
     default: return false;
     }
 }

@@ -812,6 +812,106 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_mean(const double *__restrict__
     if (threadIdx.x == 0) beta_out[r] = acc / static_cast<double>(K);
 }
 
+// ---------------------------------------------------------------- frame sums, histogram
+
+constexpr int kSumLevels = 24;  // frame sums of up to 2^24 terms
+
+// J[k][p] = pairwise tree over i < n_sum of I[k s_out + i s_sum][p]: a binary
+// counter holds the complete subtrees (st[l]: 2^l terms while bit l of n_done
+// is set; a new term merges left + right up the set bits), then the fold from
+// the right, which is the bottom-up tree with the odd element carried up.  The
+// counter is the same in every lane, so its branches are uniform.
+__global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict__ I, int64_t n_q, int64_t n_out,
+                                                       int64_t s_out, int64_t n_sum, int64_t s_sum,
+                                                       double *__restrict__ J) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (idx >= n_out * n_q) return;
+    const int64_t k = idx / n_q, p = idx - k * n_q;
+    double st[kSumLevels];
+    int64_t n_done = 0;
+    const double *src = I + k * s_out * n_q + p;
+    for (int64_t i = 0; i < n_sum; ++i) {
+        double v = src[i * s_sum * n_q];
+        bool carry = true;
+#pragma unroll
+        for (int l = 0; l < kSumLevels; ++l) {
+            if (carry) {
+                if ((n_done >> l) & 1) {
+                    v = st[l] + v;
+                } else {
+                    st[l] = v;
+                    carry = false;
+                }
+            }
+        }
+        ++n_done;
+    }
+    double sum = 0.0;
+    bool have = false;
+#pragma unroll
+    for (int l = 0; l < kSumLevels; ++l)
+        if ((n_done >> l) & 1) {
+            sum = have ? st[l] + sum : st[l];
+            have = true;
+        }
+    J[idx] = sum;
+}
+
+// Ring-ordered rows of the frames: X[m][t] = I[t][list[m]] for the in-ring
+// pixels m < ring_start[R] (list holds no pixel beyond them).
+__global__ __launch_bounds__(kBlock) void k_ring_rows(const double *__restrict__ I, int64_t F, int64_t n_q,
+                                                      const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ ring_start, int32_t R,
+                                                      double *__restrict__ X) {
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t m = idx / F, t = idx - m * F;
+    if (m >= ring_start[R]) return;
+    X[idx] = I[t * n_q + list[m]];
+}
+
+// Histogram of u = (I / <I>_ring) * scale per (frame, ring): bin floor(u) for
+// 0 <= u < n_bins (u <= 0: bin 0), else the overflow bin n_bins (NaN too).
+// Block = (pixel chunk of one frame); counts gathered in LDS, then added to
+// counts[(t R + r)(n_bins + 1) + b] with global atomics.
+__global__ __launch_bounds__(kBlock) void k_ring_hist(const double *__restrict__ I, int64_t n_q,
+                                                      const int32_t *__restrict__ key, int32_t R,
+                                                      const double *__restrict__ mean, int32_t n_bins,
+                                                      double scale, unsigned long long *__restrict__ counts) {
+    extern __shared__ unsigned int h[];
+    const int nb1 = n_bins + 1, nh = R * nb1;
+    for (int i = threadIdx.x; i < nh; i += kBlock) h[i] = 0u;
+    __syncthreads();
+    const int64_t t = blockIdx.y;
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (p < n_q) {
+        const int r = key[p];
+        if (r >= 0) {
+            const double u = (I[t * n_q + p] / mean[t * R + r]) * scale;
+            int b = n_bins;
+            if (u < static_cast<double>(n_bins)) b = u > 0.0 ? static_cast<int>(floor(u)) : 0;
+            atomicAdd(&h[r * nb1 + b], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nh; i += kBlock)
+        if (h[i]) atomicAdd(&counts[t * nh + i], static_cast<unsigned long long>(h[i]));
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long *__restrict__ p, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock)
+        p[i] = 0ull;
+}
+
+// out[c][r] = in[r][c] for an R x C table.
+__global__ __launch_bounds__(kBlock) void k_transpose_rt(const double *__restrict__ in, int64_t R, int64_t C,
+                                                         double *__restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= R * C) return;
+    const int64_t r = i / C, c = i - r * C;
+    out[c * R + r] = in[i];
+}
+
 // ---------------------------------------------------------------- host side
 
 // Tree levels above the leaves so that every ring of up to n_q leaves ends with one value.
@@ -1064,6 +1164,55 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         K >>= kLvDepth;
     }
     timer_end(s, TIMER_XSVS, tok, static_cast<double>(F) * n_q * sizeof(double));
+    return XS_OK;
+}
+
+xs_status frame_sums(hipStream_t s, const double *I, int64_t n_q, int64_t n_out, int64_t s_out, int64_t n_sum,
+                     int64_t s_sum, double *J) {
+    if (n_sum > (int64_t(1) << kSumLevels)) return set_error(XS_EINVAL, "n_sum must be <= 2^%d", kSumLevels);
+    if (n_out * n_q > 0)
+        hipLaunchKernelGGL(k_frame_sums, dim3(blocks_for(n_out * n_q)), dim3(kBlock), 0, s, I, n_q, n_out, s_out,
+                           n_sum, s_sum, J);
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+xs_status ring_histogram(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,
+                         const RingEdges &edges, int32_t n_bins, double kappa_max, int64_t *counts, double *mean) {
+    const int32_t R = edges.n_rings;
+    const int64_t nh = static_cast<int64_t>(R) * (n_bins + 1);
+    if (nh * static_cast<int64_t>(sizeof(unsigned int)) > 65536)
+        return set_error(XS_EINVAL, "n_rings * (n_bins + 1) must be <= 16384");
+    void *key = nullptr, *X = nullptr, *X2 = nullptr, *mu = nullptr;
+    XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
+    XS_TRY(scratch(s, SLOT_G, sizeof(double) * std::max<int64_t>(n_q * F, 1), &X));
+    XS_TRY(scratch(s, SLOT_LEVEL_B, sizeof(double) * level_bound(n_q, R, 1) * F, &X2));
+    XS_TRY(scratch(s, SLOT_BWIN, sizeof(double) * 2 * std::max<int64_t>(F * R, 1), &mu));
+    if (!mean) mean = static_cast<double *>(mu) + std::max<int64_t>(F * R, 1);  // [F][R] kept internally
+    int32_t *k = static_cast<int32_t *>(key);
+    if (n_q > 0) hipLaunchKernelGGL(k_ring_key, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, q, n_q, edges, k);
+    Partition P;
+    XS_TRY(partition(s, k, n_q, R, &P));
+    if (n_q > 0)
+        hipLaunchKernelGGL(k_ring_rows, dim3(blocks_for(n_q * F)), dim3(kBlock), 0, s, I, F, n_q,
+                           static_cast<const int32_t *>(P.list), static_cast<const int32_t *>(P.start), R,
+                           static_cast<double *>(X));
+    // ring means per frame: pairwise tree over the ring-ordered rows (columns = frames)
+    const double *top = reduce_tree(s, P, R, 0, n_q, F, static_cast<double *>(X), static_cast<double *>(X2));
+    double *m_rt = static_cast<double *>(mu);  // [R][F]
+    hipLaunchKernelGGL(k_ring_mean_finish, dim3(blocks_for(static_cast<int64_t>(R) * F)), dim3(kBlock), 0, s, top,
+                       F, R, P.start, P.lev + static_cast<int64_t>(P.levels) * (R + 1), m_rt,
+                       static_cast<int32_t *>(nullptr));
+    hipLaunchKernelGGL(k_transpose_rt, dim3(blocks_for(static_cast<int64_t>(R) * F)), dim3(kBlock), 0, s,
+                       static_cast<const double *>(m_rt), static_cast<int64_t>(R), F, mean);
+    hipLaunchKernelGGL(k_fill_u64, dim3(std::min<unsigned>(blocks_for(nh * F), 4096u)), dim3(kBlock), 0, s,
+                       reinterpret_cast<unsigned long long *>(counts), nh * F);
+    if (n_q > 0)
+        hipLaunchKernelGGL(k_ring_hist, dim3(blocks_for(n_q), static_cast<unsigned>(F)), dim3(kBlock),
+                           sizeof(unsigned int) * nh, s, I, n_q, static_cast<const int32_t *>(k), R,
+                           static_cast<const double *>(mean), n_bins, static_cast<double>(n_bins) / kappa_max,
+                           reinterpret_cast<unsigned long long *>(counts));
+    XS_HIP(hipGetLastError());
     return XS_OK;
 }
 

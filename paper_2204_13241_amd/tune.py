@@ -22,7 +22,7 @@ from . import api
 
 # (pixels per lane, waves-per-SIMD bound) x atom tiles per item
 FWD_CANDIDATES = [(ql, occ, split)
-                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0))
+                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4))
                   for split in (16, 32, 64, 128)]
 # (atoms per lane, waves-per-SIMD bound) x pixels per item
 GRAD_CANDIDATES = [(al, occ, pc)
@@ -45,7 +45,7 @@ def signature(systems, planar: bool) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v2|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
+    return "v3|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved")
 
