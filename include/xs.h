@@ -260,21 +260,27 @@ xs_status xs_siegert(const double *g2, const double *F, int32_t n_rings, int32_t
                      double *lhs_out, double *fhat2_out, double *beta_out, void *stream);
 
 /*
- * Sums of frames, one definition for two uses of Sec. 4.5 and Eq. (inte_Iq):
- *     J[k][p] = sum_{i < n_sum} I[k * s_out + i * s_sum][p],   k < n_out,
+ * Sums of frames, one definition for the uses of Sec. 4.5, Eq. (inte_Iq) and
+ * the pixel integral of Sec. 3.1:
+ *     J[k][p] = scale * sum_{i < n_sum} I[k * s_out + i * s_sum][p],   k < n_out,
  * - incoherent superposition of M independent configurations stored as blocks
  *   of F frames: n_out = F, s_out = 1, n_sum = M, s_sum = F;
  * - exposure integrals over W frames (rectangle rule): n_sum = W, s_sum = 1,
  *   s_out = W (non-overlapping) or 1 (sliding); xs_g2_rings of J is then the
- *   g2 of the exposure-integrated intensity, Eq. (g2_def_pulse).
+ *   g2 of the exposure-integrated intensity, Eq. (g2_def_pulse);
+ * - a detector pixel's mean over S sub-pixel wavevectors (Sec. 3.1: a pixel
+ *   covers a small range of q), the intensity computed on q stored as S blocks
+ *   of the Q pixels, so that a frame's row reads as S rows of Q: n_frames =
+ *   F S, n_out = F, s_out = S, n_sum = S, s_sum = 1, scale = 1/S.
  *   I      device double [n_frames][n_q];  J_out device double [n_out][n_q]
+ *   scale  finite; the sum is multiplied by it once (1: the plain sum)
  * Each sum is the pairwise tree over i in ascending order (adjacent pairs added
  * level by level, an odd last element carried up; for n_sum = 2^l, s_sum = 1 it
  * is the dyadic window sum of xs_xsvs_contrast), bit-for-bit equal to the
  * oracle.  Needs (n_out-1) s_out + (n_sum-1) s_sum < n_frames, n_sum <= 2^24.
  */
 xs_status xs_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t n_out, int64_t s_out,
-                        int64_t n_sum, int64_t s_sum, double *J_out, void *stream);
+                        int64_t n_sum, int64_t s_sum, double scale, double *J_out, void *stream);
 
 /*
  * Distribution of the normalized intensity kappa = I / <I>_ring per frame and
@@ -313,7 +319,8 @@ xs_status xs_shutdown(void);
  *   waves_per_simd  0: compiler's register allocation; 4: variant bounded to
  *                   128 VGPRs (4 wavefronts per SIMD), built for forward
  *                   q_per_lane 2, 4 and (lattice form only; the general form
- *                   keeps its own allocation) 8, and gradient q_per_lane 4
+ *                   keeps its own allocation) 8, and gradient q_per_lane 4;
+ *                   5: bounded to 96 VGPRs, built for gradient q_per_lane 2
  *   lattice         plans only (0 or 1): when a system's pixels come in rows
  *                   of n2 consecutive q-vectors that each step by one common
  *                   vector a (a planar detector grid stored row by row; see

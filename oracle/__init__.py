@@ -77,7 +77,7 @@ def _load():
         "or_form_factors": (c_int, [i64, P, i32, P, P]),
         "or_intensity_species": (c_int, [i64, P, P, i32, P, i64, P, P, P, c_int]),
         "or_intensity_species_grad": (c_int, [i64, P, P, i32, P, i64, P, P, P, P, c_int]),
-        "or_frame_sums": (c_int, [P, i64, i64, i64, i64, i64, i64, P, c_int]),
+        "or_frame_sums": (c_int, [P, i64, i64, i64, i64, i64, i64, d, P, c_int]),
         "or_ring_histogram": (c_int, [P, i64, i64, P, P, i32, i32, d, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -306,14 +306,14 @@ def intensity_species_grad(pos, species, coef, q, amp, dL_dI, threads: int = 0):
     return g
 
 
-def frame_sums(I, n_out: int, s_out: int, n_sum: int, s_sum: int, threads: int = 0):
-    """J [n_out, Q]: J[k] = pairwise sum over i < n_sum of I[k s_out + i s_sum] (I [F, Q])."""
+def frame_sums(I, n_out: int, s_out: int, n_sum: int, s_sum: int, scale: float = 1.0, threads: int = 0):
+    """J [n_out, Q]: J[k] = scale * pairwise sum over i < n_sum of I[k s_out + i s_sum] (I [F, Q])."""
     I = _f64(I)
     if I.ndim != 2:
         raise ValueError("I must be [frames, pixels]")
     J = np.empty((n_out, I.shape[1]))
     _check(_load().or_frame_sums(_ptr(I), I.shape[0], I.shape[1], int(n_out), int(s_out), int(n_sum),
-                                 int(s_sum), _ptr(J), int(threads)), "frame_sums")
+                                 int(s_sum), float(scale), _ptr(J), int(threads)), "frame_sums")
     return J
 
 

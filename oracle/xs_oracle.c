@@ -784,11 +784,15 @@ int or_intensity_species_grad(int64_t n_atoms, const double *pos, const int32_t 
  *     J[k][p] = sum_{i < n_sum} I[k * s_out + i * s_sum][p],   k < n_out,
  * each sum the pairwise tree over i in ascending order (adjacent pairs added
  * level by level, an odd last element carried up: for n_sum = 2^l and
- * s_sum = 1 this is the dyadic window sum of or_xsvs_contrast).
+ * s_sum = 1 this is the dyadic window sum of or_xsvs_contrast), then
+ * multiplied by `scale` (one rounding; 1 leaves the sum as it is).  With
+ * scale = 1/S over S sub-pixel wavevectors stored as S blocks of a frame's
+ * pixels, J is the pixel's mean intensity: the integral over the pixel's
+ * small range of q that Sec. 3.1 notes a detector pixel needs.
  * I: [n_frames][n_q]; J: [n_out][n_q].
  */
 int or_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t n_out, int64_t s_out,
-                  int64_t n_sum, int64_t s_sum, double *J, int n_threads)
+                  int64_t n_sum, int64_t s_sum, double scale, double *J, int n_threads)
 {
     if (n_frames <= 0 || n_q < 0 || n_out <= 0 || n_sum <= 0 || s_out < 0 || s_sum < 0 || !J ||
         (n_out - 1) * s_out + (n_sum - 1) * s_sum >= n_frames || (n_q > 0 && !I))
@@ -801,7 +805,7 @@ int or_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t n_out,
         double *buf = bufs + (size_t)omp_thread_index() * (size_t)n_sum;
         for (int64_t k = 0; k < n_out; ++k) {
             for (int64_t i = 0; i < n_sum; ++i) buf[i] = I[(k * s_out + i * s_sum) * n_q + p];
-            J[k * n_q + p] = or_pairwise(buf, n_sum);
+            J[k * n_q + p] = or_pairwise(buf, n_sum) * scale;
         }
     }
     free(bufs);

@@ -97,7 +97,7 @@ def load():
         "xs_siegert": (i32, [_P, _P, i32, i32, i32, _P, _P, _P, _P]),
         "xs_intensity_species": (i32, [bp, _P, _P, i32, _P, _P, i32, _P, _P, _P]),
         "xs_intensity_species_grad": (i32, [bp, _P, _P, i32, _P, _P, _P, _P, i32, _P, _P, _P]),
-        "xs_frame_sums": (i32, [_P, i64, i64, i64, i64, i64, i64, _P, _P]),
+        "xs_frame_sums": (i32, [_P, i64, i64, i64, i64, i64, i64, ctypes.c_double, _P, _P]),
         "xs_ring_histogram": (i32, [_P, i64, i64, _P, _P, i32, i32, ctypes.c_double, _P, _P, _P]),
         "xs_last_error": (ctypes.c_char_p, []),
         "xs_version": (i32, []),

@@ -318,15 +318,31 @@ def siegert(g2: torch.Tensor, F: torch.Tensor, n_levels: int):
     return lhs, fh, beta
 
 
-def frame_sums(I: torch.Tensor, n_out: int, s_out: int, n_sum: int, s_sum: int):
-    """J [n_out, Q]: J[k] = pairwise sum over i < n_sum of I[k s_out + i s_sum] (I [F, Q])."""
+def frame_sums(I: torch.Tensor, n_out: int, s_out: int, n_sum: int, s_sum: int, scale: float = 1.0):
+    """J [n_out, Q]: J[k] = scale * pairwise sum over i < n_sum of I[k s_out + i s_sum] (I [F, Q])."""
     _need(I, "I")
     if I.dim() != 2:
         raise ValueError("I must be [F, Q]")
     J = torch.empty((int(n_out), I.shape[1]), dtype=torch.float64, device=I.device)
     _lib.check(_lib.load().xs_frame_sums(_ptr(I), I.shape[0], I.shape[1], int(n_out), int(s_out), int(n_sum),
-                                         int(s_sum), _ptr(J), _stream()))
+                                         int(s_sum), float(scale), _ptr(J), _stream()))
     return J
+
+
+def intensity_pixel_mean(pos: torch.Tensor, f: torch.Tensor, q_sub: torch.Tensor, precision="fp32c", box=None):
+    """Detector-pixel intensity as the mean over S sub-pixel wavevectors (the pixel
+    integral of Sec. 3.1).  q_sub [S, Q, 3]: S sub-samples of each of Q pixels.
+    Returns [F, Q] (or [Q] for pos [N, 3])."""
+    _need(q_sub, "q_sub")
+    if q_sub.dim() != 3 or q_sub.shape[2] != 3:
+        raise ValueError("q_sub must be [S, Q, 3]")
+    S, Q = int(q_sub.shape[0]), int(q_sub.shape[1])
+    single = pos.dim() == 2
+    I = intensity(pos, f, q_sub.reshape(S * Q, 3), precision=precision, box=box)
+    I2 = I.reshape(-1, Q)                   # frames x S rows of Q pixels
+    F = I2.shape[0] // S
+    J = frame_sums(I2, F, S, S, 1, 1.0 / S)
+    return J[0] if single else J
 
 
 def ring_histogram(I: torch.Tensor, q: torch.Tensor, edges, n_bins: int, kappa_max: float):

@@ -1682,7 +1682,9 @@ bool launch_grad_variant(hipStream_t s, int al, int occ, bool lat, const GradIte
     const bool o4 = occ == 4;
     switch (al) {
     case 1: launch_grad<1, 1>(s, lat, items, n, cnt, b); return true;
-    case 2: launch_grad<2, 1>(s, lat, items, n, cnt, b); return true;
+    case 2:
+        occ == 5 ? launch_grad<2, 5>(s, lat, items, n, cnt, b) : launch_grad<2, 1>(s, lat, items, n, cnt, b);
+        return true;
     case 4:
         o4 ? launch_grad<4, 4>(s, lat, items, n, cnt, b) : launch_grad<4, 1>(s, lat, items, n, cnt, b);
         return true;

@@ -816,13 +816,13 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_mean(const double *__restrict__
 
 constexpr int kSumLevels = 24;  // frame sums of up to 2^24 terms
 
-// J[k][p] = pairwise tree over i < n_sum of I[k s_out + i s_sum][p]: a binary
+// J[k][p] = scale * pairwise tree over i < n_sum of I[k s_out + i s_sum][p]: a binary
 // counter holds the complete subtrees (st[l]: 2^l terms while bit l of n_done
 // is set; a new term merges left + right up the set bits), then the fold from
 // the right, which is the bottom-up tree with the odd element carried up.  The
 // counter is the same in every lane, so its branches are uniform.
 __global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict__ I, int64_t n_q, int64_t n_out,
-                                                       int64_t s_out, int64_t n_sum, int64_t s_sum,
+                                                       int64_t s_out, int64_t n_sum, int64_t s_sum, double scale,
                                                        double *__restrict__ J) {
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (idx >= n_out * n_q) return;
@@ -854,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict_
             sum = have ? st[l] + sum : st[l];
             have = true;
         }
-    J[idx] = sum;
+    J[idx] = sum * scale;
 }
 
 // Ring-ordered rows of the frames: X[m][t] = I[t][list[m]] for the in-ring
@@ -1168,11 +1168,11 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
 }
 
 xs_status frame_sums(hipStream_t s, const double *I, int64_t n_q, int64_t n_out, int64_t s_out, int64_t n_sum,
-                     int64_t s_sum, double *J) {
+                     int64_t s_sum, double scale, double *J) {
     if (n_sum > (int64_t(1) << kSumLevels)) return set_error(XS_EINVAL, "n_sum must be <= 2^%d", kSumLevels);
     if (n_out * n_q > 0)
         hipLaunchKernelGGL(k_frame_sums, dim3(blocks_for(n_out * n_q)), dim3(kBlock), 0, s, I, n_q, n_out, s_out,
-                           n_sum, s_sum, J);
+                           n_sum, s_sum, scale, J);
     XS_HIP(hipGetLastError());
     return XS_OK;
 }

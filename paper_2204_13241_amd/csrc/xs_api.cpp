@@ -172,7 +172,7 @@ void release_all_scratch() {
 namespace {
 
 // Defaults: the autotuner's choice on a 65,536-atom, 512x512-pixel single frame.
-xs_tile_shape g_shape[2] = {{64, 8, 32, 0, 4, 1}, {64, 2, 0, 2048, 0, 1}};
+xs_tile_shape g_shape[2] = {{64, 8, 32, 0, 4, 1}, {64, 2, 0, 2048, 5, 1}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
@@ -430,7 +430,7 @@ xs_status xs_siegert(const double *g2, const double *F, int32_t n_rings, int32_t
 }
 
 xs_status xs_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t n_out, int64_t s_out,
-                        int64_t n_sum, int64_t s_sum, double *J_out, void *stream) {
+                        int64_t n_sum, int64_t s_sum, double scale, double *J_out, void *stream) {
     XS_TRY(begin(stream));
     if (n_frames < 1) return set_error(XS_EINVAL, "n_frames must be >= 1");
     if (n_q < 0 || n_q >= (int64_t(1) << 31)) return set_error(XS_EINVAL, "n_q out of range");
@@ -440,7 +440,8 @@ xs_status xs_frame_sums(const double *I, int64_t n_frames, int64_t n_q, int64_t 
         s_sum > (int64_t(1) << 40) || (n_out - 1) * s_out + (n_sum - 1) * s_sum >= n_frames)
         return set_error(XS_EINVAL, "frame index (n_out-1)*s_out + (n_sum-1)*s_sum must be < n_frames");
     if (n_q > 0 && (!I || !J_out)) return set_error(XS_EINVAL, "I / J_out is NULL");
-    return frame_sums(static_cast<hipStream_t>(stream), I, n_q, n_out, s_out, n_sum, s_sum, J_out);
+    if (!std::isfinite(scale)) return set_error(XS_EINVAL, "scale must be finite");
+    return frame_sums(static_cast<hipStream_t>(stream), I, n_q, n_out, s_out, n_sum, s_sum, scale, J_out);
 }
 
 xs_status xs_ring_histogram(const double *I, int64_t n_frames, int64_t n_q, const double *q,
@@ -601,11 +602,13 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
     if (kind == 0 && shape->atom_split < 1) return set_error(XS_EINVAL, "atom_split must be >= 1");
     if (kind == 1 && (shape->pixel_split < 64 || shape->pixel_split % 64))
         return set_error(XS_EINVAL, "pixel_split must be a positive multiple of 64");
-    if (shape->waves_per_simd != 0 && shape->waves_per_simd != 4)
-        return set_error(XS_EINVAL, "waves_per_simd must be 0 or 4");
+    if (shape->waves_per_simd != 0 && shape->waves_per_simd != 4 && shape->waves_per_simd != 5)
+        return set_error(XS_EINVAL, "waves_per_simd must be 0, 4 or 5");
     if (shape->waves_per_simd == 4 && !((kind == 0 && (ql == 2 || ql == 4 || ql == 8)) || (kind == 1 && ql == 4)))
         return set_error(XS_ENOTSUP, "the 4-waves-per-SIMD variant is built for forward q_per_lane 2, 4, 8 "
                                      "and gradient q_per_lane 4");
+    if (shape->waves_per_simd == 5 && !(kind == 1 && ql == 2))
+        return set_error(XS_ENOTSUP, "the 5-waves-per-SIMD variant is built for gradient q_per_lane 2");
     if (shape->lattice != 0 && shape->lattice != 1) return set_error(XS_EINVAL, "lattice must be 0 or 1");
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[kind] = *shape;

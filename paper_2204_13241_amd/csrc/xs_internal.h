@@ -153,7 +153,7 @@ xs_status species_grad(hipStream_t s, const std::vector<Segment> &segs, const do
                        const double *amp, const double *dL_dI, int32_t precision, float *dL_dr, double *dL_dr64,
                        const xs_tile_shape &fsh, const xs_tile_shape &gsh);
 xs_status frame_sums(hipStream_t s, const double *I, int64_t n_q, int64_t n_out, int64_t s_out, int64_t n_sum,
-                     int64_t s_sum, double *J);
+                     int64_t s_sum, double scale, double *J);
 xs_status ring_histogram(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,
                          const RingEdges &edges, int32_t n_bins, double kappa_max, int64_t *counts, double *mean);
 xs_status isf_rings(hipStream_t s, const double *amp, int64_t n_frames, int64_t n_q, const double *q,

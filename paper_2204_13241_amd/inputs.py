@@ -77,6 +77,24 @@ def planar_grid(n: int, q_lim: float) -> np.ndarray:
     return np.stack([qx, qy, np.zeros_like(qx)], axis=-1)
 
 
+def planar_subpixels(n: int, q_lim: float, s: int) -> np.ndarray:
+    """Sub-pixel wavevectors of the planar grid planar_grid(n, q_lim): s x s points at the
+    centres of an even split of each pixel's cell (cell width = the pixel step), laid
+    out as [s*s][n*n][3] (sub-sample major, pixels in planar_grid order)."""
+    g = planar_grid(n, q_lim)
+    step = 2.0 * q_lim / (n - 1)
+    offs = (np.arange(s) + 0.5) / s - 0.5
+    out = np.empty((s * s, g.shape[0], 3))
+    k = 0
+    for oy in offs:
+        for ox in offs:
+            out[k] = g
+            out[k, :, 0] += ox * step
+            out[k, :, 1] += oy * step
+            k += 1
+    return out
+
+
 def ewald_detector(n: int, q_max: float, wavelength: float = WAVELENGTH) -> np.ndarray:
     """n x n pixels on the Ewald sphere, beam k_i = (0, 0, k), k = 2 pi / lambda.
 

@@ -26,7 +26,7 @@ FWD_CANDIDATES = [(ql, occ, split)
                   for split in (16, 32, 64, 128)]
 # (atoms per lane, waves-per-SIMD bound) x pixels per item
 GRAD_CANDIDATES = [(al, occ, pc)
-                   for al, occ in ((1, 0), (2, 0), (4, 0), (4, 4), (8, 0))
+                   for al, occ in ((1, 0), (2, 0), (2, 5), (4, 0), (4, 4), (8, 0))
                    for pc in (2048, 4096, 8192, 16384)]
 
 

@@ -100,3 +100,32 @@ def test_incoherent_sum_of_library_speckle_is_erlang(api):
     # about 1,000 independent speckles (pixel step 0.03 vs speckle 2 pi / L = 0.16 per axis):
     # the contrast estimate scatters by about 5% of 1/M
     assert abs(beta * M - 1.0) < 0.15
+
+
+def test_frame_sums_scale_bitwise(api):
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(10)
+    I = rng.exponential(1.0, (9, 300))
+    J = api.frame_sums(dev(I), 3, 3, 3, 1, 1.0 / 3.0)
+    assert bitwise_equal(host(J), oracle.frame_sums(I, 3, 3, 3, 1, scale=1.0 / 3.0))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_pixel_mean_over_subpixels(api, prec):
+    """Pixel integral of Sec. 3.1 as the mean over s x s sub-pixel wavevectors: the FP64
+    path (intensity, then the scaled frame sum) is bit for bit the oracle's; FP32C within
+    the intensity tolerance."""
+    from _gpu import dev, host, bitwise_equal, scaled_err
+    rng = np.random.default_rng(11)
+    N, L, n, s = 300, 30.0, 24, 3
+    pos = rng.uniform(0, L, (2, N, 3))
+    qs = X.planar_subpixels(n, 2.0, s)                      # [9, 576, 3]
+    print("pixel mean %s S=%d Q=%d" % (prec, s * s, n * n), flush=True)
+    J = api.intensity_pixel_mean(dev(pos), dev(np.ones(N)), dev(qs), precision=prec, box=L)
+    for t in range(2):
+        I, _ = oracle.intensity(pos[t], np.ones(N), qs.reshape(-1, 3))
+        Jr = oracle.frame_sums(I.reshape(s * s, n * n), 1, 0, s * s, 1, scale=1.0 / (s * s))[0]
+        if prec == "fp64":
+            assert bitwise_equal(host(J)[t], Jr)
+        else:
+            assert scaled_err(host(J)[t], Jr, np.ones(N)) < 1e-5

@@ -722,3 +722,22 @@ def test_incoherent_sum_of_m_configurations_follows_erlang():
         assert np.max(np.abs(emp - pdf)) < 0.06 * pdf.max() + 0.02
         beta = oracle.xsvs_contrast(J, q, [0.0, 1.0], 1)[0, 0]
         assert abs(beta * M - 1.0) < 0.03
+
+
+def test_pixel_mean_over_subpixel_wavevectors():
+    """The pixel integral Sec. 3.1 calls for, as the mean of I over S sub-pixel
+    wavevectors: for one atom (I = f^2 at every q) it is f^2 exactly; for two atoms it is
+    the mean of the two-atom closed form over the sub-pixel q (mpmath)."""
+    rng = np.random.default_rng(53)
+    S, Q = 4, 9
+    qs = rng.normal(size=(S * Q, 3))                       # S blocks of Q sub-pixel wavevectors
+    I1, _ = oracle.intensity(np.zeros((1, 3)), np.array([1.5]), qs)
+    J = oracle.frame_sums(I1.reshape(S, Q), 1, 0, S, 1, scale=1.0 / S)
+    assert np.all(J == 2.25)
+    pos = rng.uniform(-2, 2, (2, 3))
+    I2, _ = oracle.intensity(pos, np.array([1.0, 2.0]), qs)
+    J = oracle.frame_sums(I2.reshape(S, Q), 1, 0, S, 1, scale=1.0 / S)
+    for p in range(Q):
+        want = sum(5 + 4 * mp.cos(mp.fdot([mp.mpf(float(c)) for c in qs[s * Q + p]],
+                                          [mp.mpf(float(c)) for c in pos[0] - pos[1]])) for s in range(S)) / S
+        assert abs(J[0, p] - float(want)) < 1e-13
