@@ -405,8 +405,9 @@ def run_species(args):
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
-    ms_sp = timed(lambda: api.intensity_species(pos, sp, coef, q, precision="fp32c", box=L))
-    ms_plain = timed(lambda: api.intensity(pos, f_eff, q, precision="fp32c", box=L))
+    # one-shot calls build their plan each time: the better of two rounds of each
+    ms_sp = min(timed(lambda: api.intensity_species(pos, sp, coef, q, precision="fp32c", box=L)) for _ in range(2))
+    ms_plain = min(timed(lambda: api.intensity(pos, f_eff, q, precision="fp32c", box=L)) for _ in range(2))
     I64 = api.intensity_species(pos, sp, coef, q, precision="fp64")
     I32 = api.intensity_species(pos, sp, coef, q, precision="fp32c", box=L)
     fq = np.zeros((Q, 2))
@@ -425,6 +426,47 @@ def run_species(args):
     return rec
 
 
+def run_trajectory(args):
+    """Trajectory workload (fcc 20^3 + jitter, 32,000 atoms, 200 Brownian frames,
+    256x256 Ewald detector: 4.19e11 pairs, the general FP32C form) through one batch
+    plan, then g2 on 32 rings: intensities of all frames per call, timed with HIP events;
+    frame 0 checked against the FP64 form."""
+    import torch
+    from paper_2204_13241_amd import api, inputs
+    dev = "cuda:0"
+    w = inputs.workload_trajectory()
+    frames, q_np, L = w.positions[0], w.q[0], w.box[0]
+    F, N, Q = frames.shape[0], frames.shape[1], q_np.shape[0]
+    pos = torch.as_tensor(frames, dtype=torch.float64, device=dev)
+    f = torch.ones(N, dtype=torch.float64, device=dev)
+    q = torch.as_tensor(q_np, dtype=torch.float64, device=dev)
+    plan = api.Plan.single(N, F, q, L)
+    I = torch.empty((F, Q), dtype=torch.float64, device=dev)
+    plan.intensity(pos, f, I, want_amp=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        plan.intensity(pos, f, I, want_amp=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    desc = plan.describe()
+    plan.close()
+    g2, _ = api.g2_rings(I, q, w.edges, w.n_tau)
+    I0 = api.intensity(pos[0], f, q, precision="fp64")
+    inc = float(N)
+    e = float(((I[0] - I0).abs() / torch.clamp(I0, min=inc)).max())
+    rec = {"workload": "fcc 20^3 + 0.3 A jitter (32,000 atoms), 200 Brownian frames, 256x256 Ewald detector "
+                       "(q_max 1.5)", "pairs": F * N * Q, "forward_ms": ms,
+           "forward_Gpair_s": F * N * Q / (ms * 1e-3) / 1e9, "form": "general (Ewald rows are not a lattice)",
+           "plan": desc, "e_I_scaled_frame0_vs_fp64": e, "g2_finite": bool(torch.isfinite(g2).all())}
+    log("trajectory: %.2f ms per 200-frame forward, %.0f Gpair/s, e_I(frame 0) %.2e"
+        % (ms, rec["forward_Gpair_s"], e))
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -439,6 +481,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--no-reductions", action="store_true", help="skip the g2 / XSVS timings")
     ap.add_argument("--no-species", action="store_true", help="skip the form-factor (species) timing")
+    ap.add_argument("--no-trajectory", action="store_true", help="skip the 200-frame trajectory timing")
     ap.add_argument("--only-reductions", action="store_true", help="time only g2 / XSVS")
     ap.add_argument("--red-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -465,6 +508,8 @@ def main():
         res["reductions"] = run_reductions(args)
     if not args.no_species:
         res["species_form_factors"] = run_species(args)
+    if not args.no_trajectory:
+        res["trajectory"] = run_trajectory(args)
     print(json.dumps(res), flush=True)
 
 
