@@ -172,7 +172,7 @@ void release_all_scratch() {
 namespace {
 
 // Defaults: the autotuner's choice on a 65,536-atom, 512x512-pixel single frame.
-xs_tile_shape g_shape[2] = {{64, 8, 32, 0, 4, 1}, {64, 2, 0, 2048, 5, 1}};
+xs_tile_shape g_shape[2] = {{64, 8, 64, 0, 4, 1}, {64, 2, 0, 8192, 5, 1}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
