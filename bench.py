@@ -372,6 +372,50 @@ def run_reductions(args):
         out[name] = rec
         del I
         torch.cuda.empty_cache()
+    out.update(run_frames(args))
+    return out
+
+
+def run_frames(args):
+    """Frame sums and kappa histograms (superposed configurations, exposure integrals,
+    Eq. (Erlang)) on seeded exponential intensities in GPU memory: 16-frame exposure sums
+    of the 1024-frame, 1M-pixel XSVS shape (HBM-bound: the frames read once, the sums
+    written once) and the kappa histogram of the 200-frame, 65,536-pixel g2 shape."""
+    import torch
+    from paper_2204_13241_amd import api, inputs
+    out = {}
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(2025)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    F, Q, W = 1024, 1024 * 1024, 16
+    I = torch.empty((F, Q), dtype=torch.float64, device="cuda:0").exponential_(1.0, generator=gen)
+    ms = timed(lambda: api.frame_sums(I, F // W, W, W, 1), args.red_reps)
+    nbytes = F * Q * 8 + (F // W) * Q * 8
+    out["frame_sums"] = {"frames": F, "pixels": Q, "window": W, "avg_ms": ms, "bound": "hbm",
+                         "algorithmic_bytes": nbytes, "achieved_GB_s": nbytes / (ms * 1e-3) / 1e9,
+                         "peak_GB_s": PEAK_HBM / 1e9, "frac": nbytes / (ms * 1e-3) / PEAK_HBM}
+    log("frame sums: %.3f ms, %.0f GB/s (%.1f%% of HBM)" % (ms, out["frame_sums"]["achieved_GB_s"],
+                                                          100 * out["frame_sums"]["frac"]))
+    del I
+    torch.cuda.empty_cache()
+    F, n_det = 200, 256
+    q = torch.as_tensor(inputs.ewald_detector(n_det, 1.5), dtype=torch.float64, device="cuda:0")
+    I = torch.empty((F, q.shape[0]), dtype=torch.float64, device="cuda:0").exponential_(1.0, generator=gen)
+    edges = inputs.ring_edges(32, 1.5)
+    ms = timed(lambda: api.ring_histogram(I, q, edges, 100, 8.0), args.red_reps)
+    out["ring_histogram"] = {"frames": F, "pixels": int(q.shape[0]), "rings": 32, "bins": 100, "avg_ms": ms,
+                             "input_GB_s": F * q.shape[0] * 8 / (ms * 1e-3) / 1e9}
+    log("ring histogram: %.3f ms" % ms)
     return out
 
 

@@ -100,3 +100,35 @@ def test_species_gradient(api, prec, tol):
         _, ampr = oracle.intensity_species(pos[t], sp, COEF, q)
         gr = oracle.intensity_species_grad(pos[t], sp, COEF, q, ampr, w[t])
         assert grad_err(host(g)[t], gr) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_species_batch_of_systems(api, prec, tol):
+    """Two systems in one call (different atom counts, frames and pixel sets): every
+    system's species order comes from its own slice of the species array."""
+    import ctypes
+    import torch
+    from paper_2204_13241_amd import _lib
+    from _gpu import dev, host
+    rng = np.random.default_rng(12)
+    N, F = [400, 250], [2, 1]
+    Ls = [30.0, 25.0]
+    qs = [X.planar_grid(20, 2.5), X.ewald_detector(16, 1.5)]
+    pos = [rng.uniform(0, Ls[i], (F[i], N[i], 3)) for i in range(2)]
+    sp = [rng.integers(0, 3, N[i]).astype(np.int32) for i in range(2)]
+    b = api.make_batch(N, [q.shape[0] for q in qs], F, np.array([[Ls[0]] * 3, [Ls[1]] * 3]))
+    pos_d = dev(np.concatenate([p.reshape(-1, 3) for p in pos]))
+    sp_d = dev(np.concatenate(sp), dtype=torch.int32)
+    q_d = dev(np.concatenate(qs))
+    I = torch.empty(b.total_out, dtype=torch.float64, device="cuda:0")
+    st = b.struct()
+    print("species batch %s" % prec, flush=True)
+    _lib.check(_lib.load().xs_intensity_species(ctypes.byref(st), api._ptr(pos_d), api._ptr(sp_d), 3,
+                                                COEF.ctypes.data_as(ctypes.c_void_p), api._ptr(q_d),
+                                                0 if prec == "fp64" else 1, api._ptr(I), None, api._stream()))
+    Ih = host(I)
+    for i in range(2):
+        for t in range(F[i]):
+            Ir, _ = oracle.intensity_species(pos[i][t], sp[i], COEF, qs[i])
+            o = b.out_off[i] + t * qs[i].shape[0]
+            assert _scaled(Ih[None, o:o + qs[i].shape[0]], Ir, sp[i], qs[i]) < tol
