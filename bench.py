@@ -75,9 +75,9 @@ def source_hash(path):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_src, kernel):
+def traffic_from_profile(kernel_src, kernel, shape):
     """HBM bytes per launch of a pair kernel from the committed PMC summary, or None
-    if the summary is missing or was taken on a different kernel source."""
+    if the summary is missing or was taken on a different kernel source or tile shape."""
     path = os.path.join(ROOT, "profiles", "pair_kernels_pmc_grad65536.json")
     try:
         d = json.load(open(path))
@@ -85,10 +85,13 @@ def traffic_from_profile(kernel_src, kernel):
         return None
     if d.get("source_sha256_16") != source_hash(kernel_src):
         return None
-    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    rec = d.get("kernels", {}).get(kernel, {})
+    if rec.get("tile_shape") != dict(shape):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(pos, f, q, amp, w, budget_s=15.0):
+def cpu_baseline(pos, f, q, amp, w, budget_s=20.0):
     """The oracle (FP64 form, OpenMP) on a bounded sample of the same workload."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -219,7 +222,7 @@ def run_grad(args):
                       "form": "lattice" if lattice else "general", "valu_per_pair": n_valu,
                       "trans_per_pair": n_trans, "achieved_Gpair_s": ach, "peak_Gpair_s": peak,
                       "frac": ach / peak, "frac_of_sincos_pair_peak": ach / (PEAK_SINCOS_PAIRS / 1e9),
-                      "traffic": traffic_from_profile(src, name)}
+                      "traffic": traffic_from_profile(src, name, shapes[kind])}
     kern["binning"] = {"avg_ms": binr["ms"] / max(binr["launches"], 1), "launches": binr["launches"]}
     dom = max(("forward_fp32c", "adjoint_fp32c"), key=lambda k: kern[k]["avg_ms"])
     roofline = {
@@ -519,7 +522,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--graph", action="store_true", help="time HIP-graph replays of the step")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
