@@ -402,6 +402,31 @@ class IntensityFn(torch.autograd.Function):
         return g, None, None, None, None
 
 
+class IntensitySpeciesFn(torch.autograd.Function):
+    """I with q-dependent form factors f_s(|q|) per species, differentiable in pos.
+
+    forward(pos [F,N,3] or [N,3] float64, species [N] int32, coef [n_species, 9] (host),
+    q, box, precision) -> I; backward calls xs_intensity_species_grad with the saved
+    amplitude.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, species, coef, q, box, precision="fp32c"):
+        I, amp = intensity_species(pos.detach(), species, coef, q.detach(), precision, box, return_amp=True)
+        ctx.save_for_backward(pos.detach(), species, q.detach(), amp)
+        ctx.coef = coef
+        ctx.box = box
+        ctx.precision = precision
+        return I
+
+    @staticmethod
+    def backward(ctx, grad_I):
+        pos, species, q, amp = ctx.saved_tensors
+        g = intensity_species_grad(pos, species, ctx.coef, q, amp, grad_I.contiguous().to(torch.float64),
+                                   ctx.precision, ctx.box, out_dtype=torch.float64)
+        return g, None, None, None, None, None
+
+
 def shutdown():
     _lib.check(_lib.load().xs_shutdown())
 

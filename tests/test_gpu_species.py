@@ -132,3 +132,22 @@ def test_species_batch_of_systems(api, prec, tol):
             Ir, _ = oracle.intensity_species(pos[i][t], sp[i], COEF, qs[i])
             o = b.out_off[i] + t * qs[i].shape[0]
             assert _scaled(Ih[None, o:o + qs[i].shape[0]], Ir, sp[i], qs[i]) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 2e-5)])
+def test_species_autograd_function(api, prec, tol):
+    import torch
+    from _gpu import dev, host, grad_err
+    pos, sp, q, L = _case(8, 400, 1, 20)
+    rng = np.random.default_rng(9)
+    target = pos[0] + 0.2 * rng.normal(size=pos[0].shape)
+    It, _ = oracle.intensity_species(target, sp, COEF, q)
+    I0, amp0 = oracle.intensity_species(pos[0], sp, COEF, q)
+    Z = float(np.sum(It ** 2))
+    g_ref = oracle.intensity_species_grad(pos[0], sp, COEF, q, amp0, 2.0 * (I0 - It) / Z)
+    print("species autograd %s" % prec, flush=True)
+    p = dev(pos[0]).requires_grad_(True)
+    I = api.IntensitySpeciesFn.apply(p, dev(sp, dtype=torch.int32), COEF, dev(q), L, prec)
+    It_d = dev(It)
+    (((I - It_d) ** 2).sum() / Z).backward()
+    assert grad_err(host(p.grad), g_ref) < tol
