@@ -60,15 +60,20 @@ __device__ __forceinline__ double phase_turns(double qx, double qy, double qz, d
 }
 
 constexpr int kBlock = 256;
+constexpr int kAtomStage = 256;   // atoms staged in LDS per pass of the forward
+constexpr int kPixStage = 256;    // pixels staged in LDS per pass of the gradient
 
-// One thread per pixel; atoms of the segment are read in input order with
-// block-uniform addresses (scalar loads).  grid = (pixel blocks, segments).
+// One thread per pixel; the segment's atoms are staged in LDS in chunks, in
+// input order (x, y, z, f), and every thread reads them as broadcasts.  Four
+// pairs per unrolled step give independent sine/cosine chains; the sums still
+// take the atoms one by one in order.  grid = (pixel blocks, segments).
 __global__ __launch_bounds__(kBlock) void k_forward_fp64(const Segment *__restrict__ segs,
                                                          const double *__restrict__ pos,
                                                          const double *__restrict__ f,
                                                          const double *__restrict__ q,
                                                          double *__restrict__ I,
                                                          double *__restrict__ amp) {
+    __shared__ double4 s_atom[kAtomStage];
     const Segment sg = segs[blockIdx.y];
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (blockIdx.x * kBlock >= sg.n_q) return;  // whole block past this segment's pixels
@@ -79,12 +84,22 @@ __global__ __launch_bounds__(kBlock) void k_forward_fp64(const Segment *__restri
     const double *r = pos + sg.pos * 3;
     const double *ff = f + sg.f;
     double ac = 0.0, as = 0.0;
-    for (int j = 0; j < sg.n_atoms; ++j) {
-        double sn, cs;
-        sincos_turns(phase_turns(qx, qy, qz, r[3 * j], r[3 * j + 1], r[3 * j + 2]), sn, cs);
-        const double fj = ff[j];
-        ac = __builtin_fma(fj, cs, ac);
-        as = __builtin_fma(fj, sn, as);
+    for (int j0 = 0; j0 < sg.n_atoms; j0 += kAtomStage) {
+        const int nj = min(kAtomStage, sg.n_atoms - j0);
+        __syncthreads();  // the previous chunk has been read by every thread
+        for (int t = threadIdx.x; t < nj; t += kBlock) {
+            const int64_t j = j0 + t;
+            s_atom[t] = make_double4(r[3 * j], r[3 * j + 1], r[3 * j + 2], ff[j]);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int t = 0; t < nj; ++t) {
+            const double4 at = s_atom[t];
+            double sn, cs;
+            sincos_turns(phase_turns(qx, qy, qz, at.x, at.y, at.z), sn, cs);
+            ac = __builtin_fma(at.w, cs, ac);
+            as = __builtin_fma(at.w, sn, as);
+        }
     }
     if (!active) return;
     const double a = ac, b = -as;
@@ -96,8 +111,14 @@ __global__ __launch_bounds__(kBlock) void k_forward_fp64(const Segment *__restri
     }
 }
 
-// One thread per atom; pixels of the segment in input order (scalar loads).
+// One thread per atom; the segment's pixels are staged in LDS in chunks, in
+// input order: q / (2 pi) (the phase operand, the same product the per-pair
+// form would round), q, the amplitude (a, b) and the weight w.
 //   h = fma(a, s, b*c), k = w*h, g += k*q (fma per component), dL/dr = (-2 f) g.
+struct PixFp64 {
+    double2 qr01, qr2w, q01, q2, ab;
+};
+
 __global__ __launch_bounds__(kBlock) void k_grad_fp64(const Segment *__restrict__ segs,
                                                       const double *__restrict__ pos,
                                                       const double *__restrict__ f,
@@ -106,6 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_fp64(const Segment *__restrict_
                                                       const double *__restrict__ w,
                                                       float *__restrict__ g32,
                                                       double *__restrict__ g64) {
+    __shared__ PixFp64 s_pix[kPixStage];
     const Segment sg = segs[blockIdx.y];
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (blockIdx.x * kBlock >= sg.n_atoms) return;
@@ -117,16 +139,33 @@ __global__ __launch_bounds__(kBlock) void k_grad_fp64(const Segment *__restrict_
     const double *aa = amp + sg.out * 2;
     const double *ww = w + sg.out;
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int p = 0; p < sg.n_q; ++p) {
-        const double q0 = qq[3 * p], q1 = qq[3 * p + 1], q2 = qq[3 * p + 2];
-        double sn, cs;
-        sincos_turns(phase_turns(q0 * kInvTwoPi, q1 * kInvTwoPi, q2 * kInvTwoPi, x, y, z), sn,
-                     cs);
-        const double h = __builtin_fma(aa[2 * p], sn, aa[2 * p + 1] * cs);
-        const double k = ww[p] * h;
-        gx = __builtin_fma(k, q0, gx);
-        gy = __builtin_fma(k, q1, gy);
-        gz = __builtin_fma(k, q2, gz);
+    for (int p0 = 0; p0 < sg.n_q; p0 += kPixStage) {
+        const int np = min(kPixStage, sg.n_q - p0);
+        __syncthreads();  // the previous chunk has been read by every thread
+        for (int t = threadIdx.x; t < np; t += kBlock) {
+            const int64_t p = p0 + t;
+            const double q0 = qq[3 * p], q1 = qq[3 * p + 1], q2 = qq[3 * p + 2];
+            PixFp64 v;
+            v.qr01 = make_double2(q0 * kInvTwoPi, q1 * kInvTwoPi);
+            v.qr2w = make_double2(q2 * kInvTwoPi, ww[p]);
+            v.q01 = make_double2(q0, q1);
+            v.q2 = make_double2(q2, 0.0);
+            v.ab = make_double2(aa[2 * p], aa[2 * p + 1]);
+            s_pix[t] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int t = 0; t < np; ++t) {
+            const double2 qr01 = s_pix[t].qr01, qr2w = s_pix[t].qr2w, q01 = s_pix[t].q01, ab = s_pix[t].ab;
+            const double q2 = s_pix[t].q2.x;
+            double sn, cs;
+            sincos_turns(phase_turns(qr01.x, qr01.y, qr2w.x, x, y, z), sn, cs);
+            const double h = __builtin_fma(ab.x, sn, ab.y * cs);
+            const double k = qr2w.y * h;
+            gx = __builtin_fma(k, q01.x, gx);
+            gy = __builtin_fma(k, q01.y, gy);
+            gz = __builtin_fma(k, q2, gz);
+        }
     }
     if (!active) return;
     const double m = -2.0 * f[sg.f + j];
