@@ -1,0 +1,36 @@
+"""Host logic of the tile-shape autotuner (no device work)."""
+from paper_2204_13241_amd import tune
+
+
+def test_candidate_spaces_hold_the_default_shapes():
+    assert (8, 4, 64) in tune.FWD_CANDIDATES
+    assert (2, 5, 8192) in tune.GRAD_CANDIDATES
+
+
+def test_current_shape_is_timed_first_and_the_rest_keep_their_order():
+    cands = tune.GRAD_CANDIDATES
+    order = tune._current_first(cands, (2, 5, 8192))
+    assert order[0] == (2, 5, 8192)
+    assert sorted(order) == sorted(cands) and len(order) == len(cands)
+    rest = [c for c in cands if c != (2, 5, 8192)]
+    assert order[1:] == rest
+    # a shape outside the list leaves the list unchanged
+    assert tune._current_first(cands, (3, 0, 1)) == list(cands)
+
+
+def test_bucket_is_the_nearest_power_of_two():
+    assert tune._bucket(0) == 0
+    assert tune._bucket(65536) == 16
+    assert tune._bucket(262144) == 18
+    assert tune._bucket(90000) == 16 and tune._bucket(100000) == 17
+
+
+def test_cache_roundtrip_and_unreadable_file(tmp_path):
+    p = str(tmp_path / "sub" / "tune.json")
+    assert tune._load_cache(p) == {}
+    tune._store_cache(p, {"k": {"forward": {"q_per_lane": 8}}})
+    assert tune._load_cache(p) == {"k": {"forward": {"q_per_lane": 8}}}
+    with open(p, "w") as fh:
+        fh.write("{not json")
+    assert tune._load_cache(p) == {}
+    assert 0.0 < tune.TIE < 0.1
