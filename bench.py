@@ -464,12 +464,29 @@ def run_species(args):
         fq[:, s_] = c + np.sum(a[None, :] * np.exp(-b[None, :] * qq[:, None]), axis=1)
     inc = (np.sum(sp_np == 0) * fq[:, 0] ** 2 + np.sum(sp_np == 1) * fq[:, 1] ** 2)
     e = float(np.max(np.abs(I32.cpu().numpy() - I64.cpu().numpy()) / np.maximum(I64.cpu().numpy(), inc)))
+    # the plan form: species split and work lists built once, then forward + adjoint per step
+    plan = api.SpeciesPlan([(N, 1, q, L)], sp, coef)
+    I = torch.empty(Q, dtype=torch.float64, device=dev)
+    amp = torch.empty((Q, 2), dtype=torch.float64, device=dev)
+    g = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    wq = torch.as_tensor(np.random.default_rng(2205).standard_normal(Q), dtype=torch.float64, device=dev)
+
+    def plan_step():
+        plan.intensity(pos, I, amp)
+        plan.grad(pos, amp, wq, retile=False, g32=g)
+    ms_plan = min(timed(plan_step) for _ in range(2))
+    e_plan = float(np.max(np.abs(I.cpu().numpy() - I64.cpu().numpy()) / np.maximum(I64.cpu().numpy(), inc)))
+    lattice = plan.describe()["n_lattice_segments"]
+    plan.close()
     rec = {"workload": "65,536 atoms (two species), 512x512 planar pixels, one frame, synthetic Gaussian-sum "
                        "form factors", "pairs": N * Q, "species_ms": ms_sp, "per_atom_weights_ms": ms_plain,
            "species_Gpair_s": N * Q / (ms_sp * 1e-3) / 1e9, "overhead": ms_sp / ms_plain - 1.0,
-           "e_I_scaled_fp32c_vs_fp64": e}
-    log("species: %.3f ms per call (per-atom weights %.3f ms), %.0f Gpair/s, e_I %.2e"
-        % (ms_sp, ms_plain, rec["species_Gpair_s"], e))
+           "e_I_scaled_fp32c_vs_fp64": e,
+           "plan_step_ms": ms_plan, "plan_step_Gpair_s": 2 * N * Q / (ms_plan * 1e-3) / 1e9,
+           "plan_lattice_segments": lattice, "plan_e_I_scaled_vs_fp64": e_plan}
+    log("species: %.3f ms per call (per-atom weights %.3f ms), %.0f Gpair/s, e_I %.2e; plan fwd+adjoint "
+        "%.3f ms (%.0f Gpair/s, e_I %.2e)" % (ms_sp, ms_plain, rec["species_Gpair_s"], e, ms_plan,
+                                             rec["plan_step_Gpair_s"], e_plan))
     return rec
 
 

@@ -376,6 +376,31 @@ xs_status xs_plan_intensity(xs_plan *plan, const double *pos, const double *f, d
 xs_status xs_plan_grad(xs_plan *plan, const double *pos, const double *f, const double *amp,
                        const double *dL_dI, int32_t retile, float *dL_dr, double *dL_dr64,
                        void *stream);
+/*
+ * Species plans: the plan form of xs_intensity_species / xs_intensity_species_grad
+ * (q-dependent form factors f_s(|q|) per species, Sec. 2.1, Eq. (pe_ri) with f_j(q)).
+ * xs_plan_create_species reads `species` (device int32, the layout of f in the
+ * batch, values in [0, n_species)) once and synchronizes `stream`; the species
+ * assignment and `ff_coef` (host, [n_species][9] as for xs_intensity_species) are
+ * fixed for the life of the plan.  The calls then only launch kernels (capturable
+ * like xs_plan_intensity / xs_plan_grad): positions are gathered into species
+ * order, the species segments run through the plan's pair sums with unit weights,
+ * and the per-species amplitudes are combined with f_s(|q|) (adjoint: weighted by
+ * f_s(|q|), gradients scattered back to the caller's atom order).  FP32C only.
+ * pos, I_out, amp_out, amp, dL_dI, dL_dr, dL_dr64 as for the one-shot calls;
+ * retile as for xs_plan_grad.  A species plan refuses xs_plan_intensity /
+ * xs_plan_grad and the reverse (XS_EINVAL).  xs_plan_describe counts its species
+ * segments.
+ */
+xs_status xs_plan_create_species(const xs_batch *b, const double *q, const int32_t *species,
+                                 int32_t n_species, const double *ff_coef, xs_plan **plan,
+                                 void *stream);
+xs_status xs_plan_intensity_species(xs_plan *plan, const double *pos, double *I_out,
+                                    double *amp_out, void *stream);
+xs_status xs_plan_grad_species(xs_plan *plan, const double *pos, const double *amp,
+                               const double *dL_dI, int32_t retile, float *dL_dr,
+                               double *dL_dr64, void *stream);
+
 /* Waits for the device, then frees the plan's memory.  NULL is accepted. */
 xs_status xs_plan_destroy(xs_plan *plan);
 

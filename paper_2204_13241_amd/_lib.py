@@ -21,7 +21,8 @@ EXPORTS = [
     "xs_speckle_loss", "xs_position_step", "xs_timing_enable", "xs_timing_read",
     "xs_roofline_probe", "xs_plan_create", "xs_plan_intensity", "xs_plan_grad", "xs_plan_destroy",
     "xs_plan_describe", "xs_isf_rings", "xs_siegert", "xs_intensity_species", "xs_intensity_species_grad",
-    "xs_frame_sums", "xs_ring_histogram",
+    "xs_frame_sums", "xs_ring_histogram", "xs_plan_create_species", "xs_plan_intensity_species",
+    "xs_plan_grad_species",
 ]
 
 _P = ctypes.c_void_p
@@ -112,6 +113,9 @@ def load():
         "xs_plan_create": (i32, [bp, _P, ctypes.POINTER(_P), _P]),
         "xs_plan_intensity": (i32, [_P, _P, _P, _P, _P, _P]),
         "xs_plan_grad": (i32, [_P, _P, _P, _P, _P, i32, _P, _P, _P]),
+        "xs_plan_create_species": (i32, [bp, _P, _P, i32, _P, ctypes.POINTER(_P), _P]),
+        "xs_plan_intensity_species": (i32, [_P, _P, _P, _P, _P]),
+        "xs_plan_grad_species": (i32, [_P, _P, _P, _P, i32, _P, _P, _P]),
         "xs_plan_destroy": (i32, [_P]),
         "xs_plan_describe": (i32, [_P, ctypes.POINTER(XsPlanInfo)]),
     }

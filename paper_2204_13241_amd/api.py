@@ -490,6 +490,14 @@ class Plan:
     """
 
     def __init__(self, systems):
+        self._layout(systems)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().xs_plan_create(ctypes.byref(self._st), _ptr(self.q), ctypes.byref(h),
+                                              _stream()))
+        self._h = h
+
+    def _layout(self, systems):
+        self._h = ctypes.c_void_p()
         if not systems:
             raise ValueError("a plan needs at least one system")
         for i, (_, _, q, _) in enumerate(systems):
@@ -504,10 +512,6 @@ class Plan:
         self.total_pos = int(np.sum(np.asarray(self.n_atoms) * np.asarray(self.n_frames)))
         self.total_f = int(np.sum(self.n_atoms))
         self._st = self.batch.struct()
-        h = ctypes.c_void_p()
-        _lib.check(_lib.load().xs_plan_create(ctypes.byref(self._st), _ptr(self.q), ctypes.byref(h),
-                                              _stream()))
-        self._h = h
 
     @classmethod
     def single(cls, n_atoms: int, n_frames: int, q: torch.Tensor, box):
@@ -554,3 +558,51 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class SpeciesPlan(Plan):
+    """FP32C batch plan with q-dependent form factors per species (xs_plan_create_species).
+
+    systems as for Plan; species: int32 GPU tensor [sum_s N_s] in the packed layout of f
+    (read once here); coef: [n_species, 9] host array (a_1..a_4, b_1..b_4, c).  After
+    construction intensity() and grad() only launch kernels (capturable in a graph).
+    """
+
+    def __init__(self, systems, species: torch.Tensor, coef):
+        self._layout(systems)
+        if not isinstance(species, torch.Tensor) or not species.is_cuda or species.dtype != torch.int32:
+            raise ValueError("species must be an int32 tensor in GPU memory")
+        if species.shape != (self.total_f,) or not species.is_contiguous():
+            raise ValueError("species must be a contiguous [sum_s N_s] tensor")
+        self.coef = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1, 9)
+        self.species = species
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().xs_plan_create_species(ctypes.byref(self._st), _ptr(self.q), _ptr(species),
+                                                      self.coef.shape[0],
+                                                      self.coef.ctypes.data_as(ctypes.c_void_p),
+                                                      ctypes.byref(h), _stream()))
+        self._h = h
+
+    def _check_pos(self, pos):
+        _need(pos, "pos")
+        if pos.numel() != 3 * self.total_pos:
+            raise ValueError("pos does not match the plan's batch layout")
+
+    def intensity(self, pos, I=None, amp=None, want_amp=True):
+        self._check_pos(pos)
+        dev = pos.device
+        if I is None:
+            I = torch.empty(self.total_out, dtype=torch.float64, device=dev)
+        if amp is None and want_amp:
+            amp = torch.empty((self.total_out, 2), dtype=torch.float64, device=dev)
+        _lib.check(_lib.load().xs_plan_intensity_species(self._h, _ptr(pos), _ptr(I), _ptr(amp), _stream()))
+        return I, amp
+
+    def grad(self, pos, amp, dL_dI, retile=True, g32=None, g64=None):
+        self._check_pos(pos)
+        _need(amp, "amp"), _need(dL_dI, "dL_dI")
+        if g32 is None and g64 is None:
+            g32 = torch.empty((self.total_pos, 3), dtype=torch.float32, device=pos.device)
+        _lib.check(_lib.load().xs_plan_grad_species(self._h, _ptr(pos), _ptr(amp), _ptr(dL_dI),
+                                                    1 if retile else 0, _ptr(g32), _ptr(g64), _stream()))
+        return g32 if g32 is not None else g64

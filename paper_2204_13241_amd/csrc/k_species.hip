@@ -222,36 +222,38 @@ struct SpeciesDev {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-xs_status upload_species(hipStream_t s, const SpeciesSplit &sp, int32_t n_species, const double *coef_host,
-                         const double *pos, SpeciesDev &d) {
+// The split's tables as one host blob of 256-byte-aligned sections: segments,
+// species order, species offsets, parent / species / output of every species
+// segment, form-factor coefficients.  off[i] = byte offset of section i.
+constexpr int kTabSections = 7;
+std::vector<char> species_tables(const SpeciesSplit &sp, int32_t n_species, const double *coef_host,
+                                 size_t (&off)[kTabSections]) {
     const size_t n_seg = sp.segs.size(), n_sub = sp.sub.size();
-    const size_t sz[] = {sizeof(SpSeg) * n_seg,
-                         sizeof(int32_t) * std::max<size_t>(sp.perm.size(), 1),
-                         sizeof(int64_t) * std::max<size_t>(sp.sub_off.size(), 1),
-                         sizeof(int32_t) * std::max<size_t>(n_sub, 1),
-                         sizeof(int32_t) * std::max<size_t>(n_sub, 1),
-                         sizeof(int64_t) * std::max<size_t>(n_sub, 1),
-                         sizeof(double) * 9 * n_species};
-    size_t tbytes = 0;
-    for (size_t x : sz) tbytes += align256(x);
-    std::vector<char> blob(tbytes, 0);
-    const void *src[] = {sp.segs.data(), sp.perm.data(), sp.sub_off.data(), sp.sub_par.data(),
-                         sp.sub_sp.data(), sp.sub_out.data(), coef_host};
-    const size_t used[] = {sizeof(SpSeg) * n_seg, sizeof(int32_t) * sp.perm.size(),
-                           sizeof(int64_t) * sp.sub_off.size(), sizeof(int32_t) * n_sub,
-                           sizeof(int32_t) * n_sub, sizeof(int64_t) * n_sub, sizeof(double) * 9 * n_species};
-    size_t off[7], o = 0;
-    for (int i = 0; i < 7; ++i) {
+    const size_t sz[kTabSections] = {sizeof(SpSeg) * n_seg,
+                                     sizeof(int32_t) * std::max<size_t>(sp.perm.size(), 1),
+                                     sizeof(int64_t) * std::max<size_t>(sp.sub_off.size(), 1),
+                                     sizeof(int32_t) * std::max<size_t>(n_sub, 1),
+                                     sizeof(int32_t) * std::max<size_t>(n_sub, 1),
+                                     sizeof(int64_t) * std::max<size_t>(n_sub, 1),
+                                     sizeof(double) * 9 * n_species};
+    const void *src[kTabSections] = {sp.segs.data(), sp.perm.data(), sp.sub_off.data(), sp.sub_par.data(),
+                                     sp.sub_sp.data(), sp.sub_out.data(), coef_host};
+    const size_t used[kTabSections] = {sizeof(SpSeg) * n_seg, sizeof(int32_t) * sp.perm.size(),
+                                       sizeof(int64_t) * sp.sub_off.size(), sizeof(int32_t) * n_sub,
+                                       sizeof(int32_t) * n_sub, sizeof(int64_t) * n_sub,
+                                       sizeof(double) * 9 * n_species};
+    size_t o = 0;
+    for (int i = 0; i < kTabSections; ++i) {
         off[i] = o;
-        if (used[i]) std::memcpy(blob.data() + o, src[i], used[i]);
         o += align256(sz[i]);
     }
-    const size_t ones_n = static_cast<size_t>(std::max(sp.max_sub_atoms, 1));
-    const size_t pos_n = static_cast<size_t>(std::max<int64_t>(sp.n_pos, 1)) * 3;
-    void *tab = nullptr, *big = nullptr;
-    XS_TRY(upload(s, SLOT_SPECIES_TAB, blob.data(), tbytes, &tab));
-    XS_TRY(scratch(s, SLOT_SPECIES_POS, sizeof(double) * (ones_n + pos_n), &big));
-    char *t = static_cast<char *>(tab);
+    std::vector<char> blob(o, 0);
+    for (int i = 0; i < kTabSections; ++i)
+        if (used[i]) std::memcpy(blob.data() + off[i], src[i], used[i]);
+    return blob;
+}
+
+void point_tables(char *t, const size_t (&off)[kTabSections], SpeciesDev &d) {
     d.segs = reinterpret_cast<SpSeg *>(t + off[0]);
     d.perm = reinterpret_cast<int32_t *>(t + off[1]);
     d.sub_off = reinterpret_cast<int64_t *>(t + off[2]);
@@ -259,15 +261,32 @@ xs_status upload_species(hipStream_t s, const SpeciesSplit &sp, int32_t n_specie
     d.sub_sp = reinterpret_cast<int32_t *>(t + off[4]);
     d.sub_out = reinterpret_cast<int64_t *>(t + off[5]);
     d.coef = reinterpret_cast<double *>(t + off[6]);
+}
+
+xs_status gather_positions(hipStream_t s, const SpeciesSplit &sp, const SpeciesDev &d, const double *pos) {
+    if (!sp.segs.empty() && sp.max_atoms > 0)
+        hipLaunchKernelGGL(k_species_gather, dim3(blocks_for(sp.max_atoms), static_cast<unsigned>(sp.segs.size())),
+                           dim3(kBlock), 0, s, d.segs, d.perm, pos, d.pos_r);
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+xs_status upload_species(hipStream_t s, const SpeciesSplit &sp, int32_t n_species, const double *coef_host,
+                         const double *pos, SpeciesDev &d) {
+    size_t off[kTabSections];
+    const std::vector<char> blob = species_tables(sp, n_species, coef_host, off);
+    const size_t ones_n = static_cast<size_t>(std::max(sp.max_sub_atoms, 1));
+    const size_t pos_n = static_cast<size_t>(std::max<int64_t>(sp.n_pos, 1)) * 3;
+    void *tab = nullptr, *big = nullptr;
+    XS_TRY(upload(s, SLOT_SPECIES_TAB, blob.data(), blob.size(), &tab));
+    XS_TRY(scratch(s, SLOT_SPECIES_POS, sizeof(double) * (ones_n + pos_n), &big));
+    point_tables(static_cast<char *>(tab), off, d);
     d.ones = static_cast<double *>(big);
     d.pos_r = d.ones + ones_n;
     hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(static_cast<int64_t>(ones_n))), dim3(kBlock), 0, s, d.ones,
                        static_cast<int64_t>(ones_n), 1.0);
-    if (n_seg > 0 && sp.max_atoms > 0)
-        hipLaunchKernelGGL(k_species_gather, dim3(blocks_for(sp.max_atoms), static_cast<unsigned>(n_seg)),
-                           dim3(kBlock), 0, s, d.segs, d.perm, pos, d.pos_r);
     XS_HIP(hipGetLastError());
-    return XS_OK;
+    return gather_positions(s, sp, d, pos);
 }
 
 }  // namespace
@@ -338,6 +357,139 @@ xs_status species_grad(hipStream_t s, const std::vector<Segment> &segs, const do
         if (dL_dr) hipLaunchKernelGGL(k_species_scatter<float>, grid, dim3(kBlock), 0, s, d.segs, d.perm, g32_r, dL_dr);
         if (dL_dr64)
             hipLaunchKernelGGL(k_species_scatter<double>, grid, dim3(kBlock), 0, s, d.segs, d.perm, g64_r, dL_dr64);
+    }
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+// ---------------------------------------------------------------- species plans
+//
+// The species split of a batch (read once, when the plan is made), its device
+// tables, the unit weights, the species-ordered positions and the per-species
+// work buffers, in one allocation owned by the plan.  The pair sums of the
+// species segments run through the caller's inner FP32C plan.  After creation
+// every call only launches kernels.
+struct SpeciesPlan {
+    SpeciesSplit sp;
+    int32_t n_species = 0;
+    void *block = nullptr;
+    SpeciesDev d;
+    double *buf = nullptr;   // forward: I_s [tq], amp_s [tq][2]; adjoint: w [tq], amp_r [tq][2]
+    int64_t tq = 0;
+    double *g64_r = nullptr;
+    float *g32_r = nullptr;
+    size_t bytes = 0;
+    ~SpeciesPlan() {
+        if (block) (void)hipFree(block);
+    }
+};
+
+xs_status species_plan_create(hipStream_t s, const std::vector<Segment> &segs, const int32_t *species,
+                              int32_t n_species, const double *coef_host, SpeciesPlan **out,
+                              std::vector<Segment> *sub) {
+    *out = nullptr;
+    auto *p = new (std::nothrow) SpeciesPlan();
+    if (!p) return set_error(XS_ENOMEM, "species plan: host allocation failed");
+    xs_status st = split_species(s, segs, species, n_species, p->sp);
+    if (st != XS_OK) {
+        delete p;
+        return st;
+    }
+    const SpeciesSplit &sp = p->sp;
+    p->n_species = n_species;
+    size_t off[kTabSections];
+    const std::vector<char> blob = species_tables(sp, n_species, coef_host, off);
+    const size_t ones_n = static_cast<size_t>(std::max(sp.max_sub_atoms, 1));
+    const size_t np = static_cast<size_t>(std::max<int64_t>(sp.n_pos, 1));
+    p->tq = (std::max<int64_t>(sp.total_q, 1) + 1) & ~int64_t(1);  // keeps the double2 rows aligned
+    // layout: tables | ones | pos_r [np][3] | buf [3 tq] | g64_r [np][3] | g32_r [np][3]
+    const size_t o_ones = blob.size();
+    const size_t o_pos = o_ones + align256(sizeof(double) * ones_n);
+    const size_t o_buf = o_pos + align256(sizeof(double) * 3 * np);
+    const size_t o_g64 = o_buf + align256(sizeof(double) * 3 * static_cast<size_t>(p->tq));
+    const size_t o_g32 = o_g64 + align256(sizeof(double) * 3 * np);
+    const size_t total = o_g32 + align256(sizeof(float) * 3 * np);
+    hipError_t e = hipMalloc(&p->block, total);
+    if (e != hipSuccess) {
+        p->block = nullptr;
+        (void)hipGetLastError();
+        delete p;
+        return set_error(XS_ENOMEM, "species plan: cannot allocate %zu bytes (%s)", total, hipGetErrorString(e));
+    }
+    p->bytes = total;
+    char *b = static_cast<char *>(p->block);
+    e = hipMemcpy(b, blob.data(), blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_error(e, "species plan: table upload");
+    }
+    point_tables(b, off, p->d);
+    p->d.ones = reinterpret_cast<double *>(b + o_ones);
+    p->d.pos_r = reinterpret_cast<double *>(b + o_pos);
+    p->buf = reinterpret_cast<double *>(b + o_buf);
+    p->g64_r = reinterpret_cast<double *>(b + o_g64);
+    p->g32_r = reinterpret_cast<float *>(b + o_g32);
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(static_cast<int64_t>(ones_n))), dim3(kBlock), 0, s, p->d.ones,
+                       static_cast<int64_t>(ones_n), 1.0);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete p;
+        return hip_error(e, "species plan: unit weights");
+    }
+    *sub = sp.sub;
+    *out = p;
+    return XS_OK;
+}
+
+void species_plan_destroy(SpeciesPlan *p) { delete p; }
+
+size_t species_plan_bytes(const SpeciesPlan *p) { return p->bytes; }
+
+xs_status species_plan_forward(hipStream_t s, SpeciesPlan *p, Plan &inner, const double *q, const double *pos,
+                               double *I, double *amp) {
+    const SpeciesSplit &sp = p->sp;
+    double *I_s = p->buf, *amp_s = p->buf + p->tq;
+    XS_TRY(gather_positions(s, sp, p->d, pos));
+    if (!sp.sub.empty()) {
+        XS_TRY(inner.tile_atoms(s, p->d.pos_r, p->d.ones));
+        XS_TRY(inner.forward(s, q, I_s, amp_s));
+    }
+    if (!sp.segs.empty() && sp.max_q > 0)
+        hipLaunchKernelGGL(k_species_combine, dim3(blocks_for(sp.max_q), static_cast<unsigned>(sp.segs.size())),
+                           dim3(kBlock), 0, s, p->d.segs, p->d.sub_off, p->n_species, p->d.coef, q,
+                           reinterpret_cast<const double2 *>(amp_s), I, reinterpret_cast<double2 *>(amp));
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+}
+
+xs_status species_plan_grad(hipStream_t s, SpeciesPlan *p, Plan &inner, const double *q, const double *pos,
+                            const double *amp, const double *dL_dI, int32_t retile, float *dL_dr,
+                            double *dL_dr64) {
+    const SpeciesSplit &sp = p->sp;
+    double *w = p->buf;
+    double2 *amp_r = reinterpret_cast<double2 *>(p->buf + p->tq);
+    const int n_sub = static_cast<int>(sp.sub.size());
+    if (n_sub > 0 && sp.max_q > 0)
+        hipLaunchKernelGGL(k_species_weights, dim3(blocks_for(sp.max_q), static_cast<unsigned>(n_sub)),
+                           dim3(kBlock), 0, s, p->d.segs, p->d.sub_par, p->d.sub_sp, p->d.sub_out, p->d.coef, q,
+                           dL_dI, reinterpret_cast<const double2 *>(amp), w, amp_r);
+    XS_HIP(hipGetLastError());
+    if (n_sub > 0) {
+        if (retile) {
+            XS_TRY(gather_positions(s, sp, p->d, pos));
+            XS_TRY(inner.tile_atoms(s, p->d.pos_r, p->d.ones));
+        }
+        XS_TRY(inner.grad(s, q, p->d.ones, reinterpret_cast<const double *>(amp_r), w, dL_dr ? p->g32_r : nullptr,
+                          dL_dr64 ? p->g64_r : nullptr));
+    }
+    if (!sp.segs.empty() && sp.max_atoms > 0) {
+        const dim3 grid(blocks_for(sp.max_atoms), static_cast<unsigned>(sp.segs.size()));
+        if (dL_dr)
+            hipLaunchKernelGGL(k_species_scatter<float>, grid, dim3(kBlock), 0, s, p->d.segs, p->d.perm, p->g32_r,
+                               dL_dr);
+        if (dL_dr64)
+            hipLaunchKernelGGL(k_species_scatter<double>, grid, dim3(kBlock), 0, s, p->d.segs, p->d.perm, p->g64_r,
+                               dL_dr64);
     }
     XS_HIP(hipGetLastError());
     return XS_OK;

@@ -499,12 +499,28 @@ xs_status xs_roofline_probe(int32_t kind, int64_t bytes, double *rate, void *str
     return roofline_probe(static_cast<hipStream_t>(stream), kind, bytes, rate);
 }
 
+namespace {
+// Work lists, buffers and pixel order of an FP32C pair-sum plan over `segs`.
+xs_status build_pair_plan(hipStream_t s, xs::Plan &plan, const std::vector<Segment> &segs, const double *box,
+                          const double *q, const xs_tile_shape &fsh, const xs_tile_shape &gsh) {
+    const int n = static_cast<int>(segs.size());
+    if (fsh.lattice || gsh.lattice) XS_TRY(plan.find_lattices(s, segs.data(), n, q));
+    XS_TRY(plan.build(segs.data(), n, box, fsh, gsh));
+    XS_TRY(plan.allocate(s, true));
+    return plan.sort_pixels(s, q);
+}
+}  // namespace
+
 struct xs_plan {
-    xs::Plan plan;
+    xs::Plan plan;                         // pair sums (of the species segments for a species plan)
+    xs::SpeciesPlan *species = nullptr;    // species split and buffers, or NULL
     int device = 0;
     const double *q = nullptr;
     int64_t total_out = 0;
     int64_t total_pos = 0;
+    ~xs_plan() {
+        if (species) xs::species_plan_destroy(species);
+    }
 };
 
 xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void *stream) {
@@ -525,11 +541,41 @@ xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void
     auto *p = new (std::nothrow) xs_plan();
     if (!p) return set_error(XS_ENOMEM, "plan: host allocation failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    xs_status st = XS_OK;
-    if (fsh.lattice || gsh.lattice) st = p->plan.find_lattices(s, segs.data(), static_cast<int>(segs.size()), q);
-    if (st == XS_OK) st = p->plan.build(segs.data(), static_cast<int>(segs.size()), b->box, fsh, gsh);
-    if (st == XS_OK) st = p->plan.allocate(s, true);
-    if (st == XS_OK) st = p->plan.sort_pixels(s, q);
+    xs_status st = build_pair_plan(s, p->plan, segs, b->box, q, fsh, gsh);
+    if (st != XS_OK) {
+        delete p;
+        return st;
+    }
+    (void)hipGetDevice(&p->device);
+    p->q = q;
+    *out = p;
+    return XS_OK;
+}
+
+xs_status xs_plan_create_species(const xs_batch *b, const double *q, const int32_t *species, int32_t n_species,
+                                 const double *ff_coef, xs_plan **out, void *stream) {
+    XS_TRY(begin(stream));
+    if (!out) return set_error(XS_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    std::vector<Segment> segs;
+    int max_atoms = 0, max_q = 0;
+    XS_TRY(expand_batch(b, segs, max_atoms, max_q));
+    XS_TRY(check_box(b));
+    XS_TRY(check_species_args(n_species, ff_coef));
+    if (max_q > 0 && !q) return set_error(XS_EINVAL, "q is NULL");
+    if (max_atoms > 0 && !species) return set_error(XS_EINVAL, "species is NULL");
+    xs_tile_shape fsh, gsh;
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        fsh = g_shape[0];
+        gsh = g_shape[1];
+    }
+    auto *p = new (std::nothrow) xs_plan();
+    if (!p) return set_error(XS_ENOMEM, "plan: host allocation failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<Segment> sub;
+    xs_status st = species_plan_create(s, segs, species, n_species, ff_coef, &p->species, &sub);
+    if (st == XS_OK) st = build_pair_plan(s, p->plan, sub, b->box, q, fsh, gsh);
     if (st != XS_OK) {
         delete p;
         return st;
@@ -544,6 +590,7 @@ xs_status xs_plan_intensity(xs_plan *p, const double *pos, const double *f, doub
                             double *amp_out, void *stream) {
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
+    if (p->species) return set_error(XS_EINVAL, "species plan: use xs_plan_intensity_species");
     if (!I_out) return set_error(XS_EINVAL, "I_out is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     XS_TRY(p->plan.tile_atoms(s, pos, f));
@@ -555,11 +602,32 @@ xs_status xs_plan_grad(xs_plan *p, const double *pos, const double *f, const dou
                        void *stream) {
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
+    if (p->species) return set_error(XS_EINVAL, "species plan: use xs_plan_grad_species");
     if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
     if (!amp || !dL_dI) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (retile) XS_TRY(p->plan.tile_atoms(s, pos, f));
     return p->plan.grad(s, p->q, f, amp, dL_dI, dL_dr, dL_dr64);
+}
+
+xs_status xs_plan_intensity_species(xs_plan *p, const double *pos, double *I_out, double *amp_out,
+                                    void *stream) {
+    XS_TRY(begin(stream));
+    if (!p) return set_error(XS_EINVAL, "plan is NULL");
+    if (!p->species) return set_error(XS_EINVAL, "not a species plan: use xs_plan_intensity");
+    if (!I_out) return set_error(XS_EINVAL, "I_out is NULL");
+    return species_plan_forward(static_cast<hipStream_t>(stream), p->species, p->plan, p->q, pos, I_out, amp_out);
+}
+
+xs_status xs_plan_grad_species(xs_plan *p, const double *pos, const double *amp, const double *dL_dI,
+                               int32_t retile, float *dL_dr, double *dL_dr64, void *stream) {
+    XS_TRY(begin(stream));
+    if (!p) return set_error(XS_EINVAL, "plan is NULL");
+    if (!p->species) return set_error(XS_EINVAL, "not a species plan: use xs_plan_grad");
+    if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
+    if (!amp || !dL_dI) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
+    return species_plan_grad(static_cast<hipStream_t>(stream), p->species, p->plan, p->q, pos, amp, dL_dI, retile,
+                             dL_dr, dL_dr64);
 }
 
 xs_status xs_plan_destroy(xs_plan *p) {
@@ -581,7 +649,8 @@ xs_status xs_plan_describe(const xs_plan *p, xs_plan_info *info) {
     info->n_lattice_segments = nl;
     info->n_forward_items = nf;
     info->n_gradient_items = ng;
-    info->device_bytes = static_cast<int64_t>(p->plan.device_bytes);
+    info->device_bytes = static_cast<int64_t>(p->plan.device_bytes) +
+                         (p->species ? static_cast<int64_t>(species_plan_bytes(p->species)) : 0);
     return XS_OK;
 }
 

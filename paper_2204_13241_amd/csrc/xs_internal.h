@@ -152,6 +152,19 @@ xs_status species_grad(hipStream_t s, const std::vector<Segment> &segs, const do
                        const int32_t *species, int32_t n_species, const double *coef_host, const double *q,
                        const double *amp, const double *dL_dI, int32_t precision, float *dL_dr, double *dL_dr64,
                        const xs_tile_shape &fsh, const xs_tile_shape &gsh);
+// Plans for q-dependent form factors: the species split and its buffers; the pair
+// sums of the species segments (*sub) run through an inner FP32C plan built by the caller.
+struct SpeciesPlan;
+xs_status species_plan_create(hipStream_t s, const std::vector<Segment> &segs, const int32_t *species,
+                              int32_t n_species, const double *coef_host, SpeciesPlan **out,
+                              std::vector<Segment> *sub);
+void species_plan_destroy(SpeciesPlan *p);
+size_t species_plan_bytes(const SpeciesPlan *p);
+xs_status species_plan_forward(hipStream_t s, SpeciesPlan *p, Plan &inner, const double *q, const double *pos,
+                               double *I, double *amp);
+xs_status species_plan_grad(hipStream_t s, SpeciesPlan *p, Plan &inner, const double *q, const double *pos,
+                            const double *amp, const double *dL_dI, int32_t retile, float *dL_dr,
+                            double *dL_dr64);
 xs_status frame_sums(hipStream_t s, const double *I, int64_t n_q, int64_t n_out, int64_t s_out, int64_t n_sum,
                      int64_t s_sum, double scale, double *J);
 xs_status ring_histogram(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,

@@ -85,3 +85,32 @@ def test_tile_shape_roundtrip_and_limits():
     with pytest.raises(_lib.XsError):
         api.set_tile_shape(1, 64, 4, 16, 100)
     api.set_tile_shape(0, **old)
+
+
+def test_plan_validation_without_device_work():
+    import numpy as np
+    from paper_2204_13241_amd.api import make_batch
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    p = ctypes.c_void_p(8)
+    coef = np.zeros((2, 9))
+    cptr = coef.ctypes.data_as(ctypes.c_void_p)
+    b = make_batch([10], [5], [1], 10.0)
+    st = b.struct()
+    rc, msg = _status(lib.xs_plan_create_species(ctypes.byref(st), p, p, 2, cptr, None, None))
+    assert rc == _lib.XS_EINVAL and "NULL" in msg
+    rc, msg = _status(lib.xs_plan_create_species(ctypes.byref(st), p, p, 0, cptr, ctypes.byref(out), None))
+    assert rc == _lib.XS_EINVAL and "n_species" in msg and not out.value
+    coef[1, 3] = np.nan
+    rc, msg = _status(lib.xs_plan_create_species(ctypes.byref(st), p, p, 2, cptr, ctypes.byref(out), None))
+    assert rc == _lib.XS_EINVAL and "finite" in msg
+    bad = make_batch([10], [5], [1], [0.0, 1.0, 1.0])
+    sb = bad.struct()
+    rc, msg = _status(lib.xs_plan_create_species(ctypes.byref(sb), p, p, 2, cptr, ctypes.byref(out), None))
+    assert rc == _lib.XS_EINVAL and "box" in msg
+    for fn, args in ((lib.xs_plan_intensity_species, (None, p, p, None, None)),
+                     (lib.xs_plan_grad_species, (None, p, p, p, 1, p, None, None)),
+                     (lib.xs_plan_intensity, (None, p, p, p, None, None))):
+        rc, msg = _status(fn(*args))
+        assert rc == _lib.XS_EINVAL and "plan is NULL" in msg
+    assert lib.xs_plan_destroy(None) == _lib.XS_OK

@@ -1,0 +1,150 @@
+"""Species plans (q-dependent form factors in the plan form): identical to the one-shot
+species calls on the same work lists, uneven batches against the oracle, HIP-graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+pytestmark = pytest.mark.gpu
+
+COEF = np.array([[1.2, 2.1, 0.6, 0.3, 11.0, 3.2, 0.9, 0.21, 0.25],
+                 [0.5, 0.3, 0.12, 0.08, 6.0, 2.0, 0.7, 0.15, 0.02],
+                 [3.0, 2.2, 1.1, 0.4, 9.0, 2.5, 0.6, 0.1, 0.3]])
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2204_13241_amd import api
+    return api
+
+
+def _scaled(I, I_ref, sp, q):
+    f = oracle.form_factors(q, COEF)[:, sp]
+    inc = np.sum(f * f, axis=1)
+    return float(np.max(np.abs(I - I_ref) / np.maximum(I_ref, inc)))
+
+
+def test_species_plan_matches_one_shot_bitwise(api):
+    """With the lattice form off, the plan runs the one-shot call's kernels on the same
+    species segments: identical intensities, amplitudes and gradients."""
+    from _gpu import dev, host
+    old = [api.get_tile_shape(k) for k in (0, 1)]
+    for k in (0, 1):
+        api.set_tile_shape(k, **dict(old[k], lattice=0))
+    try:
+        rng = np.random.default_rng(21)
+        N, L = 3000, 40.0
+        pos = dev(rng.uniform(0, L, (N, 3)))
+        sp = dev(rng.integers(0, 3, N), dtype=torch.int32)
+        q = dev(X.planar_grid(40, 3.0))
+        wgt = dev(rng.standard_normal(q.shape[0]))
+        print("species plan vs one-shot", flush=True)
+        I1, a1 = api.intensity_species(pos, sp, COEF, q, "fp32c", box=L, return_amp=True)
+        g1 = api.intensity_species_grad(pos, sp, COEF, q, a1, wgt, "fp32c", box=L)
+        plan = api.SpeciesPlan([(N, 1, q, L)], sp, COEF)
+        I2, a2 = plan.intensity(pos)
+        g2 = plan.grad(pos, a2, wgt, retile=False)
+        g3 = plan.grad(pos, a2, wgt, retile=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(I1), host(I2)) and np.array_equal(host(a1).ravel(), host(a2).ravel())
+        assert np.array_equal(host(g1), host(g2)) and np.array_equal(host(g2), host(g3))
+        info = plan.describe()
+        assert info["n_segments"] == 3 and info["device_bytes"] > 0
+        plan.close()
+    finally:
+        for k in (0, 1):
+            api.set_tile_shape(k, **old[k])
+
+
+def test_species_plan_uneven_batch_against_oracle(api):
+    """Two systems of uneven size and frame count, one planar (lattice form) and one
+    Ewald detector, one species absent from the second system."""
+    from _gpu import dev, host, grad_err
+    rng = np.random.default_rng(22)
+    N, F, Ls = [700, 350], [2, 1], [32.0, 28.0]
+    qs = [X.planar_grid(24, 2.5), X.ewald_detector(16, 1.5)]
+    pos = [rng.uniform(0, Ls[i], (F[i], N[i], 3)) for i in range(2)]
+    sp = [rng.integers(0, 3, N[0]).astype(np.int32), rng.integers(0, 2, N[1]).astype(np.int32)]
+    systems = [(N[i], F[i], dev(qs[i]), Ls[i]) for i in range(2)]
+    plan = api.SpeciesPlan(systems, dev(np.concatenate(sp), dtype=torch.int32), COEF)
+    pos_d = dev(np.concatenate([p.reshape(-1, 3) for p in pos]))
+    print("species plan batch", flush=True)
+    I, amp = plan.intensity(pos_d)
+    w = [rng.standard_normal((F[i], qs[i].shape[0])) for i in range(2)]
+    g = plan.grad(pos_d, amp, dev(np.concatenate([x.ravel() for x in w])), retile=False,
+                  g64=torch.empty((plan.total_pos, 3), dtype=torch.float64, device="cuda:0"))
+    Ih, gh = host(I), host(g)
+    off, poff = plan.batch.out_off, plan.batch.pos_off
+    for i in range(2):
+        for t in range(F[i]):
+            Ir, ar = oracle.intensity_species(pos[i][t], sp[i], COEF, qs[i])
+            o = off[i] + t * qs[i].shape[0]
+            assert _scaled(Ih[o: o + qs[i].shape[0]], Ir, sp[i], qs[i]) < 1e-5
+            gr = oracle.intensity_species_grad(pos[i][t], sp[i], COEF, qs[i], ar, w[i][t])
+            po = poff[i] + t * N[i]
+            assert grad_err(gh[po: po + N[i]], gr) < 2e-5
+    assert plan.describe()["n_lattice_segments"] >= 1
+    plan.close()
+
+
+def test_species_plan_refuses_the_per_atom_calls(api):
+    from _gpu import dev
+    rng = np.random.default_rng(23)
+    q = dev(X.planar_grid(16, 2.0))
+    plan = api.SpeciesPlan([(100, 1, q, 20.0)], dev(rng.integers(0, 3, 100), dtype=torch.int32), COEF)
+    pos = dev(rng.uniform(0, 20.0, (100, 3)))
+    with pytest.raises(RuntimeError, match="species plan"):
+        api.Plan.intensity(plan, pos, dev(np.ones(100)))
+    plan.close()
+    with pytest.raises(RuntimeError, match="species"):
+        api.SpeciesPlan([(100, 1, q, 20.0)], dev(np.full(100, 3), dtype=torch.int32), COEF)
+
+
+def test_species_plan_graph_replay(api):
+    """Capture forward + adjoint of a species plan; every replay equals the eager result."""
+    from _gpu import dev, host
+    rng = np.random.default_rng(24)
+    N, L = 2000, 36.0
+    q = dev(X.planar_grid(32, 3.0))
+    pos = dev(rng.uniform(0, L, (N, 3)))
+    plan = api.SpeciesPlan([(N, 1, q, L)], dev(rng.integers(0, 3, N), dtype=torch.int32), COEF)
+    wgt = dev(rng.standard_normal(q.shape[0]))
+    I = torch.empty(q.shape[0], dtype=torch.float64, device="cuda:0")
+    amp = torch.empty((q.shape[0], 2), dtype=torch.float64, device="cuda:0")
+    g = torch.empty((N, 3), dtype=torch.float32, device="cuda:0")
+    print("species plan graph", flush=True)
+    plan.intensity(pos, I, amp)
+    plan.grad(pos, amp, wgt, retile=False, g32=g)
+    torch.cuda.synchronize()
+    I_ref, g_ref = host(I).copy(), host(g).copy()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.intensity(pos, I, amp)
+        plan.grad(pos, amp, wgt, retile=False, g32=g)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.intensity(pos, I, amp)
+        plan.grad(pos, amp, wgt, retile=False, g32=g)
+    for rep in range(3):
+        I.zero_()
+        g.zero_()
+        _ = (pos * 1.0).sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(I), I_ref), rep
+        assert np.array_equal(host(g), g_ref), rep
+    pos.add_(0.05)
+    graph.replay()
+    torch.cuda.synchronize()
+    I_moved = host(I).copy()
+    I2, _ = plan.intensity(pos)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(I2), I_moved)
+    del graph
+    plan.close()
