@@ -366,8 +366,9 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape);
  * replays in place.  Arguments as for xs_intensity_direct / xs_intensity_grad
  * with the plan's batch layout.  xs_plan_grad re-tiles the atoms when
  * `retile` is non-zero; with retile = 0 it reuses the tiles of the last
- * xs_plan_intensity (the positions must not have changed since).  Calls on
- * one plan must be ordered (one stream); plans are not thread-safe.
+ * xs_plan_intensity (the positions must not have changed since; XS_EINVAL if
+ * the plan has no tiles yet).  Calls on one plan must be ordered (one
+ * stream); plans are not thread-safe.
  */
 typedef struct xs_plan xs_plan;
 xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **plan, void *stream);

@@ -1597,7 +1597,10 @@ xs_status Plan::sort_pixels(hipStream_t s, const double *q) {
 xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
     Tables &t = *T;
     Buffers &b = *B;
-    if (t.max_atoms == 0) return XS_OK;
+    if (t.max_atoms == 0) {
+        tiled = true;
+        return XS_OK;
+    }
     void *tok = nullptr;
     timer_begin(s, TIMER_BIN, &tok);
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
@@ -1616,6 +1619,7 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
                        b.bsegs, pos, f, b.sorted, b.t_hi, b.t_lo, b.origins, b.tile_atom);
     timer_end(s, TIMER_BIN, tok, static_cast<double>(t.atoms));
     XS_HIP(hipGetLastError());
+    tiled = true;
     return XS_OK;
 }
 

@@ -469,6 +469,9 @@ xs_status species_plan_grad(hipStream_t s, SpeciesPlan *p, Plan &inner, const do
     double *w = p->buf;
     double2 *amp_r = reinterpret_cast<double2 *>(p->buf + p->tq);
     const int n_sub = static_cast<int>(sp.sub.size());
+    if (n_sub > 0 && !retile && !inner.tiled)
+        return set_error(XS_EINVAL,
+                         "retile = 0 needs the atom tiles of an earlier xs_plan_intensity_species on this plan");
     if (n_sub > 0 && sp.max_q > 0)
         hipLaunchKernelGGL(k_species_weights, dim3(blocks_for(sp.max_q), static_cast<unsigned>(n_sub)),
                            dim3(kBlock), 0, s, p->d.segs, p->d.sub_par, p->d.sub_sp, p->d.sub_out, p->d.coef, q,

@@ -548,6 +548,10 @@ xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void
     }
     (void)hipGetDevice(&p->device);
     p->q = q;
+    for (const Segment &g : segs) {
+        p->total_out += g.n_q;
+        p->total_pos += g.n_atoms;
+    }
     *out = p;
     return XS_OK;
 }
@@ -575,13 +579,17 @@ xs_status xs_plan_create_species(const xs_batch *b, const double *q, const int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<Segment> sub;
     xs_status st = species_plan_create(s, segs, species, n_species, ff_coef, &p->species, &sub);
-    if (st == XS_OK) st = build_pair_plan(s, p->plan, sub, b->box, q, fsh, gsh);
+    if (st == XS_OK && !sub.empty()) st = build_pair_plan(s, p->plan, sub, b->box, q, fsh, gsh);
     if (st != XS_OK) {
         delete p;
         return st;
     }
     (void)hipGetDevice(&p->device);
     p->q = q;
+    for (const Segment &g : segs) {
+        p->total_out += g.n_q;
+        p->total_pos += g.n_atoms;
+    }
     *out = p;
     return XS_OK;
 }
@@ -591,7 +599,7 @@ xs_status xs_plan_intensity(xs_plan *p, const double *pos, const double *f, doub
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
     if (p->species) return set_error(XS_EINVAL, "species plan: use xs_plan_intensity_species");
-    if (!I_out) return set_error(XS_EINVAL, "I_out is NULL");
+    if (p->total_out > 0 && !I_out) return set_error(XS_EINVAL, "I_out is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     XS_TRY(p->plan.tile_atoms(s, pos, f));
     return p->plan.forward(s, p->q, I_out, amp_out);
@@ -603,8 +611,10 @@ xs_status xs_plan_grad(xs_plan *p, const double *pos, const double *f, const dou
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
     if (p->species) return set_error(XS_EINVAL, "species plan: use xs_plan_grad_species");
-    if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
-    if (!amp || !dL_dI) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
+    if (p->total_pos > 0 && !dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
+    if (p->total_out > 0 && (!amp || !dL_dI)) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
+    if (!retile && !p->plan.tiled)
+        return set_error(XS_EINVAL, "retile = 0 needs the atom tiles of an earlier xs_plan_intensity on this plan");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (retile) XS_TRY(p->plan.tile_atoms(s, pos, f));
     return p->plan.grad(s, p->q, f, amp, dL_dI, dL_dr, dL_dr64);
@@ -615,7 +625,7 @@ xs_status xs_plan_intensity_species(xs_plan *p, const double *pos, double *I_out
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
     if (!p->species) return set_error(XS_EINVAL, "not a species plan: use xs_plan_intensity");
-    if (!I_out) return set_error(XS_EINVAL, "I_out is NULL");
+    if (p->total_out > 0 && !I_out) return set_error(XS_EINVAL, "I_out is NULL");
     return species_plan_forward(static_cast<hipStream_t>(stream), p->species, p->plan, p->q, pos, I_out, amp_out);
 }
 
@@ -624,8 +634,8 @@ xs_status xs_plan_grad_species(xs_plan *p, const double *pos, const double *amp,
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
     if (!p->species) return set_error(XS_EINVAL, "not a species plan: use xs_plan_grad");
-    if (!dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
-    if (!amp || !dL_dI) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
+    if (p->total_pos > 0 && !dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
+    if (p->total_out > 0 && (!amp || !dL_dI)) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
     return species_plan_grad(static_cast<hipStream_t>(stream), p->species, p->plan, p->q, pos, amp, dL_dI, retile,
                              dL_dr, dL_dr64);
 }

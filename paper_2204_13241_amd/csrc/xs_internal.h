@@ -121,6 +121,7 @@ public:
     Buffers *B;
     void *owned_block = nullptr;
     size_t device_bytes = 0;
+    bool tiled = false;        // tile_atoms has been enqueued at least once
     int n_seg = 0;
     xs_tile_shape fshape{}, gshape{};
 };

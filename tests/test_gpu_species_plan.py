@@ -148,3 +148,41 @@ def test_species_plan_graph_replay(api):
     assert np.array_equal(host(I2), I_moved)
     del graph
     plan.close()
+
+
+def test_plans_refuse_reusing_tiles_before_any_forward(api):
+    """retile = 0 on a fresh plan has no atom tiles to reuse: a clear error, no launch."""
+    from _gpu import dev
+    rng = np.random.default_rng(25)
+    q = dev(X.planar_grid(16, 2.0))
+    pos = dev(rng.uniform(0, 20.0, (100, 3)))
+    amp = dev(np.ones((q.shape[0], 2)))
+    w = dev(np.ones(q.shape[0]))
+    sp_plan = api.SpeciesPlan([(100, 1, q, 20.0)], dev(rng.integers(0, 3, 100), dtype=torch.int32), COEF)
+    with pytest.raises(RuntimeError, match="retile = 0"):
+        sp_plan.grad(pos, amp, w, retile=False)
+    g = sp_plan.grad(pos, amp, w, retile=True)     # re-tiling is always allowed
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all()
+    sp_plan.close()
+    plan = api.Plan.single(100, 1, q, 20.0)
+    f = dev(np.ones(100))
+    with pytest.raises(RuntimeError, match="retile = 0"):
+        plan.grad(pos, f, amp, w, retile=False)
+    plan.intensity(pos, f)
+    plan.grad(pos, f, amp, w, retile=False)
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def test_species_plan_without_atoms_gives_zero_intensity(api):
+    from _gpu import dev, host
+    q = dev(X.planar_grid(8, 2.0))
+    plan = api.SpeciesPlan([(0, 2, q, 20.0)], torch.empty(0, dtype=torch.int32, device="cuda:0"), COEF)
+    pos = torch.empty((0, 3), dtype=torch.float64, device="cuda:0")
+    I, amp = plan.intensity(pos)
+    g = plan.grad(pos, amp, dev(np.ones(2 * q.shape[0])), retile=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(I), np.zeros(2 * q.shape[0])) and g.numel() == 0
+    assert plan.describe()["n_segments"] == 0
+    plan.close()
