@@ -70,9 +70,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+DEVICE_END = b"// ---------------------------------------------------------------- host side"
+
+
 def source_hash(path):
+    """sha256[:16] of the device-code part of a kernel source (everything before its host
+    section), so host-side edits do not invalidate the kernels' counter profiles."""
     with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+        src = fh.read()
+    cut = src.find(DEVICE_END)
+    return hashlib.sha256(src if cut < 0 else src[:cut]).hexdigest()[:16]
 
 
 def traffic_from_profile(kernel_src, kernel, shape):

@@ -72,7 +72,7 @@ def _store_cache(path, data):
 # A candidate replaces the best shape so far only when it is faster by more than this
 # fraction: launch-to-launch noise is about 1%, and a stable pick keeps results (and the
 # profiles taken with the default shapes) comparable from run to run.
-TIE = 0.02
+TIE = 0.03
 
 
 def _current_first(candidates, current):
@@ -81,19 +81,23 @@ def _current_first(candidates, current):
     return [c for c in cands if tuple(c) == tuple(current)] + [c for c in cands if tuple(c) != tuple(current)]
 
 
-def _time_kernel(kind: str, run, reps: int) -> float:
+def _time_kernel(kind: str, run, reps: int, rounds: int = 2) -> float:
+    """Mean launch time of the pair kernel over `reps` calls, the best of `rounds` rounds."""
     run()                                 # warm-up (also builds code objects)
     torch.cuda.synchronize()
-    api.timing_enable(True)
-    for _ in range(reps):
-        run()
-    torch.cuda.synchronize()
-    rec = api.timing_read(kind)
-    api.timing_enable(False)
-    return rec["ms"] / max(rec["launches"], 1)
+    best = float("inf")
+    for _ in range(rounds):
+        api.timing_enable(True)
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        rec = api.timing_read(kind)
+        api.timing_enable(False)
+        best = min(best, rec["ms"] / max(rec["launches"], 1))
+    return best
 
 
-def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 3, use_cache: bool = True,
+def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: bool = True,
          fwd_candidates: Optional[List] = None, grad_candidates: Optional[List] = None,
          apply: bool = True) -> dict:
     """Pick the fastest forward and gradient tile shapes for this batch.
