@@ -81,6 +81,27 @@ def _current_first(candidates, current):
     return [c for c in cands if tuple(c) == tuple(current)] + [c for c in cands if tuple(c) != tuple(current)]
 
 
+def _search(candidates, current, timer) -> dict:
+    """Time every candidate (installed shape first); the installed shape is timed again
+    at the end, when the clocks have settled, and keeps the better of its two times."""
+    times = {}
+    for c in _current_first(candidates, current):
+        times[tuple(c)] = timer(tuple(c))
+    cur = tuple(current)
+    if cur in times:
+        times[cur] = min(times[cur], timer(cur))
+    return times
+
+
+def _pick(times: dict, current):
+    """The installed shape unless another one is faster by more than TIE (the fastest then)."""
+    fastest = min(times, key=times.get)
+    cur = tuple(current)
+    if cur in times and not times[fastest] < times[cur] * (1.0 - TIE):
+        return cur
+    return fastest
+
+
 def _time_kernel(kind: str, run, reps: int, rounds: int = 2) -> float:
     """Mean launch time of the pair kernel over `reps` calls, the best of `rounds` rounds."""
     run()                                 # warm-up (also builds code objects)
@@ -119,22 +140,26 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
         return dict(best, source="cache", key=key)
     old_f, old_g = api.get_tile_shape(0), api.get_tile_shape(1)
     timings = {"forward": {}, "gradient": {}}
-    # forward: candidate shapes with the current gradient shape; the current shape is
-    # timed first and a later candidate must beat the best so far by more than TIE
-    best_f, best_ft = None, float("inf")
-    for ql, occ, split in _current_first(fwd_candidates or FWD_CANDIDATES,
-                                         (old_f["q_per_lane"], old_f["waves_per_simd"], old_f["atom_split"])):
-        shape = dict(atoms_per_tile=64, q_per_lane=ql, atom_split=split, pixel_split=old_f["pixel_split"],
-                     waves_per_simd=occ)
-        api.set_tile_shape(0, **shape)
+
+    def fwd_shape(c):
+        ql, occ, split = c
+        return dict(atoms_per_tile=64, q_per_lane=ql, atom_split=split, pixel_split=old_f["pixel_split"],
+                    waves_per_simd=occ)
+
+    def time_fwd(c):
+        api.set_tile_shape(0, **fwd_shape(c))
         plan = api.Plan(systems)
         I = torch.empty(plan.total_out, dtype=torch.float64, device=pos.device)
         amp = torch.empty((plan.total_out, 2), dtype=torch.float64, device=pos.device)
         t = _time_kernel("fwd32", lambda: plan.intensity(pos, f, I, amp), reps)
         plan.close()
-        timings["forward"]["ql%d_occ%d_split%d" % (ql, occ, split)] = t
-        if t < best_ft * (1.0 - TIE):
-            best_f, best_ft = shape, t
+        return t
+
+    cur_f = (old_f["q_per_lane"], old_f["waves_per_simd"], old_f["atom_split"])
+    tf = _search(fwd_candidates or FWD_CANDIDATES, cur_f, time_fwd)
+    pick_f = _pick(tf, cur_f)
+    timings["forward"] = {"ql%d_occ%d_split%d" % c: t for c, t in tf.items()}
+    best_f, best_ft = fwd_shape(pick_f), tf[pick_f]
     api.set_tile_shape(0, **best_f)
     # gradient: amplitudes of the tuned forward, unit-variance weights
     plan = api.Plan(systems)
@@ -145,19 +170,25 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
     gen.manual_seed(1234)
     w = torch.randn(plan.total_out, dtype=torch.float64, device=pos.device, generator=gen)
     plan.close()
-    best_g, best_gt = None, float("inf")
-    for al, occ, pc in _current_first(grad_candidates or GRAD_CANDIDATES,
-                                      (old_g["q_per_lane"], old_g["waves_per_simd"], old_g["pixel_split"])):
-        shape = dict(atoms_per_tile=64, q_per_lane=al, atom_split=old_g["atom_split"], pixel_split=pc,
-                     waves_per_simd=occ)
-        api.set_tile_shape(1, **shape)
+
+    def grad_shape(c):
+        al, occ, pc = c
+        return dict(atoms_per_tile=64, q_per_lane=al, atom_split=old_g["atom_split"], pixel_split=pc,
+                    waves_per_simd=occ)
+
+    def time_grad(c):
+        api.set_tile_shape(1, **grad_shape(c))
         plan = api.Plan(systems)
         g = torch.empty((plan.total_pos, 3), dtype=torch.float32, device=pos.device)
         t = _time_kernel("grad32", lambda: plan.grad(pos, f, amp, w, retile=True, g32=g), reps)
         plan.close()
-        timings["gradient"]["al%d_occ%d_pix%d" % (al, occ, pc)] = t
-        if t < best_gt * (1.0 - TIE):
-            best_g, best_gt = shape, t
+        return t
+
+    cur_g = (old_g["q_per_lane"], old_g["waves_per_simd"], old_g["pixel_split"])
+    tg = _search(grad_candidates or GRAD_CANDIDATES, cur_g, time_grad)
+    pick_g = _pick(tg, cur_g)
+    timings["gradient"] = {"al%d_occ%d_pix%d" % c: t for c, t in tg.items()}
+    best_g, best_gt = grad_shape(pick_g), tg[pick_g]
     result = {"forward": best_f, "gradient": best_g, "forward_ms": best_ft, "gradient_ms": best_gt}
     if use_cache:
         cache[key] = result

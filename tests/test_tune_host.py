@@ -34,3 +34,26 @@ def test_cache_roundtrip_and_unreadable_file(tmp_path):
         fh.write("{not json")
     assert tune._load_cache(p) == {}
     assert 0.0 < tune.TIE < 0.1
+
+
+def test_pick_keeps_the_installed_shape_within_the_margin():
+    cur = (8, 4, 64)
+    t = {cur: 1.00, (8, 0, 32): 0.98, (4, 4, 64): 1.20}
+    assert tune._pick(t, cur) == cur
+    t[(8, 0, 32)] = 0.95
+    assert tune._pick(t, cur) == (8, 0, 32)
+    # a shape that is not a candidate: the fastest wins
+    assert tune._pick({(1, 0, 16): 2.0, (2, 0, 16): 1.5}, cur) == (2, 0, 16)
+
+
+def test_search_times_the_installed_shape_twice_and_keeps_the_better():
+    calls = []
+    seq = iter([1.10, 1.05, 1.20, 0.99])
+
+    def timer(c):
+        calls.append(c)
+        return next(seq)
+    cands = [(1, 0, 16), (8, 4, 64), (2, 0, 16)]
+    times = tune._search(cands, (8, 4, 64), timer)
+    assert calls == [(8, 4, 64), (1, 0, 16), (2, 0, 16), (8, 4, 64)]
+    assert times[(8, 4, 64)] == 0.99 and times[(1, 0, 16)] == 1.05
