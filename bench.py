@@ -187,7 +187,9 @@ def run_grad(args):
         torch.cuda.current_stream().wait_stream(s_cap)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
+        # capture on the warmed-up stream: the library's scratch is cached per stream and
+        # cannot grow during capture
+        with torch.cuda.graph(graph, stream=s_cap):
             loss_g = step()
         graph.replay()
         torch.cuda.synchronize()
@@ -203,6 +205,13 @@ def run_grad(args):
             loss = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if graph is not None:
+        # event timers are not recorded inside a replayed graph: the per-kernel figures
+        # come from the same number of eager steps right after the timed replays
+        api.timing_enable(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
     fwd = api.timing_read("fwd32")
     grd = api.timing_read("grad32")
     binr = api.timing_read("bin")

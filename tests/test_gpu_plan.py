@@ -117,3 +117,53 @@ def test_plan_graph_replay(api):
     assert np.array_equal(host(I2), I_moved)
     del graph
     plan.close()
+
+
+def test_training_step_graph_replay(api):
+    """The whole differentiation step (plan forward, speckle loss, plan adjoint, position
+    update) captured once: replays, with eager work between them, reproduce eager steps
+    bit for bit."""
+    from _gpu import dev, host
+    w = X.workload_grad(n_atoms=2000, n_det=32)
+    L = w.box[0]
+    q = dev(w.q[0])
+    f = dev(w.f[0])
+    It = api.intensity(dev(w.extra["r_target"]), f, q, "fp64")
+    plan = api.Plan.single(2000, 1, q, L)
+    I = torch.empty(q.shape[0], dtype=torch.float64, device="cuda:0")
+    amp = torch.empty((q.shape[0], 2), dtype=torch.float64, device="cuda:0")
+    g = torch.empty((2000, 3), dtype=torch.float32, device="cuda:0")
+
+    def step(pos):
+        plan.intensity(pos, f, I, amp)
+        loss, dLdI = api.speckle_loss(I, It)
+        plan.grad(pos, f, amp, dLdI, retile=False, g32=g)
+        api.position_step(pos, g, 0.01)
+        return loss
+
+    pos_e = dev(w.positions[0][0])
+    for _ in range(3):
+        step(pos_e)
+    torch.cuda.synchronize()
+    ref = host(pos_e).copy()
+    pos_g = dev(w.positions[0][0])
+    start = pos_g.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(pos_g)                                   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    pos_g.copy_(start)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        step(pos_g)
+    pos_g.copy_(start)                                # capture does not run the work
+    torch.cuda.synchronize()
+    for _ in range(3):
+        graph.replay()
+        _ = (pos_g * 2.0).sum()                       # unrelated eager work between replays
+        torch.cuda.synchronize()
+    assert np.array_equal(host(pos_g), ref)
+    del graph
+    plan.close()
