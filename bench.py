@@ -40,30 +40,39 @@ PEAK_TRANS = CUS * CLOCK * TRANS_LANES          # transcendental lane-ops/s
 PEAK_SINCOS_PAIRS = PEAK_TRANS / 2.0           # pairs/s with one sin + one cos each
 PEAK_HBM = 8.0e12                              # bytes/s
 PEAK_FMA64 = CUS * CLOCK * 64                  # FP64 FMA lane-ops/s (78.6 TFLOP/s)
+PEAK_F16_MFMA = 2.5e15                          # dense FP16 matrix flop/s
 
 
-def alu_peak(n_valu, n_trans):
-    """Pairs/s when every CU issues only the kernel's per-pair VALU and
-    transcendental instructions back to back (no overlap between the two)."""
-    return CUS * CLOCK / (n_valu / VALU_LANES + n_trans / TRANS_LANES)
+def alu_peak(n_valu, n_trans, mfma_flops=0.0):
+    """Pairs/s when every CU issues only the kernel's per-pair VALU, transcendental and
+    FP16 matrix work back to back (no overlap between them, as measured)."""
+    f16_per_cu_clk = PEAK_F16_MFMA / (CUS * CLOCK)
+    return CUS * CLOCK / (n_valu / VALU_LANES + n_trans / TRANS_LANES + mfma_flops / f16_per_cu_clk)
 
 
 def pair_mix(kernel, lattice, ql, qz_zero):
-    """Per-pair instruction mix (FP32 VALU, transcendental) of the inner loops.
+    """Per-pair work (FP32 VALU, transcendental, FP16 matrix flops) of the inner loops.
     forward, general: 2 FMA phase (3 with dq_z), sin + cos, 2 FMA accumulate.
     forward, lattice run of QL pixels: per atom 2 FMA phase (3 with dq_z) + sin + cos
     + 2 FMA for pixel 0 + 4 FMA (complex multiply-add) for each further pixel.
+    forward, matrix-core lattice (runs of 32): per (run, atom) add + 2 FMA phase (3 with
+    dq_z), sin + cos and the FP16 split of both parts (~10 VALU), shared by the run's 32
+    pixels; per (atom, pixel column) of a block the G factor (~20 VALU + sin + cos, shared
+    by 128 pixels); per tile and pixel the FP64 fold (3 ops / 64 atoms); 12 matrix
+    instructions of 32x32x16 per 16 atoms and 32x32 pixels = 24 flops per pair.
     adjoint, general: add + 2 FMA phase (3 with dq_z), sin, 2 FMA (3 with W_z).
     adjoint, lattice: FMA + add phase, sin, 2 FMA (3 with W_z)."""
     if kernel == "forward_fp32c":
         ph = 2 if qz_zero else 3
+        if lattice and ql == 32:
+            return (1 + ph + 10) / 32 + 20 / 128 + 3 / 64, 2 / 32 + 2 / 128, 24.0
         if lattice:
-            return (ph + 2 + 4 * (ql - 1)) / ql, 2.0 / ql
-        return ph + 2, 2.0
+            return (ph + 2 + 4 * (ql - 1)) / ql, 2.0 / ql, 0.0
+        return ph + 2, 2.0, 0.0
     acc = 2 if qz_zero else 3
     if lattice:
-        return 2 + acc, 1.0
-    return 1 + (2 if qz_zero else 3) + acc, 1.0
+        return 2 + acc, 1.0, 0.0
+    return 1 + (2 if qz_zero else 3) + acc, 1.0, 0.0
 
 
 def log(*a):
@@ -232,11 +241,12 @@ def run_grad(args):
         work = rec["work"] / max(rec["launches"], 1)
         ach = work / (avg_ms * 1e-3) / 1e9
         ql = max(2, shapes[kind]["q_per_lane"]) if lattice else shapes[kind]["q_per_lane"]
-        n_valu, n_trans = pair_mix(name, lattice, ql, qz_zero)
-        peak = alu_peak(n_valu, n_trans) / 1e9
+        n_valu, n_trans, n_mfma = pair_mix(name, lattice, ql, qz_zero)
+        peak = alu_peak(n_valu, n_trans, n_mfma) / 1e9
         kern[name] = {"avg_ms": avg_ms, "launches": rec["launches"], "pairs_per_launch": work,
-                      "form": "lattice" if lattice else "general", "valu_per_pair": n_valu,
-                      "trans_per_pair": n_trans, "achieved_Gpair_s": ach, "peak_Gpair_s": peak,
+                      "form": ("lattice-mfma" if lattice and ql == 32 else "lattice") if lattice else "general",
+                      "valu_per_pair": n_valu, "trans_per_pair": n_trans, "f16_mfma_flops_per_pair": n_mfma,
+                      "achieved_Gpair_s": ach, "peak_Gpair_s": peak,
                       "frac": ach / peak, "frac_of_sincos_pair_peak": ach / (PEAK_SINCOS_PAIRS / 1e9),
                       "traffic": traffic_from_profile(src, name, shapes[kind])}
     kern["binning"] = {"avg_ms": binr["ms"] / max(binr["launches"], 1), "launches": binr["launches"]}

@@ -394,7 +394,10 @@ __global__ __launch_bounds__(kBlock) void k_make_tiles(const BinSeg *__restrict_
     t_hi[ti * kTile + lane] = vh;
     t_lo[ti * kTile + lane] = vl;
     tile_atom[ti * kTile + lane] = j;
-    if (lane == 0) origins[ti] = make_double4(o[0], o[1], o[2], 0.0);
+    // largest |f| of the tile (the scale of the matrix-core form's FP16 factors)
+    float fmax = fabsf(vh.w);
+    for (int off = 32; off > 0; off >>= 1) fmax = fmaxf(fmax, __shfl_xor(fmax, off));
+    if (lane == 0) origins[ti] = make_double4(o[0], o[1], o[2], static_cast<double>(fmax));
 }
 
 __global__ void k_reset_counters(int32_t *counter, int n) {
@@ -794,6 +797,229 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice(
         for (int k = 0; k < QL; ++k)
             if (k < nk)
                 partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + p0 + k] = make_double2(re64[k], im64[k]);
+    }
+}
+
+// ---------------------------------------------------------------- forward, lattice form on matrix cores
+//
+// On a row lattice the sum over the atoms of one tile for a run of 32 pixels
+// q_c + k' a (k' = k - 15.5, k < 32, q_c the run's midpoint) factorizes into a complex
+// matrix product,
+//   sum_j f_j e^{2 pi i q.r_j} = F * sum_j Z(run, j) G(j, k),
+//   Z(run, j) = e^{2 pi i (theta_run + beta_j + dq_run.d_j)},   theta_run = frac(q_c.o)  (FP64)
+//   G(j, k)   = (f_j / F) e^{2 pi i frac(k' a.r_j)},             a.r_j = a.o + a.d_j   (FP64)
+// with o the tile origin, d_j = r_j - o, beta_j = frac(q_w.d_j) (FP64) for the centre q_w
+// of the wavefront's pixels, dq_run = q_c - q_w and F the largest |f| of the tile (so
+// every factor lies in the unit disk).  A wavefront owns 32 runs x 32 pixels (a 32 x 32
+// square of the lattice), a block 64 x 64 pixels; per tile that is a 32x32x64 complex
+// product.  Z and G come from FP32 sincos of phases reduced in FP64 (|phase| <= 0.5 for
+// G; theta and beta in [-0.5, 0.5] plus the small in-square term for Z); each part is
+// split into FP16 hi + lo (the exact FP32 residual rounded once) and the product keeps
+// hi*hi + hi*lo + lo*hi (relative error ~2^-22) on v_mfma_f32_32x32x16_f16 with FP32
+// accumulation: 12 matrix instructions per 16 atoms.  The tile sum times F is folded
+// into the pixel's FP64 item sum, as in the other forms.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+constexpr int kMfEdge = 32;                  // wavefront square: 32 runs x 32 pixels
+constexpr int kMfRows = 2 * kMfEdge;         // block rectangle: 64 rows
+constexpr int kMfCols = 2 * kMfEdge;         //                  x 64 pixels per row
+
+// x = hi + lo with hi the leading 11 significant bits of x (Veltkamp's split with the
+// factor 2^13 + 1) and lo the exact FP32 remainder rounded once to FP16.  The hi part is
+// formed in FP32, so its conversion to FP16 is exact (|x| >= 2^-14) and every use of it
+// agrees; a hi rounded to FP16 directly can be rounded one way where it is packed into
+// the matrix operand and the other way where the remainder is taken, at exact ties.
+__device__ __forceinline__ void split_f16(float x, _Float16 &hi, _Float16 &lo) {
+    const float c = x * 8193.0f;
+    const float h = c - (c - x);
+    hi = static_cast<_Float16>(h);
+    lo = static_cast<_Float16>(x - h);
+}
+
+__device__ __forceinline__ half8_t neg8(half8_t v) {
+    uint4 u = __builtin_bit_cast(uint4, v);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(half8_t, u);
+}
+
+template <int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice_mfma(
+    const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
+    const FwdSeg *__restrict__ segs, const double *__restrict__ q, const float4 *__restrict__ t_hi,
+    const float4 *__restrict__ t_lo, const double4 *__restrict__ origins, double2 *__restrict__ partial) {
+    // G pieces: [buf][re_hi, re_lo, im_hi, im_lo][16-atom step][pixel k][8-atom half]
+    __shared__ half8_t s_g[2][4][kTile / 16][kMfEdge][2];
+    __shared__ float4 s_d[2][kTile];           // (d_x, d_y, d_z, 0)
+    __shared__ float s_beta[2][kWaves][kTile];  // beta_j for each wavefront's centre
+    __shared__ double4 s_orig[2];
+    __shared__ double4 s_cen[kWaves];
+    __shared__ int32_t s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int run = lane & 31, hz = lane >> 5;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const FwdItem item = items[it];
+        const FwdSeg sg = segs[item.seg];
+        const int n1 = sg.n_q / sg.n2;
+        const int ib = item.p0 / sg.n_jb, jb = item.p0 - ib * sg.n_jb;
+        const int row0 = ib * kMfRows + (wave >> 1) * kMfEdge;
+        const int col0 = jb * kMfCols + (wave & 1) * kMfEdge;
+        const int row = row0 + run;
+        const bool active = row < n1 && col0 < sg.n2;
+        const int nk = active ? min(kMfEdge, sg.n2 - col0) : 0;
+        const int p0 = active ? row * sg.n2 + col0 : 0;
+        const double ax = sg.a[0], ay = sg.a[1], az = sg.a[2];
+        // the run's midpoint q_{p0} + 15.5 a (revolutions / A), from the lattice model
+        double qc[3];
+        {
+            const double e[3] = {ax, ay, az};
+            for (int c = 0; c < 3; ++c)
+                qc[c] = __builtin_fma(0.5 * (kMfEdge - 1), e[c], q[(sg.q + p0) * 3 + c] * kInvTwoPi);
+        }
+        // wavefront centre: bounding box of its active pixels
+        double lo[3], hi[3];
+        {
+            const double e[3] = {ax, ay, az};
+            for (int c = 0; c < 3; ++c) {
+                const double v0 = __builtin_fma(-0.5 * (kMfEdge - 1), e[c], qc[c]);
+                const double v1 = __builtin_fma(static_cast<double>(nk > 0 ? nk - 1 : 0), e[c], v0);
+                lo[c] = active ? fmin(v0, v1) : INFINITY;
+                hi[c] = active ? fmax(v0, v1) : -INFINITY;
+            }
+        }
+        for (int c = 0; c < 3; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+                hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+            }
+        // a wavefront without pixels (past the last row) keeps a finite centre
+        double cw[3];
+        for (int c = 0; c < 3; ++c) cw[c] = lo[c] <= hi[c] ? 0.5 * (lo[c] + hi[c]) : qc[c];
+        const bool planar = !(lo[2] < hi[2]);
+        if (lane == 0) s_cen[wave] = make_double4(cw[0], cw[1], cw[2], 0.0);
+        __syncthreads();
+        const float dqx = static_cast<float>(qc[0] - cw[0]);
+        const float dqy = static_cast<float>(qc[1] - cw[1]);
+        const float dqz = static_cast<float>(qc[2] - cw[2]);
+        const int64_t tbase = sg.tile0 + item.t0;
+        // staging of tile tt into buffer buf: atom offsets and the four wavefronts' beta
+        // by the first wavefront; the G factors of pixel gk, 16-atom step gks and
+        // 8-atom half ghh by every thread
+        const int gk = tid & 31, gks = (tid >> 5) & 3, ghh = tid >> 7;
+        const double kc = static_cast<double>(gk) - 0.5 * (kMfEdge - 1);
+        auto stage = [&](int buf, int tt) {
+            const int64_t ti = tbase + tt;
+            const double4 o = origins[ti];
+            if (tid < kTile) {
+                const float4 h = t_hi[ti * kTile + tid], l = t_lo[ti * kTile + tid];
+                const double dx = double(h.x) + double(l.x), dy = double(h.y) + double(l.y),
+                             dz = double(h.z) + double(l.z);
+                s_d[buf][tid] = make_float4(h.x, h.y, h.z, 0.f);
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) {
+                    const double4 c = s_cen[w];
+                    s_beta[buf][w][tid] = frac_f32(__builtin_fma(c.z, dz, __builtin_fma(c.y, dy, c.x * dx)));
+                }
+            }
+            if (tid == 0) s_orig[buf] = o;
+            const double t1 = __builtin_fma(az, o.z, __builtin_fma(ay, o.y, ax * o.x));
+            const float sc = o.w > 0.0 ? static_cast<float>(1.0 / o.w) : 0.f;
+            half8_t grh, grl, gih, gil;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t ai = ti * kTile + 16 * gks + 8 * ghh + u;
+                const float4 h = t_hi[ai], l = t_lo[ai];
+                const double ar = t1 + __builtin_fma(az, double(h.z) + double(l.z),
+                                       __builtin_fma(ay, double(h.y) + double(l.y), ax * (double(h.x) + double(l.x))));
+                const float ph = frac_f32(kc * ar);
+                const float w = h.w * sc;
+                const float gr = w * __builtin_amdgcn_cosf(ph), gi = w * __builtin_amdgcn_sinf(ph);
+                _Float16 a, bb;
+                split_f16(gr, a, bb);
+                grh[u] = a;
+                grl[u] = bb;
+                split_f16(gi, a, bb);
+                gih[u] = a;
+                gil[u] = bb;
+            }
+            s_g[buf][0][gks][gk][ghh] = grh;
+            s_g[buf][1][gks][gk][ghh] = grl;
+            s_g[buf][2][gks][gk][ghh] = gih;
+            s_g[buf][3][gks][gk][ghh] = gil;
+        };
+        double dre[16], dim[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) dre[i] = dim[i] = 0.0;
+        if (item.nt > 0) stage(0, 0);
+        __syncthreads();
+        for (int tt = 0; tt < item.nt; ++tt) {
+            const int buf = tt & 1;
+            const double4 o = s_orig[buf];
+            const float th = frac_f32(__builtin_fma(qc[2], o.z, __builtin_fma(qc[1], o.y, qc[0] * o.x)));
+            float16_t are, aim;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) are[i] = aim[i] = 0.f;
+#pragma unroll
+            for (int ks = 0; ks < kTile / 16; ++ks) {
+                half8_t zrh, zrl, zih, zil;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int j = 16 * ks + 8 * hz + u;
+                    const float4 d = s_d[buf][j];
+                    float ph = th + s_beta[buf][wave][j];
+                    ph = __builtin_fmaf(dqx, d.x, ph);
+                    ph = __builtin_fmaf(dqy, d.y, ph);
+                    if (!planar) ph = __builtin_fmaf(dqz, d.z, ph);
+                    _Float16 a, bb;
+                    split_f16(__builtin_amdgcn_cosf(ph), a, bb);
+                    zrh[u] = a;
+                    zrl[u] = bb;
+                    split_f16(__builtin_amdgcn_sinf(ph), a, bb);
+                    zih[u] = a;
+                    zil[u] = bb;
+                }
+                const half8_t grh = s_g[buf][0][ks][run][hz], grl = s_g[buf][1][ks][run][hz];
+                const half8_t gih = s_g[buf][2][ks][run][hz], gil = s_g[buf][3][ks][run][hz];
+                const half8_t nzih = neg8(zih), nzil = neg8(zil);
+                are = __builtin_amdgcn_mfma_f32_32x32x16_f16(zrh, grh, are, 0, 0, 0);
+                aim = __builtin_amdgcn_mfma_f32_32x32x16_f16(zrh, gih, aim, 0, 0, 0);
+                are = __builtin_amdgcn_mfma_f32_32x32x16_f16(zrh, grl, are, 0, 0, 0);
+                aim = __builtin_amdgcn_mfma_f32_32x32x16_f16(zrh, gil, aim, 0, 0, 0);
+                are = __builtin_amdgcn_mfma_f32_32x32x16_f16(zrl, grh, are, 0, 0, 0);
+                aim = __builtin_amdgcn_mfma_f32_32x32x16_f16(zrl, gih, aim, 0, 0, 0);
+                are = __builtin_amdgcn_mfma_f32_32x32x16_f16(nzih, gih, are, 0, 0, 0);
+                aim = __builtin_amdgcn_mfma_f32_32x32x16_f16(zih, grh, aim, 0, 0, 0);
+                are = __builtin_amdgcn_mfma_f32_32x32x16_f16(nzih, gil, are, 0, 0, 0);
+                aim = __builtin_amdgcn_mfma_f32_32x32x16_f16(zih, grl, aim, 0, 0, 0);
+                are = __builtin_amdgcn_mfma_f32_32x32x16_f16(nzil, gih, are, 0, 0, 0);
+                aim = __builtin_amdgcn_mfma_f32_32x32x16_f16(zil, grh, aim, 0, 0, 0);
+            }
+            const float F = static_cast<float>(o.w);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                dre[i] += static_cast<double>(F * are[i]);
+                dim[i] += static_cast<double>(F * aim[i]);
+            }
+            if (tt + 1 < item.nt) stage(buf ^ 1, tt + 1);
+            __syncthreads();
+        }
+        // accumulator entry i: run (i/4)*8 + hz*4 + i%4, pixel k = lane % 32
+        const int k = lane & 31;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = (i >> 2) * 8 + hz * 4 + (i & 3);
+            const int prow = row0 + r, pcol = col0 + k;
+            if (prow < n1 && pcol < sg.n2)
+                partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + static_cast<int64_t>(prow) * sg.n2 + pcol] =
+                    make_double2(dre[i], dim[i]);
+        }
     }
 }
 
@@ -1337,8 +1563,11 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         t.groups += (t.psets[k].n_q + kPixStage - 1) / kPixStage;
     }
     // forward work lists (general and lattice form)
-    const int QL = fsh.q_per_lane, split = std::max(1, fsh.atom_split), ppi = kBlock * QL;
-    const int LQ = std::max(2, QL), lcols = kLatRuns * LQ;
+    // q_per_lane 32 selects the matrix-core lattice form (64 x 64 pixel items); the
+    // general form then runs 8 pixels per lane
+    const bool mfma = fsh.q_per_lane == 32;
+    const int QL = mfma ? 8 : fsh.q_per_lane, split = std::max(1, fsh.atom_split), ppi = kBlock * QL;
+    const int LQ = std::max(2, QL), lcols = mfma ? kMfCols : kLatRuns * LQ, lrows = mfma ? kMfRows : kLatRows;
     t.fsegs.resize(n_segs);
     std::vector<FwdItem> items, litems;
     std::vector<int64_t> cost, lcost;
@@ -1362,7 +1591,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
             g.n2 = ls->n2;
             for (int c = 0; c < 3; ++c) g.a[c] = ls->a[c] * kInvTwoPi;
             g.n_jb = (g.n2 + lcols - 1) / lcols;
-            const int n_ib = (g.n_q / g.n2 + kLatRows - 1) / kLatRows;
+            const int n_ib = (g.n_q / g.n2 + lrows - 1) / lrows;
             for (int r = 0; r < n_ib * g.n_jb; ++r)
                 for (int c = 0; c < g.n_chunks; ++c) {
                     FwdItem it;
@@ -1373,7 +1602,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
                     it.chunk = c;
                     it.pad = 0;
                     litems.push_back(it);
-                    const int64_t rows = std::min(kLatRows, g.n_q / g.n2 - (r / g.n_jb) * kLatRows);
+                    const int64_t rows = std::min(lrows, g.n_q / g.n2 - (r / g.n_jb) * lrows);
                     const int64_t cols = std::min(lcols, g.n2 - (r % g.n_jb) * lcols);
                     lcost.push_back(rows * cols * it.nt);
                     t.lwork += static_cast<double>(rows * cols) * it.nt * kTile;
@@ -1655,10 +1884,19 @@ void launch_lattice(hipStream_t s, int n, int32_t *counter, const Plan::Buffers 
                        b.fsegs, q, b.t_hi, b.t_lo, b.origins, b.fpart);
 }
 
+template <int OCC>
+void launch_lattice_mfma(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q) {
+    const int slots =
+        std::min(n, resident_blocks(reinterpret_cast<const void *>(k_forward_lattice_mfma<OCC>), kBlock));
+    hipLaunchKernelGGL((k_forward_lattice_mfma<OCC>), dim3(slots), dim3(kBlock), 0, s, b.litems, n, counter,
+                       b.fsegs, q, b.t_hi, b.t_lo, b.origins, b.fpart);
+}
+
 bool launch_lattice_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, const Plan::Buffers &b,
                             const double *q) {
     const bool o4 = occ == 4;
     switch (ql) {
+    case 32: launch_lattice_mfma<1>(s, n, cnt, b, q); return true;
     case 1:
     case 2: o4 ? launch_lattice<2, 4>(s, n, cnt, b, q) : launch_lattice<2, 1>(s, n, cnt, b, q); return true;
     case 4: o4 ? launch_lattice<4, 4>(s, n, cnt, b, q) : launch_lattice<4, 1>(s, n, cnt, b, q); return true;
@@ -1706,7 +1944,8 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, 2);
         void *tok = nullptr;
         timer_begin(s, TIMER_FWD32, &tok);
-        if (n > 0 && !launch_forward_variant(s, fshape.q_per_lane, fshape.waves_per_simd, n, b.counters, b, q))
+        const int qlg = fshape.q_per_lane == 32 ? 8 : fshape.q_per_lane;  // general items of the matrix-core shape
+        if (n > 0 && !launch_forward_variant(s, qlg, fshape.waves_per_simd, n, b.counters, b, q))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
         if (nl > 0 &&
             !launch_lattice_variant(s, fshape.q_per_lane, fshape.waves_per_simd, nl, b.counters + 1, b, q))

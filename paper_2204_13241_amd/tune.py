@@ -20,9 +20,10 @@ import torch
 
 from . import api
 
-# (pixels per lane, waves-per-SIMD bound) x atom tiles per item
+# (pixels per lane, waves-per-SIMD bound) x atom tiles per item; 32 pixels per run is
+# the matrix-core lattice form (the general form then runs 8 pixels per lane)
 FWD_CANDIDATES = [(ql, occ, split)
-                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4))
+                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4), (32, 0))
                   for split in (16, 32, 64, 128)]
 # (atoms per lane, waves-per-SIMD bound) x pixels per item
 GRAD_CANDIDATES = [(al, occ, pc)
@@ -45,7 +46,7 @@ def signature(systems, planar: bool) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v4|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
+    return "v5|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved")
 

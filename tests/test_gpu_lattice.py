@@ -57,9 +57,10 @@ def _plan_I(api, r, f, q, L, ql, lattice, split=8):
     return out, info
 
 
-@pytest.mark.parametrize("ql", [2, 4, 8])
+@pytest.mark.parametrize("ql", [2, 4, 8, 32])
 def test_lattice_rows_match_oracle(api, shapes, ql):
-    """40 rows x 75 pixels (neither a multiple of the 32-row x 8-run item), 3000 atoms."""
+    """40 rows x 75 pixels (neither a multiple of the 32-row x 8-run item nor of the
+    64 x 64 matrix-core item), 3000 atoms, f = 1 or 2.5."""
     from _gpu import scaled_err
     r, f, L = _system(3000, 21)
     q = _rows(40, 75, 3.0)
@@ -75,12 +76,13 @@ def test_lattice_rows_match_oracle(api, shapes, ql):
     assert scaled_err(I, I0, f) < TOL
 
 
-def test_lattice_rows_stepping_in_z(api, shapes):
+@pytest.mark.parametrize("ql", [4, 32])
+def test_lattice_rows_stepping_in_z(api, shapes, ql):
     """Rows whose step has a z component (the non-planar lattice branch)."""
     from _gpu import scaled_err
     r, f, L = _system(2000, 22)
     q = _rows(33, 64, 2.5, tilt=0.3, z0=-0.2)
-    I, info = _plan_I(api, r, f, q, L, 4, 1)
+    I, info = _plan_I(api, r, f, q, L, ql, 1)
     assert info["n_lattice_segments"] == 1
     assert scaled_err(I, oracle.intensity(r, f, q)[0], f) < TOL
 
@@ -99,15 +101,17 @@ def test_non_lattice_sets_keep_general_form(api, shapes):
         assert bitwise_equal(I1, I0)
 
 
-def test_lattice_in_uneven_batch(api, shapes):
-    """A lattice system (2 frames) and an Ewald system (1 frame) in one plan."""
+@pytest.mark.parametrize("ql", [8, 32])
+def test_lattice_in_uneven_batch(api, shapes, ql):
+    """A lattice system (2 frames) and an Ewald system (1 frame) in one plan (with the
+    matrix-core shape the Ewald system runs the general form at 8 pixels per lane)."""
     from _gpu import dev, host, scaled_err
     ra, fa, La = _system(2500, 24)
     rb, fb, Lb = _system(900, 25)
     rng = np.random.default_rng(26)
     ra2 = np.stack([ra, ra + 0.2 * rng.standard_normal(ra.shape)])
     qa, qb = _rows(35, 70, 3.0), X.ewald_detector(30, 1.5)
-    api.set_tile_shape(0, 64, 8, 16, 0, 0, 1)
+    api.set_tile_shape(0, 64, ql, 16, 0, 0, 1)
     plan = api.Plan([(2500, 2, dev(qa), La), (900, 1, dev(qb), Lb)])
     info = plan.describe()
     assert info["n_segments"] == 3 and info["n_lattice_segments"] == 2
