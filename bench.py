@@ -61,7 +61,12 @@ def pair_mix(kernel, lattice, ql, qz_zero):
     by 128 pixels); per tile and pixel the FP64 fold (3 ops / 64 atoms); 12 matrix
     instructions of 32x32x16 per 16 atoms and 32x32 pixels = 24 flops per pair.
     adjoint, general: add + 2 FMA phase (3 with dq_z), sin, 2 FMA (3 with W_z).
-    adjoint, lattice: FMA + add phase, sin, 2 FMA (3 with W_z)."""
+    adjoint, lattice: FMA + add phase, sin, 2 FMA (3 with W_z).
+    adjoint, matrix-core lattice (runs of 32): per (run, atom) add + 2 FMA phase (3 with
+    dq_z), sin + cos and 2 FMA per component (2 components at q_z = 0, else 3), shared by
+    the run's 32 pixels; the G factor per (pixel column, atom) as in the forward (shared by
+    128 pixels); 12 matrix instructions of 32x32x16 per component, 16 pixels of a row and
+    32 runs x 32 atoms = 24 flops per pair and component."""
     if kernel == "forward_fp32c":
         ph = 2 if qz_zero else 3
         if lattice and ql == 32:
@@ -70,6 +75,8 @@ def pair_mix(kernel, lattice, ql, qz_zero):
             return (ph + 2 + 4 * (ql - 1)) / ql, 2.0 / ql, 0.0
         return ph + 2, 2.0, 0.0
     acc = 2 if qz_zero else 3
+    if lattice and ql == 32:
+        return (1 + (2 if qz_zero else 3) + 2 * acc) / 32 + 20 / 128, 2 / 32 + 2 / 128, 24.0 * acc
     if lattice:
         return 2 + acc, 1.0, 0.0
     return 1 + (2 if qz_zero else 3) + acc, 1.0, 0.0

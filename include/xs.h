@@ -313,8 +313,13 @@ xs_status xs_shutdown(void);
 /*
  * Tile shape of the FP32C pair kernels (the autotuner's search space):
  *   atoms_per_tile  atoms in one spatial tile (64: one wavefront)
- *   q_per_lane      pixels (forward) or atoms (gradient) per lane (1, 2, 4, 8)
- *   atom_split      atom tiles per forward work item (>= 1)
+ *   q_per_lane      pixels (forward) or atoms (gradient) per lane (1, 2, 4, 8);
+ *                   32 selects the matrix-core lattice form for the lattice
+ *                   systems of a plan (FP16 split factors, 64 x 64 pixel
+ *                   rectangles; other systems run at 8 pixels or 2 atoms per
+ *                   lane)
+ *   atom_split      atom tiles per forward work item (>= 1); with q_per_lane
+ *                   32 also per gradient work item
  *   pixel_split     pixels per gradient work item (multiple of 64)
  *   waves_per_simd  0: compiler's register allocation; 4: variant bounded to
  *                   128 VGPRs (4 wavefronts per SIMD), built for forward

@@ -115,6 +115,10 @@ struct GradSeg {
     int32_t n_chunks;
     int32_t lat;           // 1: every 64-pixel group is a run along a lattice row
     double a[3];           // lattice row step (revolutions / A)
+    int32_t mf;            // 1: matrix-core lattice form (partials per 64 x 64 pixel rectangle)
+    int32_t n2;            // matrix-core form: pixels per row
+    int32_t n_jb;          // matrix-core form: rectangles across a row
+    int32_t pad;
 };
 
 struct GradItem {
@@ -1322,6 +1326,270 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
     }
 }
 
+// ---------------------------------------------------------------- adjoint, lattice form on matrix cores
+//
+// With A_p the amplitude, w_p = dL/dI_p and phi_pj = 2 pi q_p.r_j, the adjoint term of atom j
+// is f_j sum_p (-2 w_p |A_p| q_p) sin(phi_pj + arg A_p) = f_j sum_p Im(V_p e^{i phi_pj}) with
+// V_p = -2 w_p q_p A_p (a complex vector per pixel).  On a 32 x 32 square of a row lattice
+// (pixel (run, k) at q_run + k' a, k' = k - 15.5) the exponential factorizes as in the
+// forward, e^{i phi} = Z(run, j) G(k, j), so per component c
+//   sum_p Im(V_pc e^{i phi_pj}) = sum_run Im( Z(run, j) H_c(run, j) ),
+//   H_c(run, j) = sum_k V_c(run, k) G(k, j),     G(k, j) = e^{2 pi i frac(k' a.r_j)},
+// a 32 x 32 x 64 complex product per tile and component on the matrix cores (V split into
+// FP16 hi + lo after scaling by the wavefront's largest |part| per component, G split
+// likewise; hi*hi + hi*lo + lo*hi), then an FP32 epilogue that forms Z for the
+// accumulator's (run, atom) entries and sums Im(Z H) over the runs.  The four
+// wavefronts' sums per atom are added in FP64 and written once per tile and 64 x 64
+// pixel rectangle; the combine step adds the rectangles and multiplies by f_j.  Components
+// are 2 when every q_z of the rectangle is 0, else 3.
+struct MfGradLds {
+    half8_t g[2][4][2][2][kTile];  // [buf][re_hi, re_lo, im_hi, im_lo][k step][k half][atom]
+    float4 d[2][kTile];            // (d_x, d_y, d_z, 0)
+    float beta[2][kWaves][kTile];  // beta_j for each wavefront's centre
+    float4 tq[2][kWaves][kMfEdge]; // per run: (theta, dq_run) with dq_run = q_run - q_w
+    double4 qc[kWaves][kMfEdge];   // run midpoints (revolutions / A)
+    double4 orig[2];
+    double4 cen[kWaves];
+    float acc[2][kWaves][3][kTile];
+    int32_t noz[kWaves];
+    int32_t item;
+};
+
+template <int NC>
+__device__ __forceinline__ void grad_lattice_item(MfGradLds &L, const FwdItem &item, const GradSeg &sg,
+                                                  int row0, int col0, int nk, bool active, int64_t p0,
+                                                  const double *__restrict__ q, const double *__restrict__ amp,
+                                                  const double *__restrict__ w, const float4 *__restrict__ t_hi,
+                                                  const float4 *__restrict__ t_lo,
+                                                  const double4 *__restrict__ origins, double *__restrict__ gpart) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int hz = lane >> 5, col = lane & 31;
+    // A operands: V_c(run = lane % 32, k = 16 s + 8 hz + u), scaled and split
+    half8_t av[NC][2][4];
+    float scale[NC];
+    {
+        float vr[NC][16], vi[NC][16];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = 16 * s + 8 * hz + u;
+                const bool ok = active && k < nk;
+                const int64_t p = ok ? p0 + k : 0;
+                const double c0 = ok ? -2.0 * w[sg.out + p] : 0.0;
+                const double re = c0 * amp[2 * (sg.out + p)], im = c0 * amp[2 * (sg.out + p) + 1];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const double qv = q[(sg.q + p) * 3 + c];
+                    vr[c][8 * s + u] = static_cast<float>(re * qv);
+                    vi[c][8 * s + u] = static_cast<float>(im * qv);
+                }
+            }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            float m = 0.f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) m = fmaxf(m, fmaxf(fabsf(vr[c][i]), fabsf(vi[c][i])));
+            for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+            scale[c] = m;
+            const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    _Float16 a, bb;
+                    split_f16(vr[c][8 * s + u] * inv, a, bb);
+                    av[c][s][0][u] = a;
+                    av[c][s][1][u] = bb;
+                    split_f16(vi[c][8 * s + u] * inv, a, bb);
+                    av[c][s][2][u] = a;
+                    av[c][s][3][u] = bb;
+                }
+        }
+    }
+    const double ax = sg.a[0], ay = sg.a[1], az = sg.a[2];
+    const int64_t tbase = sg.tile0 + item.t0;
+    // staging of tile tt: atom offsets and beta (threads < 64), run phases theta and
+    // offsets (threads 128..255), the G factors of atom gj, k step gs and k half gh (every thread)
+    const int gj = tid & 63, gh = (tid >> 6) & 1, gs = tid >> 7;
+    auto stage = [&](int buf, int tt) {
+        const int64_t ti = tbase + tt;
+        const double4 o = origins[ti];
+        const float4 h = t_hi[ti * kTile + gj], l = t_lo[ti * kTile + gj];
+        const double dx = double(h.x) + double(l.x), dy = double(h.y) + double(l.y), dz = double(h.z) + double(l.z);
+        if (tid < kTile) {
+            L.d[buf][tid] = make_float4(h.x, h.y, h.z, 0.f);
+#pragma unroll
+            for (int v = 0; v < kWaves; ++v) {
+                const double4 c = L.cen[v];
+                L.beta[buf][v][tid] = frac_f32(__builtin_fma(c.z, dz, __builtin_fma(c.y, dy, c.x * dx)));
+            }
+        } else if (tid >= 2 * kTile) {
+            const int v = (tid - 2 * kTile) >> 5, r = tid & 31;
+            const double4 c = L.qc[v][r], cw = L.cen[v];
+            L.tq[buf][v][r] = make_float4(frac_f32(__builtin_fma(c.z, o.z, __builtin_fma(c.y, o.y, c.x * o.x))),
+                                          static_cast<float>(c.x - cw.x), static_cast<float>(c.y - cw.y),
+                                          static_cast<float>(c.z - cw.z));
+        }
+        if (tid == 0) L.orig[buf] = o;
+        const double ar = __builtin_fma(az, o.z + dz, __builtin_fma(ay, o.y + dy, ax * (o.x + dx)));
+        half8_t grh, grl, gih, gil;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double kc = static_cast<double>(16 * gs + 8 * gh + u) - 0.5 * (kMfEdge - 1);
+            const float ph = frac_f32(kc * ar);
+            _Float16 a, bb;
+            split_f16(__builtin_amdgcn_cosf(ph), a, bb);
+            grh[u] = a;
+            grl[u] = bb;
+            split_f16(__builtin_amdgcn_sinf(ph), a, bb);
+            gih[u] = a;
+            gil[u] = bb;
+        }
+        L.g[buf][0][gs][gh][gj] = grh;
+        L.g[buf][1][gs][gh][gj] = grl;
+        L.g[buf][2][gs][gh][gj] = gih;
+        L.g[buf][3][gs][gh][gj] = gil;
+    };
+    if (item.nt > 0) stage(0, 0);
+    __syncthreads();
+    for (int tt = 0; tt < item.nt; ++tt) {
+        const int buf = tt & 1;
+        float gsum[2][NC];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            float16_t hre[NC], him[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) hre[c][i] = him[c][i] = 0.f;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int j = 32 * nb + col;
+                const half8_t grh = L.g[buf][0][s][hz][j], grl = L.g[buf][1][s][hz][j];
+                const half8_t gih = L.g[buf][2][s][hz][j], gil = L.g[buf][3][s][hz][j];
+                const half8_t ngih = neg8(gih), ngil = neg8(gil);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const half8_t vrh = av[c][s][0], vrl = av[c][s][1], vih = av[c][s][2], vil = av[c][s][3];
+                    hre[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vrh, grh, hre[c], 0, 0, 0);
+                    him[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vrh, gih, him[c], 0, 0, 0);
+                    hre[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vrh, grl, hre[c], 0, 0, 0);
+                    him[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vrh, gil, him[c], 0, 0, 0);
+                    hre[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vrl, grh, hre[c], 0, 0, 0);
+                    him[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vrl, gih, him[c], 0, 0, 0);
+                    hre[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vih, ngih, hre[c], 0, 0, 0);
+                    him[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vih, grh, him[c], 0, 0, 0);
+                    hre[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vih, ngil, hre[c], 0, 0, 0);
+                    him[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vih, grl, him[c], 0, 0, 0);
+                    hre[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vil, ngih, hre[c], 0, 0, 0);
+                    him[c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(vil, grh, him[c], 0, 0, 0);
+                }
+            }
+            // epilogue: atom 32 nb + lane % 32 and the lane's accumulator rows, runs
+            // (i / 4) * 8 + 4 hz + i % 4 (one LDS address per half-wavefront)
+            const int j = 32 * nb + col;
+            const float4 d = L.d[buf][j];
+            const float bj = L.beta[buf][wave][j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) gsum[nb][c] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float4 tq = L.tq[buf][wave][(i >> 2) * 8 + 4 * hz + (i & 3)];
+                float ph = __builtin_fmaf(tq.y, d.x, tq.x + bj);
+                ph = __builtin_fmaf(tq.z, d.y, ph);
+                if (NC == 3) ph = __builtin_fmaf(tq.w, d.z, ph);
+                const float zr = __builtin_amdgcn_cosf(ph), zi = __builtin_amdgcn_sinf(ph);
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    gsum[nb][c] = __builtin_fmaf(zr, him[c][i], __builtin_fmaf(zi, hre[c][i], gsum[nb][c]));
+            }
+        }
+        // lanes l and l ^ 32 hold the two halves of the runs: lane l keeps atom l
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const float send = hz ? gsum[0][c] : gsum[1][c];
+            const float recv = __shfl_xor(send, 32);
+            L.acc[buf][wave][c][lane] = ((hz ? gsum[1][c] : gsum[0][c]) + recv) * scale[c];
+        }
+        if (tt + 1 < item.nt) stage(buf ^ 1, tt + 1);
+        __syncthreads();
+        if (tid < 3 * kTile) {
+            const int j = tid / 3, c = tid - 3 * j;
+            double v = 0.0;
+            if (c < NC)
+#pragma unroll
+                for (int u = 0; u < kWaves; ++u) v += static_cast<double>(L.acc[buf][u][c][j]);
+            const int64_t slot = sg.part + (static_cast<int64_t>(item.chunk) * sg.n_tiles + item.t0 + tt) * kTile + j;
+            gpart[3 * slot + c] = v;
+        }
+    }
+}
+
+template <int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_grad_lattice_mfma(
+    const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
+    const GradSeg *__restrict__ segs, const double *__restrict__ q, const double *__restrict__ amp,
+    const double *__restrict__ w, const float4 *__restrict__ t_hi, const float4 *__restrict__ t_lo,
+    const double4 *__restrict__ origins, double *__restrict__ gpart) {
+    __shared__ MfGradLds L;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int run = lane & 31, hz = lane >> 5;
+    for (;;) {
+        if (tid == 0) L.item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = L.item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const FwdItem item = items[it];
+        const GradSeg sg = segs[item.seg];
+        const int n1 = sg.n_q / sg.n2;
+        const int ib = item.p0 / sg.n_jb, jb = item.p0 - ib * sg.n_jb;
+        const int row0 = ib * kMfRows + (wave >> 1) * kMfEdge;
+        const int col0 = jb * kMfCols + (wave & 1) * kMfEdge;
+        const int row = row0 + run;
+        const bool active = row < n1 && col0 < sg.n2;
+        const int nk = active ? min(kMfEdge, sg.n2 - col0) : 0;
+        const int64_t p0 = active ? static_cast<int64_t>(row) * sg.n2 + col0 : 0;
+        const double e[3] = {sg.a[0], sg.a[1], sg.a[2]};
+        double qc[3], lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+            qc[c] = __builtin_fma(0.5 * (kMfEdge - 1), e[c], q[(sg.q + p0) * 3 + c] * kInvTwoPi);
+            const double v0 = __builtin_fma(-0.5 * (kMfEdge - 1), e[c], qc[c]);
+            const double v1 = __builtin_fma(static_cast<double>(nk > 0 ? nk - 1 : 0), e[c], v0);
+            lo[c] = active ? fmin(v0, v1) : INFINITY;
+            hi[c] = active ? fmax(v0, v1) : -INFINITY;
+        }
+        for (int c = 0; c < 3; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+                hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+            }
+        // every q_z of the lane's 16 pixels zero?
+        bool zero_z = true;
+        for (int s = 0; s < 2; ++s)
+            for (int u = 0; u < 8; ++u) {
+                const int k = 16 * s + 8 * hz + u;
+                if (active && k < nk) zero_z = zero_z && q[(sg.q + p0 + k) * 3 + 2] == 0.0;
+            }
+        zero_z = __all(zero_z);
+        if (lane == 0) {
+            double cw[3];
+            for (int c = 0; c < 3; ++c) cw[c] = lo[c] <= hi[c] ? 0.5 * (lo[c] + hi[c]) : qc[c];
+            L.cen[wave] = make_double4(cw[0], cw[1], cw[2], 0.0);
+            L.noz[wave] = zero_z ? 1 : 0;
+        }
+        if (hz == 0) L.qc[wave][run] = make_double4(qc[0], qc[1], qc[2], 0.0);
+        __syncthreads();
+        const bool noz = L.noz[0] && L.noz[1] && L.noz[2] && L.noz[3];
+        if (noz)
+            grad_lattice_item<2>(L, item, sg, row0, col0, nk, active, p0, q, amp, w, t_hi, t_lo, origins, gpart);
+        else
+            grad_lattice_item<3>(L, item, sg, row0, col0, nk, active, p0, q, amp, w, t_hi, t_lo, origins, gpart);
+        __syncthreads();
+    }
+}
+
 // Sum pixel-chunk partials in chunk order, scale by f_j, scatter to the
 // original atom index.
 __global__ __launch_bounds__(kBlock) void k_grad_combine(const GradSeg *__restrict__ segs,
@@ -1391,6 +1659,8 @@ struct Plan::Tables {
     std::vector<double> gsub_work;
     std::vector<int> gsub_maxq;
     std::vector<int> gsub_lat;            // form of each sub-batch (1: lattice)
+    std::vector<FwdItem> mitems;          // matrix-core gradient: (segment, rectangle, atom tiles)
+    double mwork = 0.0;
     int64_t atoms = 0, cells = 0, tiles = 0, slots = 0, groups = 0, fpart = 0, gpart = 0;
     int max_atoms = 0, max_tiles = 0, max_q = 0, max_set_q = 0, max_slots_seg = 0;
     double fwork = 0.0, lwork = 0.0;
@@ -1405,6 +1675,7 @@ struct Plan::Buffers {
     FwdItem *litems = nullptr;
     GradSeg *gsegs = nullptr;
     GradItem *gitems = nullptr;
+    FwdItem *mitems = nullptr;
     int32_t *counters = nullptr;
     int32_t *hist = nullptr, *start = nullptr, *cursor = nullptr, *scan_sums = nullptr;
     uint32_t *keys = nullptr;
@@ -1626,8 +1897,11 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
     }
     t.fitems = largest_first(items, cost);
     t.litems = largest_first(litems, lcost);
-    // gradient work lists: segments sharing a pixel set go to different sub-batches
-    const int AL = gsh.q_per_lane, group = kWaves * AL;
+    // gradient work lists: segments sharing a pixel set go to different sub-batches;
+    // q_per_lane 32 selects the matrix-core lattice form for lattice segments (their own
+    // queue of 64 x 64 pixel rectangles x atom tiles), the others run 2 atoms per lane
+    const bool gmfma = gsh.q_per_lane == 32;
+    const int AL = gmfma ? 2 : gsh.q_per_lane, group = kWaves * AL;
     const int pchunk = std::max(kPixStage, (gsh.pixel_split / kPixStage) * kPixStage);
     t.gsegs.resize(n_segs);
     for (int i = 0; i < n_segs; ++i) {
@@ -1649,6 +1923,16 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
             for (const LatSet &l : t.lat)
                 if (l.q == g.q && l.n_q == g.n_q)
                     for (int c = 0; c < 3; ++c) g.a[c] = l.a[c] * kInvTwoPi;
+        g.mf = g.n2 = g.n_jb = g.pad = 0;
+        if (gmfma && gsh.lattice && g.n_q > 0 && g.n_tiles > 0)
+            for (const LatSet &l : t.lat)
+                if (l.q == g.q && l.n_q == g.n_q) {
+                    g.mf = 1;
+                    g.n2 = l.n2;
+                    g.n_jb = (l.n2 + kMfCols - 1) / kMfCols;
+                    g.n_chunks = ((g.n_q / l.n2 + kMfRows - 1) / kMfRows) * g.n_jb;  // one partial per rectangle
+                    for (int c = 0; c < 3; ++c) g.a[c] = l.a[c] * kInvTwoPi;
+                }
         t.gpart += static_cast<int64_t>(g.n_chunks) * g.n_tiles * kTile;
     }
     int i0 = 0;
@@ -1666,6 +1950,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         for (int i = i0; i < i1; ++i) {
             const GradSeg &g = t.gsegs[i];
             mq = std::max(mq, g.n_q);
+            if (g.mf) continue;  // matrix-core queue below
             for (int t0 = 0; t0 < g.n_tiles; t0 += group)
                 for (int c = 0; c < g.n_chunks; ++c) {
                     GradItem it;
@@ -1690,6 +1975,32 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         t.gsub_lat.push_back(t.gsegs[i0].lat);
         t.gitems.insert(t.gitems.end(), sub.begin(), sub.end());
         i0 = i1;
+    }
+    if (gmfma) {
+        const int msplit = gsh.atom_split > 0 ? gsh.atom_split : 64;
+        std::vector<FwdItem> mi;
+        std::vector<int64_t> mc;
+        for (int i = 0; i < n_segs; ++i) {
+            const GradSeg &g = t.gsegs[i];
+            if (!g.mf) continue;
+            const int n1 = g.n_q / g.n2;
+            for (int r = 0; r < g.n_chunks; ++r)
+                for (int t0 = 0; t0 < g.n_tiles; t0 += msplit) {
+                    FwdItem it;
+                    it.seg = i;
+                    it.p0 = r;
+                    it.t0 = t0;
+                    it.nt = std::min(msplit, g.n_tiles - t0);
+                    it.chunk = r;
+                    it.pad = 0;
+                    mi.push_back(it);
+                    const int64_t rows = std::min(kMfRows, n1 - (r / g.n_jb) * kMfRows);
+                    const int64_t cols = std::min(kMfCols, g.n2 - (r % g.n_jb) * kMfCols);
+                    mc.push_back(rows * cols * it.nt);
+                    t.mwork += static_cast<double>(rows * cols) * it.nt * kTile;
+                }
+        }
+        t.mitems = largest_first(mi, mc);
     }
     // radix-sort workspace for the pixel order
     if (t.slots > 0) {
@@ -1721,9 +2032,11 @@ size_t Plan::layout(char *base) {
     b.litems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.litems.size()));
     b.gsegs = reinterpret_cast<GradSeg *>(take(sizeof(GradSeg) * t.gsegs.size()));
     b.gitems = reinterpret_cast<GradItem *>(take(sizeof(GradItem) * t.gitems.size()));
+    b.mitems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.mitems.size()));
     b.table_bytes = off - tb0;
-    // counters: [0] general forward, [1] lattice forward, [2 + k] gradient sub-batch k
-    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 2)));
+    // counters: [0] general forward, [1] lattice forward, [2 + k] gradient sub-batch k,
+    // [2 + sub-batches] matrix-core gradient
+    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 3)));
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
@@ -1756,7 +2069,7 @@ void Plan::describe(int *n_lattice_segs, int *n_fwd_items, int *n_grad_items) co
     for (const FwdSeg &g : t.fsegs) nl += g.n2 > 0;
     *n_lattice_segs = nl;
     *n_fwd_items = static_cast<int>(t.fitems.size() + t.litems.size());
-    *n_grad_items = static_cast<int>(t.gitems.size());
+    *n_grad_items = static_cast<int>(t.gitems.size() + t.mitems.size());
 }
 
 // Host blob of all tables in the order and alignment of layout().
@@ -1775,6 +2088,7 @@ std::vector<char> Plan::table_blob() const {
     put(t.litems.data(), sizeof(FwdItem) * t.litems.size());
     put(t.gsegs.data(), sizeof(GradSeg) * t.gsegs.size());
     put(t.gitems.data(), sizeof(GradItem) * t.gitems.size());
+    put(t.mitems.data(), sizeof(FwdItem) * t.mitems.size());
     return blob;
 }
 
@@ -1892,6 +2206,15 @@ void launch_lattice_mfma(hipStream_t s, int n, int32_t *counter, const Plan::Buf
                        b.fsegs, q, b.t_hi, b.t_lo, b.origins, b.fpart);
 }
 
+template <int OCC>
+void launch_grad_lattice_mfma(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q,
+                              const double *amp, const double *w) {
+    const int slots =
+        std::min(n, resident_blocks(reinterpret_cast<const void *>(k_grad_lattice_mfma<OCC>), kBlock));
+    hipLaunchKernelGGL((k_grad_lattice_mfma<OCC>), dim3(slots), dim3(kBlock), 0, s, b.mitems, n, counter,
+                       b.gsegs, q, amp, w, b.t_hi, b.t_lo, b.origins, b.gpart);
+}
+
 bool launch_lattice_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, const Plan::Buffers &b,
                             const double *q) {
     const bool o4 = occ == 4;
@@ -1977,9 +2300,20 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
         const GradItem *items = b.gitems + t.gsub_item0[k];
         void *tok = nullptr;
         timer_begin(s, TIMER_GRAD32, &tok);
-        if (!launch_grad_variant(s, gshape.q_per_lane, gshape.waves_per_simd, t.gsub_lat[k] != 0, items, n, cnt, b))
+        const int al = gshape.q_per_lane == 32 ? 2 : gshape.q_per_lane;  // non-lattice systems of a ql-32 plan
+        if (!launch_grad_variant(s, al, gshape.waves_per_simd, t.gsub_lat[k] != 0, items, n, cnt, b))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
         timer_end(s, TIMER_GRAD32, tok, t.gsub_work[k]);
+        XS_HIP(hipGetLastError());
+    }
+    if (!t.mitems.empty()) {
+        const int n = static_cast<int>(t.mitems.size());
+        int32_t *cnt = b.counters + 2 + t.gsub_seg0.size();
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 1);
+        void *tok = nullptr;
+        timer_begin(s, TIMER_GRAD32, &tok);
+        launch_grad_lattice_mfma<1>(s, n, cnt, b, q, amp, dL_dI);
+        timer_end(s, TIMER_GRAD32, tok, t.mwork);
         XS_HIP(hipGetLastError());
     }
     if (t.max_slots_seg > 0) {

@@ -173,7 +173,7 @@ namespace {
 
 // Defaults: the fastest shapes on a 65,536-atom, 512x512-pixel single frame (forward: the
 // matrix-core lattice form, 64 atom tiles per item; gradient: 2 atoms per lane, 5 waves).
-xs_tile_shape g_shape[2] = {{64, 32, 64, 0, 0, 1}, {64, 2, 0, 8192, 5, 1}};
+xs_tile_shape g_shape[2] = {{64, 32, 64, 0, 0, 1}, {64, 32, 128, 8192, 0, 1}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
@@ -677,8 +677,8 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
     const int ql = shape->q_per_lane;
     if (shape->atoms_per_tile != 64)
         return set_error(XS_ENOTSUP, "atoms_per_tile: only 64 is built (got %d)", shape->atoms_per_tile);
-    if (ql != 1 && ql != 2 && ql != 4 && ql != 8 && !(kind == 0 && ql == 32))
-        return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8, or 32 for the forward (got %d)", ql);
+    if (ql != 1 && ql != 2 && ql != 4 && ql != 8 && ql != 32)
+        return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4, 8 or 32 (got %d)", ql);
     if (ql == 32 && shape->waves_per_simd != 0)
         return set_error(XS_ENOTSUP, "the matrix-core lattice form (q_per_lane 32) is built without a register bound");
     if (kind == 0 && shape->atom_split < 1) return set_error(XS_EINVAL, "atom_split must be >= 1");

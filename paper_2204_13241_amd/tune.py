@@ -25,10 +25,13 @@ from . import api
 FWD_CANDIDATES = [(ql, occ, split)
                   for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4), (32, 0))
                   for split in (16, 32, 64, 128)]
-# (atoms per lane, waves-per-SIMD bound) x pixels per item
-GRAD_CANDIDATES = [(al, occ, pc)
-                   for al, occ in ((1, 0), (2, 0), (2, 5), (4, 0), (4, 4), (8, 0))
-                   for pc in (2048, 4096, 8192, 16384)]
+# (atoms per lane, waves-per-SIMD bound) x pixels per item; 32 is the matrix-core
+# lattice form, whose third entry is the atom tiles per item (the other systems of such
+# a plan run 2 atoms per lane)
+GRAD_CANDIDATES = ([(al, occ, pc)
+                    for al, occ in ((1, 0), (2, 0), (2, 5), (4, 0), (4, 4), (8, 0))
+                    for pc in (2048, 4096, 8192, 16384)]
+                   + [(32, 0, split) for split in (32, 64, 128, 256)])
 
 
 def _cache_path() -> str:
@@ -46,7 +49,7 @@ def signature(systems, planar: bool) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v5|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
+    return "v6|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved")
 
@@ -174,6 +177,9 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
 
     def grad_shape(c):
         al, occ, pc = c
+        if al == 32:
+            return dict(atoms_per_tile=64, q_per_lane=32, atom_split=pc, pixel_split=old_g["pixel_split"],
+                        waves_per_simd=0)
         return dict(atoms_per_tile=64, q_per_lane=al, atom_split=old_g["atom_split"], pixel_split=pc,
                     waves_per_simd=occ)
 
@@ -185,10 +191,12 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
         plan.close()
         return t
 
-    cur_g = (old_g["q_per_lane"], old_g["waves_per_simd"], old_g["pixel_split"])
+    cur_g = (old_g["q_per_lane"], old_g["waves_per_simd"],
+             old_g["atom_split"] if old_g["q_per_lane"] == 32 else old_g["pixel_split"])
     tg = _search(grad_candidates or GRAD_CANDIDATES, cur_g, time_grad)
     pick_g = _pick(tg, cur_g)
-    timings["gradient"] = {"al%d_occ%d_pix%d" % c: t for c, t in tg.items()}
+    timings["gradient"] = {("mfma_split%d" % c[2] if c[0] == 32 else "al%d_occ%d_pix%d" % c): t
+                           for c, t in tg.items()}
     best_g, best_gt = grad_shape(pick_g), tg[pick_g]
     result = {"forward": best_f, "gradient": best_g, "forward_ms": best_ft, "gradient_ms": best_gt}
     if use_cache:

@@ -1,0 +1,130 @@
+"""Lattice forms of the adjoint pair sum against the FP64 oracle: 2 atoms per lane on
+the vector units (rows of a multiple of 64 pixels) and the matrix-core form
+(gradient q_per_lane 32: FP16 split factors on 64 x 64 pixel rectangles, any row
+length).  Cases: a flat grid at q_z = 0 (two components), a flat grid off q_z = 0 and
+rows stepping in z (three components), ragged rectangles and tiles, a batch mixing
+lattice and non-lattice systems, and a plan replayed after re-tiling."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+pytestmark = pytest.mark.gpu
+TOL_G = 1e-5
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2204_13241_amd import api
+    return api
+
+
+@pytest.fixture
+def shapes(api):
+    old = [api.get_tile_shape(k) for k in (0, 1)]
+    yield
+    for k in (0, 1):
+        api.set_tile_shape(k, **old[k])
+
+
+def _rows(n1, n2, qlim, tilt=0.0, z0=0.0):
+    x = np.linspace(-qlim, qlim, n2)
+    y = np.linspace(-0.8 * qlim, 0.9 * qlim, n1)
+    q = np.zeros((n1 * n2, 3))
+    q[:, 0] = np.tile(x, n1)
+    q[:, 1] = np.repeat(y, n2)
+    q[:, 2] = z0 + tilt * q[:, 0]
+    return q
+
+
+def _case(n_atoms, q, seed):
+    rng = np.random.default_rng(seed)
+    L = X.box_for(n_atoms)
+    r = X.uniform_positions(rng, n_atoms, L)
+    f = np.where(rng.random(n_atoms) < 0.2, 2.5, 1.0)
+    _, amp = oracle.intensity(r, f, q)
+    w = rng.standard_normal(q.shape[0])
+    return r, f, L, amp, w
+
+
+def _set(api, gql, split=8):
+    api.set_tile_shape(0, 64, 8, 16, 0, 0, 1)
+    api.set_tile_shape(1, 64, gql, split, 1024, 0, 1)
+
+
+def _plan_grad(api, systems, amps, ws, retile=True):
+    from _gpu import dev, host
+    plan = api.Plan([(r.shape[0], 1, dev(q), L) for r, _, q, L in systems])
+    pos = torch.cat([dev(r).reshape(-1) for r, _, _, _ in systems])
+    f = torch.cat([dev(f) for _, f, _, _ in systems])
+    amp = torch.cat([dev(a).reshape(-1) for a in amps])
+    w = torch.cat([dev(x) for x in ws])
+    info = plan.describe()
+    g64 = torch.empty((pos.numel() // 3, 3), dtype=torch.float64, device=pos.device)
+    plan.grad(pos, f, amp, w, retile=retile, g64=g64)
+    torch.cuda.synchronize()
+    out = host(g64).copy()
+    plan.close()
+    return out, info
+
+
+@pytest.mark.parametrize("gql", [2, 32])
+@pytest.mark.parametrize("n1,n2,tilt,z0", [
+    (64, 128, 0.0, 0.0),    # flat at q_z = 0: every rectangle whole
+    (70, 90, 0.0, 0.0),     # ragged rectangles (matrix-core form only)
+    (40, 128, 0.0, 0.35),   # flat off q_z = 0
+    (48, 64, 0.25, 0.0),    # rows stepping in z
+])
+def test_lattice_grad_matches_oracle(api, shapes, gql, n1, n2, tilt, z0):
+    from _gpu import grad_err
+    print("lattice grad gql=%d rows %d x %d tilt %g z0 %g" % (gql, n1, n2, tilt, z0), flush=True)
+    q = _rows(n1, n2, 2.5, tilt, z0)
+    r, f, L, amp, w = _case(2500, q, 11)
+    _set(api, gql)
+    g, info = _plan_grad(api, [(r, f, q, L)], [amp], [w])
+    g_ref = oracle.intensity_grad(r, f, q, amp, w)
+    e = grad_err(g, g_ref)
+    print("e_grad lattice gql=%d: %.3g (%s)" % (gql, e, info), flush=True)
+    assert info["n_lattice_segments"] == 1
+    assert e < TOL_G
+
+
+def test_matrix_core_grad_in_mixed_batch(api, shapes):
+    """A lattice system (matrix-core form), a detector that is no lattice (vector form)
+    and a lattice system with a single tile of atoms, in one plan."""
+    from _gpu import grad_err
+    qa = _rows(66, 100, 2.0)
+    qb = X.ewald_detector(40, 2.0)
+    qc = _rows(33, 70, 1.5, 0.1)
+    systems, amps, ws, refs = [], [], [], []
+    for k, (n, q) in enumerate(((3000, qa), (1800, qb), (50, qc))):
+        r, f, L, amp, w = _case(n, q, 20 + k)
+        systems.append((r, f, q, L))
+        amps.append(amp)
+        ws.append(w)
+        refs.append(oracle.intensity_grad(r, f, q, amp, w))
+    _set(api, 32, split=5)
+    g, info = _plan_grad(api, systems, amps, ws)
+    print("mixed batch: %s" % info, flush=True)
+    o = 0
+    for ref in refs:
+        e = grad_err(g[o:o + ref.shape[0]], ref)
+        print("e_grad system of %d atoms: %.3g" % (ref.shape[0], e), flush=True)
+        assert e < TOL_G
+        o += ref.shape[0]
+
+
+def test_matrix_core_grad_agrees_with_vector_form(api, shapes):
+    """Same 512-pixel-row grid on both lattice adjoints: the two differ by rounding only."""
+    from _gpu import grad_err
+    q = _rows(32, 512, 3.0)
+    r, f, L, amp, w = _case(4096, q, 31)
+    _set(api, 2)
+    g2, _ = _plan_grad(api, [(r, f, q, L)], [amp], [w])
+    _set(api, 32)
+    g32, _ = _plan_grad(api, [(r, f, q, L)], [amp], [w])
+    e = grad_err(g32, g2)
+    print("matrix-core vs vector adjoint: %.3g" % e, flush=True)
+    assert e < TOL_G

@@ -4,7 +4,7 @@ from paper_2204_13241_amd import tune
 
 def test_candidate_spaces_hold_the_default_shapes():
     assert (32, 0, 64) in tune.FWD_CANDIDATES and (8, 4, 64) in tune.FWD_CANDIDATES
-    assert (2, 5, 8192) in tune.GRAD_CANDIDATES
+    assert (2, 5, 8192) in tune.GRAD_CANDIDATES and (32, 0, 128) in tune.GRAD_CANDIDATES
 
 
 def test_current_shape_is_timed_first_and_the_rest_keep_their_order():
