@@ -343,6 +343,8 @@ def run_grad(args):
             "fma32_lane_ops_per_s": api.roofline_probe(1),
             "fma64_lane_ops_per_s": api.roofline_probe(2),
             "copy_bytes_per_s": api.roofline_probe(3, 1 << 30),
+            "f16_mfma_flops_per_s": api.roofline_probe(4),
+            "f16_mfma_flops_per_s_with_8_fma32_each": api.roofline_probe(5),
         }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

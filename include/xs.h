@@ -461,6 +461,9 @@ xs_status xs_timing_read(int32_t kind, double *total_ms, int64_t *launches, doub
  *   kind 1: FP32 fused multiply-add lane operations per second (not packed)
  *   kind 2: FP64 fused multiply-add lane operations per second
  *   kind 3: HBM bytes per second (read + write) of a plain copy of `bytes`
+ *   kind 4: FP16 matrix flops per second (v_mfma_f32_32x32x16_f16)
+ *   kind 5: the same, each matrix instruction followed by 8 independent FP32
+ *           FMAs of the same wavefront (equal to kind 4 if the two overlap)
  * `rate` is a host double.  Uses the library's scratch memory.
  */
 xs_status xs_roofline_probe(int32_t kind, int64_t bytes, double *rate, void *stream);

@@ -90,6 +90,8 @@ struct LatSet {            // a pixel set that passed the row-lattice test
     int32_t n_q;
     int32_t n2;
     double a[3];           // row step, 1 / Angstrom
+    int32_t flat;          // 1: every q_z of the set is 0
+    int32_t pad;
 };
 
 struct FwdItem {
@@ -115,7 +117,7 @@ struct GradSeg {
     int32_t n_chunks;
     int32_t lat;           // 1: every 64-pixel group is a run along a lattice row
     double a[3];           // lattice row step (revolutions / A)
-    int32_t mf;            // 1: matrix-core lattice form (partials per 64 x 64 pixel rectangle)
+    int32_t mf;            // matrix-core lattice form: components (2 if every q_z is 0, else 3); 0: off
     int32_t n2;            // matrix-core form: pixels per row
     int32_t n_jb;          // matrix-core form: rectangles across a row
     int32_t pad;
@@ -1028,12 +1030,13 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_lattice_mfma(
 }
 
 // Largest deviation of a pixel set from the row lattice q_p = q_{row start} + j a
-// (j = p mod n2), per block; NaN counts as infinite.
+// (j = p mod n2), per block, and the largest |q_z| (after the gridDim.x deviations);
+// NaN counts as infinite.
 __global__ __launch_bounds__(kBlock) void k_lattice_check(const double *__restrict__ q, int32_t n_q, int32_t n2,
                                                           double ax, double ay, double az,
                                                           double *__restrict__ block_max) {
-    __shared__ double red[kBlock];
-    double m = 0.0;
+    __shared__ double red[kBlock], redz[kBlock];
+    double m = 0.0, mz = 0.0;
     const double a[3] = {ax, ay, az};
     for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_q;
          p += static_cast<int64_t>(gridDim.x) * kBlock) {
@@ -1042,14 +1045,23 @@ __global__ __launch_bounds__(kBlock) void k_lattice_check(const double *__restri
             const double d = fabs(q[3 * p + c] - __builtin_fma(static_cast<double>(j), a[c], q[3 * r0 + c]));
             m = d == d ? fmax(m, d) : INFINITY;
         }
+        const double z = fabs(q[3 * p + 2]);
+        mz = z == z ? fmax(mz, z) : INFINITY;
     }
     red[threadIdx.x] = m;
+    redz[threadIdx.x] = mz;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < static_cast<unsigned>(off)) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        if (threadIdx.x < static_cast<unsigned>(off)) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+            redz[threadIdx.x] = fmax(redz[threadIdx.x], redz[threadIdx.x + off]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) block_max[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        block_max[blockIdx.x] = red[0];
+        block_max[gridDim.x + blockIdx.x] = redz[0];
+    }
 }
 
 // Sum the chunk partials of every pixel in chunk order; a = sum f cos,
@@ -1340,8 +1352,9 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
 // likewise; hi*hi + hi*lo + lo*hi), then an FP32 epilogue that forms Z for the
 // accumulator's (run, atom) entries and sums Im(Z H) over the runs.  The four
 // wavefronts' sums per atom are added in FP64 and written once per tile and 64 x 64
-// pixel rectangle; the combine step adds the rectangles and multiplies by f_j.  Components
-// are 2 when every q_z of the rectangle is 0, else 3.
+// pixel rectangle; the combine step adds the rectangles and multiplies by f_j.  NC is the
+// number of components: 2 for pixel sets whose q_z are all 0 (found when a plan is
+// created; the smaller register set then allows two wavefronts per SIMD), else 3.
 struct MfGradLds {
     half8_t g[2][4][2][2][kTile];  // [buf][re_hi, re_lo, im_hi, im_lo][k step][k half][atom]
     float4 d[2][kTile];            // (d_x, d_y, d_z, 0)
@@ -1351,13 +1364,12 @@ struct MfGradLds {
     double4 orig[2];
     double4 cen[kWaves];
     float acc[2][kWaves][3][kTile];
-    int32_t noz[kWaves];
     int32_t item;
 };
 
 template <int NC>
 __device__ __forceinline__ void grad_lattice_item(MfGradLds &L, const FwdItem &item, const GradSeg &sg,
-                                                  int row0, int col0, int nk, bool active, int64_t p0,
+                                                  int nk, bool active, int64_t p0,
                                                   const double *__restrict__ q, const double *__restrict__ amp,
                                                   const double *__restrict__ w, const float4 *__restrict__ t_hi,
                                                   const float4 *__restrict__ t_lo,
@@ -1455,8 +1467,9 @@ __device__ __forceinline__ void grad_lattice_item(MfGradLds &L, const FwdItem &i
     __syncthreads();
     for (int tt = 0; tt < item.nt; ++tt) {
         const int buf = tt & 1;
+        // the two 32-atom halves one after the other (one set of accumulators live)
         float gsum[2][NC];
-#pragma unroll
+#pragma unroll 1
         for (int nb = 0; nb < 2; ++nb) {
             float16_t hre[NC], him[NC];
 #pragma unroll
@@ -1491,8 +1504,9 @@ __device__ __forceinline__ void grad_lattice_item(MfGradLds &L, const FwdItem &i
             const int j = 32 * nb + col;
             const float4 d = L.d[buf][j];
             const float bj = L.beta[buf][wave][j];
+            float g[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) gsum[nb][c] = 0.f;
+            for (int c = 0; c < NC; ++c) g[c] = 0.f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const float4 tq = L.tq[buf][wave][(i >> 2) * 8 + 4 * hz + (i & 3)];
@@ -1501,8 +1515,12 @@ __device__ __forceinline__ void grad_lattice_item(MfGradLds &L, const FwdItem &i
                 if (NC == 3) ph = __builtin_fmaf(tq.w, d.z, ph);
                 const float zr = __builtin_amdgcn_cosf(ph), zi = __builtin_amdgcn_sinf(ph);
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    gsum[nb][c] = __builtin_fmaf(zr, him[c][i], __builtin_fmaf(zi, hre[c][i], gsum[nb][c]));
+                for (int c = 0; c < NC; ++c) g[c] = __builtin_fmaf(zr, him[c][i], __builtin_fmaf(zi, hre[c][i], g[c]));
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (nb == 0) gsum[0][c] = g[c];
+                else gsum[1][c] = g[c];
             }
         }
         // lanes l and l ^ 32 hold the two halves of the runs: lane l keeps atom l
@@ -1526,7 +1544,7 @@ __device__ __forceinline__ void grad_lattice_item(MfGradLds &L, const FwdItem &i
     }
 }
 
-template <int OCC>
+template <int NC, int OCC>
 __global__ __launch_bounds__(kBlock, OCC) void k_grad_lattice_mfma(
     const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
     const GradSeg *__restrict__ segs, const double *__restrict__ q, const double *__restrict__ amp,
@@ -1565,27 +1583,14 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_lattice_mfma(
                 lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
                 hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
             }
-        // every q_z of the lane's 16 pixels zero?
-        bool zero_z = true;
-        for (int s = 0; s < 2; ++s)
-            for (int u = 0; u < 8; ++u) {
-                const int k = 16 * s + 8 * hz + u;
-                if (active && k < nk) zero_z = zero_z && q[(sg.q + p0 + k) * 3 + 2] == 0.0;
-            }
-        zero_z = __all(zero_z);
         if (lane == 0) {
             double cw[3];
             for (int c = 0; c < 3; ++c) cw[c] = lo[c] <= hi[c] ? 0.5 * (lo[c] + hi[c]) : qc[c];
             L.cen[wave] = make_double4(cw[0], cw[1], cw[2], 0.0);
-            L.noz[wave] = zero_z ? 1 : 0;
         }
         if (hz == 0) L.qc[wave][run] = make_double4(qc[0], qc[1], qc[2], 0.0);
         __syncthreads();
-        const bool noz = L.noz[0] && L.noz[1] && L.noz[2] && L.noz[3];
-        if (noz)
-            grad_lattice_item<2>(L, item, sg, row0, col0, nk, active, p0, q, amp, w, t_hi, t_lo, origins, gpart);
-        else
-            grad_lattice_item<3>(L, item, sg, row0, col0, nk, active, p0, q, amp, w, t_hi, t_lo, origins, gpart);
+        grad_lattice_item<NC>(L, item, sg, nk, active, p0, q, amp, w, t_hi, t_lo, origins, gpart);
         __syncthreads();
     }
 }
@@ -1659,7 +1664,8 @@ struct Plan::Tables {
     std::vector<double> gsub_work;
     std::vector<int> gsub_maxq;
     std::vector<int> gsub_lat;            // form of each sub-batch (1: lattice)
-    std::vector<FwdItem> mitems;          // matrix-core gradient: (segment, rectangle, atom tiles)
+    std::vector<FwdItem> mitems;          // matrix-core gradient: (segment, rectangle, atom tiles),
+    int mcount2 = 0;                      // two-component items first
     double mwork = 0.0;
     int64_t atoms = 0, cells = 0, tiles = 0, slots = 0, groups = 0, fpart = 0, gpart = 0;
     int max_atoms = 0, max_tiles = 0, max_q = 0, max_set_q = 0, max_slots_seg = 0;
@@ -1711,7 +1717,7 @@ xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, co
     std::vector<std::pair<int64_t, int32_t>> seen;
     double *dmax = nullptr;
     constexpr int kCheckBlocks = 512;
-    std::vector<double> hmax(kCheckBlocks);
+    std::vector<double> hmax(2 * kCheckBlocks);
     xs_status st = XS_OK;
     for (int i = 0; i < n_segs && st == XS_OK; ++i) {
         const int64_t qo = segs[i].q;
@@ -1744,7 +1750,7 @@ xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, co
         if (n2 < 8 || n_q % n2 != 0) continue;
         for (int c = 0; c < 3; ++c) a[c] = (h[3 * (n2 - 1) + c] - h[c]) / static_cast<double>(n2 - 1);
         if (!dmax) {
-            if (hipMalloc(&dmax, sizeof(double) * kCheckBlocks) != hipSuccess) {
+            if (hipMalloc(&dmax, sizeof(double) * 2 * kCheckBlocks) != hipSuccess) {
                 (void)hipGetLastError();
                 st = set_error(XS_ENOMEM, "lattice test: cannot allocate");
                 break;
@@ -1754,15 +1760,18 @@ xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, co
         hipLaunchKernelGGL(k_lattice_check, dim3(nb), dim3(kBlock), 0, s, q + 3 * qo, n_q, static_cast<int32_t>(n2),
                            a[0], a[1], a[2], dmax);
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(hmax.data(), dmax, sizeof(double) * nb, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hmax.data(), dmax, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             st = set_error(XS_EDEVICE, "lattice test: device check failed");
             break;
         }
-        double worst = 0.0;
+        double worst = 0.0, zmax = 0.0;
         for (int k = 0; k < nb; ++k) worst = std::max(worst, hmax[k]);
+        for (int k = 0; k < nb; ++k) zmax = hmax[nb + k] == hmax[nb + k] ? std::max(zmax, hmax[nb + k]) : INFINITY;
         if (!(worst <= kLatTol)) continue;
         LatSet ls;
+        ls.flat = zmax == 0.0 ? 1 : 0;
+        ls.pad = 0;
         ls.q = qo;
         ls.n_q = n_q;
         ls.n2 = static_cast<int32_t>(n2);
@@ -1927,7 +1936,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         if (gmfma && gsh.lattice && g.n_q > 0 && g.n_tiles > 0)
             for (const LatSet &l : t.lat)
                 if (l.q == g.q && l.n_q == g.n_q) {
-                    g.mf = 1;
+                    g.mf = l.flat ? 2 : 3;
                     g.n2 = l.n2;
                     g.n_jb = (l.n2 + kMfCols - 1) / kMfCols;
                     g.n_chunks = ((g.n_q / l.n2 + kMfRows - 1) / kMfRows) * g.n_jb;  // one partial per rectangle
@@ -1978,11 +1987,12 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
     }
     if (gmfma) {
         const int msplit = gsh.atom_split > 0 ? gsh.atom_split : 64;
-        std::vector<FwdItem> mi;
-        std::vector<int64_t> mc;
+        std::vector<FwdItem> mi[2];
+        std::vector<int64_t> mc[2];
         for (int i = 0; i < n_segs; ++i) {
             const GradSeg &g = t.gsegs[i];
             if (!g.mf) continue;
+            const int cls = g.mf == 2 ? 0 : 1;
             const int n1 = g.n_q / g.n2;
             for (int r = 0; r < g.n_chunks; ++r)
                 for (int t0 = 0; t0 < g.n_tiles; t0 += msplit) {
@@ -1993,14 +2003,17 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
                     it.nt = std::min(msplit, g.n_tiles - t0);
                     it.chunk = r;
                     it.pad = 0;
-                    mi.push_back(it);
+                    mi[cls].push_back(it);
                     const int64_t rows = std::min(kMfRows, n1 - (r / g.n_jb) * kMfRows);
                     const int64_t cols = std::min(kMfCols, g.n2 - (r % g.n_jb) * kMfCols);
-                    mc.push_back(rows * cols * it.nt);
+                    mc[cls].push_back(rows * cols * it.nt);
                     t.mwork += static_cast<double>(rows * cols) * it.nt * kTile;
                 }
         }
-        t.mitems = largest_first(mi, mc);
+        t.mitems = largest_first(mi[0], mc[0]);
+        t.mcount2 = static_cast<int>(t.mitems.size());
+        const std::vector<FwdItem> m3 = largest_first(mi[1], mc[1]);
+        t.mitems.insert(t.mitems.end(), m3.begin(), m3.end());
     }
     // radix-sort workspace for the pixel order
     if (t.slots > 0) {
@@ -2035,8 +2048,8 @@ size_t Plan::layout(char *base) {
     b.mitems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.mitems.size()));
     b.table_bytes = off - tb0;
     // counters: [0] general forward, [1] lattice forward, [2 + k] gradient sub-batch k,
-    // [2 + sub-batches] matrix-core gradient
-    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 3)));
+    // [2 + sub-batches] and [3 + sub-batches] matrix-core gradient (2 and 3 components)
+    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 4)));
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
@@ -2206,12 +2219,12 @@ void launch_lattice_mfma(hipStream_t s, int n, int32_t *counter, const Plan::Buf
                        b.fsegs, q, b.t_hi, b.t_lo, b.origins, b.fpart);
 }
 
-template <int OCC>
-void launch_grad_lattice_mfma(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q,
-                              const double *amp, const double *w) {
+template <int NC, int OCC>
+void launch_grad_lattice_mfma(hipStream_t s, const FwdItem *items, int n, int32_t *counter, const Plan::Buffers &b,
+                              const double *q, const double *amp, const double *w) {
     const int slots =
-        std::min(n, resident_blocks(reinterpret_cast<const void *>(k_grad_lattice_mfma<OCC>), kBlock));
-    hipLaunchKernelGGL((k_grad_lattice_mfma<OCC>), dim3(slots), dim3(kBlock), 0, s, b.mitems, n, counter,
+        std::min(n, resident_blocks(reinterpret_cast<const void *>(k_grad_lattice_mfma<NC, OCC>), kBlock));
+    hipLaunchKernelGGL((k_grad_lattice_mfma<NC, OCC>), dim3(slots), dim3(kBlock), 0, s, items, n, counter,
                        b.gsegs, q, amp, w, b.t_hi, b.t_lo, b.origins, b.gpart);
 }
 
@@ -2307,12 +2320,13 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
         XS_HIP(hipGetLastError());
     }
     if (!t.mitems.empty()) {
-        const int n = static_cast<int>(t.mitems.size());
+        const int n2 = t.mcount2, n3 = static_cast<int>(t.mitems.size()) - t.mcount2;
         int32_t *cnt = b.counters + 2 + t.gsub_seg0.size();
-        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 1);
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 2);
         void *tok = nullptr;
         timer_begin(s, TIMER_GRAD32, &tok);
-        launch_grad_lattice_mfma<1>(s, n, cnt, b, q, amp, dL_dI);
+        if (n2 > 0) launch_grad_lattice_mfma<2, 2>(s, b.mitems, n2, cnt, b, q, amp, dL_dI);
+        if (n3 > 0) launch_grad_lattice_mfma<3, 1>(s, b.mitems + n2, n3, cnt + 1, b, q, amp, dL_dI);
         timer_end(s, TIMER_GRAD32, tok, t.mwork);
         XS_HIP(hipGetLastError());
     }

@@ -132,6 +132,39 @@ __global__ __launch_bounds__(kBlock) void k_probe_fma64(double *sink, int iters)
     if (r == 12345.678) sink[threadIdx.x] = r;
 }
 
+// FP16 matrix instructions (v_mfma_f32_32x32x16_f16) on four independent accumulators;
+// with MIX each is followed by eight independent FP32 FMAs of the same wavefront, which
+// shows whether the vector unit issues while the matrix core works.
+typedef _Float16 probe_half8 __attribute__((ext_vector_type(8)));
+typedef float probe_float16 __attribute__((ext_vector_type(16)));
+template <bool MIX>
+__global__ __launch_bounds__(kBlock) void k_probe_mfma(float *sink, int iters) {
+    probe_half8 a, b;
+    for (int u = 0; u < 8; ++u) {
+        a[u] = static_cast<_Float16>(1e-3f * (u + 1));
+        b[u] = static_cast<_Float16>(1e-3f * (threadIdx.x & 7));
+    }
+    probe_float16 c[4];
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 16; ++i) c[k][i] = 0.f;
+    float x[8];
+    for (int k = 0; k < 8; ++k) x[k] = 0.01f * k + 1e-6f * threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c[k], 0, 0, 0);
+            if (MIX)
+#pragma unroll
+                for (int m = 0; m < 8; ++m) x[m] = __builtin_fmaf(x[m], 0.999f, 1e-3f);
+        }
+    }
+    float r = 0.f;
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 16; ++i) r += c[k][i];
+    for (int k = 0; k < 8; ++k) r += x[k];
+    if (r == 12345.678f) sink[threadIdx.x] = r;
+}
+
 __global__ __launch_bounds__(kBlock) void k_probe_copy(const float4 *__restrict__ a,
                                                        float4 *__restrict__ b, int64_t n) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
@@ -273,6 +306,18 @@ xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate) {
         for (int r = 0; r < 5; ++r) launch();
         XS_HIP(hipEventRecord(e1, s));
         ops = 5.0 * blocks * kBlock * static_cast<double>(iters) * 16.0;
+    } else if (kind == 4 || kind == 5) {
+        XS_TRY(scratch(s, SLOT_BWIN, sizeof(double) * kBlock, &sink));
+        const int mb = cus * 8, mi = 1024;
+        auto launch = [&]() {
+            if (kind == 4) hipLaunchKernelGGL(k_probe_mfma<false>, dim3(mb), dim3(kBlock), 0, s, static_cast<float *>(sink), mi);
+            else hipLaunchKernelGGL(k_probe_mfma<true>, dim3(mb), dim3(kBlock), 0, s, static_cast<float *>(sink), mi);
+        };
+        launch();
+        XS_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r) launch();
+        XS_HIP(hipEventRecord(e1, s));
+        ops = 5.0 * mb * (kBlock / 64) * static_cast<double>(mi) * 4.0 * 2.0 * 32 * 32 * 16;
     } else if (kind == 3) {
         if (bytes < 16) bytes = 16;
         const int64_t nv = bytes / 16;
@@ -289,7 +334,7 @@ xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate) {
     } else {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        return set_error(XS_EINVAL, "probe kind must be 0..3");
+        return set_error(XS_EINVAL, "probe kind must be 0..5");
     }
     XS_HIP(hipGetLastError());
     XS_HIP(hipEventSynchronize(e1));
