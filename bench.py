@@ -45,7 +45,10 @@ PEAK_F16_MFMA = 2.5e15                          # dense FP16 matrix flop/s
 
 def alu_peak(n_valu, n_trans, mfma_flops=0.0):
     """Pairs/s when every CU issues only the kernel's per-pair VALU, transcendental and
-    FP16 matrix work back to back (no overlap between them, as measured)."""
+    FP16 matrix work back to back: transcendental and other VALU instructions do not
+    overlap (probes kinds 0 and 1); matrix and VALU instructions overlap about half of the
+    VALU time (probes kinds 4 and 5), so for the matrix-core kernels the sum is a
+    conservative peak."""
     f16_per_cu_clk = PEAK_F16_MFMA / (CUS * CLOCK)
     return CUS * CLOCK / (n_valu / VALU_LANES + n_trans / TRANS_LANES + mfma_flops / f16_per_cu_clk)
 
