@@ -325,7 +325,8 @@ xs_status xs_shutdown(void);
  *                   128 VGPRs (4 wavefronts per SIMD), built for forward
  *                   q_per_lane 2, 4 and (lattice form only; the general form
  *                   keeps its own allocation) 8, and gradient q_per_lane 4;
- *                   5: bounded to 96 VGPRs, built for gradient q_per_lane 2
+ *                   5: bounded to 96 VGPRs, built for gradient q_per_lane 2;
+ *                   3: bounded to 168 registers, built for forward q_per_lane 32
  *   lattice         plans only (0 or 1): when a system's pixels come in rows
  *                   of n2 consecutive q-vectors that each step by one common
  *                   vector a (a planar detector grid stored row by row; see

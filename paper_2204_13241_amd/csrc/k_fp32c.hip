@@ -2232,7 +2232,7 @@ bool launch_lattice_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt,
                             const double *q) {
     const bool o4 = occ == 4;
     switch (ql) {
-    case 32: launch_lattice_mfma<1>(s, n, cnt, b, q); return true;
+    case 32: occ == 3 ? launch_lattice_mfma<3>(s, n, cnt, b, q) : launch_lattice_mfma<1>(s, n, cnt, b, q); return true;
     case 1:
     case 2: o4 ? launch_lattice<2, 4>(s, n, cnt, b, q) : launch_lattice<2, 1>(s, n, cnt, b, q); return true;
     case 4: o4 ? launch_lattice<4, 4>(s, n, cnt, b, q) : launch_lattice<4, 1>(s, n, cnt, b, q); return true;

@@ -679,13 +679,17 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
         return set_error(XS_ENOTSUP, "atoms_per_tile: only 64 is built (got %d)", shape->atoms_per_tile);
     if (ql != 1 && ql != 2 && ql != 4 && ql != 8 && ql != 32)
         return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4, 8 or 32 (got %d)", ql);
-    if (ql == 32 && shape->waves_per_simd != 0)
-        return set_error(XS_ENOTSUP, "the matrix-core lattice form (q_per_lane 32) is built without a register bound");
+    if (ql == 32 && shape->waves_per_simd != 0 && !(kind == 0 && shape->waves_per_simd == 3))
+        return set_error(XS_ENOTSUP, "the matrix-core lattice form (q_per_lane 32) is built without a register bound, "
+                                     "and for the forward also bounded to 3 waves per SIMD");
     if (kind == 0 && shape->atom_split < 1) return set_error(XS_EINVAL, "atom_split must be >= 1");
     if (kind == 1 && (shape->pixel_split < 64 || shape->pixel_split % 64))
         return set_error(XS_EINVAL, "pixel_split must be a positive multiple of 64");
-    if (shape->waves_per_simd != 0 && shape->waves_per_simd != 4 && shape->waves_per_simd != 5)
-        return set_error(XS_EINVAL, "waves_per_simd must be 0, 4 or 5");
+    if (shape->waves_per_simd != 0 && shape->waves_per_simd != 3 && shape->waves_per_simd != 4 &&
+        shape->waves_per_simd != 5)
+        return set_error(XS_EINVAL, "waves_per_simd must be 0, 3, 4 or 5");
+    if (shape->waves_per_simd == 3 && !(kind == 0 && ql == 32))
+        return set_error(XS_ENOTSUP, "the 3-waves-per-SIMD variant is built for the matrix-core forward (q_per_lane 32)");
     if (shape->waves_per_simd == 4 && !((kind == 0 && (ql == 2 || ql == 4 || ql == 8)) || (kind == 1 && ql == 4)))
         return set_error(XS_ENOTSUP, "the 4-waves-per-SIMD variant is built for forward q_per_lane 2, 4, 8 "
                                      "and gradient q_per_lane 4");

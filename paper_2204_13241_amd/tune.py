@@ -23,7 +23,7 @@ from . import api
 # (pixels per lane, waves-per-SIMD bound) x atom tiles per item; 32 pixels per run is
 # the matrix-core lattice form (the general form then runs 8 pixels per lane)
 FWD_CANDIDATES = [(ql, occ, split)
-                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4), (32, 0))
+                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4), (32, 0), (32, 3))
                   for split in (16, 32, 64, 128)]
 # (atoms per lane, waves-per-SIMD bound) x pixels per item; 32 is the matrix-core
 # lattice form, whose third entry is the atom tiles per item (the other systems of such

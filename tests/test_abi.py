@@ -84,6 +84,16 @@ def test_tile_shape_roundtrip_and_limits():
         api.set_tile_shape(0, 64, 3, 16, 8192)
     with pytest.raises(_lib.XsError):
         api.set_tile_shape(1, 64, 4, 16, 100)
+    # register-bound variants exist only where they are built
+    api.set_tile_shape(0, 64, 32, 32, 0, 3)
+    assert api.get_tile_shape(0)["waves_per_simd"] == 3
+    for kind, ql, occ in ((0, 8, 3), (1, 32, 3), (1, 32, 5), (0, 32, 4)):
+        with pytest.raises(_lib.XsError):
+            api.set_tile_shape(kind, 64, ql, 32, 8192, occ)
+    old_g = api.get_tile_shape(1)
+    api.set_tile_shape(1, 64, 32, 128, 8192, 0)
+    assert api.get_tile_shape(1)["q_per_lane"] == 32
+    api.set_tile_shape(1, **old_g)
     api.set_tile_shape(0, **old)
 
 

@@ -45,9 +45,9 @@ def _system(n_atoms, seed):
     return r, f, L
 
 
-def _plan_I(api, r, f, q, L, ql, lattice, split=8):
+def _plan_I(api, r, f, q, L, ql, lattice, split=8, occ=0):
     from _gpu import dev, host
-    api.set_tile_shape(0, 64, ql, split, 0, 0, lattice)
+    api.set_tile_shape(0, 64, ql, split, 0, occ, lattice)
     plan = api.Plan.single(r.shape[0], 1, dev(q), L)
     info = plan.describe()
     I, _ = plan.intensity(dev(r), dev(f), want_amp=False)
@@ -57,15 +57,16 @@ def _plan_I(api, r, f, q, L, ql, lattice, split=8):
     return out, info
 
 
-@pytest.mark.parametrize("ql", [2, 4, 8, 32])
-def test_lattice_rows_match_oracle(api, shapes, ql):
+@pytest.mark.parametrize("ql,occ", [(2, 0), (4, 0), (8, 0), (32, 0), (32, 3)])
+def test_lattice_rows_match_oracle(api, shapes, ql, occ):
     """40 rows x 75 pixels (neither a multiple of the 32-row x 8-run item nor of the
-    64 x 64 matrix-core item), 3000 atoms, f = 1 or 2.5."""
+    64 x 64 matrix-core item), 3000 atoms, f = 1 or 2.5; the matrix-core form also
+    bounded to 3 waves per SIMD."""
     from _gpu import scaled_err
     r, f, L = _system(3000, 21)
     q = _rows(40, 75, 3.0)
-    print("lattice ql=%d: %d pixels" % (ql, q.shape[0]), flush=True)
-    I, info = _plan_I(api, r, f, q, L, ql, 1)
+    print("lattice ql=%d occ=%d: %d pixels" % (ql, occ, q.shape[0]), flush=True)
+    I, info = _plan_I(api, r, f, q, L, ql, 1, occ=occ)
     assert info["n_lattice_segments"] == 1
     ref = oracle.intensity(r, f, q)[0]
     e = scaled_err(I, ref, f)
