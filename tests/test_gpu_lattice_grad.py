@@ -128,3 +128,37 @@ def test_matrix_core_grad_agrees_with_vector_form(api, shapes):
     e = grad_err(g32, g2)
     print("matrix-core vs vector adjoint: %.3g" % e, flush=True)
     assert e < TOL_G
+
+
+def test_matrix_core_grad_over_frames(api, shapes):
+    """Three frames of one system on a ragged lattice grid: the frames' segments share the
+    pixel set, each with its own partials; every frame against the oracle."""
+    from _gpu import dev, host, grad_err
+    q = _rows(50, 77, 2.2)
+    rng = np.random.default_rng(41)
+    n, n_frames = 1500, 3
+    L = X.box_for(n)
+    f = np.where(rng.random(n) < 0.2, 2.5, 1.0)
+    frames = np.stack(list(X.brownian_frames(X.uniform_positions(rng, n, L), n_frames, 0.3, L,
+                                             np.random.default_rng(42))))
+    amps, ws, refs = [], [], []
+    for r in frames:
+        _, amp = oracle.intensity(r, f, q)
+        w = rng.standard_normal(q.shape[0])
+        amps.append(amp)
+        ws.append(w)
+        refs.append(oracle.intensity_grad(r, f, q, amp, w))
+    _set(api, 32, split=7)
+    plan = api.Plan([(n, n_frames, dev(q), L)])
+    g64 = torch.empty((n_frames * n, 3), dtype=torch.float64, device="cuda:0")
+    plan.grad(dev(frames).reshape(-1), dev(f), dev(np.stack(amps)).reshape(-1), dev(np.stack(ws)).reshape(-1),
+              retile=True, g64=g64)
+    torch.cuda.synchronize()
+    g = host(g64).reshape(n_frames, n, 3)
+    info = plan.describe()
+    plan.close()
+    assert info["n_lattice_segments"] == n_frames
+    for t in range(n_frames):
+        e = grad_err(g[t], refs[t])
+        print("e_grad frame %d: %.3g" % (t, e), flush=True)
+        assert e < TOL_G
