@@ -336,6 +336,10 @@ xs_status xs_shutdown(void);
  *                   per-atom factors f_j exp(2 pi i k a.d_j).  Gradient (rows
  *                   of a multiple of 64 pixels): pixels stay in row order and
  *                   the in-group phase offset of pixel m is (m - 31.5) a.d_j.
+ *                   With q_per_lane 32 (the defaults) both directions run as
+ *                   complex matrix products per atom tile on 64 x 64 pixel
+ *                   rectangles (any row length), the adjoint with two
+ *                   components when every q_z of the set is 0, else three.
  * Shapes apply to calls and plans created after they are set.
  */
 typedef struct xs_tile_shape {
