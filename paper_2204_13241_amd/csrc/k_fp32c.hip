@@ -2303,7 +2303,8 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
     Buffers &b = *B;
     for (size_t k = 0; k < t.gsub_seg0.size(); ++k) {
         const int i0 = t.gsub_seg0[k], i1 = t.gsub_seg1[k];
-        if (t.gsub_maxq[k] > 0)
+        // the prologue feeds the vector-unit queue only (matrix-core segments read amp and w)
+        if (t.gsub_maxq[k] > 0 && t.gsub_nitem[k] > 0)
             hipLaunchKernelGGL(k_grad_prep, dim3((t.gsub_maxq[k] + kBlock - 1) / kBlock, i1 - i0), dim3(kBlock), 0,
                                s, b.gsegs + i0, q, b.pix_order, amp, dL_dI, b.pdq, b.pw, b.pq64, b.centre);
         const int n = t.gsub_nitem[k];
