@@ -23,6 +23,9 @@ Functions (each cites the passage it follows in ``xs_oracle.c``):
 - ``intensity_species_grad``  chain rule through the same, FP64 form
 - ``frame_sums``         incoherent sums of configurations / exposure integrals (Sec. 4.5, Eq. (inte_Iq))
 - ``ring_histogram``     distribution of I / <I>_ring per frame and ring (Sec. 4.5, Eq. (Erlang))
+- ``speckle_loss``       loss of the differentiation workload, sum (I - I_t)^2 / sum I_t^2, and dL/dI
+- ``position_step``      gradient-descent update r <- r - alpha g (one rounding per value)
+- ``fd_loss_grad``       central differences of that loss for selected atoms (rank-one updates)
 """
 from __future__ import annotations
 
@@ -79,6 +82,9 @@ def _load():
         "or_intensity_species_grad": (c_int, [i64, P, P, i32, P, i64, P, P, P, P, c_int]),
         "or_frame_sums": (c_int, [P, i64, i64, i64, i64, i64, i64, d, P, c_int]),
         "or_ring_histogram": (c_int, [P, i64, i64, P, P, i32, i32, d, P, P]),
+        "or_speckle_loss": (c_int, [i64, P, P, P, P]),
+        "or_position_step": (c_int, [i64, P, P, d]),
+        "or_fd_loss_grad": (c_int, [i64, P, P, i64, P, P, i64, P, d, P, c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -330,3 +336,41 @@ def ring_histogram(I, q, edges, n_bins: int, kappa_max: float):
     _check(_load().or_ring_histogram(_ptr(I), I.shape[0], I.shape[1], _ptr(q), _ptr(edges), nr, int(n_bins),
                                      float(kappa_max), _ptr(counts), _ptr(mean)), "ring_histogram")
     return counts, mean
+
+
+def speckle_loss(I, It):
+    """(L, S, dL/dI [n]) of L = sum (I - It)^2 / S, S = sum It^2 (compensated long-double sums)."""
+    I = _f64(I).reshape(-1)
+    It = _f64(It).reshape(-1)
+    if I.shape != It.shape:
+        raise ValueError("I and I_target differ in size")
+    out = np.empty(2)
+    w = np.empty_like(I)
+    _check(_load().or_speckle_loss(I.shape[0], _ptr(I), _ptr(It), _ptr(out), _ptr(w)), "speckle_loss")
+    return float(out[0]), float(out[1]), w
+
+
+def position_step(pos, g, alpha: float):
+    """pos - alpha g with one rounding per value (fma), as a new array."""
+    pos = np.array(_f64(pos), copy=True)
+    g = _f64(g)
+    if g.size != pos.size:
+        raise ValueError("pos and g differ in size")
+    _check(_load().or_position_step(pos.size, _ptr(pos), _ptr(g), float(alpha)), "position_step")
+    return pos
+
+
+def fd_loss_grad(pos, f, q, It, atoms, h: float = 1e-4, threads: int = 0):
+    """Central differences of L = sum (I - It)^2 / sum It^2 for the selected atoms: [n_sel, 3]."""
+    pos = _f64(pos, 3).reshape(-1, 3)
+    f = _f64(f).reshape(-1)
+    q = _f64(q, 3).reshape(-1, 3)
+    It = _f64(It).reshape(-1)
+    if It.shape[0] != q.shape[0]:
+        raise ValueError("I_target does not match the pixel count")
+    atoms = np.ascontiguousarray(atoms, dtype=np.int64).reshape(-1)
+    out = np.empty((atoms.shape[0], 3))
+    _check(_load().or_fd_loss_grad(pos.shape[0], _ptr(pos), _ptr(f), q.shape[0], _ptr(q), _ptr(It),
+                                   atoms.shape[0], _ptr(atoms), float(h), _ptr(out), int(threads)),
+           "fd_loss_grad")
+    return out

@@ -858,3 +858,113 @@ int or_ring_histogram(const double *I, int64_t n_frames, int64_t n_q, const doub
     free(ring); free(buf); free(start); free(list);
     return OR_OK;
 }
+
+/*
+ * Speckle-matching loss of the differentiation workload (fitting positions to a
+ * target speckle pattern I_t through Eqs. (pe_ri), (Iq_pq)):
+ *     L       = sum_p (I_p - It_p)^2 / S,   S = sum_p It_p^2,
+ *     dL/dI_p = 2 (I_p - It_p) / S.
+ * Both sums are long-double compensated sums over p in order (accurate to
+ * about one double rounding), so this is the definition evaluated as exactly
+ * as a double result allows, not a particular summation order.  d = I - It is
+ * one double subtraction, as the definition reads; dL/dI_p is (2 d) / S with
+ * S rounded once to double.  out: (L, S).  dL_dI may be NULL.  S = 0 gives
+ * L = NaN (0/0) or Inf, as the formula does.
+ */
+int or_speckle_loss(int64_t n, const double *I, const double *It, double *out, double *dL_dI)
+{
+    if (n < 0 || !out || (n > 0 && (!I || !It))) return OR_EINVAL;
+    long double a = 0.0L, ac = 0.0L, b = 0.0L, bc = 0.0L;
+    for (int64_t p = 0; p < n; ++p) {
+        long double d = (long double)(I[p] - It[p]);
+        or_nsum(&a, &ac, d * d);
+        or_nsum(&b, &bc, (long double)It[p] * (long double)It[p]);
+    }
+    double S = (double)(b + bc);
+    out[0] = (double)((a + ac) / (b + bc));
+    out[1] = S;
+    if (dL_dI)
+        for (int64_t p = 0; p < n; ++p) dL_dI[p] = (2.0 * (I[p] - It[p])) / S;
+    return OR_OK;
+}
+
+/*
+ * Gradient-descent update of the positions, r <- r - alpha g, each component
+ * rounded once: r = fma(-alpha, g, r).  n values, in place.
+ */
+int or_position_step(int64_t n, double *pos, const double *g, double alpha)
+{
+    if (n < 0 || (n > 0 && (!pos || !g))) return OR_EINVAL;
+    for (int64_t i = 0; i < n; ++i) pos[i] = fma(-alpha, g[i], pos[i]);
+    return OR_OK;
+}
+
+/*
+ * Central finite differences of the speckle-matching loss itself (not of a
+ * linearisation), for selected atoms:
+ *     dL/dr_{j,c} ~ (L(r + h e_{jc}) - L(r - h e_{jc})) / (2h),
+ * L as in or_speckle_loss with the target fixed.  One displaced atom changes
+ * the amplitude by a rank-one term (as in or_fd_grad), and
+ *     L+ - L- = sum_p (I+_p - I-_p)(I+_p + I-_p - 2 It_p) / S,
+ * so the difference is formed term by term in long double (compensated), with
+ * no cancellation of two O(1) losses.  Sines and cosines from the C library.
+ * out: [n_sel][3].
+ */
+int or_fd_loss_grad(int64_t n_atoms, const double *pos, const double *f,
+                    int64_t n_q, const double *q, const double *It,
+                    int64_t n_sel, const int64_t *atoms, double h, double *out,
+                    int n_threads)
+{
+    if (n_atoms <= 0 || n_q < 0 || n_sel < 0 || !(h > 0.0)) return OR_EINVAL;
+    for (int64_t s = 0; s < n_sel; ++s)
+        if (atoms[s] < 0 || atoms[s] >= n_atoms) return OR_EINVAL;
+    long double *ar = malloc(sizeof(long double) * (size_t)(n_q > 0 ? n_q : 1));
+    long double *ai = malloc(sizeof(long double) * (size_t)(n_q > 0 ? n_q : 1));
+    if (!ar || !ai) { free(ar); free(ai); return OR_ENOMEM; }
+    long double S = 0.0L, Sc = 0.0L;
+    for (int64_t p = 0; p < n_q; ++p) or_nsum(&S, &Sc, (long double)It[p] * (long double)It[p]);
+    S += Sc;
+#pragma omp parallel for schedule(static) num_threads(or_threads(n_threads))
+    for (int64_t p = 0; p < n_q; ++p) {
+        long double sr = 0.0L, si = 0.0L;
+        for (int64_t j = 0; j < n_atoms; ++j) {
+            long double ph = (long double)q[3 * p] * pos[3 * j] +
+                             (long double)q[3 * p + 1] * pos[3 * j + 1] +
+                             (long double)q[3 * p + 2] * pos[3 * j + 2];
+            sr += f[j] * cosl(ph);
+            si -= f[j] * sinl(ph);
+        }
+        ar[p] = sr; ai[p] = si;
+    }
+    for (int64_t s = 0; s < n_sel; ++s) {
+        int64_t j = atoms[s];
+        for (int c = 0; c < 3; ++c) {
+            long double sum = 0.0L, comp = 0.0L;
+#pragma omp parallel num_threads(or_threads(n_threads))
+            {
+                long double lsum = 0.0L, lcomp = 0.0L;
+#pragma omp for schedule(static)
+                for (int64_t p = 0; p < n_q; ++p) {
+                    long double ph0 = (long double)q[3 * p] * pos[3 * j] +
+                                      (long double)q[3 * p + 1] * pos[3 * j + 1] +
+                                      (long double)q[3 * p + 2] * pos[3 * j + 2];
+                    long double dph = (long double)q[3 * p + c] * h;
+                    long double br = ar[p] - f[j] * cosl(ph0);
+                    long double bi = ai[p] + f[j] * sinl(ph0);
+                    long double pr = br + f[j] * cosl(ph0 + dph), pi = bi - f[j] * sinl(ph0 + dph);
+                    long double mr = br + f[j] * cosl(ph0 - dph), mi = bi - f[j] * sinl(ph0 - dph);
+                    long double Ip = pr * pr + pi * pi, Im = mr * mr + mi * mi;
+                    or_nsum(&lsum, &lcomp, (Ip - Im) * (Ip + Im - 2.0L * It[p]));
+                }
+#pragma omp critical
+                {
+                    or_nsum(&sum, &comp, lsum);
+                    or_nsum(&sum, &comp, lcomp);
+                }
+            }
+            out[3 * s + c] = (double)((sum + comp) / (S * 2.0L * h));
+        }
+    }
+    free(ar); free(ai);
+    return OR_OK;
+}

@@ -741,3 +741,95 @@ def test_pixel_mean_over_subpixel_wavevectors():
         want = sum(5 + 4 * mp.cos(mp.fdot([mp.mpf(float(c)) for c in qs[s * Q + p]],
                                           [mp.mpf(float(c)) for c in pos[0] - pos[1]])) for s in range(S)) / S
         assert abs(J[0, p] - float(want)) < 1e-13
+
+
+# ---------------------------------------------------------------- loss and update (differentiation workload)
+
+def test_speckle_loss_hand_example():
+    import json
+    import os
+    from fractions import Fraction
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "loss_hand_5.json")))
+    L, S, w = oracle.speckle_loss(d["I"], d["I_target"])
+    assert L == float(Fraction(d["L"]))
+    assert S == float(Fraction(d["S"]))
+    assert np.array_equal(w, np.array([float(Fraction(x)) for x in d["dL_dI"]]))
+    st = d["step"]
+    new = oracle.position_step(st["pos"], st["g"], st["alpha"])
+    assert np.array_equal(new, np.array(st["new_pos"]))
+
+
+def test_speckle_loss_invariants_and_derivative():
+    rng = np.random.default_rng(40)
+    It = rng.exponential(1.0, 257)
+    I = It * (1.0 + 0.3 * rng.standard_normal(257))
+    # at the target the loss and its gradient vanish exactly
+    L0, _, w0 = oracle.speckle_loss(It, It)
+    assert L0 == 0.0 and np.all(w0 == 0.0)
+    # a power-of-two rescaling of both patterns changes nothing (every step scales exactly)
+    L, S, w = oracle.speckle_loss(I, It)
+    L4, S4, w4 = oracle.speckle_loss(4.0 * I, 4.0 * It)
+    assert L4 == L and S4 == 16.0 * S and np.array_equal(w4, w / 4.0)
+    # the loss against mpmath at 200 bits, and dL/dI against mpmath's numerical derivative
+    Im = [mp.mpf(x) for x in I]
+    Itm = [mp.mpf(x) for x in It]
+    Sm = mp.fsum(x * x for x in Itm)
+    Lm = mp.fsum((a - b) ** 2 for a, b in zip(Im, Itm)) / Sm
+    assert abs(L - float(Lm)) <= 2 * np.spacing(L)
+    for p in (0, 17, 256):
+        def Lp(x, p=p):
+            return mp.fsum(((x if k == p else Im[k]) - Itm[k]) ** 2 for k in range(257)) / Sm
+        dm = mp.diff(Lp, Im[p])
+        assert abs(w[p] - float(dm)) <= 4 * np.spacing(abs(w[p])) + 1e-300
+
+
+def test_position_step_rounds_once():
+    from fractions import Fraction
+    rng = np.random.default_rng(41)
+    pos = rng.uniform(-100, 100, 300)
+    g = rng.standard_normal(300) * 10.0 ** rng.integers(-6, 3, 300)
+    alpha = 0.0371
+    new = oracle.position_step(pos, g, alpha)
+    ref = [float(Fraction(p) - Fraction(alpha) * Fraction(x)) for p, x in zip(pos, g)]
+    assert np.array_equal(new, np.array(ref))
+
+
+def test_fd_loss_grad_two_atoms_closed_form():
+    # I_p = f1^2 + f2^2 + 2 f1 f2 cos(q_p.(r1 - r2)), so
+    # dL/dr1 = sum_p 2 (I_p - It_p) / S * (-2 f1 f2 sin(q_p.(r1 - r2)) q_p) = -dL/dr2
+    rng = np.random.default_rng(42)
+    q = rng.uniform(-2, 2, (48, 3))
+    pos = np.array([[0.25, -1.5, 2.0], [3.0, 0.75, -1.25]])
+    f = np.array([1.0, 2.5])
+    It = rng.exponential(7.0, 48)
+    S = mp.fsum(mp.mpf(x) ** 2 for x in It)
+    ref = [mp.mpf(0)] * 3
+    for p in range(48):
+        ph = mp.fsum(mp.mpf(q[p, k]) * (mp.mpf(pos[0, k]) - mp.mpf(pos[1, k])) for k in range(3))
+        Ip = mp.mpf(f[0]) ** 2 + mp.mpf(f[1]) ** 2 + 2 * f[0] * f[1] * mp.cos(ph)
+        c = 2 * (Ip - mp.mpf(It[p])) / S * (-2 * f[0] * f[1] * mp.sin(ph))
+        ref = [ref[k] + c * mp.mpf(q[p, k]) for k in range(3)]
+    ref = np.array([float(x) for x in ref])
+    fd = oracle.fd_loss_grad(pos, f, q, It, [0, 1], h=1e-4)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(fd[0] - ref)) <= 1e-7 * scale
+    assert np.max(np.abs(fd[1] + ref)) <= 1e-7 * scale
+
+
+def test_loss_gradient_chain_rule_against_central_differences():
+    # the analytic chain dL/dr = sum_p (dL/dI_p) dI_p/dr (or_intensity_grad fed with the
+    # loss's dL/dI) against central differences of the loss itself
+    rng = np.random.default_rng(43)
+    L = 25.0
+    pos = rng.uniform(0, L, (300, 3))
+    f = np.where(rng.random(300) < 0.2, 2.5, 1.0)
+    q = X.ewald_detector(20, 1.5)
+    It, _ = oracle.intensity(pos + 0.2 * rng.standard_normal(pos.shape), f, q)
+    I, amp = oracle.intensity(pos, f, q)
+    _, _, w = oracle.speckle_loss(I, It)
+    g = oracle.intensity_grad(pos, f, q, amp, w)
+    atoms = rng.choice(300, 24, replace=False)
+    fd = oracle.fd_loss_grad(pos, f, q, It, atoms, h=1e-4)
+    rms = math.sqrt(np.mean(np.sum(g * g, axis=1)))
+    err = np.max(np.linalg.norm(fd - g[atoms], axis=1)) / rms
+    assert err <= 1e-6, err
