@@ -155,7 +155,20 @@ def rel_grad_err(g, g_ref):
     return float(np.max(np.linalg.norm(g - g_ref, axis=1)) / rms)
 
 
-def run_grad(args):
+# Tile shapes of the matrix-core lattice leg (the autotuner's pick for this workload
+# among the lattice shapes); that leg is reported beside the headline, not as it.
+LATTICE_MFMA_SHAPES = (dict(atoms_per_tile=64, q_per_lane=32, atom_split=32, pixel_split=0,
+                            waves_per_simd=3, lattice=1),
+                       dict(atoms_per_tile=64, q_per_lane=32, atom_split=128, pixel_split=8192,
+                            waves_per_simd=0, lattice=1))
+
+
+def run_grad(args, form="per-pair"):
+    """One training step of the differentiation workload, timed.  form "per-pair": the
+    direct method as the metric counts it (every atom-pixel pair evaluates its own sine and
+    cosine in the forward and its own sine in the adjoint), tile shapes autotuned among the
+    per-pair shapes.  form "lattice-mfma": the planar grid factorized into complex matrix
+    products on FP16 matrix cores (opt-in form, reported separately)."""
     import torch
     from paper_2204_13241_amd import api, inputs
 
@@ -170,10 +183,17 @@ def run_grad(args):
     log("inputs ready: N=%d Q=%d" % (N, Q))
 
     tuned = None
-    if not args.no_tune:
+    old_shapes = [api.get_tile_shape(0), api.get_tile_shape(1)]
+    if form == "lattice-mfma":
+        api.set_tile_shape(0, **LATTICE_MFMA_SHAPES[0])
+        api.set_tile_shape(1, **LATTICE_MFMA_SHAPES[1])
+    elif not args.no_tune:
         from paper_2204_13241_amd import tune
-        tuned = tune.tune([(N, 1, q, L)], pos, f, use_cache=not args.retune)
+        tuned = tune.tune([(N, 1, q, L)], pos, f, use_cache=not args.retune, lattice=0)
         log("tile shapes (%s): fwd %s  grad %s" % (tuned["source"], tuned["forward"], tuned["gradient"]))
+    else:
+        for k in (0, 1):
+            api.set_tile_shape(k, **dict(old_shapes[k], lattice=0))
     shapes = [api.get_tile_shape(0), api.get_tile_shape(1)]
     # one plan for the whole run: work lists, buffers and pixel order built once
     plan = api.Plan.single(N, 1, q, L)
@@ -194,6 +214,15 @@ def run_grad(args):
     _, dLdI = api.speckle_loss(I, It)
     plan.grad(pos, f, amp, dLdI, retile=False, g32=g)
     state["step"] = 0.05 / float(g.abs().max())
+    e_chain_r0 = None
+    if not args.no_fp64:
+        # FP32C chain (forward -> loss -> adjoint) against the FP64 chain at r0, where
+        # I - I_t is not small
+        I64, amp64 = api.intensity(pos, f, q, "fp64", return_amp=True)
+        _, w64 = api.speckle_loss(I64, It)
+        g64 = api.intensity_grad(pos, f, q, amp64, w64, "fp64", out_dtype=torch.float64)
+        e_chain_r0 = rel_grad_err(g.double().cpu().numpy(), g64.cpu().numpy())
+        del I64, amp64, w64, g64
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -242,7 +271,7 @@ def run_grad(args):
                                                                       float(loss[0])))
 
     info = plan.describe()
-    lattice = info["n_lattice_segments"] == info["n_segments"]
+    lattice = info["n_segments"] > 0 and info["n_lattice_segments"] == info["n_segments"]
     qz_zero = bool(np.all(q_np[:, 2] == 0.0))
     src = os.path.join(ROOT, "paper_2204_13241_amd", "csrc", "k_fp32c.hip")
     kern = {}
@@ -253,23 +282,30 @@ def run_grad(args):
         ql = max(2, shapes[kind]["q_per_lane"]) if lattice else shapes[kind]["q_per_lane"]
         n_valu, n_trans, n_mfma = pair_mix(name, lattice, ql, qz_zero)
         peak = alu_peak(n_valu, n_trans, n_mfma) / 1e9
+        # transcendental-issue bound: the unit a per-pair kernel saturates (one v_sin +
+        # one v_cos per forward pair, one v_sin per adjoint pair)
+        trans_peak = PEAK_TRANS / n_trans / 1e9
         kern[name] = {"avg_ms": avg_ms, "launches": rec["launches"], "pairs_per_launch": work,
-                      "form": ("lattice-mfma" if lattice and ql == 32 else "lattice") if lattice else "general",
+                      "form": ("lattice-mfma" if lattice and ql == 32 else "lattice") if lattice else "per-pair",
                       "valu_per_pair": n_valu, "trans_per_pair": n_trans, "f16_mfma_flops_per_pair": n_mfma,
-                      "achieved_Gpair_s": ach, "peak_Gpair_s": peak,
-                      "frac": ach / peak, "frac_of_sincos_pair_peak": ach / (PEAK_SINCOS_PAIRS / 1e9),
+                      "achieved_Gpair_s": ach,
+                      "trans_peak_Gpair_s": trans_peak, "frac_of_trans_peak": ach / trans_peak,
+                      "mix_peak_Gpair_s": peak, "frac_of_mix_peak": ach / peak,
+                      "frac_of_sincos_pair_peak": ach / (PEAK_SINCOS_PAIRS / 1e9),
                       "traffic": traffic_from_profile(src, name, shapes[kind])}
     kern["binning"] = {"avg_ms": binr["ms"] / max(binr["launches"], 1), "launches": binr["launches"]}
     dom = max(("forward_fp32c", "adjoint_fp32c"), key=lambda k: kern[k]["avg_ms"])
-    roofline = {
-        "bound": "alu",
-        "kernel": dom,
-        "achieved": kern[dom]["achieved_Gpair_s"],
-        "peak": kern[dom]["peak_Gpair_s"],
-        "unit": "Gpair/s",
-        "frac": kern[dom]["frac"],
-        "traffic": kern[dom]["traffic"],
-    }
+    if lattice:
+        # the factorized form evaluates no sine per pair: its own instruction-mix bound
+        roofline = {"bound": "alu", "kernel": dom, "achieved": kern[dom]["achieved_Gpair_s"],
+                    "peak": kern[dom]["mix_peak_Gpair_s"], "unit": "Gpair/s",
+                    "frac": kern[dom]["frac_of_mix_peak"], "traffic": kern[dom]["traffic"],
+                    "peak_kind": "instruction mix incl. FP16 matrix flops"}
+    else:
+        roofline = {"bound": "alu", "kernel": dom, "achieved": kern[dom]["achieved_Gpair_s"],
+                    "peak": kern[dom]["trans_peak_Gpair_s"], "unit": "Gpair/s",
+                    "frac": kern[dom]["frac_of_trans_peak"], "traffic": kern[dom]["traffic"],
+                    "peak_kind": "v_sin_f32 + v_cos_f32 issue (256 CUs x 2.4 GHz x 32 lanes / transcendentals per pair)"}
 
     # accuracy against the exact FP64 form at the final positions, and FP64 timing
     extra = {}
@@ -297,9 +333,14 @@ def run_grad(args):
         extra["accuracy_vs_fp64_form"] = {
             "e_I_scaled": e_I,
             "e_I_l2": float(np.linalg.norm(I32h - I64h) / np.linalg.norm(I64h)),
-            "e_grad_chain": rel_grad_err(g32.cpu().numpy(), g64h),
             "e_grad_kernel": rel_grad_err(g32k.cpu().numpy(), g64h),
+            "e_grad_chain_r0": e_chain_r0,
+            "e_grad_chain_final": rel_grad_err(g32.cpu().numpy(), g64h),
             "tolerance": 1e-5,
+            "note": ("e_I and e_grad_kernel are the kernels' errors (the adjoint fed the FP64 amplitude "
+                     "and dL/dI); e_grad_chain is forward -> loss -> adjoint in FP32C against the same chain "
+                     "in FP64, at r0 and after the timed steps, where I - I_t is small and the loss amplifies "
+                     "the forward's relative error"),
         }
         fp64_ms = t64f + t64g
         extra["fp64_form"] = {"fwd_ms": t64f, "grad_ms": t64g,
@@ -312,6 +353,8 @@ def run_grad(args):
         cpu_amp = np.zeros((Q, 2))
         cpu_w = np.zeros(Q)
     plan.close()
+    for k in (0, 1):
+        api.set_tile_shape(k, **old_shapes[k])
 
     result = {
         "metric": METRIC,
@@ -324,23 +367,26 @@ def run_grad(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "fp16-split x2 (matrix), f32 epilogue" if lattice else "f32",
         "data": "synthetic",
         "config": {"workload": "differentiation: N=65536 uniform atoms (rho 0.021/A^3), f=1, 512x512 "
                                "planar q in [-3,3]/A, FP32C forward + loss + FP32C adjoint + GD update",
+                   "form": form,
                    "graph": bool(args.graph),
-                   "n_atoms": N, "n_q": Q, "pairs_per_step": pairs_step, "precision": "fp32c",
-                   "tile_shape_fwd": api.get_tile_shape(0), "tile_shape_grad": api.get_tile_shape(1)},
+                   "n_atoms": N, "n_q": Q, "pairs_per_step": pairs_step,
+                   "precision": ("fp32c: FP32 sine/cosine and tile sums, FP64 phase bases and folds"
+                                 if not lattice else "fp32c lattice: FP16 hi/lo split factors on matrix cores"),
+                   "tile_shape_fwd": shapes[0], "tile_shape_grad": shapes[1]},
         "roofline": roofline,
-        # headline fraction: pair evaluations per second over the sincos-pair roofline
-        # (one v_sin + one v_cos per pair at 32 transcendental lanes/clk/CU)
+        # headline fraction: step pair evaluations per second over the sincos-pair rate
+        # R_pair (one v_sin + one v_cos per pair at 32 transcendental lanes/clk/CU, nominal)
         "valu_roofline_frac": value / (PEAK_SINCOS_PAIRS / 1e9),
         "kernels": kern,
     }
     if tuned is not None:
         result["autotune"] = {k: tuned[k] for k in ("source", "key", "forward_ms", "gradient_ms") if k in tuned}
     result.update(extra)
-    if not args.no_probe:
+    if not args.no_probe and form == "per-pair":
         result["measured_peaks"] = {
             "sincos_lane_ops_per_s": api.roofline_probe(0),
             "fma32_lane_ops_per_s": api.roofline_probe(1),
@@ -349,7 +395,9 @@ def run_grad(args):
             "f16_mfma_flops_per_s": api.roofline_probe(4),
             "f16_mfma_flops_per_s_with_8_fma32_each": api.roofline_probe(5),
         }
-    if not args.no_cpu_baseline:
+        # the same fraction against R_pair from the measured v_sin + v_cos issue rate
+        result["valu_roofline_frac_measured"] = value / (result["measured_peaks"]["sincos_lane_ops_per_s"] / 2 / 1e9)
+    if not args.no_cpu_baseline and form == "per-pair":
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(r0, f_np, q_np, cpu_amp, cpu_w, budget_s=args.cpu_budget)
     return result
@@ -557,15 +605,170 @@ def run_trajectory(args):
     desc = plan.describe()
     plan.close()
     g2, _ = api.g2_rings(I, q, w.edges, w.n_tau)
-    I0 = api.intensity(pos[0], f, q, precision="fp64")
+    # every frame in the exact FP64 form (bit for bit the oracle's), then g2 of both
+    api.timing_enable(True)
+    I64 = api.intensity(pos, f, q, precision="fp64")
+    torch.cuda.synchronize()
+    ms64 = api.timing_read("fwd64")["ms"]
+    api.timing_enable(False)
+    g2_64, _ = api.g2_rings(I64, q, w.edges, w.n_tau)
     inc = float(N)
-    e = float(((I[0] - I0).abs() / torch.clamp(I0, min=inc)).max())
+    e = float(((I - I64).abs() / torch.clamp(I64, min=inc)).max())
+    e_g2 = float(((g2 - g2_64).abs() / g2_64.abs()).max())
     rec = {"workload": "fcc 20^3 + 0.3 A jitter (32,000 atoms), 200 Brownian frames, 256x256 Ewald detector "
                        "(q_max 1.5)", "pairs": F * N * Q, "forward_ms": ms,
-           "forward_Gpair_s": F * N * Q / (ms * 1e-3) / 1e9, "form": "general (Ewald rows are not a lattice)",
-           "plan": desc, "e_I_scaled_frame0_vs_fp64": e, "g2_finite": bool(torch.isfinite(g2).all())}
-    log("trajectory: %.2f ms per 200-frame forward, %.0f Gpair/s, e_I(frame 0) %.2e"
-        % (ms, rec["forward_Gpair_s"], e))
+           "forward_Gpair_s": F * N * Q / (ms * 1e-3) / 1e9,
+           "frac_of_sincos_pair_peak": F * N * Q / (ms * 1e-3) / PEAK_SINCOS_PAIRS,
+           "form": "per-pair (Ewald rows are not a lattice)", "tile_shape_fwd": api.get_tile_shape(0),
+           "plan": desc, "e_I_scaled_all_frames_vs_fp64": e,
+           "e_g2_vs_fp64": e_g2, "g2_rings": int(g2.shape[0]), "g2_n_tau": int(g2.shape[1]),
+           "fp64_forward_ms": ms64, "speedup_vs_fp64_form": ms64 / ms}
+    log("trajectory: %.2f ms per 200-frame forward, %.0f Gpair/s, e_I %.2e, e_g2 %.2e (FP64 form %.1f ms)"
+        % (ms, rec["forward_Gpair_s"], e, e_g2, ms64))
+    del I64
+    return rec
+
+
+def run_batch(args):
+    """Uneven batch (64 systems, N log-uniform in [2000, 64000), uniform positions, f 1.0 /
+    2.5 at 80/20, 512x512 Ewald detectors to q_max 1.5): one plan over the whole batch, tile
+    shapes autotuned among the per-pair shapes, forward and adjoint of every system in one
+    persistent launch each, timed with HIP events; 4 systems checked against the FP64 form."""
+    import torch
+    from paper_2204_13241_amd import api, inputs, tune
+    dev = "cuda:0"
+    w = inputs.workload_batch()
+    systems, pos_l, f_l = [], [], []
+    q = torch.as_tensor(w.q[0], dtype=torch.float64, device=dev)   # one detector for all systems
+    for r, f_, L in zip(w.positions, w.f, w.box):
+        systems.append((r.shape[1], 1, q, L))
+        pos_l.append(r[0])
+        f_l.append(f_)
+    pos = torch.as_tensor(np.concatenate(pos_l), dtype=torch.float64, device=dev)
+    f = torch.as_tensor(np.concatenate(f_l), dtype=torch.float64, device=dev)
+    n_atoms = sum(s[0] for s in systems)
+    Q = int(q.shape[0])
+    pairs = n_atoms * Q
+    old = [api.get_tile_shape(0), api.get_tile_shape(1)]
+    # a reduced candidate set: each candidate plan runs 3.0e11 pairs per launch
+    fc = [(ql, occ, sp) for ql, occ in ((4, 0), (4, 4), (8, 0), (8, 4)) for sp in (32, 64, 128)]
+    gc = [(al, occ, pc) for al, occ in ((2, 0), (2, 5), (4, 0)) for pc in (4096, 8192, 16384)]
+    tuned = tune.tune(systems, pos, f, reps=3, use_cache=not args.retune, fwd_candidates=fc,
+                      grad_candidates=gc, lattice=0)
+    plan = api.Plan(systems)
+    I = torch.empty(plan.total_out, dtype=torch.float64, device=dev)
+    amp = torch.empty((plan.total_out, 2), dtype=torch.float64, device=dev)
+    g = torch.empty((plan.total_pos, 3), dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(77)
+    wq = torch.randn(plan.total_out, dtype=torch.float64, device=dev, generator=gen)
+    plan.intensity(pos, f, I, amp)
+    plan.grad(pos, f, amp, wq, retile=False, g32=g)
+    torch.cuda.synchronize()
+    api.timing_enable(True)
+    reps = 5
+    for _ in range(reps):
+        plan.intensity(pos, f, I, amp)
+        plan.grad(pos, f, amp, wq, retile=False, g32=g)
+    torch.cuda.synchronize()
+    fwd, grd = api.timing_read("fwd32"), api.timing_read("grad32")
+    api.timing_enable(False)
+    ms_f = fwd["ms"] / max(fwd["launches"], 1)
+    ms_g = grd["ms"] / max(grd["launches"], 1)
+    desc = plan.describe()
+    # accuracy on 4 systems (smallest, two middle, largest) against the FP64 form
+    order = np.argsort([s[0] for s in systems])
+    check = [int(order[0]), int(order[len(order) // 3]), int(order[2 * len(order) // 3]), int(order[-1])]
+    off = np.concatenate([[0], np.cumsum([s[0] for s in systems])])
+    e_I, e_g = 0.0, 0.0
+    g32b = plan.grad(pos, f, amp, wq, retile=False)  # FP32C adjoint of the whole batch
+    for k in check:
+        sl = slice(int(off[k]), int(off[k + 1]))
+        I64, amp64 = api.intensity(pos[sl], f[sl], q, "fp64", return_amp=True)
+        wk = wq[k * Q:(k + 1) * Q]
+        g64 = api.intensity_grad(pos[sl], f[sl], q, amp64, wk, "fp64", out_dtype=torch.float64)
+        inc = float((f[sl] ** 2).sum())
+        Ik = I[k * Q:(k + 1) * Q]
+        e_I = max(e_I, float(((Ik - I64).abs() / torch.clamp(I64, min=inc)).max()))
+        e_g = max(e_g, rel_grad_err(g32b[sl].double().cpu().numpy(), g64.cpu().numpy()))
+    plan.close()
+    for k in (0, 1):
+        api.set_tile_shape(k, **old[k])
+    rec = {"workload": "64 systems, N log-uniform in [2000, 64000) (sum %d atoms), uniform positions at "
+                       "0.021/A^3, f 1.0/2.5 at 80/20, 512x512 Ewald detectors (q_max 1.5)" % n_atoms,
+           "pairs_per_pass": pairs, "forward_ms": ms_f, "adjoint_ms": ms_g,
+           "forward_Gpair_s": pairs / (ms_f * 1e-3) / 1e9, "adjoint_Gpair_s": pairs / (ms_g * 1e-3) / 1e9,
+           "fwd_adjoint_Gpair_s": 2 * pairs / ((ms_f + ms_g) * 1e-3) / 1e9,
+           "frac_of_sincos_pair_peak": 2 * pairs / ((ms_f + ms_g) * 1e-3) / PEAK_SINCOS_PAIRS,
+           "form": "per-pair", "tile_shapes": tuned.get("forward"), "tile_shapes_grad": tuned.get("gradient"),
+           "autotune_source": tuned.get("source"), "plan": desc,
+           "e_I_scaled_vs_fp64_4_systems": e_I, "e_grad_vs_fp64_4_systems": e_g,
+           "e_grad_note": "FP32C forward amplitude + FP32C adjoint against the FP64 form of both, fixed random dL/dI",
+           "checked_systems_atoms": [int(systems[k][0]) for k in check]}
+    log("batch: fwd %.2f ms (%.0f Gpair/s), adjoint %.2f ms (%.0f Gpair/s), e_I %.2e, e_g %.2e"
+        % (ms_f, rec["forward_Gpair_s"], ms_g, rec["adjoint_Gpair_s"], e_I, e_g))
+    return rec
+
+
+def run_xsvs_pairs(args):
+    """XSVS workload (fcc 40^3 + 0.3 A jitter, 256,000 atoms, Brownian D dt = 0.005, 1024x1024
+    Ewald detector to q_max 2) on its first `xsvs_frames` frames: the pair sums of every frame
+    through one plan (per-pair form), timed with HIP events, then the XSVS contrast of those
+    FP32C intensities over 64 rings and W = 1 .. frames; the same frames in the exact FP64
+    form give e_I and e_beta."""
+    import itertools
+    import torch
+    from paper_2204_13241_amd import api, inputs
+    dev = "cuda:0"
+    F = args.xsvs_frames
+    w = inputs.workload_xsvs(materialize=False)
+    frames = np.stack(list(itertools.islice(w.positions[0], F)))
+    N, q_np, L = frames.shape[1], w.q[0], w.box[0]
+    Q = q_np.shape[0]
+    pos = torch.as_tensor(frames, dtype=torch.float64, device=dev)
+    del frames
+    f = torch.ones(N, dtype=torch.float64, device=dev)
+    q = torch.as_tensor(q_np, dtype=torch.float64, device=dev)
+    old = api.get_tile_shape(0)
+    # one atom chunk per pixel group (4000 tiles): partial sums stay one per pixel and frame
+    api.set_tile_shape(0, 64, 8, 4096, 0, 0, 0)
+    plan = api.Plan.single(N, F, q, L)
+    I = torch.empty((F, Q), dtype=torch.float64, device=dev)
+    plan.intensity(pos, f, I, want_amp=False)
+    torch.cuda.synchronize()
+    api.timing_enable(True)
+    plan.intensity(pos, f, I, want_amp=False)
+    torch.cuda.synchronize()
+    rec_t = api.timing_read("fwd32")
+    api.timing_enable(False)
+    ms = rec_t["ms"] / max(rec_t["launches"], 1)
+    desc = plan.describe()
+    plan.close()
+    api.set_tile_shape(0, **old)
+    n_levels = int(math.log2(F)) + 1
+    beta32 = api.xsvs_contrast(I, q, w.edges, n_levels)
+    api.timing_enable(True)
+    I64 = api.intensity(pos, f, q, precision="fp64")
+    torch.cuda.synchronize()
+    ms64 = api.timing_read("fwd64")["ms"]
+    api.timing_enable(False)
+    beta64 = api.xsvs_contrast(I64, q, w.edges, n_levels)
+    e_I = float(((I - I64).abs() / torch.clamp(I64, min=float(N))).max())
+    b32, b64 = beta32.cpu().numpy(), beta64.cpu().numpy()
+    ok = np.isfinite(b64)
+    e_b = float(np.max(np.abs(b32[ok] - b64[ok]) / np.abs(b64[ok])))
+    pairs = F * N * Q
+    rec = {"workload": "fcc 40^3 + 0.3 A jitter (256,000 atoms), Brownian D dt 0.005, 1024x1024 Ewald detector "
+                       "(q_max 2), first %d of 1024 frames; XSVS over 64 rings, W = 1..%d" % (F, 2 ** (n_levels - 1)),
+           "frames": F, "pairs": pairs, "forward_ms": ms, "forward_Gpair_s": pairs / (ms * 1e-3) / 1e9,
+           "frac_of_sincos_pair_peak": pairs / (ms * 1e-3) / PEAK_SINCOS_PAIRS,
+           "form": "per-pair", "tile_shape_fwd": {"q_per_lane": 8, "atom_split": 4096}, "plan": desc,
+           "e_I_scaled_vs_fp64": e_I, "e_beta_vs_fp64": e_b, "beta_levels": n_levels,
+           "fp64_forward_ms": ms64, "speedup_vs_fp64_form": ms64 / ms}
+    log("xsvs pairs: %d frames in %.1f ms (%.0f Gpair/s), e_I %.2e, e_beta %.2e (FP64 form %.0f ms)"
+        % (F, ms, rec["forward_Gpair_s"], e_I, e_b, ms64))
+    del I64, I, pos
+    torch.cuda.empty_cache()
     return rec
 
 
@@ -585,6 +788,12 @@ def main():
     ap.add_argument("--no-species", action="store_true", help="skip the form-factor (species) timing")
     ap.add_argument("--no-trajectory", action="store_true", help="skip the 200-frame trajectory timing")
     ap.add_argument("--only-reductions", action="store_true", help="time only g2 / XSVS")
+    ap.add_argument("--no-step", action="store_true",
+                    help="skip the headline step (profiling runs of the other legs only)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-system uneven batch")
+    ap.add_argument("--no-xsvs-pairs", action="store_true", help="skip the XSVS-workload pair sums")
+    ap.add_argument("--no-lattice", action="store_true", help="skip the matrix-core lattice step")
+    ap.add_argument("--xsvs-frames", type=int, default=64)
     ap.add_argument("--red-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the library's plain copy kernel on BYTES (HBM counter calibration)")
@@ -605,7 +814,19 @@ def main():
     if args.only_reductions:
         print(json.dumps({"reductions": run_reductions(args)}), flush=True)
         return
-    res = run_grad(args)
+    res = {} if args.no_step else run_grad(args, "per-pair")
+    if not args.no_lattice:
+        lat = run_grad(argparse.Namespace(**dict(vars(args), no_cpu_baseline=True, no_probe=True)),
+                       "lattice-mfma")
+        res["lattice_mfma_step"] = {k: lat[k] for k in ("value", "unit", "ms_per_step", "dtype", "config",
+                                                         "roofline", "valu_roofline_frac", "kernels",
+                                                         "accuracy_vs_fp64_form") if k in lat}
+        res["lattice_mfma_step"]["note"] = ("planar-grid factorization into complex matrix products on FP16 "
+                                            "matrix cores: not a per-pair evaluation, so not the metric")
+    if not args.no_batch:
+        res["batch"] = run_batch(args)
+    if not args.no_xsvs_pairs:
+        res["xsvs_pairs"] = run_xsvs_pairs(args)
     if not args.no_reductions:
         res["reductions"] = run_reductions(args)
     if not args.no_species:

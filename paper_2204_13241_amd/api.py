@@ -370,10 +370,11 @@ def get_tile_shape(kind: int) -> dict:
 
 def set_tile_shape(kind: int, atoms_per_tile=64, q_per_lane=4, atom_split=64, pixel_split=8192,
                    waves_per_simd=0, lattice=None):
-    """Set the forward (kind 0) or gradient (kind 1) tile shape (xs_set_tile_shape);
-    lattice None means 1 (use the lattice form where a plan finds row lattices)."""
+    """Set the forward (kind 0) or gradient (kind 1) tile shape (xs_set_tile_shape).
+    lattice None means 1 for q_per_lane 32 (the matrix-core lattice form, which needs
+    it) and 0 otherwise (the per-pair form everywhere)."""
     if lattice is None:
-        lattice = 1
+        lattice = 1 if int(q_per_lane) == 32 else 0
     s = _lib.XsTileShape(int(atoms_per_tile), int(q_per_lane), int(atom_split), int(pixel_split),
                          int(waves_per_simd), int(lattice))
     _lib.check(_lib.load().xs_set_tile_shape(int(kind), ctypes.byref(s)))

@@ -173,7 +173,9 @@ namespace {
 
 // Defaults: the fastest shapes on a 65,536-atom, 512x512-pixel single frame (forward: the
 // matrix-core lattice form, 64 atom tiles per item; gradient: 2 atoms per lane, 5 waves).
-xs_tile_shape g_shape[2] = {{64, 32, 64, 0, 0, 1}, {64, 32, 128, 8192, 0, 1}};
+// Defaults: the per-pair form (one sine and cosine per atom-pixel pair in the forward,
+// one sine per pair in the adjoint); the factorized lattice forms are opt-in.
+xs_tile_shape g_shape[2] = {{64, 8, 64, 0, 0, 0}, {64, 2, 128, 8192, 0, 0}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,

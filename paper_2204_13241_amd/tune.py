@@ -45,13 +45,13 @@ def _bucket(n: int) -> int:
     return 0 if n <= 0 else int(round(math.log2(n)))
 
 
-def signature(systems, planar: bool) -> str:
+def signature(systems, planar: bool, lattice: int = 1) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v6|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s" % (
+    return "v7|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
-        "planar" if planar else "curved")
+        "planar" if planar else "curved", "lattice" if lattice else "per-pair")
 
 
 def _load_cache(path):
@@ -124,16 +124,21 @@ def _time_kernel(kind: str, run, reps: int, rounds: int = 2) -> float:
 
 def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: bool = True,
          fwd_candidates: Optional[List] = None, grad_candidates: Optional[List] = None,
-         apply: bool = True) -> dict:
+         apply: bool = True, lattice: int = 1) -> dict:
     """Pick the fastest forward and gradient tile shapes for this batch.
 
     systems: as for api.Plan; pos, f: packed positions and form factors.
+    lattice 0 restricts the search to the per-pair form (no lattice factorization, no
+    matrix-core shapes); 1 also tries the lattice forms where a plan finds row lattices.
     Returns {"forward": shape, "gradient": shape, "source": "cache"|"search",
     "timings_ms": {...}} and, if apply, installs the shapes (xs_set_tile_shape).
     """
+    lattice = 1 if lattice else 0
     qz = torch.cat([q[:, 2] for _, _, q, _ in systems])
     planar = bool((qz == qz[0]).all().item()) if qz.numel() else True
-    key = signature(systems, planar)
+    key = signature(systems, planar, lattice)
+    fwd_candidates = [c for c in (fwd_candidates or FWD_CANDIDATES) if lattice or c[0] != 32]
+    grad_candidates = [c for c in (grad_candidates or GRAD_CANDIDATES) if lattice or c[0] != 32]
     path = _cache_path()
     cache = _load_cache(path) if use_cache else {}
     if use_cache and key in cache:
@@ -148,7 +153,7 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
     def fwd_shape(c):
         ql, occ, split = c
         return dict(atoms_per_tile=64, q_per_lane=ql, atom_split=split, pixel_split=old_f["pixel_split"],
-                    waves_per_simd=occ)
+                    waves_per_simd=occ, lattice=lattice)
 
     def time_fwd(c):
         api.set_tile_shape(0, **fwd_shape(c))
@@ -160,7 +165,7 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
         return t
 
     cur_f = (old_f["q_per_lane"], old_f["waves_per_simd"], old_f["atom_split"])
-    tf = _search(fwd_candidates or FWD_CANDIDATES, cur_f, time_fwd)
+    tf = _search(fwd_candidates, cur_f, time_fwd)
     pick_f = _pick(tf, cur_f)
     timings["forward"] = {"ql%d_occ%d_split%d" % c: t for c, t in tf.items()}
     best_f, best_ft = fwd_shape(pick_f), tf[pick_f]
@@ -179,9 +184,9 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
         al, occ, pc = c
         if al == 32:
             return dict(atoms_per_tile=64, q_per_lane=32, atom_split=pc, pixel_split=old_g["pixel_split"],
-                        waves_per_simd=0)
+                        waves_per_simd=0, lattice=lattice)
         return dict(atoms_per_tile=64, q_per_lane=al, atom_split=old_g["atom_split"], pixel_split=pc,
-                    waves_per_simd=occ)
+                    waves_per_simd=occ, lattice=lattice)
 
     def time_grad(c):
         api.set_tile_shape(1, **grad_shape(c))
@@ -193,7 +198,7 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
 
     cur_g = (old_g["q_per_lane"], old_g["waves_per_simd"],
              old_g["atom_split"] if old_g["q_per_lane"] == 32 else old_g["pixel_split"])
-    tg = _search(grad_candidates or GRAD_CANDIDATES, cur_g, time_grad)
+    tg = _search(grad_candidates, cur_g, time_grad)
     pick_g = _pick(tg, cur_g)
     timings["gradient"] = {("mfma_split%d" % c[2] if c[0] == 32 else "al%d_occ%d_pix%d" % c): t
                            for c, t in tg.items()}

@@ -96,10 +96,13 @@ def test_species_gradient(api, prec, tol):
                                    box=L, return_amp=True)
     g = api.intensity_species_grad(dev(pos), dev(sp, dtype=torch.int32), COEF, dev(q), amp, dev(w),
                                    precision=prec, box=L, out_dtype=torch.float64)
+    errs = []
     for t in range(2):
         _, ampr = oracle.intensity_species(pos[t], sp, COEF, q)
         gr = oracle.intensity_species_grad(pos[t], sp, COEF, q, ampr, w[t])
-        assert grad_err(host(g)[t], gr) < tol
+        errs.append(grad_err(host(g)[t], gr))
+    print("species grad %s: e_grad %s" % (prec, ["%.2e" % e for e in errs]), flush=True)
+    assert max(errs) < tol, errs
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
@@ -150,4 +153,6 @@ def test_species_autograd_function(api, prec, tol):
     I = api.IntensitySpeciesFn.apply(p, dev(sp, dtype=torch.int32), COEF, dev(q), L, prec)
     It_d = dev(It)
     (((I - It_d) ** 2).sum() / Z).backward()
-    assert grad_err(host(p.grad), g_ref) < tol
+    e = grad_err(host(p.grad), g_ref)
+    print("species autograd %s: e_grad %.2e" % (prec, e), flush=True)
+    assert e < tol, e

@@ -58,9 +58,28 @@ def test_species_plan_matches_one_shot_bitwise(api):
             api.set_tile_shape(k, **old[k])
 
 
-def test_species_plan_uneven_batch_against_oracle(api):
-    """Two systems of uneven size and frame count, one planar (lattice form) and one
-    Ewald detector, one species absent from the second system."""
+# matrix-core lattice shapes (opt-in form for planar grids) and the per-pair defaults
+LATTICE_SHAPES = (dict(atoms_per_tile=64, q_per_lane=32, atom_split=64, pixel_split=0, waves_per_simd=0,
+                       lattice=1),
+                  dict(atoms_per_tile=64, q_per_lane=32, atom_split=128, pixel_split=8192, waves_per_simd=0,
+                       lattice=1))
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_species_plan_uneven_batch_against_oracle(api, lattice):
+    """Two systems of uneven size and frame count, one planar (lattice form when asked
+    for) and one Ewald detector, one species absent from the second system."""
+    old = [api.get_tile_shape(0), api.get_tile_shape(1)]
+    try:
+        for k in (0, 1):
+            api.set_tile_shape(k, **(LATTICE_SHAPES[k] if lattice else dict(old[k], lattice=0)))
+        _species_uneven_batch(api, lattice)
+    finally:
+        for k in (0, 1):
+            api.set_tile_shape(k, **old[k])
+
+
+def _species_uneven_batch(api, lattice):
     from _gpu import dev, host, grad_err
     rng = np.random.default_rng(22)
     N, F, Ls = [700, 350], [2, 1], [32.0, 28.0]
@@ -77,15 +96,18 @@ def test_species_plan_uneven_batch_against_oracle(api):
                   g64=torch.empty((plan.total_pos, 3), dtype=torch.float64, device="cuda:0"))
     Ih, gh = host(I), host(g)
     off, poff = plan.batch.out_off, plan.batch.pos_off
+    e_I, e_g = 0.0, 0.0
     for i in range(2):
         for t in range(F[i]):
             Ir, ar = oracle.intensity_species(pos[i][t], sp[i], COEF, qs[i])
             o = off[i] + t * qs[i].shape[0]
-            assert _scaled(Ih[o: o + qs[i].shape[0]], Ir, sp[i], qs[i]) < 1e-5
+            e_I = max(e_I, _scaled(Ih[o: o + qs[i].shape[0]], Ir, sp[i], qs[i]))
             gr = oracle.intensity_species_grad(pos[i][t], sp[i], COEF, qs[i], ar, w[i][t])
             po = poff[i] + t * N[i]
-            assert grad_err(gh[po: po + N[i]], gr) < 2e-5
-    assert plan.describe()["n_lattice_segments"] >= 1
+            e_g = max(e_g, grad_err(gh[po: po + N[i]], gr))
+    print("species plan lattice=%d: e_I %.2e  e_grad %.2e" % (lattice, e_I, e_g), flush=True)
+    assert e_I < 1e-5 and e_g < 2e-5, (e_I, e_g)
+    assert (plan.describe()["n_lattice_segments"] >= 1) == bool(lattice)
     plan.close()
 
 
