@@ -198,6 +198,26 @@ xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const doub
                       double *g2_out, int32_t *ring_count, void *stream);
 
 /*
+ * xs_g2_rings without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments, results and summation order are those of
+ * xs_g2_rings (bit-for-bit equal).  The working buffers (ring keys, ring-order
+ * lists, per-pixel lag rows, tree levels) are carved from one fixed array of
+ * 64 MiB per device that the library holds until the process ends; no
+ * hipMalloc, hipFree or allocating library routine is called, and no timing
+ * event is recorded.  Requires n_q * n_tau * 8 bytes (the lag rows) plus the
+ * smaller buffers to fit in 64 MiB (e.g. 65,536 pixels x 100 lags); larger
+ * requests return XS_EINVAL before anything is enqueued.  Every call on one
+ * device shares that array: calls that overlap on one device (different
+ * streams or host threads without ordering) race and give wrong results; the
+ * array keeps the last call's contents, and each call rewrites every value it
+ * reads.
+ */
+xs_status xs_g2_rings_noalloc(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                              const double *ring_edges, int32_t n_rings, int32_t n_tau,
+                              double *g2_out, int32_t *ring_count, void *stream);
+
+/*
  * XSVS contrast versus exposure time, Sec. 2.3 Eqs. (inte_Iq) and (bq_Iq):
  * exposure windows of W = 2^l frames (l = 0 .. n_levels-1), non-overlapping
  * from frame 0, trailing partial window dropped, window sums built pairwise

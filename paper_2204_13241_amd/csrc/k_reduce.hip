@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "xs_internal.h"
 
@@ -932,6 +933,24 @@ int64_t level_bound(int64_t n_q, int32_t R, int l) {
     return e;
 }
 
+// Where a reduction's working buffers come from: the library's per-stream cached
+// scratch (base == nullptr), or consecutive 256-byte-aligned pieces of one fixed
+// device buffer of cap bytes (the no-allocation entry point).
+struct Arena {
+    hipStream_t s;
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    xs_status get(Slot slot, size_t bytes, void **p) {
+        if (!base) return scratch(s, slot, bytes, p);
+        const size_t need = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        if (need > cap - used)
+            return set_error(XS_EINVAL, "working buffers need more than the %zu-byte fixed scratch", cap);
+        *p = base + used;
+        used += need;
+        return XS_OK;
+    }
+};
+
 struct Partition {
     int32_t *start = nullptr;  // ring starts [R + 1] = tree level 0 offsets
     int32_t *rank = nullptr;
@@ -943,13 +962,13 @@ struct Partition {
 
 // Ring starts, ring-order ranks (-1 for pixels with key -1), the inverse list
 // and the tree offsets.
-xs_status partition(hipStream_t s, const int32_t *key, int64_t n_q, int32_t R, Partition *P) {
+xs_status partition(Arena &A, const int32_t *key, int64_t n_q, int32_t R, Partition *P) {
+    hipStream_t s = A.s;
     const int64_t nb = (n_q + kPartChunk - 1) / kPartChunk;
     const int levels = tree_levels(n_q);
     void *cnt = nullptr, *rk = nullptr;
-    XS_TRY(scratch(s, SLOT_RING_CNT,
-                   sizeof(int32_t) * (nb * R + R + (levels + 1) * (R + 1) + (R + 1)), &cnt));
-    XS_TRY(scratch(s, SLOT_RING_LIST, sizeof(int32_t) * 2 * std::max<int64_t>(n_q, 1), &rk));
+    XS_TRY(A.get(SLOT_RING_CNT, sizeof(int32_t) * (nb * R + R + (levels + 1) * (R + 1) + (R + 1)), &cnt));
+    XS_TRY(A.get(SLOT_RING_LIST, sizeof(int32_t) * 2 * std::max<int64_t>(n_q, 1), &rk));
     int32_t *c = static_cast<int32_t *>(cnt);
     int32_t *tot = c + nb * R;
     P->lev = tot + R;
@@ -988,18 +1007,19 @@ double *reduce_tree(hipStream_t s, const Partition &P, int32_t R, int from, int6
     return in;
 }
 
-}  // namespace
-
-xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,
-                   const RingEdges &edges, int32_t n_tau, double *g2_out, int32_t *ring_count) {
+// g2 with its working buffers from `A`; timed (HIP events) only on the cached-scratch path.
+xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const double *q,
+                      const RingEdges &edges, int32_t n_tau, double *g2_out, int32_t *ring_count) {
+    hipStream_t s = A.s;
     const int32_t R = edges.n_rings;
     void *tok = nullptr;
-    timer_begin(s, TIMER_G2, &tok);
+    const bool timed = A.base == nullptr;
+    if (timed) timer_begin(s, TIMER_G2, &tok);
     void *key = nullptr, *G = nullptr, *G2 = nullptr, *den = nullptr;
-    XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
-    XS_TRY(scratch(s, SLOT_PIXEL2, sizeof(double) * std::max<int64_t>(n_q, 1), &den));
-    XS_TRY(scratch(s, SLOT_G, sizeof(double) * std::max<int64_t>(n_q * n_tau, 1), &G));
-    XS_TRY(scratch(s, SLOT_LEVEL_B, sizeof(double) * level_bound(n_q, R, 1) * n_tau, &G2));
+    XS_TRY(A.get(SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
+    XS_TRY(A.get(SLOT_PIXEL2, sizeof(double) * std::max<int64_t>(n_q, 1), &den));
+    XS_TRY(A.get(SLOT_G, sizeof(double) * std::max<int64_t>(n_q * n_tau, 1), &G));
+    XS_TRY(A.get(SLOT_LEVEL_B, sizeof(double) * level_bound(n_q, R, 1) * n_tau, &G2));
     int32_t *k = static_cast<int32_t *>(key);
     double *dn = static_cast<double *>(den);
     if (n_q > 0) {
@@ -1008,7 +1028,7 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
         XS_HIP(hipGetLastError());
     }
     Partition P;
-    XS_TRY(partition(s, k, n_q, R, &P));
+    XS_TRY(partition(A, k, n_q, R, &P));
     if (n_q > 0) {
         // pixels per block for the LDS path: largest power of two <= 64 with the
         // series in at most 64 KiB
@@ -1032,10 +1052,54 @@ xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const
     hipLaunchKernelGGL(k_ring_mean_finish, dim3(blocks_for(static_cast<int64_t>(R) * n_tau)), dim3(kBlock), 0, s,
                        top, static_cast<int64_t>(n_tau), R, P.start,
                        P.lev + static_cast<int64_t>(P.levels) * (R + 1), g2_out, ring_count);
-    timer_end(s, TIMER_G2, tok, static_cast<double>(F) * n_q * sizeof(double));
+    if (timed) timer_end(s, TIMER_G2, tok, static_cast<double>(F) * n_q * sizeof(double));
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
+
+// Fixed working memory of the no-allocation g2 call: one array per device, mapped
+// when the code object is loaded.  Host code must never pass `g2_fixed_scratch`
+// itself to a kernel (in host code the name is a host-side stand-in); its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kFixedScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char g2_fixed_scratch[kFixedScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+char *g_fixed_ptr[kMaxDevices] = {};
+
+xs_status fixed_scratch(char **out) {
+    int dev = 0;
+    XS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(XS_ENOTSUP, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (!g_fixed_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g2_fixed_scratch));
+        if (e != hipSuccess || !p) return hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_fixed_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_fixed_ptr[dev];
+    return XS_OK;
+}
+
+}  // namespace
+
+xs_status g2_rings(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,
+                   const RingEdges &edges, int32_t n_tau, double *g2_out, int32_t *ring_count) {
+    Arena A{s};
+    return g2_rings_in(A, I, F, n_q, q, edges, n_tau, g2_out, ring_count);
+}
+
+xs_status g2_rings_fixed(hipStream_t s, const double *I, int64_t F, int64_t n_q, const double *q,
+                         const RingEdges &edges, int32_t n_tau, double *g2_out, int32_t *ring_count) {
+    char *base = nullptr;
+    XS_TRY(fixed_scratch(&base));
+    Arena A{s, base, kFixedScratchBytes, 0};
+    return g2_rings_in(A, I, F, n_q, q, edges, n_tau, g2_out, ring_count);
+}
+
+size_t g2_fixed_scratch_bytes() { return kFixedScratchBytes; }
 
 xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, const double *q,
                     const RingEdges &edges, int32_t n_tau, double f2, double *F_out, int32_t *ring_count) {
@@ -1053,7 +1117,8 @@ xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, co
         XS_HIP(hipGetLastError());
     }
     Partition P;
-    XS_TRY(partition(s, k, n_q, R, &P));
+    Arena cached{s};
+    XS_TRY(partition(cached, k, n_q, R, &P));
     const double2 *a2 = reinterpret_cast<const double2 *>(amp);
     if (n_q > 0) {
         // pixels per block for the LDS path: largest power of two <= 64 with the
@@ -1110,7 +1175,8 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
     if (n_q > 0)
         hipLaunchKernelGGL(k_ring_key, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, q, n_q, edges, k);
     Partition P;
-    XS_TRY(partition(s, k, n_q, R, &P));
+    Arena cached{s};
+    XS_TRY(partition(cached, k, n_q, R, &P));
     const int64_t rows = std::max<int64_t>(n_q, 1);  // bounds the pixels in rings
     const int64_t groups_bound = level_bound(n_q, R, 1) / kLvChunksPerBlock + R + 1;
     const double *src = nullptr;
@@ -1192,7 +1258,8 @@ xs_status ring_histogram(hipStream_t s, const double *I, int64_t F, int64_t n_q,
     int32_t *k = static_cast<int32_t *>(key);
     if (n_q > 0) hipLaunchKernelGGL(k_ring_key, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, q, n_q, edges, k);
     Partition P;
-    XS_TRY(partition(s, k, n_q, R, &P));
+    Arena cached{s};
+    XS_TRY(partition(cached, k, n_q, R, &P));
     if (n_q > 0)
         hipLaunchKernelGGL(k_ring_rows, dim3(blocks_for(n_q * F)), dim3(kBlock), 0, s, I, F, n_q,
                            static_cast<const int32_t *>(P.list), static_cast<const int32_t *>(P.start), R,

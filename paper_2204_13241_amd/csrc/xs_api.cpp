@@ -385,6 +385,25 @@ xs_status xs_g2_rings(const double *I, int64_t n_frames, int64_t n_q, const doub
                     ring_count);
 }
 
+xs_status xs_g2_rings_noalloc(const double *I, int64_t n_frames, int64_t n_q, const double *q,
+                              const double *ring_edges, int32_t n_rings, int32_t n_tau, double *g2_out,
+                              int32_t *ring_count, void *stream) {
+    XS_TRY(begin(stream));
+    if (n_frames < 1) return set_error(XS_EINVAL, "n_frames must be >= 1");
+    if (n_q < 0 || n_q >= (int64_t(1) << 31)) return set_error(XS_EINVAL, "n_q out of range");
+    if (n_tau < 1 || n_tau > n_frames) return set_error(XS_EINVAL, "n_tau must be in [1, n_frames]");
+    if (!g2_out) return set_error(XS_EINVAL, "g2_out is NULL");
+    if (n_q > 0 && (!I || !q)) return set_error(XS_EINVAL, "I / q is NULL");
+    // the largest working set (per-pixel lag rows) must fit the fixed array; the call
+    // re-checks the exact total as it carves the buffers
+    if (static_cast<double>(n_q) * n_tau * sizeof(double) > static_cast<double>(g2_fixed_scratch_bytes()))
+        return set_error(XS_EINVAL, "n_q * n_tau * 8 = %.0f bytes exceeds the %zu-byte fixed scratch",
+                         static_cast<double>(n_q) * n_tau * sizeof(double), g2_fixed_scratch_bytes());
+    RingEdges e;
+    XS_TRY(read_edges(ring_edges, n_rings, e));
+    return g2_rings_fixed(static_cast<hipStream_t>(stream), I, n_frames, n_q, q, e, n_tau, g2_out, ring_count);
+}
+
 xs_status xs_xsvs_contrast(const double *I, int64_t n_frames, int64_t n_q, const double *q,
                            const double *ring_edges, int32_t n_rings, int32_t n_levels,
                            double *beta_out, double *beta_win, void *stream) {

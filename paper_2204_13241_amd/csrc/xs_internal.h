@@ -142,6 +142,12 @@ struct RingEdges {
 xs_status g2_rings(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
                    const double *q, const RingEdges &edges, int32_t n_tau, double *g2_out,
                    int32_t *ring_count);
+// g2_rings with every working buffer carved from the library's fixed per-device
+// array (g2_fixed_scratch_bytes() bytes): no allocation; XS_EINVAL if it does not fit.
+xs_status g2_rings_fixed(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
+                         const double *q, const RingEdges &edges, int32_t n_tau, double *g2_out,
+                         int32_t *ring_count);
+size_t g2_fixed_scratch_bytes();
 xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t n_frames, int64_t n_q,
                         const double *q, const RingEdges &edges, int32_t n_levels,
                         double *beta_out, double *beta_win);
