@@ -772,6 +772,83 @@ def run_xsvs_pairs(args):
     return rec
 
 
+def run_fft(args):
+    """FFT-based method (Sec. 3.2, Algorithm 2) beside the direct method, on the shape of
+    the paper's Table 1: 4000 atoms (uniform stand-in for the liquid-argon frames) in a
+    59.19 A box, N_grid = 400, k = 11, eta = 0.1485 A; the direct method on the same grid's
+    81 x 81 slice (l = 0) and 81^3 block of wavevectors (per-pair FP32C plan and FP64 form).
+    Accuracy of the FFT method against the exact FP64 form on the 81^3 block, and its
+    convergence with N_grid at the wavevector (0, 14, -11) 2 pi / L (Sec. 4.2)."""
+    import torch
+    from paper_2204_13241_amd import api
+    dev = "cuda:0"
+    L, N, eta = 59.19, 4000, 0.1485
+    rng = np.random.default_rng(2204)
+    pos_np = rng.random((N, 3)) * L
+    pos = torch.as_tensor(pos_np, dtype=torch.float64, device=dev)
+    f = torch.ones(N, dtype=torch.float64, device=dev)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    n = 400
+    k = int(math.floor(10.0 * eta * n / L)) + 1
+    ms_fft = timed(lambda: api.fft_intensity(pos, f, L, n, eta, k))
+    I_fft = api.fft_intensity(pos, f, L, n, eta, k)
+    h = np.arange(-40, 41)
+    hx, hy = np.meshgrid(h, h, indexing="ij")
+    q_slice = np.stack([hx.ravel(), hy.ravel(), np.zeros(hx.size)], axis=-1) * (2 * math.pi / L)
+    hx3, hy3, hz3 = np.meshgrid(h, h, h, indexing="ij")
+    hkl3 = np.stack([hx3.ravel(), hy3.ravel(), hz3.ravel()], axis=-1)
+    q_block = hkl3 * (2 * math.pi / L)
+    out = {"workload": "4000 uniform atoms in a 59.19 A box (Table 1 shape), eta 0.1485 A, k %d" % k,
+           "fft_n_grid": n, "fft_ms_per_frame": ms_fft}
+    for name, qn in (("slice_81x81", q_slice), ("block_81x81x81", q_block)):
+        qt = torch.as_tensor(qn, dtype=torch.float64, device=dev)
+        plan = api.Plan.single(N, 1, qt, L)
+        ms32 = timed(lambda: plan.intensity(pos, f, want_amp=False))
+        plan.close()
+        api.timing_enable(True)
+        api.intensity(pos, f, qt, "fp64")
+        torch.cuda.synchronize()
+        ms64 = api.timing_read("fwd64")["ms"]
+        api.timing_enable(False)
+        out[name] = {"pixels": int(qn.shape[0]), "direct_fp32c_ms": ms32, "direct_fp64_ms": ms64,
+                     "direct_fp32c_Gpair_s": N * qn.shape[0] / (ms32 * 1e-3) / 1e9}
+    # accuracy of the FFT method on the 81^3 block against the exact FP64 form
+    qt = torch.as_tensor(q_block, dtype=torch.float64, device=dev)
+    I64 = api.intensity(pos, f, qt, "fp64").cpu().numpy()
+    idx = np.mod(hkl3, n)
+    If = I_fft.cpu().numpy()[idx[:, 0], idx[:, 1], idx[:, 2]]
+    out["fft_vs_direct_81cube_max_scaled_err"] = float(np.max(np.abs(If - I64) / np.maximum(I64, N)))
+    # convergence with the grid at (0, 14, -11) 2 pi / L (eta fixed, k from 10 eta / delta)
+    hq = np.array([[0, 14, -11]])
+    I_ref = float(api.intensity(pos, f, torch.as_tensor(hq * (2 * math.pi / L), dtype=torch.float64,
+                                                         device=dev), "fp64").cpu()[0])
+    conv = []
+    for ng in (100, 150, 200, 250, 300, 400):
+        kk = int(math.floor(10.0 * eta * ng / L)) + 1
+        In = api.fft_intensity(pos, f, L, ng, eta, kk)
+        v = float(In[0, 14 % ng, (-11) % ng].cpu())
+        conv.append({"n_grid": ng, "k": kk, "rel_err": abs(v - I_ref) / I_ref})
+        del In
+    out["convergence_at_0_14_m11"] = conv
+    out["table1_paper_cpu_s_per_frame"] = {"direct_81x81": 4.1836, "direct_81cube": 416.8243, "fft_400": 0.4527,
+                                           "hardware": "32 CPUs (paper, Table 1)"}
+    torch.cuda.empty_cache()
+    log("fft: %.2f ms per frame at N_grid 400; direct 81x81 %.3f ms, 81^3 %.2f ms (FP32C); err %.1e; conv %s"
+        % (ms_fft, out["slice_81x81"]["direct_fp32c_ms"], out["block_81x81x81"]["direct_fp32c_ms"],
+           out["fft_vs_direct_81cube_max_scaled_err"], ["%d:%.1e" % (c["n_grid"], c["rel_err"]) for c in conv]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -794,6 +871,7 @@ def main():
     ap.add_argument("--no-xsvs-pairs", action="store_true", help="skip the XSVS-workload pair sums")
     ap.add_argument("--no-lattice", action="store_true", help="skip the matrix-core lattice step")
     ap.add_argument("--xsvs-frames", type=int, default=64)
+    ap.add_argument("--no-fft", action="store_true", help="skip the FFT-method comparison")
     ap.add_argument("--red-reps", type=int, default=3)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run the library's plain copy kernel on BYTES (HBM counter calibration)")
@@ -827,6 +905,8 @@ def main():
         res["batch"] = run_batch(args)
     if not args.no_xsvs_pairs:
         res["xsvs_pairs"] = run_xsvs_pairs(args)
+    if not args.no_fft:
+        res["fft_method"] = run_fft(args)
     if not args.no_reductions:
         res["reductions"] = run_reductions(args)
     if not args.no_species:

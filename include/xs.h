@@ -78,9 +78,10 @@ enum {
  *
  * box[s*3 + c] is the orthorhombic box edge of system s (Sec. 3.1: the
  * simulation cell; Algorithm 1 takes q on its reciprocal lattice, but any q
- * is accepted).  The FP32C form uses it to size its spatial bins; atoms
- * outside [0, box) are clamped into the edge bins, which changes nothing but
- * tile compactness.  The FP64 form ignores it.
+ * is accepted).  It must be positive and finite for the FP32C form, which
+ * bins each frame's atoms on a grid over the bounding box of that frame's
+ * positions (so atoms outside [0, box), as in unwrapped trajectories, still form
+ * compact tiles).  The FP64 form ignores it.
  *
  * Limits: 1 <= n_sys; 0 <= n_atoms[s] < 2^31; 0 <= n_q[s] < 2^31;
  * 1 <= n_frames[s]; offsets >= 0.
@@ -320,6 +321,29 @@ xs_status xs_ring_histogram(const double *I, int64_t n_frames, int64_t n_q, cons
                             const double *ring_edges, int32_t n_rings, int32_t n_bins, double kappa_max,
                             int64_t *counts_out, double *mean_out, void *stream);
 
+/*
+ * FFT-based method of Sec. 3.2 (Algorithm 2, Eqs. (modified_r), (pq_rq_app_alt),
+ * (Iq_pq_new)): the comparison baseline of the direct method, one frame, FP64.
+ * Every atom's Gaussian of width eta (weight f_j) is added to the k grid points
+ * nearest to it along each axis of an n_grid^3 grid over the periodic box
+ * [0, box)^3 (indices modulo n_grid); the grid is Fourier transformed (hipFFT);
+ * f^eta is the same transform of one Gaussian centred at the origin, and
+ *     I(q_h) = |p^eta(q_h)|^2 / f^eta(q_h)^2,   q_h = 2 pi h / box,
+ * amp = p^eta / f^eta (the amplitude of Eq. (pe_ri), exp(-i q.r) convention).
+ *   pos, f     device double [n_atoms][3] (inside [0, box)) and [n_atoms]
+ *   box        cube edge, Angstrom;  n_grid in [2, 1024];  eta > 0 (Angstrom);
+ *              k in [1, n_grid] (the paper takes the nearest integer above
+ *              10 eta n_grid / box)
+ *   I_out      device double [n_grid][n_grid][n_grid], index h per axis in FFT
+ *              order (h for h < n_grid / 2, h - n_grid above)
+ *   amp_out    device double [n_grid^3][2], or NULL
+ * The density is accumulated with FP64 atomics (last bits vary from run to run).
+ * Working memory (about 40 n_grid^3 bytes) comes from the stream's scratch; the
+ * FFT plan and the Gaussian's transform are cached per (device, stream).
+ */
+xs_status xs_fft_intensity(const double *pos, const double *f, int64_t n_atoms, double box, int32_t n_grid,
+                           double eta, int32_t k, double *I_out, double *amp_out, void *stream);
+
 /* Thread-local message for the last non-OK status returned to this thread. */
 const char *xs_last_error(void);
 
@@ -347,20 +371,30 @@ xs_status xs_shutdown(void);
  *                   keeps its own allocation) 8, and gradient q_per_lane 4;
  *                   5: bounded to 96 VGPRs, built for gradient q_per_lane 2;
  *                   3: bounded to 168 registers, built for forward q_per_lane 32
- *   lattice         plans only (0 or 1): when a system's pixels come in rows
- *                   of n2 consecutive q-vectors that each step by one common
- *                   vector a (a planar detector grid stored row by row; see
- *                   xs_plan_create).  Forward: a lane owns a run of q_per_lane
- *                   (2, 4 or 8; 1 acts as 2) pixels along a row and forms the
- *                   in-tile phase factors of the run from one v_sin/v_cos and
- *                   per-atom factors f_j exp(2 pi i k a.d_j).  Gradient (rows
- *                   of a multiple of 64 pixels): pixels stay in row order and
- *                   the in-group phase offset of pixel m is (m - 31.5) a.d_j.
- *                   With q_per_lane 32 (the defaults) both directions run as
- *                   complex matrix products per atom tile on 64 x 64 pixel
- *                   rectangles (any row length), the adjoint with two
- *                   components when every q_z of the set is 0, else three.
+ *   lattice         plans only.  0 (default): the per-pair forms, in which every
+ *                   atom-pixel pair takes the sine and cosine of its own phase
+ *                   (forward) or the sine (adjoint); on pixel sets stored as rows
+ *                   (every run of n2 >= 8 consecutive pixels shares q_y exactly, as
+ *                   planar and Ewald-sphere detectors stored row by row do; see
+ *                   xs_plan_create) the row form: a lane's q_per_lane pixels lie in
+ *                   one row, the q_y part of the phase is formed once per (lane,
+ *                   atom), and the adjoint's 64-pixel groups run along rows (rows
+ *                   of a multiple of 64 pixels).  2: the general per-pair form
+ *                   only (rows ignored).  1: the lattice factorizations where a
+ *                   system's pixels come in rows of n2 consecutive q-vectors that
+ *                   each step by one common vector a (a planar grid stored row by
+ *                   row), the row form elsewhere.  Forward: a lane owns a run of
+ *                   q_per_lane (2, 4 or 8; 1 acts as 2) pixels along a row and
+ *                   forms the in-tile phase factors of the run from one
+ *                   v_sin/v_cos and per-atom factors f_j exp(2 pi i k a.d_j).
+ *                   Gradient (rows of a multiple of 64 pixels): the in-group
+ *                   phase offset of pixel m is (m - 31.5) a.d_j.  With q_per_lane
+ *                   32 both directions run as complex matrix products per atom
+ *                   tile on 64 x 64 pixel rectangles (any row length), the
+ *                   adjoint with two components when every q_z of the set is 0,
+ *                   else three.  The factorized forms evaluate no sine per pair.
  * Shapes apply to calls and plans created after they are set.
+ * Defaults: forward {64, 8, 64, 0, 0, 0}, gradient {64, 2, 128, 8192, 0, 0}.
  */
 typedef struct xs_tile_shape {
     int32_t atoms_per_tile;
@@ -384,11 +418,11 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape);
  * device memory the calls need, and orders the pixels along a Hilbert curve in
  * q (enqueued on `stream`).  The q array must stay at the same address and
  * unchanged for the life of the plan.  Tile shapes are those set by
- * xs_set_tile_shape when the plan is created.  With either shape's
- * `lattice` set, it also tests every system's pixels for the row lattice
- * (each q_p within 1e-11 per Angstrom of q_row_start + j a, rows of n2 >= 8
- * pixels) and synchronizes `stream` to read the result; systems that pass use
- * the lattice form of the pair sums whose shape asks for it.
+ * xs_set_tile_shape when the plan is created.  It also tests every distinct
+ * pixel set for rows (runs of n2 >= 8 consecutive pixels, n2 dividing n_q, whose
+ * q_y are bitwise equal within each run) and for the row lattice (each q_p
+ * within 1e-11 per Angstrom of q_row_start + j a), synchronizing `stream` to
+ * read the results; the tile shapes' `lattice` then picks each set's form.
  *
  * xs_plan_intensity and xs_plan_grad then only launch kernels on `stream`
  * (no allocation, copy or memset), so a caller may capture them in a HIP
@@ -436,14 +470,17 @@ xs_status xs_plan_grad_species(xs_plan *plan, const double *pos, const double *a
 xs_status xs_plan_destroy(xs_plan *plan);
 
 /* What a plan holds: segments (systems x frames), the segments whose forward
- * pair sum uses the lattice form, the work items of the forward (both forms)
- * and gradient queues, and the device memory owned by the plan. */
+ * pair sum uses the lattice form, the work items of the forward (all forms)
+ * and gradient queues, the device memory owned by the plan, and the segments
+ * whose forward pair sum uses the row form. */
 typedef struct xs_plan_info {
     int32_t n_segments;
     int32_t n_lattice_segments;
     int32_t n_forward_items;
     int32_t n_gradient_items;
     int64_t device_bytes;
+    int32_t n_row_segments;
+    int32_t pad;             /* 0 */
 } xs_plan_info;
 xs_status xs_plan_describe(const xs_plan *plan, xs_plan_info *info);
 

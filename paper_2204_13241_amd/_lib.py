@@ -22,7 +22,7 @@ EXPORTS = [
     "xs_roofline_probe", "xs_plan_create", "xs_plan_intensity", "xs_plan_grad", "xs_plan_destroy",
     "xs_plan_describe", "xs_isf_rings", "xs_siegert", "xs_intensity_species", "xs_intensity_species_grad",
     "xs_frame_sums", "xs_ring_histogram", "xs_plan_create_species", "xs_plan_intensity_species",
-    "xs_plan_grad_species", "xs_g2_rings_noalloc",
+    "xs_plan_grad_species", "xs_g2_rings_noalloc", "xs_fft_intensity",
 ]
 
 _P = ctypes.c_void_p
@@ -63,6 +63,8 @@ class XsPlanInfo(ctypes.Structure):
         ("n_forward_items", ctypes.c_int32),
         ("n_gradient_items", ctypes.c_int32),
         ("device_bytes", ctypes.c_int64),
+        ("n_row_segments", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
 
@@ -94,6 +96,7 @@ def load():
         "xs_intensity_grad": (i32, [bp, _P, _P, _P, _P, _P, i32, _P, _P, _P]),
         "xs_g2_rings": (i32, [_P, i64, i64, _P, _P, i32, i32, _P, _P, _P]),
         "xs_g2_rings_noalloc": (i32, [_P, i64, i64, _P, _P, i32, i32, _P, _P, _P]),
+        "xs_fft_intensity": (i32, [_P, _P, i64, ctypes.c_double, i32, ctypes.c_double, i32, _P, _P, _P]),
         "xs_xsvs_contrast": (i32, [_P, i64, i64, _P, _P, i32, i32, _P, _P, _P]),
         "xs_isf_rings": (i32, [_P, i64, i64, _P, _P, i32, i32, ctypes.c_double, _P, _P, _P]),
         "xs_siegert": (i32, [_P, _P, i32, i32, i32, _P, _P, _P, _P]),

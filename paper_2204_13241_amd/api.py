@@ -7,6 +7,7 @@ documented dtype; nothing is moved to or computed on the CPU here.
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -358,6 +359,24 @@ def ring_histogram(I: torch.Tensor, q: torch.Tensor, edges, n_bins: int, kappa_m
                                              e.ctypes.data_as(ctypes.c_void_p), R, int(n_bins), float(kappa_max),
                                              _ptr(counts), _ptr(mean), _stream()))
     return counts, mean
+
+
+def fft_intensity(pos: torch.Tensor, f: torch.Tensor, box: float, n_grid: int, eta: float, k: int = None,
+                  return_amp: bool = False):
+    """FFT-based method (Algorithm 2) for one frame: I [n, n, n] on q_h = 2 pi h / box (FFT
+    order), and the amplitude [n, n, n, 2] if asked.  k defaults to the nearest integer
+    above 10 eta n / box."""
+    _need(pos, "pos"), _need(f, "f")
+    if pos.dim() != 2 or pos.shape[1] != 3 or f.shape != (pos.shape[0],):
+        raise ValueError("pos must be [N, 3] and f [N]")
+    n = int(n_grid)
+    if k is None:
+        k = int(math.floor(10.0 * eta * n / box)) + 1
+    I = torch.empty((n, n, n), dtype=torch.float64, device=pos.device)
+    amp = torch.empty((n, n, n, 2), dtype=torch.float64, device=pos.device) if return_amp else None
+    _lib.check(_lib.load().xs_fft_intensity(_ptr(pos), _ptr(f), pos.shape[0], float(box), n, float(eta), int(k),
+                                            _ptr(I), _ptr(amp), _stream()))
+    return (I, amp) if return_amp else I
 
 
 def get_tile_shape(kind: int) -> dict:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libxs.so")
-SOURCES = ["xs_api.cpp", "k_fp64.hip", "k_fp32c.hip", "k_reduce.hip", "k_misc.hip", "k_species.hip"]
+SOURCES = ["xs_api.cpp", "k_fp64.hip", "k_fp32c.hip", "k_reduce.hip", "k_misc.hip", "k_species.hip", "k_fft.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
@@ -40,7 +40,8 @@ def build(verbose: bool = False) -> str:
     """Compile every source into libxs.so; returns its path.  Always recompiles."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *FLAGS, "-x", "hip", *srcs, "-o", tmp]
+    cmd = [hipcc(), *FLAGS, "-x", "hip", *srcs, "-o", tmp, "-L/opt/rocm/lib", "-lhipfft",
+           "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

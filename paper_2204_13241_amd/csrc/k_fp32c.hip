@@ -47,6 +47,8 @@ constexpr double kInvTwoPi = 0x1.45f306dc9c883p-3;  // RN(1/(2 pi))
 constexpr int kLatRuns = 8;                         // lattice item: runs across a row per lane row
 constexpr int kLatRows = kBlock / kLatRuns;         // lattice item: rows (32)
 constexpr double kLatTol = 1e-11;                   // lattice test: |q_p - model| bound, 1 / Angstrom
+constexpr int kFwdCounters = 3;                     // work-queue counters of the forward forms
+constexpr int kRotTiles = 2;                        // tiles sharing one origin and one rotation (forward)
 
 // ---------------------------------------------------------------- tables
 
@@ -56,8 +58,7 @@ struct BinSeg {            // tiling view of one segment (system x frame)
     int64_t atom0;         // offset of this segment's atoms in the key / index arrays
     int64_t cell0;         // offset of this segment's cells in the cell histogram
     int64_t tile0;         // first tile of this segment
-    double scale[3];       // cells per Angstrom along each box edge
-    int32_t bits;          // Hilbert bits per dimension (2^bits cells per edge)
+    int32_t bits;          // Hilbert bits per dimension (2^bits cells per edge of the bounding box)
     int32_t n_atoms;
     int32_t n_tiles;
     int32_t pad;
@@ -81,8 +82,8 @@ struct FwdSeg {            // pair-sum view of one segment
     int32_t n_chunks;
     int32_t n2;            // lattice form: pixels per row (0: general form)
     double a[3];           // lattice form: step between neighbours of a row (revolutions / A)
-    int32_t n_jb;          // lattice form: item rectangles across a row
-    int32_t pad;
+    int32_t n_jb;          // lattice and row forms: item rectangles across a row
+    int32_t form;          // 0 general (sorted pixels), 1 lattice, 2 rows
 };
 
 struct LatSet {            // a pixel set that passed the row-lattice test
@@ -92,6 +93,12 @@ struct LatSet {            // a pixel set that passed the row-lattice test
     double a[3];           // row step, 1 / Angstrom
     int32_t flat;          // 1: every q_z of the set is 0
     int32_t pad;
+};
+
+struct RowSet {            // a pixel set stored as rows of n2 pixels sharing q_y exactly
+    int64_t q;
+    int32_t n_q;
+    int32_t n2;
 };
 
 struct FwdItem {
@@ -187,16 +194,76 @@ __global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *__restrict__ p, in
         p[i] = 0;
 }
 
+// Bounding box of every segment's positions, in two passes: kBoxParts blocks per segment
+// reduce strided chunks (NaN coordinates are skipped by fmin / fmax), then one block per
+// segment folds their partials: box[6 s + c] = lo_c, box[6 s + 3 + c] = hi_c.  The cell
+// grid spans this box, so positions anywhere (wrapped into the simulation cell or not)
+// give compact cells and tiles.
+constexpr int kBoxParts = 64;
+__global__ __launch_bounds__(kBlock) void k_seg_bbox_part(const BinSeg *__restrict__ segs,
+                                                          const double *__restrict__ pos,
+                                                          double *__restrict__ part) {
+    const BinSeg sg = segs[blockIdx.y];
+    __shared__ double s_lo[3][kBlock], s_hi[3][kBlock];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < sg.n_atoms; j += kBoxParts * kBlock) {
+        const double *r = pos + (sg.pos + j) * 3;
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fmin(lo[c], r[c]);
+            hi[c] = fmax(hi[c], r[c]);
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        s_lo[c][threadIdx.x] = lo[c];
+        s_hi[c][threadIdx.x] = hi[c];
+    }
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < static_cast<unsigned>(off))
+            for (int c = 0; c < 3; ++c) {
+                s_lo[c][threadIdx.x] = fmin(s_lo[c][threadIdx.x], s_lo[c][threadIdx.x + off]);
+                s_hi[c][threadIdx.x] = fmax(s_hi[c][threadIdx.x], s_hi[c][threadIdx.x + off]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        double *o = part + (static_cast<int64_t>(blockIdx.y) * kBoxParts + blockIdx.x) * 6;
+        o[threadIdx.x] = s_lo[threadIdx.x][0];
+        o[3 + threadIdx.x] = s_hi[threadIdx.x][0];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_seg_bbox(const double *__restrict__ part, double *__restrict__ box) {
+    if (threadIdx.x >= 3) return;
+    const int c = threadIdx.x;
+    double l = INFINITY, h = -INFINITY;
+    for (int b = 0; b < kBoxParts; ++b) {
+        const double *o = part + (static_cast<int64_t>(blockIdx.x) * kBoxParts + b) * 6;
+        l = fmin(l, o[c]);
+        h = fmax(h, o[3 + c]);
+    }
+    const bool ok = l <= h;  // false for a segment without finite positions
+    box[6 * blockIdx.x + c] = ok ? l : 0.0;
+    box[6 * blockIdx.x + 3 + c] = ok ? h : 0.0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cell_keys(const BinSeg *__restrict__ segs,
                                                       const double *__restrict__ pos,
+                                                      const double *__restrict__ box,
                                                       uint32_t *__restrict__ keys,
                                                       int32_t *__restrict__ hist) {
     const BinSeg sg = segs[blockIdx.y];
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= sg.n_atoms) return;
     const double *r = pos + (sg.pos + j) * 3;
-    const uint32_t h = hilbert3(cell_of(r[0], sg.scale[0], sg.bits), cell_of(r[1], sg.scale[1], sg.bits),
-                                cell_of(r[2], sg.scale[2], sg.bits), sg.bits);
+    const double *bx = box + 6 * blockIdx.y;
+    double sc[3];
+    for (int c = 0; c < 3; ++c) {
+        const double span = bx[3 + c] - bx[c];
+        sc[c] = span > 0.0 ? double(1 << sg.bits) / span : 0.0;
+    }
+    const uint32_t h = hilbert3(cell_of(r[0] - bx[0], sc[0], sg.bits), cell_of(r[1] - bx[1], sc[1], sg.bits),
+                                cell_of(r[2] - bx[2], sc[2], sg.bits), sg.bits);
     keys[sg.atom0 + j] = h;
     atomicAdd(&hist[sg.cell0 + h], 1);
 }
@@ -419,9 +486,10 @@ __device__ __forceinline__ float frac_f32(double t) { return static_cast<float>(
 // tiles of the item's chunk are staged 4 at a time into LDS (double buffered)
 // with their beta(j) = frac(q_c.d_j), and read back as broadcasts.
 // Per pair the in-tile phase xi = beta + dq.d (2 FMA, or 3 when the item has
-// dq_z != 0) feeds v_sin/v_cos and 2 FMA into the tile sums
-// (C, S) = sum_j f_j (cos, sin)(2 pi xi).  The tile's base phase
-// theta = frac(q_p.o_k) (FP64) enters once per (pixel, tile) as a rotation,
+// dq_z != 0) feeds v_sin/v_cos and 2 FMA into the group sums
+// (C, S) = sum_j f_j (cos, sin)(2 pi xi), over the 4 tiles of a staged group,
+// whose offsets d are taken from one group origin O.  The base phase
+// theta = frac(q_p.O) (FP64) enters once per (pixel, group) as a rotation,
 // sum_j f_j e^{2 pi i (theta + xi)} = e^{2 pi i theta} (C + i S), whose result
 // folds into FP64.
 template <int QL, bool PLANAR>
@@ -523,25 +591,46 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
         }
         const int64_t tbase = sg.tile0 + item.t0;
         const int n_groups = (item.nt + kWaves - 1) / kWaves;
+        // The kWaves tiles of a staged group share one origin O (the midpoint of their
+        // origins' bounding box): atom offsets are re-expressed as d' = (r - o_k) + (o_k - O)
+        // in FP64, and one rotation by theta = frac(q_p.O) per (pixel, group) replaces one
+        // per (pixel, tile).
+        auto group_origin = [&](int g) {  // shared origin of the pair of tiles g (item-relative)
+            double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+            const int n_here = min(kRotTiles, item.nt - g * kRotTiles);
+            for (int w = 0; w < n_here; ++w) {
+                const double4 o = origins[tbase + g * kRotTiles + w];
+                lo3[0] = fmin(lo3[0], o.x); hi3[0] = fmax(hi3[0], o.x);
+                lo3[1] = fmin(lo3[1], o.y); hi3[1] = fmax(hi3[1], o.y);
+                lo3[2] = fmin(lo3[2], o.z); hi3[2] = fmax(hi3[2], o.z);
+            }
+            return make_double4(0.5 * (lo3[0] + hi3[0]), 0.5 * (lo3[1] + hi3[1]), 0.5 * (lo3[2] + hi3[2]), 0.0);
+        };
+        // atom of tile tt (relative to the item), offset from the group origin O
+        auto stage = [&](const float4 h, const float4 l, const double4 ot, const double4 O, int buf) {
+            const double dx = (double(h.x) + double(l.x)) + (ot.x - O.x);
+            const double dy = (double(h.y) + double(l.y)) + (ot.y - O.y);
+            const double dz = (double(h.z) + double(l.z)) + (ot.z - O.z);
+            const double b = __builtin_fma(cen[2], dz, __builtin_fma(cen[1], dy, cen[0] * dx));
+            s_atoms[buf][tid] = make_float4(static_cast<float>(dx), static_cast<float>(dy), static_cast<float>(dz), h.w);
+            s_beta[buf][tid] = frac_f32(b);
+        };
         // stage group 0
         {
             const int tt = tid / kTile;
+            const double4 O = group_origin(tt / kRotTiles);
             if (tt < item.nt) {
                 const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
-                const float4 h = t_hi[ai], l = t_lo[ai];
-                const double b = __builtin_fma(cen[2], double(h.z) + double(l.z),
-                                 __builtin_fma(cen[1], double(h.y) + double(l.y), cen[0] * (double(h.x) + double(l.x))));
-                s_atoms[0][tid] = h;
-                s_beta[0][tid] = frac_f32(b);
+                stage(t_hi[ai], t_lo[ai], origins[tbase + tt], O, 0);
             }
-            if (tid < kWaves && tid < item.nt) s_orig[0][tid] = origins[tbase + tid];
+            if ((tid & (kRotTiles * kTile - 1)) == 0) s_orig[0][tid / (kRotTiles * kTile)] = O;
         }
         __syncthreads();
         for (int g = 0; g < n_groups; ++g) {
             const int buf = g & 1;
             // fetch the next group into registers; stored after this group's work
             float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nl = nh;
-            double4 no = make_double4(0.0, 0.0, 0.0, 0.0);
+            double4 no = make_double4(0.0, 0.0, 0.0, 0.0), nO = no;
             const int ng = g + 1;
             const bool have_next = ng < n_groups;
             bool next_real = false;
@@ -552,19 +641,22 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
                     const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
                     nh = t_hi[ai];
                     nl = t_lo[ai];
+                    no = origins[tbase + tt];
                 }
-                if (tid < kWaves && ng * kWaves + tid < item.nt) no = origins[tbase + ng * kWaves + tid];
+                nO = group_origin(tt / kRotTiles);
             }
             const int tiles_here = min(kWaves, item.nt - g * kWaves);
-            for (int w = 0; w < tiles_here; ++w) {
+            for (int w0 = 0; w0 < tiles_here; w0 += kRotTiles) {
                 float cs[QL], sn[QL];
 #pragma unroll
                 for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
-                const float4 *at = &s_atoms[buf][w * kTile];
-                const float *bt = &s_beta[buf][w * kTile];
-                if (planar) tile_pairs<QL, true>(at, bt, dqx, dqy, dqz, cs, sn);
-                else tile_pairs<QL, false>(at, bt, dqx, dqy, dqz, cs, sn);
-                const double4 o = s_orig[buf][w];
+                for (int w = w0; w < min(w0 + kRotTiles, tiles_here); ++w) {
+                    const float4 *at = &s_atoms[buf][w * kTile];
+                    const float *bt = &s_beta[buf][w * kTile];
+                    if (planar) tile_pairs<QL, true>(at, bt, dqx, dqy, dqz, cs, sn);
+                    else tile_pairs<QL, false>(at, bt, dqx, dqy, dqz, cs, sn);
+                }
+                const double4 o = s_orig[buf][w0 / kRotTiles];
 #pragma unroll
                 for (int k = 0; k < QL; ++k) {
                     const float th = frac_f32(__builtin_fma(s_q[2][k][tid], o.z,
@@ -575,13 +667,8 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
                 }
             }
             if (have_next) {
-                if (next_real) {
-                    const double b = __builtin_fma(cen[2], double(nh.z) + double(nl.z),
-                                     __builtin_fma(cen[1], double(nh.y) + double(nl.y), cen[0] * (double(nh.x) + double(nl.x))));
-                    s_atoms[buf ^ 1][tid] = nh;
-                    s_beta[buf ^ 1][tid] = frac_f32(b);
-                }
-                if (tid < kWaves) s_orig[buf ^ 1][tid] = no;
+                if (next_real) stage(nh, nl, no, nO, buf ^ 1);
+                if ((tid & (kRotTiles * kTile - 1)) == 0) s_orig[buf ^ 1][tid / (kRotTiles * kTile)] = nO;
             }
             __syncthreads();
         }
@@ -590,6 +677,204 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
             if (orig[k] >= 0)
                 partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + orig[k]] =
                     make_double2(re64[k], im64[k]);
+    }
+}
+
+// ---------------------------------------------------------------- forward, row form
+//
+// Pixels of a detector stored row by row: every run of n2 consecutive pixels
+// shares q_y exactly (planar grids and the Ewald-sphere detectors alike).  An
+// item is a rectangle of kRowRows rows x kRowRuns runs of QL pixels; lane
+// (row, run) owns QL consecutive pixels of one row, so its dq_y is one value
+// and the part of the in-tile phase common to its pixels is formed once per
+// (lane, atom):
+//   Y_j = beta_j + dq_y d_y,j,    xi_pj = Y_j + dq_x,p d_x,j (+ dq_z,p d_z,j).
+// Every pair still takes v_sin and v_cos of its own phase xi_pj (1 FMA of phase
+// per pair on a q_z = 0 grid, 2 on a curved detector, 2 FMA of sums).  Atom
+// offsets, group origins and the rotation by frac(q_p.O) per (pixel, group)
+// are those of the general form.
+constexpr int kRowRuns = 8;                  // runs across a row per lane row
+constexpr int kRowRows = kBlock / kRowRuns;  // rows per item (32)
+
+template <int QL, bool FLAT>
+__device__ __forceinline__ void row_pairs(const float4 *__restrict__ at, const float *__restrict__ bt,
+                                          const float dqy, const float (&dqx)[QL], const float (&dqz)[QL],
+                                          float (&cs)[QL], float (&sn)[QL]) {
+#pragma unroll 4
+    for (int j = 0; j < kTile; ++j) {
+        const float4 a = at[j];
+        const float y = __builtin_fmaf(dqy, a.y, bt[j]);
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            float ph = __builtin_fmaf(dqx[k], a.x, y);
+            if (!FLAT) ph = __builtin_fmaf(dqz[k], a.z, ph);
+            cs[k] = __builtin_fmaf(a.w, __builtin_amdgcn_cosf(ph), cs[k]);
+            sn[k] = __builtin_fmaf(a.w, __builtin_amdgcn_sinf(ph), sn[k]);
+        }
+    }
+}
+
+template <int QL, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_forward_rows(
+    const FwdItem *__restrict__ items, int32_t n_items, int32_t *__restrict__ counter,
+    const FwdSeg *__restrict__ segs, const double *__restrict__ q, const float4 *__restrict__ t_hi,
+    const float4 *__restrict__ t_lo, const double4 *__restrict__ origins, double2 *__restrict__ partial) {
+    __shared__ float4 s_atoms[2][kWaves * kTile];
+    __shared__ float s_beta[2][kWaves * kTile];
+    __shared__ double4 s_orig[2][kWaves / kRotTiles];
+    __shared__ double s_q[2][QL][kBlock];  // q_x and q_z of the lane's pixels, revolutions per Angstrom
+    __shared__ double s_red[6][kWaves];
+    __shared__ int32_t s_item;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        __syncthreads();  // everyone has read s_item before it is rewritten
+        if (it >= n_items) break;
+        const FwdItem item = items[it];
+        const FwdSeg sg = segs[item.seg];
+        const int n1 = sg.n_q / sg.n2;
+        const int ib = item.p0 / sg.n_jb, jb = item.p0 - ib * sg.n_jb;
+        const int row = ib * kRowRows + tid / kRowRuns;
+        const int col0 = jb * kRowRuns * QL + (tid % kRowRuns) * QL;
+        const bool active = row < n1 && col0 < sg.n2;
+        const int nk = active ? min(QL, sg.n2 - col0) : 0;
+        const int64_t p0 = active ? static_cast<int64_t>(row) * sg.n2 + col0 : 0;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double qy = 0.0;
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            const bool real = k < nk;
+            const double *qp = q + (sg.q + p0 + (real ? k : 0)) * 3;
+            const double vx = qp[0] * kInvTwoPi, vy = qp[1] * kInvTwoPi, vz = qp[2] * kInvTwoPi;
+            s_q[0][k][tid] = vx;
+            s_q[1][k][tid] = vz;
+            if (k == 0) qy = vy;
+            if (real) {
+                lo[0] = fmin(lo[0], vx); hi[0] = fmax(hi[0], vx);
+                lo[1] = fmin(lo[1], vy); hi[1] = fmax(hi[1], vy);
+                lo[2] = fmin(lo[2], vz); hi[2] = fmax(hi[2], vz);
+            }
+        }
+        // item centre q_c: bounding-box centre (wavefront then block reduction)
+        for (int c = 0; c < 3; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                lo[c] = fmin(lo[c], __shfl_xor(lo[c], off));
+                hi[c] = fmax(hi[c], __shfl_xor(hi[c], off));
+            }
+        if (lane == 0)
+            for (int c = 0; c < 3; ++c) {
+                s_red[c][wave] = lo[c];
+                s_red[3 + c][wave] = hi[c];
+            }
+        __syncthreads();
+        double cen[3];
+        bool flat;
+        {
+            double l3[3], h3[3];
+            for (int c = 0; c < 3; ++c) {
+                l3[c] = s_red[c][0];
+                h3[c] = s_red[3 + c][0];
+                for (int w = 1; w < kWaves; ++w) {
+                    l3[c] = fmin(l3[c], s_red[c][w]);
+                    h3[c] = fmax(h3[c], s_red[3 + c][w]);
+                }
+                cen[c] = 0.5 * (l3[c] + h3[c]);
+            }
+            flat = l3[2] == h3[2];  // dq_z = 0 for every pixel of the item
+        }
+        const float dqy = static_cast<float>(qy - cen[1]);
+        float dqx[QL], dqz[QL];
+        double re64[QL], im64[QL];
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            dqx[k] = static_cast<float>(s_q[0][k][tid] - cen[0]);
+            dqz[k] = static_cast<float>(s_q[1][k][tid] - cen[2]);
+            re64[k] = 0.0;
+            im64[k] = 0.0;
+        }
+        const int64_t tbase = sg.tile0 + item.t0;
+        const int n_groups = (item.nt + kWaves - 1) / kWaves;
+        auto group_origin = [&](int g) {  // shared origin of the pair of tiles g (item-relative)
+            double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+            const int n_here = min(kRotTiles, item.nt - g * kRotTiles);
+            for (int w = 0; w < n_here; ++w) {
+                const double4 o = origins[tbase + g * kRotTiles + w];
+                lo3[0] = fmin(lo3[0], o.x); hi3[0] = fmax(hi3[0], o.x);
+                lo3[1] = fmin(lo3[1], o.y); hi3[1] = fmax(hi3[1], o.y);
+                lo3[2] = fmin(lo3[2], o.z); hi3[2] = fmax(hi3[2], o.z);
+            }
+            return make_double4(0.5 * (lo3[0] + hi3[0]), 0.5 * (lo3[1] + hi3[1]), 0.5 * (lo3[2] + hi3[2]), 0.0);
+        };
+        auto stage = [&](const float4 h, const float4 l, const double4 ot, const double4 O, int buf) {
+            const double dx = (double(h.x) + double(l.x)) + (ot.x - O.x);
+            const double dy = (double(h.y) + double(l.y)) + (ot.y - O.y);
+            const double dz = (double(h.z) + double(l.z)) + (ot.z - O.z);
+            const double b = __builtin_fma(cen[2], dz, __builtin_fma(cen[1], dy, cen[0] * dx));
+            s_atoms[buf][tid] = make_float4(static_cast<float>(dx), static_cast<float>(dy), static_cast<float>(dz), h.w);
+            s_beta[buf][tid] = frac_f32(b);
+        };
+        {
+            const int tt = tid / kTile;
+            const double4 O = group_origin(tt / kRotTiles);
+            if (tt < item.nt) {
+                const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
+                stage(t_hi[ai], t_lo[ai], origins[tbase + tt], O, 0);
+            }
+            if ((tid & (kRotTiles * kTile - 1)) == 0) s_orig[0][tid / (kRotTiles * kTile)] = O;
+        }
+        __syncthreads();
+        for (int g = 0; g < n_groups; ++g) {
+            const int buf = g & 1;
+            float4 nh = make_float4(0.f, 0.f, 0.f, 0.f), nl = nh;
+            double4 no = make_double4(0.0, 0.0, 0.0, 0.0), nO = no;
+            const int ng = g + 1;
+            const bool have_next = ng < n_groups;
+            bool next_real = false;
+            if (have_next) {
+                const int tt = ng * kWaves + tid / kTile;
+                next_real = tt < item.nt;
+                if (next_real) {
+                    const int64_t ai = (tbase + tt) * kTile + (tid & (kTile - 1));
+                    nh = t_hi[ai];
+                    nl = t_lo[ai];
+                    no = origins[tbase + tt];
+                }
+                nO = group_origin(tt / kRotTiles);
+            }
+            const int tiles_here = min(kWaves, item.nt - g * kWaves);
+            for (int w0 = 0; w0 < tiles_here; w0 += kRotTiles) {
+                float cs[QL], sn[QL];
+#pragma unroll
+                for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
+                for (int w = w0; w < min(w0 + kRotTiles, tiles_here); ++w) {
+                    const float4 *at = &s_atoms[buf][w * kTile];
+                    const float *bt = &s_beta[buf][w * kTile];
+                    if (flat) row_pairs<QL, true>(at, bt, dqy, dqx, dqz, cs, sn);
+                    else row_pairs<QL, false>(at, bt, dqy, dqx, dqz, cs, sn);
+                }
+                const double4 o = s_orig[buf][w0 / kRotTiles];
+                const double yo = qy * o.y;
+#pragma unroll
+                for (int k = 0; k < QL; ++k) {
+                    const float th =
+                        frac_f32(__builtin_fma(s_q[1][k][tid], o.z, __builtin_fma(s_q[0][k][tid], o.x, yo)));
+                    const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
+                    re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
+                    im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
+                }
+            }
+            if (have_next) {
+                if (next_real) stage(nh, nl, no, nO, buf ^ 1);
+                if ((tid & (kRotTiles * kTile - 1)) == 0) s_orig[buf ^ 1][tid / (kRotTiles * kTile)] = nO;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < QL; ++k)
+            if (k < nk)
+                partial[sg.part + static_cast<int64_t>(item.chunk) * sg.n_q + p0 + k] = make_double2(re64[k], im64[k]);
     }
 }
 
@@ -1064,6 +1349,26 @@ __global__ __launch_bounds__(kBlock) void k_lattice_check(const double *__restri
     }
 }
 
+// Rows of n2 pixels sharing q_y: per block, the number of pixels whose q_y differs
+// from the first pixel of their row (NaN counts as a difference).
+__global__ __launch_bounds__(kBlock) void k_row_check(const double *__restrict__ q, int32_t n_q, int32_t n2,
+                                                      double *__restrict__ block_bad) {
+    __shared__ double red[kBlock];
+    double bad = 0.0;
+    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n_q;
+         p += static_cast<int64_t>(gridDim.x) * kBlock) {
+        const int64_t r0 = p - p % n2;
+        bad += q[3 * p + 1] == q[3 * r0 + 1] ? 0.0 : 1.0;
+    }
+    red[threadIdx.x] = bad;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < static_cast<unsigned>(off)) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_bad[blockIdx.x] = red[0];
+}
+
 // Sum the chunk partials of every pixel in chunk order; a = sum f cos,
 // b = -sum f sin (the amplitude carries exp(-i q.r)), I = a*a + b*b.
 __global__ __launch_bounds__(kBlock) void k_forward_combine(const FwdSeg *__restrict__ segs,
@@ -1096,7 +1401,7 @@ __global__ __launch_bounds__(kBlock) void k_forward_combine(const FwdSeg *__rest
 // a sin(phi) + b cos(phi) = |A| sin(phi + arg A) for A = a + ib.
 // Pixel prologue, in sorted order, groups of 64 consecutive sorted pixels
 // sharing a centre q_c: FP32 (dq, 0), FP32 (W, 0), FP64 (q_rev, psi) and the
-// group centre (FP64; w = 1 if every dq_z of the group is zero).
+// group centre (FP64; w = flags of the components that vanish in the group).
 constexpr int kPixStage = 64;
 __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict__ segs,
                                                       const double *__restrict__ q,
@@ -1133,10 +1438,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict_
     pw[i] = make_float4(static_cast<float>(c * qp[0]), static_cast<float>(c * qp[1]),
                         static_cast<float>(c * qp[2]), 0.f);
     pq64[i] = make_double4(rx, ry, rz, psi);
-    // group kind: 0 general, 1 all q_z equal (dq_z = 0), 2 all q_z = 0 (also W_z = 0)
+    // group kind, a sum of flags: 1 all q_z equal (dq_z = 0), 2 all q_z = 0 (also W_z = 0),
+    // 4 all q_y equal (dq_y = 0: a run along one detector row)
     if ((threadIdx.x & 63) == 0)
         centre[sg.grp0 + sp / kPixStage] =
-            make_double4(cx, cy, cz, lo[2] == hi[2] ? (lo[2] == 0.0 ? 2.0 : 1.0) : 0.0);
+            make_double4(cx, cy, cz, (lo[2] == hi[2] ? (lo[2] == 0.0 ? 3.0 : 1.0) : 0.0) + (lo[1] == hi[1] ? 4.0 : 0.0));
 }
 
 // Workgroup = 4 wavefronts; wavefront w owns tiles t0 + w*AL + a (a < AL),
@@ -1145,9 +1451,10 @@ __global__ __launch_bounds__(kBlock) void k_grad_prep(const GradSeg *__restrict_
 // beta = frac(q_c.d) for its atoms (FP64, from the exact offset) and each
 // wavefront the base phases theta'(p, tile) = frac(q_p.o + psi_p); the next
 // group's pixel data is fetched from memory while this one is summed.  Per
-// pair: add + 3 FMA (2 when the group has dq_z = 0), one v_sin, 3 FMA (2 when
-// every q_z of the group is 0, so W_z = 0).  Group partials fold into FP64.
-template <int AL, bool PLANAR, bool NOZ>
+// pair: add + 3 FMA (one fewer when the group has dq_z = 0, one fewer when it has
+// dq_y = 0: a run along a detector row), one v_sin, 3 FMA (2 when every q_z of the
+// group is 0, so W_z = 0).  Group partials fold into FP64.
+template <int AL, bool PLANAR, bool NOZ, bool NOY>
 __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const float4 *__restrict__ sw,
                                             const float (*__restrict__ sth)[kPixStage],
                                             const float (&dx)[AL], const float (&dy)[AL],
@@ -1163,7 +1470,7 @@ __device__ __forceinline__ void pixel_pairs(const float4 *__restrict__ sq, const
 #pragma unroll
             for (int a = 0; a < AL; ++a) {
                 float ph = __builtin_fmaf(qv.x, dx[a], sth[a][m0 + k] + beta[a]);
-                ph = __builtin_fmaf(qv.y, dy[a], ph);
+                if (!NOY) ph = __builtin_fmaf(qv.y, dy[a], ph);
                 if (!PLANAR) ph = __builtin_fmaf(qv.z, dz[a], ph);
                 sn[k][a] = ph;
             }
@@ -1307,15 +1614,21 @@ __global__ __launch_bounds__(kBlock, OCC) void k_grad_fp32c(
             float gx[AL], gy[AL], gz[AL];
 #pragma unroll
             for (int a = 0; a < AL; ++a) gx[a] = gy[a] = gz[a] = 0.f;
+            const int kind = static_cast<int>(c.w);
+            const bool z0 = (kind & 2) != 0, dz0 = (kind & 1) != 0, dy0 = (kind & 4) != 0;
             if (LAT) {
-                if (c.w == 2.0) pixel_pairs_lattice<AL, true>(s_w, s_th[wave], e, beta, gx, gy, gz);
+                if (z0) pixel_pairs_lattice<AL, true>(s_w, s_th[wave], e, beta, gx, gy, gz);
                 else pixel_pairs_lattice<AL, false>(s_w, s_th[wave], e, beta, gx, gy, gz);
-            } else if (c.w == 2.0) {
-                pixel_pairs<AL, true, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
-            } else if (c.w == 1.0) {
-                pixel_pairs<AL, true, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            } else if (dy0) {
+                if (z0) pixel_pairs<AL, true, true, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+                else if (dz0) pixel_pairs<AL, true, false, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+                else pixel_pairs<AL, false, false, true>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            } else if (z0) {
+                pixel_pairs<AL, true, true, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+            } else if (dz0) {
+                pixel_pairs<AL, true, false, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
             } else {
-                pixel_pairs<AL, false, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
+                pixel_pairs<AL, false, false, false>(s_q, s_w, s_th[wave], dx, dy, dz, beta, gx, gy, gz);
             }
 #pragma unroll
             for (int a = 0; a < AL; ++a) {
@@ -1654,9 +1967,11 @@ struct Plan::Tables {
     std::vector<PixSet> psets;
     std::vector<int> seg_set;
     std::vector<LatSet> lat;              // pixel sets found to be row lattices
+    std::vector<RowSet> rows;             // pixel sets stored as rows sharing q_y
     std::vector<FwdSeg> fsegs;
     std::vector<FwdItem> fitems;          // general form
     std::vector<FwdItem> litems;          // lattice form
+    std::vector<FwdItem> ritems;          // row form
     std::vector<GradSeg> gsegs;
     std::vector<GradItem> gitems;         // concatenated over sub-batches
     std::vector<int> gsub_seg0, gsub_seg1; // segment range of each sub-batch
@@ -1669,7 +1984,7 @@ struct Plan::Tables {
     double mwork = 0.0;
     int64_t atoms = 0, cells = 0, tiles = 0, slots = 0, groups = 0, fpart = 0, gpart = 0;
     int max_atoms = 0, max_tiles = 0, max_q = 0, max_set_q = 0, max_slots_seg = 0;
-    double fwork = 0.0, lwork = 0.0;
+    double fwork = 0.0, lwork = 0.0, rwork = 0.0;
     size_t sort_tmp = 0;
 };
 
@@ -1679,11 +1994,13 @@ struct Plan::Buffers {
     FwdSeg *fsegs = nullptr;
     FwdItem *fitems = nullptr;
     FwdItem *litems = nullptr;
+    FwdItem *ritems = nullptr;
     GradSeg *gsegs = nullptr;
     GradItem *gitems = nullptr;
     FwdItem *mitems = nullptr;
     int32_t *counters = nullptr;
     int32_t *hist = nullptr, *start = nullptr, *cursor = nullptr, *scan_sums = nullptr;
+    double *segbox = nullptr, *boxpart = nullptr;
     uint32_t *keys = nullptr;
     int32_t *sorted = nullptr;
     float4 *t_hi = nullptr, *t_lo = nullptr;
@@ -1714,6 +2031,7 @@ Plan::~Plan() {
 xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, const double *q) {
     Tables &t = *T;
     t.lat.clear();
+    t.rows.clear();
     std::vector<std::pair<int64_t, int32_t>> seen;
     double *dmax = nullptr;
     constexpr int kCheckBlocks = 512;
@@ -1734,6 +2052,39 @@ xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, co
             st = set_error(XS_EDEVICE, "lattice test: cannot read q");
             break;
         }
+        if (!dmax) {
+            if (hipMalloc(&dmax, sizeof(double) * 2 * kCheckBlocks) != hipSuccess) {
+                (void)hipGetLastError();
+                st = set_error(XS_ENOMEM, "structure test: cannot allocate");
+                break;
+            }
+        }
+        const int nb = static_cast<int>(std::min<int64_t>(kCheckBlocks, (n_q + kBlock - 1) / kBlock));
+        // rows sharing q_y: row length from the prefix, then every pixel on the device
+        {
+            int64_t r2 = m;
+            for (int64_t p = 1; p < m && r2 == m; ++p)
+                if (!(h[3 * p + 1] == h[1])) r2 = p;
+            if (!(r2 == m && m < n_q) && r2 >= 8 && n_q % r2 == 0) {
+                hipLaunchKernelGGL(k_row_check, dim3(nb), dim3(kBlock), 0, s, q + 3 * qo, n_q,
+                                   static_cast<int32_t>(r2), dmax);
+                if (hipGetLastError() != hipSuccess ||
+                    hipMemcpyAsync(hmax.data(), dmax, sizeof(double) * nb, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    st = set_error(XS_EDEVICE, "row test: device check failed");
+                    break;
+                }
+                double bad = 0.0;
+                for (int k = 0; k < nb; ++k) bad += hmax[k];
+                if (bad == 0.0) {
+                    RowSet rs;
+                    rs.q = qo;
+                    rs.n_q = n_q;
+                    rs.n2 = static_cast<int32_t>(r2);
+                    t.rows.push_back(rs);
+                }
+            }
+        }
         double a[3];
         for (int c = 0; c < 3; ++c) a[c] = h[3 + c] - h[c];
         if (a[0] == 0.0 && a[1] == 0.0 && a[2] == 0.0) continue;
@@ -1749,14 +2100,6 @@ xs_status Plan::find_lattices(hipStream_t s, const Segment *segs, int n_segs, co
         if (n2 == m && m < n_q) continue;  // row longer than the prefix read
         if (n2 < 8 || n_q % n2 != 0) continue;
         for (int c = 0; c < 3; ++c) a[c] = (h[3 * (n2 - 1) + c] - h[c]) / static_cast<double>(n2 - 1);
-        if (!dmax) {
-            if (hipMalloc(&dmax, sizeof(double) * 2 * kCheckBlocks) != hipSuccess) {
-                (void)hipGetLastError();
-                st = set_error(XS_ENOMEM, "lattice test: cannot allocate");
-                break;
-            }
-        }
-        const int nb = static_cast<int>(std::min<int64_t>(kCheckBlocks, (n_q + kBlock - 1) / kBlock));
         hipLaunchKernelGGL(k_lattice_check, dim3(nb), dim3(kBlock), 0, s, q + 3 * qo, n_q, static_cast<int32_t>(n2),
                            a[0], a[1], a[2], dmax);
         if (hipGetLastError() != hipSuccess ||
@@ -1789,6 +2132,33 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
     fshape = fsh;
     gshape = gsh;
     n_seg = n_segs;
+    auto find_lat = [&](int64_t q, int32_t n) -> const LatSet * {
+        for (const LatSet &l : t.lat)
+            if (l.q == q && l.n_q == n) return &l;
+        return nullptr;
+    };
+    auto find_row = [&](int64_t q, int32_t n) -> const RowSet * {
+        for (const RowSet &r : t.rows)
+            if (r.q == q && r.n_q == n) return &r;
+        return nullptr;
+    };
+    // forward form of a pixel set: 1 lattice (opt-in), 2 rows, 0 general (sorted pixels)
+    auto fwd_form = [&](int64_t q, int32_t n) {
+        if (fsh.lattice == 1 && find_lat(q, n)) return 1;
+        if (fsh.lattice != 2 && find_row(q, n)) return 2;
+        return 0;
+    };
+    // vector-unit gradient form: 1 lattice, 2 rows (both with the pixels in input order,
+    // in groups of 64 along a row), 0 general (sorted pixels).  Input order only where the
+    // forward does not read the sorted order.
+    auto grad_form = [&](int64_t q, int32_t n) {
+        if (fwd_form(q, n) == 0) return 0;
+        const LatSet *l = find_lat(q, n);
+        if (gsh.lattice == 1 && l && l->n2 % kPixStage == 0) return 1;
+        const RowSet *r = find_row(q, n);
+        if (gsh.lattice != 2 && r && r->n2 % kPixStage == 0) return 2;
+        return 0;
+    };
     t.bsegs.resize(n_segs);
     t.seg_set.resize(n_segs);
     for (int i = 0; i < n_segs; ++i) {
@@ -1806,8 +2176,6 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         int bits = 1;
         while (bits < 10 && (int64_t(1) << (3 * (bits + 1))) * 2 <= sg.n_atoms) ++bits;
         b.bits = bits;
-        const double *L = box + 3 * sg.sys;
-        for (int d = 0; d < 3; ++d) b.scale[d] = double(1 << bits) / L[d];
         t.atoms += sg.n_atoms;
         t.tiles += b.n_tiles;
         t.cells += int64_t(1) << (3 * bits);
@@ -1823,10 +2191,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
             ps.q = sg.q;
             ps.n_q = sg.n_q;
             ps.slot0 = t.slots;
-            ps.lattice = 0;
-            if (gsh.lattice)
-                for (const LatSet &l : t.lat)
-                    if (l.q == sg.q && l.n_q == sg.n_q && l.n2 % kPixStage == 0) ps.lattice = 1;
+            ps.lattice = grad_form(sg.q, sg.n_q) != 0 ? 1 : 0;
             t.slots += sg.n_q;
             t.psets.push_back(ps);
             set = static_cast<int>(t.psets.size()) - 1;
@@ -1849,8 +2214,8 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
     const int QL = mfma ? 8 : fsh.q_per_lane, split = std::max(1, fsh.atom_split), ppi = kBlock * QL;
     const int LQ = std::max(2, QL), lcols = mfma ? kMfCols : kLatRuns * LQ, lrows = mfma ? kMfRows : kLatRows;
     t.fsegs.resize(n_segs);
-    std::vector<FwdItem> items, litems;
-    std::vector<int64_t> cost, lcost;
+    std::vector<FwdItem> items, litems, ritems;
+    std::vector<int64_t> cost, lcost, rcost;
     for (int i = 0; i < n_segs; ++i) {
         FwdSeg &g = t.fsegs[i];
         std::memset(&g, 0, sizeof(g));
@@ -1863,10 +2228,33 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         g.n_chunks = g.n_tiles > 0 ? (g.n_tiles + split - 1) / split : 0;
         g.part = t.fpart;
         t.fpart += static_cast<int64_t>(g.n_chunks) * g.n_q;
-        const LatSet *ls = nullptr;
-        if (fsh.lattice)
-            for (const LatSet &l : t.lat)
-                if (l.q == g.q && l.n_q == g.n_q) ls = &l;
+        const int form = fwd_form(g.q, g.n_q);
+        const LatSet *ls = form == 1 ? find_lat(g.q, g.n_q) : nullptr;
+        const RowSet *rs = form == 2 ? find_row(g.q, g.n_q) : nullptr;
+        g.form = form;
+        if (rs) {
+            const int rcols = kRowRuns * QL;
+            g.n2 = rs->n2;
+            g.n_jb = (g.n2 + rcols - 1) / rcols;
+            const int n1 = g.n_q / g.n2;
+            const int n_ib = (n1 + kRowRows - 1) / kRowRows;
+            for (int r = 0; r < n_ib * g.n_jb; ++r)
+                for (int c = 0; c < g.n_chunks; ++c) {
+                    FwdItem it;
+                    it.seg = i;
+                    it.p0 = r;
+                    it.t0 = c * split;
+                    it.nt = std::min(split, g.n_tiles - c * split);
+                    it.chunk = c;
+                    it.pad = 0;
+                    ritems.push_back(it);
+                    const int64_t rows = std::min(kRowRows, n1 - (r / g.n_jb) * kRowRows);
+                    const int64_t cols = std::min(rcols, g.n2 - (r % g.n_jb) * rcols);
+                    rcost.push_back(rows * cols * it.nt);
+                    t.rwork += static_cast<double>(rows * cols) * it.nt * kTile;
+                }
+            continue;
+        }
         if (ls) {
             g.n2 = ls->n2;
             for (int c = 0; c < 3; ++c) g.a[c] = ls->a[c] * kInvTwoPi;
@@ -1906,6 +2294,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
     }
     t.fitems = largest_first(items, cost);
     t.litems = largest_first(litems, lcost);
+    t.ritems = largest_first(ritems, rcost);
     // gradient work lists: segments sharing a pixel set go to different sub-batches;
     // q_per_lane 32 selects the matrix-core lattice form for lattice segments (their own
     // queue of 64 x 64 pixel rectangles x atom tiles), the others run 2 atoms per lane
@@ -1926,14 +2315,14 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         g.n_tiles = t.bsegs[i].n_tiles;
         g.n_chunks = (g.n_q > 0 && g.n_tiles > 0) ? (g.n_q + pchunk - 1) / pchunk : 0;
         g.part = t.gpart;
-        g.lat = t.psets[t.seg_set[i]].lattice;
+        g.lat = grad_form(g.q, g.n_q) == 1 ? 1 : 0;
         for (int c = 0; c < 3; ++c) g.a[c] = 0.0;
         if (g.lat)
             for (const LatSet &l : t.lat)
                 if (l.q == g.q && l.n_q == g.n_q)
                     for (int c = 0; c < 3; ++c) g.a[c] = l.a[c] * kInvTwoPi;
         g.mf = g.n2 = g.n_jb = g.pad = 0;
-        if (gmfma && gsh.lattice && g.n_q > 0 && g.n_tiles > 0)
+        if (gmfma && gsh.lattice == 1 && g.n_q > 0 && g.n_tiles > 0)
             for (const LatSet &l : t.lat)
                 if (l.q == g.q && l.n_q == g.n_q) {
                     g.mf = l.flat ? 2 : 3;
@@ -2043,15 +2432,18 @@ size_t Plan::layout(char *base) {
     b.fsegs = reinterpret_cast<FwdSeg *>(take(sizeof(FwdSeg) * t.fsegs.size()));
     b.fitems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.fitems.size()));
     b.litems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.litems.size()));
+    b.ritems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.ritems.size()));
     b.gsegs = reinterpret_cast<GradSeg *>(take(sizeof(GradSeg) * t.gsegs.size()));
     b.gitems = reinterpret_cast<GradItem *>(take(sizeof(GradItem) * t.gitems.size()));
     b.mitems = reinterpret_cast<FwdItem *>(take(sizeof(FwdItem) * t.mitems.size()));
     b.table_bytes = off - tb0;
-    // counters: [0] general forward, [1] lattice forward, [2 + k] gradient sub-batch k,
-    // [2 + sub-batches] and [3 + sub-batches] matrix-core gradient (2 and 3 components)
-    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + 4)));
+    // counters: [0] general forward, [1] lattice forward, [2] row forward, [3 + k] gradient
+    // sub-batch k, [3 + sub-batches] and [4 + sub-batches] matrix-core gradient (2 and 3 components)
+    b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + kFwdCounters + 2)));
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
+    b.segbox = reinterpret_cast<double *>(take(sizeof(double) * 6 * t.bsegs.size()));
+    b.boxpart = reinterpret_cast<double *>(take(sizeof(double) * 6 * kBoxParts * t.bsegs.size()));
     b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.cursor = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.scan_sums = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nsb));
@@ -2076,12 +2468,16 @@ size_t Plan::layout(char *base) {
     return off;
 }
 
-void Plan::describe(int *n_lattice_segs, int *n_fwd_items, int *n_grad_items) const {
+void Plan::describe(int *n_lattice_segs, int *n_row_segs, int *n_fwd_items, int *n_grad_items) const {
     const Tables &t = *T;
-    int nl = 0;
-    for (const FwdSeg &g : t.fsegs) nl += g.n2 > 0;
+    int nl = 0, nr = 0;
+    for (const FwdSeg &g : t.fsegs) {
+        nl += g.form == 1;
+        nr += g.form == 2;
+    }
     *n_lattice_segs = nl;
-    *n_fwd_items = static_cast<int>(t.fitems.size() + t.litems.size());
+    *n_row_segs = nr;
+    *n_fwd_items = static_cast<int>(t.fitems.size() + t.litems.size() + t.ritems.size());
     *n_grad_items = static_cast<int>(t.gitems.size() + t.mitems.size());
 }
 
@@ -2099,6 +2495,7 @@ std::vector<char> Plan::table_blob() const {
     put(t.fsegs.data(), sizeof(FwdSeg) * t.fsegs.size());
     put(t.fitems.data(), sizeof(FwdItem) * t.fitems.size());
     put(t.litems.data(), sizeof(FwdItem) * t.litems.size());
+    put(t.ritems.data(), sizeof(FwdItem) * t.ritems.size());
     put(t.gsegs.data(), sizeof(GradSeg) * t.gsegs.size());
     put(t.gitems.data(), sizeof(GradItem) * t.gitems.size());
     put(t.mitems.data(), sizeof(FwdItem) * t.mitems.size());
@@ -2162,8 +2559,10 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     const unsigned zb = static_cast<unsigned>(std::min<int64_t>((t.cells + kBlock - 1) / kBlock, 4096));
     hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(kBlock), 0, s, b.hist, t.cells);
+    hipLaunchKernelGGL(k_seg_bbox_part, dim3(kBoxParts, n_seg), dim3(kBlock), 0, s, b.bsegs, pos, b.boxpart);
+    hipLaunchKernelGGL(k_seg_bbox, dim3(n_seg), dim3(64), 0, s, b.boxpart, b.segbox);
     const dim3 ga((t.max_atoms + kBlock - 1) / kBlock, n_seg);
-    hipLaunchKernelGGL(k_cell_keys, ga, dim3(kBlock), 0, s, b.bsegs, pos, b.keys, b.hist);
+    hipLaunchKernelGGL(k_cell_keys, ga, dim3(kBlock), 0, s, b.bsegs, pos, b.segbox, b.keys, b.hist);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kBlock), 0, s, b.hist, t.cells, b.scan_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, b.scan_sums, nsb);
     hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kBlock), 0, s, b.hist, t.cells, b.scan_sums, b.start,
@@ -2255,6 +2654,25 @@ bool launch_forward_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt,
     }
 }
 
+template <int QL, int OCC>
+void launch_rows(hipStream_t s, int n, int32_t *counter, const Plan::Buffers &b, const double *q) {
+    const int slots = std::min(n, resident_blocks(reinterpret_cast<const void *>(k_forward_rows<QL, OCC>), kBlock));
+    hipLaunchKernelGGL((k_forward_rows<QL, OCC>), dim3(slots), dim3(kBlock), 0, s, b.ritems, n, counter, b.fsegs, q,
+                       b.t_hi, b.t_lo, b.origins, b.fpart);
+}
+
+bool launch_rows_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, const Plan::Buffers &b,
+                         const double *q) {
+    const bool o4 = occ == 4;
+    switch (ql) {
+    case 1: launch_rows<1, 1>(s, n, cnt, b, q); return true;
+    case 2: o4 ? launch_rows<2, 4>(s, n, cnt, b, q) : launch_rows<2, 1>(s, n, cnt, b, q); return true;
+    case 4: o4 ? launch_rows<4, 4>(s, n, cnt, b, q) : launch_rows<4, 1>(s, n, cnt, b, q); return true;
+    case 8: launch_rows<8, 1>(s, n, cnt, b, q); return true;
+    default: return false;
+    }
+}
+
 bool launch_grad_variant(hipStream_t s, int al, int occ, bool lat, const GradItem *items, int n, int32_t *cnt,
                          const Plan::Buffers &b) {
     const bool o4 = occ == 4;
@@ -2276,8 +2694,9 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
     Tables &t = *T;
     Buffers &b = *B;
     const int n = static_cast<int>(t.fitems.size()), nl = static_cast<int>(t.litems.size());
-    if (n + nl > 0) {
-        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, 2);
+    const int nr = static_cast<int>(t.ritems.size());
+    if (n + nl + nr > 0) {
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, kFwdCounters);
         void *tok = nullptr;
         timer_begin(s, TIMER_FWD32, &tok);
         const int qlg = fshape.q_per_lane == 32 ? 8 : fshape.q_per_lane;  // general items of the matrix-core shape
@@ -2286,7 +2705,9 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
         if (nl > 0 &&
             !launch_lattice_variant(s, fshape.q_per_lane, fshape.waves_per_simd, nl, b.counters + 1, b, q))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
-        timer_end(s, TIMER_FWD32, tok, t.fwork + t.lwork);
+        if (nr > 0 && !launch_rows_variant(s, qlg, fshape.waves_per_simd, nr, b.counters + 2, b, q))
+            return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
+        timer_end(s, TIMER_FWD32, tok, t.fwork + t.lwork + t.rwork);
         XS_HIP(hipGetLastError());
     }
     if (t.max_q > 0) {
@@ -2309,7 +2730,7 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
                                s, b.gsegs + i0, q, b.pix_order, amp, dL_dI, b.pdq, b.pw, b.pq64, b.centre);
         const int n = t.gsub_nitem[k];
         if (n == 0) continue;
-        int32_t *cnt = b.counters + 2 + k;
+        int32_t *cnt = b.counters + kFwdCounters + k;
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 1);
         const GradItem *items = b.gitems + t.gsub_item0[k];
         void *tok = nullptr;
@@ -2322,7 +2743,7 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
     }
     if (!t.mitems.empty()) {
         const int n2 = t.mcount2, n3 = static_cast<int>(t.mitems.size()) - t.mcount2;
-        int32_t *cnt = b.counters + 2 + t.gsub_seg0.size();
+        int32_t *cnt = b.counters + kFwdCounters + t.gsub_seg0.size();
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 2);
         void *tok = nullptr;
         timer_begin(s, TIMER_GRAD32, &tok);

@@ -362,6 +362,16 @@ __global__ __launch_bounds__(kBlock) void k_pixel_mean(const double *__restrict_
 // thread owns one pixel and kLagBlock consecutive lags, sliding a window of
 // the kLagBlock later values along t, so each lag's sum runs t = 0, 1, ... in
 // order.  The main loop covers the t where every lag of the block is in range.
+// Lag products of the staged series: thread (pixel pp, slot) owns lag blocks of L
+// consecutive lags, lb = slot, slot + n_slots, ...; for lag block tau0 it keeps a window
+// y[j] = x[t + tau0 + j] in registers that slides by one element per step, so each
+// step reads two values from LDS (x[t] and the window's new end) for L fused
+// multiply-adds.  The series is followed by L rows of zeros in LDS, so every lag of the
+// block runs the F - tau0 steps of its smallest lag: the extra terms are x[t] * 0, which
+// leave a finite sum unchanged bit for bit, and every G_p(tau) stays the sequential sum
+// over t of x[t] x[t + tau].  L is chosen per call so that the lag blocks spread evenly
+// over the slots.
+template <int L>
 __global__ __launch_bounds__(kBlock) void k_g2_lags(const double *__restrict__ I, int32_t F,
                                                     int64_t n_q, int32_t n_tau, int32_t lpw,
                                                     const int32_t *__restrict__ rank,
@@ -371,6 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags(const double *__restrict__ I
     const int pw = 1 << lpw;
     const int64_t p0 = static_cast<int64_t>(blockIdx.x) * pw;
     stage_series<16>(lds, I, F, lpw, n_q, p0);
+    for (int i = (F << lpw) + static_cast<int>(threadIdx.x); i < ((F + L) << lpw); i += kBlock) lds[i] = 0.0;
     __syncthreads();
     const int pp = threadIdx.x & (pw - 1);
     const int slot = threadIdx.x >> lpw, n_slots = kBlock >> lpw;
@@ -379,38 +390,27 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags(const double *__restrict__ I
     const int32_t row = rank[p];
     if (row < 0) return;
     const double dn = den[p];
-    const int n_lb = (n_tau + kLagBlock - 1) / kLagBlock;
+    const int n_lb = (n_tau + L - 1) / L;
     for (int lb = slot; lb < n_lb; lb += n_slots) {
-        const int tau0 = lb * kLagBlock;
-        double acc[kLagBlock], y[kLagBlock];
+        const int tau0 = lb * L;
+        double acc[L], y[L];
 #pragma unroll
-        for (int j = 0; j < kLagBlock; ++j) {
+        for (int j = 0; j < L; ++j) {
             acc[j] = 0.0;
-            y[j] = tau0 + j < F ? lds[(tau0 + j) * pw + pp] : 0.0;
+            y[j] = lds[(tau0 + j) * pw + pp];  // tau0 + j < F + L: staged or zero
         }
-        const int t_main = F - tau0 - kLagBlock;  // t < t_main: lags and the next load in range
-        int t = 0;
+        const int steps = F - tau0;
 #pragma unroll 8
-        for (; t < t_main; ++t) {
+        for (int t = 0; t < steps; ++t) {
             const double x = lds[t * pw + pp];
 #pragma unroll
-            for (int j = 0; j < kLagBlock; ++j) acc[j] = __builtin_fma(x, y[j], acc[j]);
+            for (int j = 0; j < L; ++j) acc[j] = __builtin_fma(x, y[j], acc[j]);
 #pragma unroll
-            for (int j = 0; j + 1 < kLagBlock; ++j) y[j] = y[j + 1];
-            y[kLagBlock - 1] = lds[(t + tau0 + kLagBlock) * pw + pp];
-        }
-        for (; t + tau0 < F; ++t) {
-            const double x = lds[t * pw + pp];
-#pragma unroll
-            for (int j = 0; j < kLagBlock; ++j)
-                if (t + tau0 + j < F) acc[j] = __builtin_fma(x, y[j], acc[j]);
-#pragma unroll
-            for (int j = 0; j + 1 < kLagBlock; ++j) y[j] = y[j + 1];
-            const int nt = t + tau0 + kLagBlock;
-            y[kLagBlock - 1] = nt < F ? lds[nt * pw + pp] : 0.0;
+            for (int j = 0; j + 1 < L; ++j) y[j] = y[j + 1];
+            y[L - 1] = lds[(t + tau0 + L) * pw + pp];  // row < F + L
         }
 #pragma unroll
-        for (int j = 0; j < kLagBlock; ++j) {
+        for (int j = 0; j < L; ++j) {
             const int tau = tau0 + j;
             if (tau < n_tau)
                 G[static_cast<int64_t>(row) * n_tau + tau] = (acc[j] / static_cast<double>(F - tau)) / dn;
@@ -418,8 +418,6 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags(const double *__restrict__ I
     }
 }
 
-// Same lag step reading global memory (series too long for LDS): one thread
-// per (pixel, lag block).
 __global__ __launch_bounds__(kBlock) void k_g2_lags_global(const double *__restrict__ I, int64_t F,
                                                            int64_t n_q, int32_t n_tau,
                                                            const int32_t *__restrict__ rank,
@@ -1032,14 +1030,28 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
     if (n_q > 0) {
         // pixels per block for the LDS path: largest power of two <= 64 with the
         // series in at most 64 KiB
+        // (series plus the largest lag block of zero rows, L <= 32)
         int lpw = 6;
-        while (lpw > 0 && (F << lpw) * static_cast<int64_t>(sizeof(double)) > 65536) --lpw;
-        if ((F << lpw) * static_cast<int64_t>(sizeof(double)) <= 65536) {
-            const size_t lds = sizeof(double) * (F << lpw);
+        while (lpw > 0 && ((F + 32) << lpw) * static_cast<int64_t>(sizeof(double)) > 65536) --lpw;
+        if (((F + 32) << lpw) * static_cast<int64_t>(sizeof(double)) <= 65536) {
+            const size_t lds = sizeof(double) * ((F + 32) << lpw);
             const int64_t pw = int64_t(1) << lpw;
-            hipLaunchKernelGGL(k_g2_lags, dim3(static_cast<unsigned>((n_q + pw - 1) / pw)), dim3(kBlock), lds, s,
-                               I, static_cast<int32_t>(F), n_q, n_tau, static_cast<int32_t>(lpw), P.rank, dn,
-                               static_cast<double *>(G));
+            // lag block: the smallest built size that leaves no slot with two blocks
+            const int n_slots = kBlock >> lpw;
+            const int want = static_cast<int>((n_tau + n_slots - 1) / n_slots);
+            const dim3 grid(static_cast<unsigned>((n_q + pw - 1) / pw));
+            const int32_t F32 = static_cast<int32_t>(F), lpw32 = static_cast<int32_t>(lpw);
+            double *Gd = static_cast<double *>(G);
+            if (want <= 8)
+                hipLaunchKernelGGL(k_g2_lags<8>, grid, dim3(kBlock), lds, s, I, F32, n_q, n_tau, lpw32, P.rank, dn, Gd);
+            else if (want <= 13)
+                hipLaunchKernelGGL(k_g2_lags<13>, grid, dim3(kBlock), lds, s, I, F32, n_q, n_tau, lpw32, P.rank, dn, Gd);
+            else if (want <= 16)
+                hipLaunchKernelGGL(k_g2_lags<16>, grid, dim3(kBlock), lds, s, I, F32, n_q, n_tau, lpw32, P.rank, dn, Gd);
+            else if (want <= 24)
+                hipLaunchKernelGGL(k_g2_lags<24>, grid, dim3(kBlock), lds, s, I, F32, n_q, n_tau, lpw32, P.rank, dn, Gd);
+            else
+                hipLaunchKernelGGL(k_g2_lags<32>, grid, dim3(kBlock), lds, s, I, F32, n_q, n_tau, lpw32, P.rank, dn, Gd);
         } else {
             const int64_t n_lb = (n_tau + kLagBlock - 1) / kLagBlock;
             hipLaunchKernelGGL(k_g2_lags_global, dim3(blocks_for(n_q * n_lb)), dim3(kBlock), 0, s, I, F, n_q,

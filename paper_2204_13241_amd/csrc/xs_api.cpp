@@ -171,8 +171,6 @@ void release_all_scratch() {
 
 namespace {
 
-// Defaults: the fastest shapes on a 65,536-atom, 512x512-pixel single frame (forward: the
-// matrix-core lattice form, 64 atom tiles per item; gradient: 2 atoms per lane, 5 waves).
 // Defaults: the per-pair form (one sine and cosine per atom-pixel pair in the forward,
 // one sine per pair in the adjoint); the factorized lattice forms are opt-in.
 xs_tile_shape g_shape[2] = {{64, 8, 64, 0, 0, 0}, {64, 2, 128, 8192, 0, 0}};
@@ -487,8 +485,22 @@ const char *xs_last_error(void) { return g_last_error.c_str(); }
 int32_t xs_version(void) { return 100; }
 
 xs_status xs_shutdown(void) {
+    release_fft_plans();
     release_all_scratch();
     return XS_OK;
+}
+
+xs_status xs_fft_intensity(const double *pos, const double *f, int64_t n_atoms, double box, int32_t n_grid,
+                           double eta, int32_t k, double *I_out, double *amp_out, void *stream) {
+    XS_TRY(begin(stream));
+    if (n_atoms < 0 || n_atoms >= (int64_t(1) << 40)) return set_error(XS_EINVAL, "n_atoms out of range");
+    if (n_grid < 2 || n_grid > 1024) return set_error(XS_EINVAL, "n_grid must be in [2, 1024]");
+    if (!(box > 0.0) || !std::isfinite(box)) return set_error(XS_EINVAL, "box must be positive and finite");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return set_error(XS_EINVAL, "eta must be positive and finite");
+    if (k < 1 || k > n_grid) return set_error(XS_EINVAL, "k must be in [1, n_grid]");
+    if (!I_out) return set_error(XS_EINVAL, "I_out is NULL");
+    if (n_atoms > 0 && (!pos || !f)) return set_error(XS_EINVAL, "pos / f is NULL");
+    return fft_intensity(static_cast<hipStream_t>(stream), pos, f, n_atoms, box, n_grid, eta, k, I_out, amp_out);
 }
 
 xs_status xs_speckle_loss(const double *I, const double *I_target, int64_t n, double *loss_out,
@@ -526,7 +538,7 @@ namespace {
 xs_status build_pair_plan(hipStream_t s, xs::Plan &plan, const std::vector<Segment> &segs, const double *box,
                           const double *q, const xs_tile_shape &fsh, const xs_tile_shape &gsh) {
     const int n = static_cast<int>(segs.size());
-    if (fsh.lattice || gsh.lattice) XS_TRY(plan.find_lattices(s, segs.data(), n, q));
+    XS_TRY(plan.find_lattices(s, segs.data(), n, q));
     XS_TRY(plan.build(segs.data(), n, box, fsh, gsh));
     XS_TRY(plan.allocate(s, true));
     return plan.sort_pixels(s, q);
@@ -675,10 +687,12 @@ xs_status xs_plan_destroy(xs_plan *p) {
 
 xs_status xs_plan_describe(const xs_plan *p, xs_plan_info *info) {
     if (!p || !info) return set_error(XS_EINVAL, "plan and info must be non-NULL");
-    int nl = 0, nf = 0, ng = 0;
-    p->plan.describe(&nl, &nf, &ng);
+    int nl = 0, nr = 0, nf = 0, ng = 0;
+    p->plan.describe(&nl, &nr, &nf, &ng);
     info->n_segments = p->plan.n_seg;
     info->n_lattice_segments = nl;
+    info->n_row_segments = nr;
+    info->pad = 0;
     info->n_forward_items = nf;
     info->n_gradient_items = ng;
     info->device_bytes = static_cast<int64_t>(p->plan.device_bytes) +
@@ -716,7 +730,7 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
                                      "and gradient q_per_lane 4");
     if (shape->waves_per_simd == 5 && !(kind == 1 && ql == 2))
         return set_error(XS_ENOTSUP, "the 5-waves-per-SIMD variant is built for gradient q_per_lane 2");
-    if (shape->lattice != 0 && shape->lattice != 1) return set_error(XS_EINVAL, "lattice must be 0 or 1");
+    if (shape->lattice < 0 || shape->lattice > 2) return set_error(XS_EINVAL, "lattice must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_shape_mu);
     g_shape[kind] = *shape;
     return XS_OK;

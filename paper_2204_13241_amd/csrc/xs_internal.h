@@ -58,6 +58,10 @@ enum Slot {
     SLOT_SPECIES_POS,   // species split: unit weights and positions in species order
     SLOT_SPECIES_OUT,   // species split: per-species amplitudes / adjoint weights
     SLOT_SPECIES_GRAD,  // species split: gradients in species order
+    SLOT_FFT_RHO,       // FFT method: smeared density on the grid
+    SLOT_FFT_SPEC,      // FFT method: its half spectrum
+    SLOT_FFT_GAUSS,     // FFT method: half spectrum of the centred Gaussian
+    SLOT_FFT_GAUSS2,    // FFT method: its squared modulus
     SLOT_COUNT
 };
 xs_status scratch(hipStream_t stream, Slot slot, size_t bytes, void **ptr);
@@ -102,8 +106,9 @@ public:
     ~Plan();
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;
-    // Row-lattice test of every distinct pixel set (device check, synchronizes s);
-    // build() then uses the lattice form for the sets that pass.
+    // Structure tests of every distinct pixel set (device checks, synchronizes s): rows of
+    // n2 pixels sharing q_y (row form of the per-pair sums) and row lattices (lattice forms);
+    // build() then picks each set's form from the tile shapes.
     xs_status find_lattices(hipStream_t s, const Segment *segs, int n_segs, const double *q);
     xs_status build(const Segment *segs, int n_segs, const double *box, const xs_tile_shape &fsh,
                     const xs_tile_shape &gsh);
@@ -115,7 +120,7 @@ public:
                    const double *dL_dI, float *g32, double *g64);
     size_t layout(char *base);
     std::vector<char> table_blob() const;
-    void describe(int *n_lattice_segs, int *n_fwd_items, int *n_grad_items) const;
+    void describe(int *n_lattice_segs, int *n_row_segs, int *n_fwd_items, int *n_grad_items) const;
 
     Tables *T;
     Buffers *B;
@@ -180,6 +185,10 @@ xs_status isf_rings(hipStream_t s, const double *amp, int64_t n_frames, int64_t 
                     const RingEdges &edges, int32_t n_tau, double f2, double *F_out, int32_t *ring_count);
 xs_status siegert(hipStream_t s, const double *g2, const double *F, int32_t n_rings, int32_t n_tau,
                   int32_t n_levels, double *lhs, double *fhat2, double *beta);
+// FFT-based method (Algorithm 2), one frame on an n^3 grid; I [n^3], amp [n^3][2] or NULL.
+xs_status fft_intensity(hipStream_t s, const double *pos, const double *f, int64_t n_atoms, double box,
+                        int32_t n, double eta, int32_t k, double *I, double *amp);
+void release_fft_plans();
 
 // ---------------------------------------------------------------- timing
 // Optional HIP-event timing of kernel launches on the stream they run on.

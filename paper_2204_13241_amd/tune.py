@@ -49,7 +49,7 @@ def signature(systems, planar: bool, lattice: int = 1) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v7|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
+    return "v8|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved", "lattice" if lattice else "per-pair")
 

@@ -155,6 +155,40 @@ def test_differentiation_full_size(api):
     plan.close()
 
 
+@pytest.mark.parametrize("form", ["per-pair", "lattice-mfma"])
+def test_differentiation_full_size_dense_weights(api, form):
+    """The full-size adjoint (65,536 atoms, 512x512 planar pixels) with dL/dI non-zero on
+    every pixel: dL/dr_j = -2 f_j sum_p w_p q_p (a_p sin q_p.r_j + b_p cos q_p.r_j) holds for
+    any amplitude, so a seeded amplitude of the intensity's scale and seeded weights feed
+    both sides; 64 atoms against the oracle, for the per-pair form and the matrix-core
+    lattice form."""
+    from _gpu import dev, host, grad_err
+    w = X.workload_grad()
+    r0, f, q, L = w.positions[0][0], w.f[0], w.q[0], w.box[0]
+    N, Q = r0.shape[0], q.shape[0]
+    rng = np.random.default_rng(6)
+    amp = rng.standard_normal((Q, 2)) * math.sqrt(N / 2.0)
+    wts = rng.standard_normal(Q) / Q
+    old = [api.get_tile_shape(0), api.get_tile_shape(1)]
+    try:
+        if form == "lattice-mfma":
+            api.set_tile_shape(0, 64, 32, 64, 0, 0, 1)
+            api.set_tile_shape(1, 64, 32, 128, 8192, 0, 1)
+        plan = api.Plan.single(N, 1, dev(q), L)
+        print("dense-w adjoint, %s: %s" % (form, plan.describe()), flush=True)
+        g = plan.grad(dev(r0), dev(f), dev(amp), dev(wts), retile=True)
+        torch.cuda.synchronize()
+        atoms = w.extra["fd_atoms"]
+        g_ref = oracle.intensity_grad(r0[atoms], f[atoms], q, amp, wts)
+        e = grad_err(host(g)[atoms], g_ref)
+        print("dense-w adjoint, %s: e_grad %.2e" % (form, e), flush=True)
+        assert e < TOL
+        plan.close()
+    finally:
+        for k in (0, 1):
+            api.set_tile_shape(k, **old[k])
+
+
 def test_gradient_descent_20_steps(api):
     """20 gradient-descent steps on L = sum (I - I_t)^2 / sum I_t^2 (65,536 atoms) with
     Armijo backtracking: the loss decreases at every step."""

@@ -16,12 +16,12 @@ def api():
 
 
 def test_plan_matches_one_shot_bitwise(api):
-    """With the lattice form off, a plan runs the one-shot call's kernels on the same
-    work lists: identical results."""
+    """With the general form only (lattice 2: rows and lattices ignored), a plan runs the
+    one-shot call's kernels on the same work lists: identical results."""
     from _gpu import dev, host, bitwise_equal
     old = [api.get_tile_shape(k) for k in (0, 1)]
     for k in (0, 1):
-        api.set_tile_shape(k, **dict(old[k], lattice=0))
+        api.set_tile_shape(k, **dict(old[k], lattice=2))
     try:
         _plan_vs_one_shot(api)
     finally:

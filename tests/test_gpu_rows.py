@@ -1,0 +1,137 @@
+"""Row form of the per-pair sums: detectors stored row by row (every run of n2
+consecutive pixels shares q_y exactly: planar grids and Ewald-sphere detectors).  The
+forward evaluates every pair's sine and cosine with the q_y part of the phase formed once
+per (lane, atom); the adjoint takes its 64-pixel groups along a row (dq_y = 0).  Checked
+against the oracle on whole and ragged detectors, in uneven batches next to sets without
+rows, and against the general form (lattice = 2: rows ignored)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2204_13241_amd import inputs as X
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2204_13241_amd import api
+    return api
+
+
+@pytest.fixture
+def shapes(api):
+    old = [api.get_tile_shape(0), api.get_tile_shape(1)]
+    yield
+    for k in (0, 1):
+        api.set_tile_shape(k, **old[k])
+
+
+def _system(n_atoms, seed, frames=1):
+    rng = np.random.default_rng(seed)
+    L = X.box_for(n_atoms)
+    r = X.uniform_positions(rng, n_atoms * frames, L).reshape(frames, n_atoms, 3)
+    f = np.where(rng.random(n_atoms) < 0.2, 2.5, 1.0)
+    return r, f, L
+
+
+def _planar_ragged(n1, n2, qlim):
+    # rows of n2 pixels at their own q_y, q_x uneven along the row, q_z = 0
+    x = np.sort(np.random.default_rng(n1 * 1000 + n2).uniform(-qlim, qlim, n2))
+    y = np.linspace(-0.9 * qlim, 0.8 * qlim, n1)
+    q = np.zeros((n1 * n2, 3))
+    q[:, 0] = np.tile(x, n1)
+    q[:, 1] = np.repeat(y, n2)
+    return q
+
+
+def _run(api, systems, fwd_shape, grad_shape):
+    """Plan over systems [(r [F, N, 3], f, q, L)]: I, amp and the FP64 gradient of
+    sum_p w_p I_p for seeded w, with the plan's description."""
+    from _gpu import dev, host
+    api.set_tile_shape(0, **fwd_shape)
+    api.set_tile_shape(1, **grad_shape)
+    plan = api.Plan([(r.shape[1], r.shape[0], dev(q), L) for r, f, q, L in systems])
+    pos = dev(np.concatenate([r.reshape(-1, 3) for r, _, _, _ in systems]))
+    f = dev(np.concatenate([f for _, f, _, _ in systems]))
+    I, amp = plan.intensity(pos, f)
+    w = np.random.default_rng(99).standard_normal(plan.total_out)
+    g = plan.grad(pos, f, amp, dev(w), retile=False,
+                  g64=torch.empty((plan.total_pos, 3), dtype=torch.float64, device="cuda:0"))
+    torch.cuda.synchronize()
+    info = plan.describe()
+    out = (host(I).copy(), host(amp).copy(), host(g).copy(), w, plan.batch.out_off, plan.batch.pos_off)
+    plan.close()
+    return out, info
+
+
+def _check(systems, res):
+    from _gpu import grad_err
+    I, amp, g, w, off, poff = res
+    e_I, e_g = 0.0, 0.0
+    for i, (r, f, q, L) in enumerate(systems):
+        Q = q.shape[0]
+        for t in range(r.shape[0]):
+            Ir, ar = oracle.intensity(r[t], f, q)
+            o = off[i] + t * Q
+            inc = float(np.sum(f * f))
+            e_I = max(e_I, float(np.max(np.abs(I[o:o + Q] - Ir) / np.maximum(Ir, inc))))
+            gr = oracle.intensity_grad(r[t], f, q, ar, w[o:o + Q])
+            po = poff[i] + t * r.shape[1]
+            e_g = max(e_g, grad_err(g[po:po + r.shape[1]], gr))
+    return e_I, e_g
+
+
+FWD = [dict(atoms_per_tile=64, q_per_lane=ql, atom_split=sp, pixel_split=0, waves_per_simd=occ, lattice=0)
+       for ql, occ, sp in ((1, 0, 4), (2, 4, 8), (4, 0, 16), (8, 0, 64))]
+GRAD = [dict(atoms_per_tile=64, q_per_lane=al, atom_split=128, pixel_split=pc, waves_per_simd=occ, lattice=0)
+        for al, occ, pc in ((2, 5, 1024), (4, 0, 2048))]
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_rows_against_oracle(api, shapes, k):
+    """Planar grid (q_z = 0, rows of 128), ragged planar rows (40 x 75: no 64-pixel groups, the
+    adjoint keeps the sorted order), Ewald detector 64 x 64 (curved rows) with 3 frames."""
+    r0, f0, L0 = _system(900, 10 + k)
+    r1, f1, L1 = _system(700, 20 + k)
+    r2, f2, L2 = _system(1200, 30 + k, frames=3)
+    systems = [(r0, f0, X.planar_grid(128, 2.5)[: 128 * 48], L0),
+               (r1, f1, _planar_ragged(40, 75, 2.0), L1),
+               (r2, f2, X.ewald_detector(64, 1.5), L2)]
+    print("rows k=%d: fwd %s grad %s" % (k, FWD[k], GRAD[k % 2]), flush=True)
+    res, info = _run(api, systems, FWD[k], GRAD[k % 2])
+    e_I, e_g = _check(systems, res)
+    print("rows k=%d: e_I %.2e  e_grad %.2e  %s" % (k, e_I, e_g, info), flush=True)
+    assert info["n_row_segments"] == 5 and info["n_lattice_segments"] == 0
+    assert e_I <= TOL and e_g <= TOL, (e_I, e_g)
+
+
+def test_rows_next_to_sets_without_rows(api, shapes):
+    """An uneven batch: a row set, a set of random q (general form) and a one-tile system."""
+    rng = np.random.default_rng(5)
+    r0, f0, L0 = _system(1500, 41)
+    r1, f1, L1 = _system(800, 42)
+    r2, f2, L2 = _system(40, 43)
+    q1 = rng.uniform(-2.0, 2.0, (3000, 3))
+    systems = [(r0, f0, X.ewald_detector(64, 1.5), L0), (r1, f1, q1, L1), (r2, f2, X.planar_grid(64, 3.0), L2)]
+    res, info = _run(api, systems, FWD[3], GRAD[0])
+    e_I, e_g = _check(systems, res)
+    print("rows batch: e_I %.2e  e_grad %.2e  %s" % (e_I, e_g, info), flush=True)
+    assert info["n_row_segments"] == 2
+    assert e_I <= TOL and e_g <= TOL, (e_I, e_g)
+
+
+def test_rows_and_general_form_agree(api, shapes):
+    """The same Ewald system through the row form (lattice 0) and the general form
+    (lattice 2): both within the tolerance of each other and of the oracle."""
+    r, f, L = _system(2000, 51)
+    systems = [(r, f, X.ewald_detector(128, 1.5), L)]
+    res0, info0 = _run(api, systems, FWD[3], GRAD[0])
+    res2, info2 = _run(api, systems, dict(FWD[3], lattice=2), dict(GRAD[0], lattice=2))
+    assert info0["n_row_segments"] == 1 and info2["n_row_segments"] == 0
+    e0 = _check(systems, res0)
+    e2 = _check(systems, res2)
+    print("rows vs general: rows %s general %s" % (e0, e2), flush=True)
+    assert max(e0) <= TOL and max(e2) <= TOL

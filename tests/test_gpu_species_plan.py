@@ -27,12 +27,13 @@ def _scaled(I, I_ref, sp, q):
 
 
 def test_species_plan_matches_one_shot_bitwise(api):
-    """With the lattice form off, the plan runs the one-shot call's kernels on the same
+    """With the general form only (lattice 2: rows and lattices ignored), the plan runs the
+    one-shot call's kernels on the same
     species segments: identical intensities, amplitudes and gradients."""
     from _gpu import dev, host
     old = [api.get_tile_shape(k) for k in (0, 1)]
     for k in (0, 1):
-        api.set_tile_shape(k, **dict(old[k], lattice=0))
+        api.set_tile_shape(k, **dict(old[k], lattice=2))
     try:
         rng = np.random.default_rng(21)
         N, L = 3000, 40.0
