@@ -53,7 +53,7 @@ def alu_peak(n_valu, n_trans, mfma_flops=0.0):
     return CUS * CLOCK / (n_valu / VALU_LANES + n_trans / TRANS_LANES + mfma_flops / f16_per_cu_clk)
 
 
-def pair_mix(kernel, lattice, ql, qz_zero):
+def pair_mix(kernel, lattice, ql, qz_zero, rows=False):
     """Per-pair work (FP32 VALU, transcendental, FP16 matrix flops) of the inner loops.
     forward, general: 2 FMA phase (3 with dq_z), sin + cos, 2 FMA accumulate.
     forward, lattice run of QL pixels: per atom 2 FMA phase (3 with dq_z) + sin + cos
@@ -63,7 +63,10 @@ def pair_mix(kernel, lattice, ql, qz_zero):
     pixels; per (atom, pixel column) of a block the G factor (~20 VALU + sin + cos, shared
     by 128 pixels); per tile and pixel the FP64 fold (3 ops / 64 atoms); 12 matrix
     instructions of 32x32x16 per 16 atoms and 32x32 pixels = 24 flops per pair.
+    forward, row form (lane's QL pixels in one detector row): fma(dq_y, d_y, beta) once per
+    (lane, atom), then per pair 1 FMA phase (2 with dq_z), sin + cos, 2 FMA accumulate.
     adjoint, general: add + 2 FMA phase (3 with dq_z), sin, 2 FMA (3 with W_z).
+    adjoint, row groups (dq_y = 0): add + 1 FMA phase (2 with dq_z), sin, 2 FMA (3 with W_z).
     adjoint, lattice: FMA + add phase, sin, 2 FMA (3 with W_z).
     adjoint, matrix-core lattice (runs of 32): per (run, atom) add + 2 FMA phase (3 with
     dq_z), sin + cos and 2 FMA per component (2 components at q_z = 0, else 3), shared by
@@ -76,12 +79,16 @@ def pair_mix(kernel, lattice, ql, qz_zero):
             return (1 + ph + 10) / 32 + 20 / 128 + 3 / 64, 2 / 32 + 2 / 128, 24.0
         if lattice:
             return (ph + 2 + 4 * (ql - 1)) / ql, 2.0 / ql, 0.0
+        if rows:
+            return (ph - 1) + 1.0 / ql + 2, 2.0, 0.0
         return ph + 2, 2.0, 0.0
     acc = 2 if qz_zero else 3
     if lattice and ql == 32:
         return (1 + (2 if qz_zero else 3) + 2 * acc) / 32 + 20 / 128, 2 / 32 + 2 / 128, 24.0 * acc
     if lattice:
         return 2 + acc, 1.0, 0.0
+    if rows:
+        return 1 + (1 if qz_zero else 2) + acc, 1.0, 0.0
     return 1 + (2 if qz_zero else 3) + acc, 1.0, 0.0
 
 
@@ -272,6 +279,7 @@ def run_grad(args, form="per-pair"):
 
     info = plan.describe()
     lattice = info["n_segments"] > 0 and info["n_lattice_segments"] == info["n_segments"]
+    rows = info["n_segments"] > 0 and info.get("n_row_segments", 0) == info["n_segments"]
     qz_zero = bool(np.all(q_np[:, 2] == 0.0))
     src = os.path.join(ROOT, "paper_2204_13241_amd", "csrc", "k_fp32c.hip")
     kern = {}
@@ -280,13 +288,14 @@ def run_grad(args, form="per-pair"):
         work = rec["work"] / max(rec["launches"], 1)
         ach = work / (avg_ms * 1e-3) / 1e9
         ql = max(2, shapes[kind]["q_per_lane"]) if lattice else shapes[kind]["q_per_lane"]
-        n_valu, n_trans, n_mfma = pair_mix(name, lattice, ql, qz_zero)
+        n_valu, n_trans, n_mfma = pair_mix(name, lattice, ql, qz_zero, rows)
         peak = alu_peak(n_valu, n_trans, n_mfma) / 1e9
         # transcendental-issue bound: the unit a per-pair kernel saturates (one v_sin +
         # one v_cos per forward pair, one v_sin per adjoint pair)
         trans_peak = PEAK_TRANS / n_trans / 1e9
         kern[name] = {"avg_ms": avg_ms, "launches": rec["launches"], "pairs_per_launch": work,
-                      "form": ("lattice-mfma" if lattice and ql == 32 else "lattice") if lattice else "per-pair",
+                      "form": (("lattice-mfma" if ql == 32 else "lattice") if lattice
+                               else ("per-pair rows" if rows else "per-pair general")),
                       "valu_per_pair": n_valu, "trans_per_pair": n_trans, "f16_mfma_flops_per_pair": n_mfma,
                       "achieved_Gpair_s": ach,
                       "trans_peak_Gpair_s": trans_peak, "frac_of_trans_peak": ach / trans_peak,
@@ -619,7 +628,8 @@ def run_trajectory(args):
                        "(q_max 1.5)", "pairs": F * N * Q, "forward_ms": ms,
            "forward_Gpair_s": F * N * Q / (ms * 1e-3) / 1e9,
            "frac_of_sincos_pair_peak": F * N * Q / (ms * 1e-3) / PEAK_SINCOS_PAIRS,
-           "form": "per-pair (Ewald rows are not a lattice)", "tile_shape_fwd": api.get_tile_shape(0),
+           "form": "per-pair rows" if desc.get("n_row_segments", 0) == desc["n_segments"] else "per-pair general",
+           "tile_shape_fwd": api.get_tile_shape(0),
            "plan": desc, "e_I_scaled_all_frames_vs_fp64": e,
            "e_g2_vs_fp64": e_g2, "g2_rings": int(g2.shape[0]), "g2_n_tau": int(g2.shape[1]),
            "fp64_forward_ms": ms64, "speedup_vs_fp64_form": ms64 / ms}
@@ -810,18 +820,29 @@ def run_fft(args):
     q_block = hkl3 * (2 * math.pi / L)
     out = {"workload": "4000 uniform atoms in a 59.19 A box (Table 1 shape), eta 0.1485 A, k %d" % k,
            "fft_n_grid": n, "fft_ms_per_frame": ms_fft}
+    old_shape = api.get_tile_shape(0)
     for name, qn in (("slice_81x81", q_slice), ("block_81x81x81", q_block)):
         qt = torch.as_tensor(qn, dtype=torch.float64, device=dev)
-        plan = api.Plan.single(N, 1, qt, L)
-        ms32 = timed(lambda: plan.intensity(pos, f, want_amp=False))
-        plan.close()
+        # a few forward shapes (small pixel sets need small items to fill the GPU); the best
+        best = None
+        for ql, split in ((1, 2), (1, 8), (2, 8), (4, 16), (8, 16), (8, 64)):
+            api.set_tile_shape(0, 64, ql, split, 0, 0, 0)
+            plan = api.Plan.single(N, 1, qt, L)
+            ms = timed(lambda: plan.intensity(pos, f, want_amp=False))
+            plan.close()
+            if best is None or ms < best[0]:
+                best = (ms, ql, split)
+        api.set_tile_shape(0, **old_shape)
+        ms32 = best[0]
         api.timing_enable(True)
         api.intensity(pos, f, qt, "fp64")
         torch.cuda.synchronize()
         ms64 = api.timing_read("fwd64")["ms"]
         api.timing_enable(False)
         out[name] = {"pixels": int(qn.shape[0]), "direct_fp32c_ms": ms32, "direct_fp64_ms": ms64,
-                     "direct_fp32c_Gpair_s": N * qn.shape[0] / (ms32 * 1e-3) / 1e9}
+                     "direct_fp32c_Gpair_s": N * qn.shape[0] / (ms32 * 1e-3) / 1e9,
+                     "direct_fp32c_shape": {"q_per_lane": best[1], "atom_split": best[2]},
+                     "note": "plan call: binning, pair sum and combine"}
     # accuracy of the FFT method on the 81^3 block against the exact FP64 form
     qt = torch.as_tensor(q_block, dtype=torch.float64, device=dev)
     I64 = api.intensity(pos, f, qt, "fp64").cpu().numpy()
