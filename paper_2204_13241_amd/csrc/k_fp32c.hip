@@ -49,6 +49,12 @@ constexpr int kLatRows = kBlock / kLatRuns;         // lattice item: rows (32)
 constexpr double kLatTol = 1e-11;                   // lattice test: |q_p - model| bound, 1 / Angstrom
 constexpr int kFwdCounters = 3;                     // work-queue counters of the forward forms
 constexpr int kRotTiles = 2;                        // tiles sharing one origin and one rotation (forward)
+// Items with a wavevector of |q| / (2 pi) below this (revolutions per Angstrom, i.e. |q| < 0.5
+// per Angstrom) fold their FP32 sums into FP64 after every tile instead of every pair of
+// tiles.  At small |q| the phases inside a tile vary little, so a tile's FP32 sum is nearly
+// coherent (a sizable fraction of its atom count) while the amplitude left after the tiles
+// cancel is small; the rounding of those long coherent FP32 sums then dominates the error.
+constexpr double kSmallQRev = 0.08;
 
 // ---------------------------------------------------------------- tables
 
@@ -566,6 +572,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
         __syncthreads();
         double cen[3];
         bool planar;
+        bool fold_each;  // fold the FP32 sums after every tile (small |q|)
         {
             double l3[3], h3[3];
             for (int c = 0; c < 3; ++c) {
@@ -578,6 +585,12 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
                 cen[c] = 0.5 * (l3[c] + h3[c]);
             }
             planar = l3[2] == h3[2];  // dq_z = 0 for every pixel of the item
+            double qn2 = 0.0;  // squared distance of the item's q box from q = 0
+            for (int c = 0; c < 3; ++c) {
+                const double m = (l3[c] <= 0.0 && h3[c] >= 0.0) ? 0.0 : fmin(fabs(l3[c]), fabs(h3[c]));
+                qn2 = __builtin_fma(m, m, qn2);
+            }
+            fold_each = qn2 < kSmallQRev * kSmallQRev;
         }
         float dqx[QL], dqy[QL], dqz[QL];
         double re64[QL], im64[QL];
@@ -647,23 +660,27 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_fp32c(
             }
             const int tiles_here = min(kWaves, item.nt - g * kWaves);
             for (int w0 = 0; w0 < tiles_here; w0 += kRotTiles) {
+                const int w1 = min(w0 + kRotTiles, tiles_here);
+                const double4 o = s_orig[buf][w0 / kRotTiles];
                 float cs[QL], sn[QL];
+                for (int w = w0; w < w1; ++w) {
+                    if (w == w0 || fold_each) {
 #pragma unroll
-                for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
-                for (int w = w0; w < min(w0 + kRotTiles, tiles_here); ++w) {
+                        for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
+                    }
                     const float4 *at = &s_atoms[buf][w * kTile];
                     const float *bt = &s_beta[buf][w * kTile];
                     if (planar) tile_pairs<QL, true>(at, bt, dqx, dqy, dqz, cs, sn);
                     else tile_pairs<QL, false>(at, bt, dqx, dqy, dqz, cs, sn);
-                }
-                const double4 o = s_orig[buf][w0 / kRotTiles];
+                    if (w + 1 < w1 && !fold_each) continue;
 #pragma unroll
-                for (int k = 0; k < QL; ++k) {
-                    const float th = frac_f32(__builtin_fma(s_q[2][k][tid], o.z,
-                                              __builtin_fma(s_q[1][k][tid], o.y, s_q[0][k][tid] * o.x)));
-                    const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
-                    re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
-                    im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
+                    for (int k = 0; k < QL; ++k) {
+                        const float th = frac_f32(__builtin_fma(s_q[2][k][tid], o.z,
+                                                  __builtin_fma(s_q[1][k][tid], o.y, s_q[0][k][tid] * o.x)));
+                        const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
+                        re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
+                        im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
+                    }
                 }
             }
             if (have_next) {
@@ -771,6 +788,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_rows(
         __syncthreads();
         double cen[3];
         bool flat;
+        bool fold_each;  // fold the FP32 sums after every tile (small |q|)
         {
             double l3[3], h3[3];
             for (int c = 0; c < 3; ++c) {
@@ -783,6 +801,12 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_rows(
                 cen[c] = 0.5 * (l3[c] + h3[c]);
             }
             flat = l3[2] == h3[2];  // dq_z = 0 for every pixel of the item
+            double qn2 = 0.0;  // squared distance of the item's q box from q = 0
+            for (int c = 0; c < 3; ++c) {
+                const double m = (l3[c] <= 0.0 && h3[c] >= 0.0) ? 0.0 : fmin(fabs(l3[c]), fabs(h3[c]));
+                qn2 = __builtin_fma(m, m, qn2);
+            }
+            fold_each = qn2 < kSmallQRev * kSmallQRev;
         }
         const float dqy = static_cast<float>(qy - cen[1]);
         float dqx[QL], dqz[QL];
@@ -845,24 +869,28 @@ __global__ __launch_bounds__(kBlock, OCC) void k_forward_rows(
             }
             const int tiles_here = min(kWaves, item.nt - g * kWaves);
             for (int w0 = 0; w0 < tiles_here; w0 += kRotTiles) {
+                const int w1 = min(w0 + kRotTiles, tiles_here);
+                const double4 o = s_orig[buf][w0 / kRotTiles];
                 float cs[QL], sn[QL];
+                for (int w = w0; w < w1; ++w) {
+                    if (w == w0 || fold_each) {
 #pragma unroll
-                for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
-                for (int w = w0; w < min(w0 + kRotTiles, tiles_here); ++w) {
+                        for (int k = 0; k < QL; ++k) cs[k] = sn[k] = 0.f;
+                    }
                     const float4 *at = &s_atoms[buf][w * kTile];
                     const float *bt = &s_beta[buf][w * kTile];
                     if (flat) row_pairs<QL, true>(at, bt, dqy, dqx, dqz, cs, sn);
                     else row_pairs<QL, false>(at, bt, dqy, dqx, dqz, cs, sn);
-                }
-                const double4 o = s_orig[buf][w0 / kRotTiles];
-                const double yo = qy * o.y;
+                    if (w + 1 < w1 && !fold_each) continue;
+                    const double yo = qy * o.y;
 #pragma unroll
-                for (int k = 0; k < QL; ++k) {
-                    const float th =
-                        frac_f32(__builtin_fma(s_q[1][k][tid], o.z, __builtin_fma(s_q[0][k][tid], o.x, yo)));
-                    const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
-                    re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
-                    im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
+                    for (int k = 0; k < QL; ++k) {
+                        const float th =
+                            frac_f32(__builtin_fma(s_q[1][k][tid], o.z, __builtin_fma(s_q[0][k][tid], o.x, yo)));
+                        const float ct = __builtin_amdgcn_cosf(th), st = __builtin_amdgcn_sinf(th);
+                        re64[k] += static_cast<double>(__builtin_fmaf(ct, cs[k], -st * sn[k]));
+                        im64[k] += static_cast<double>(__builtin_fmaf(st, cs[k], ct * sn[k]));
+                    }
                 }
             }
             if (have_next) {

@@ -34,6 +34,12 @@ GRAD_CANDIDATES = ([(al, occ, pc)
                    + [(32, 0, split) for split in (32, 64, 128, 256)])
 
 
+def candidates(cands, lattice: int) -> list:
+    """The search space for a lattice setting: with lattice 0 the matrix-core shapes
+    (32 per lane, factorized forms) are left out, so only per-pair kernels are timed."""
+    return [tuple(c) for c in cands if lattice or c[0] != 32]
+
+
 def _cache_path() -> str:
     p = os.environ.get("XS_TUNE_CACHE")
     if p:
@@ -137,8 +143,8 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
     qz = torch.cat([q[:, 2] for _, _, q, _ in systems])
     planar = bool((qz == qz[0]).all().item()) if qz.numel() else True
     key = signature(systems, planar, lattice)
-    fwd_candidates = [c for c in (fwd_candidates or FWD_CANDIDATES) if lattice or c[0] != 32]
-    grad_candidates = [c for c in (grad_candidates or GRAD_CANDIDATES) if lattice or c[0] != 32]
+    fwd_candidates = candidates(fwd_candidates or FWD_CANDIDATES, lattice)
+    grad_candidates = candidates(grad_candidates or GRAD_CANDIDATES, lattice)
     path = _cache_path()
     cache = _load_cache(path) if use_cache else {}
     if use_cache and key in cache:

@@ -57,3 +57,10 @@ def test_search_times_the_installed_shape_twice_and_keeps_the_better():
     times = tune._search(cands, (8, 4, 64), timer)
     assert calls == [(8, 4, 64), (1, 0, 16), (2, 0, 16), (8, 4, 64)]
     assert times[(8, 4, 64)] == 0.99 and times[(1, 0, 16)] == 1.05
+
+
+def test_per_pair_search_leaves_out_the_factorized_shapes():
+    f0, g0 = tune.candidates(tune.FWD_CANDIDATES, 0), tune.candidates(tune.GRAD_CANDIDATES, 0)
+    assert f0 and g0 and all(c[0] in (1, 2, 4, 8) for c in f0 + g0)
+    assert (32, 0, 64) in tune.candidates(tune.FWD_CANDIDATES, 1)
+    assert len(tune.candidates(tune.GRAD_CANDIDATES, 1)) == len(tune.GRAD_CANDIDATES)
