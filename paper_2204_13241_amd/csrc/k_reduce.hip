@@ -610,6 +610,81 @@ __global__ __launch_bounds__(kBlock) void k_siegert(const double *__restrict__ g
 
 // ---------------------------------------------------------------- XSVS
 
+// Launch order of the gathering XSVS blocks.  A block group (kLvChunksPerBlock
+// chunks of one ring, kLvSpan ring rows) starts at the pixel whose position in
+// its ring's list is a multiple of kLvSpan; order[] lists the groups by that
+// pixel's index, so that the groups of neighbouring rings over the same detector
+// rows come next to each other (their rows share cache lines).
+constexpr int32_t kLvSpan = kLvChunksPerBlock * kLvRows;
+
+__device__ __forceinline__ int32_t group_started_at(int64_t p, const int32_t *__restrict__ key,
+                                                    const int32_t *__restrict__ rank, const int32_t *start_s,
+                                                    const int32_t *grp_s) {
+    const int32_t r = key[p];
+    if (r < 0) return -1;
+    const int32_t j = rank[p] - start_s[r];
+    return j % kLvSpan == 0 ? grp_s[r] + j / kLvSpan : -1;
+}
+
+// cnt[b] = groups starting in pixel block b (kPartChunk pixels).
+__global__ __launch_bounds__(kBlock) void k_group_count(const int32_t *__restrict__ key,
+                                                        const int32_t *__restrict__ rank, int64_t n_q, int32_t R,
+                                                        const int32_t *__restrict__ ring_start,
+                                                        const int32_t *__restrict__ grp_off,
+                                                        int32_t *__restrict__ cnt) {
+    __shared__ int32_t start_s[kMaxRings + 1], grp_s[kMaxRings + 1], wsum[kBlock / 64];
+    for (int i = threadIdx.x; i <= R; i += kBlock) {
+        start_s[i] = ring_start[i];
+        grp_s[i] = grp_off[i];
+    }
+    __syncthreads();
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kPartChunk;
+    int32_t c = 0;
+    for (int i = threadIdx.x; i < kPartChunk; i += kBlock)
+        if (base + i < n_q && group_started_at(base + i, key, rank, start_s, grp_s) >= 0) ++c;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += wsum[w];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+// order[k] = the k-th group in ascending index of its first pixel: block b
+// starts at off[b] (the exclusive scan of the counts) and places its groups in
+// pixel order (one ballot per wave and step).
+__global__ __launch_bounds__(kBlock) void k_group_scatter(const int32_t *__restrict__ key,
+                                                          const int32_t *__restrict__ rank, int64_t n_q, int32_t R,
+                                                          const int32_t *__restrict__ ring_start,
+                                                          const int32_t *__restrict__ grp_off,
+                                                          const int32_t *__restrict__ off_b,
+                                                          int32_t *__restrict__ order) {
+    constexpr int kWaves = kBlock / 64;
+    __shared__ int32_t start_s[kMaxRings + 1], grp_s[kMaxRings + 1], wsum[kWaves];
+    for (int i = threadIdx.x; i <= R; i += kBlock) {
+        start_s[i] = ring_start[i];
+        grp_s[i] = grp_off[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t run = off_b[blockIdx.x];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kPartChunk;
+    for (int st = 0; st < kPartChunk / kBlock; ++st) {
+        const int64_t p = base + st * kBlock + threadIdx.x;
+        const int32_t g = p < n_q ? group_started_at(p, key, rank, start_s, grp_s) : -1;
+        const uint64_t m = __ballot(g >= 0);
+        __syncthreads();  // wsum of the previous step read
+        if (lane == 0) wsum[wave] = __builtin_popcountll(m);
+        __syncthreads();
+        int32_t off = run;
+        for (int w = 0; w < wave; ++w) off += wsum[w];
+        if (g >= 0) order[off + __builtin_popcountll(m & ((uint64_t(1) << lane) - 1))] = g;
+        for (int w = 0; w < kWaves; ++w) run += wsum[w];
+    }
+}
+
 // Windows of base level L (K per row) and the next kLvDepth - 1 levels.
 // Block (block group of kLvChunksPerBlock consecutive 32-row chunks of one
 // ring, 64-window tile k0..).  Each chunk of the ring's rows of the tile's 64
@@ -623,29 +698,48 @@ __global__ __launch_bounds__(kBlock) void k_siegert(const double *__restrict__ g
 // csum[chunk][tile * 256 + t] and [tile * 256 + 128 + t] (the two moments of
 // Eq. (bq_Iq)).  Level L+6 (one window per full tile) also goes to `next`
 // [rank][K >> 6] for the launch that continues from it.
-// kGather: rows gathered from the frames I[k][list[m]] (ld = pixels);
-// otherwise read from a ring-ordered table X[m][k] (ld = K).
+// kGather: rows gathered from the frames I[k][list[m]] (ld = pixels), on a
+// one-dimensional grid: the (tile, group) work items, tile-major with the groups
+// in the order of `order`, are split into eight equal consecutive runs, run x
+// taken by blocks x, x + 8, x + 16, ... (consecutive blocks go to different XCDs,
+// so each XCD walks its run in order and its L2 sees the rows of neighbouring
+// rings together).  Otherwise read from a ring-ordered table X[m][k] (ld = K),
+// grid (group, tile).
 template <bool kGather>
 __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
                                                         const int32_t *__restrict__ list, int32_t R,
                                                         const int32_t *__restrict__ ring_start,
                                                         const int32_t *__restrict__ chunk_off,
-                                                        const int32_t *__restrict__ grp_off, int64_t ncol,
-                                                        double *__restrict__ csum, double *__restrict__ next) {
+                                                        const int32_t *__restrict__ grp_off,
+                                                        const int32_t *__restrict__ order, int64_t n_tiles,
+                                                        int64_t ncol, double *__restrict__ csum,
+                                                        double *__restrict__ next) {
     __shared__ double tile[kLvRows * kLvStride];
     __shared__ int32_t g_s[kMaxRings + 1];
     for (int i = threadIdx.x; i <= R; i += kBlock) g_s[i] = grp_off[i];
     __syncthreads();
-    const int64_t gb = blockIdx.x;
-    if (gb >= g_s[R]) return;  // block-uniform
+    int64_t gb, tile_idx;
+    if (kGather) {
+        const int64_t G = g_s[R], work = G * n_tiles, per = (work + 7) >> 3;
+        const int64_t j = blockIdx.x >> 3;
+        if (j >= per) return;  // block-uniform, as below
+        const int64_t w = static_cast<int64_t>(blockIdx.x & 7) * per + j;
+        if (w >= work) return;
+        tile_idx = w / G;
+        gb = order[w - tile_idx * G];
+    } else {
+        gb = blockIdx.x;
+        tile_idx = blockIdx.y;
+        if (gb >= g_s[R]) return;
+    }
     const int r = ring_of(g_s, R, gb);
-    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kLvTile;
+    const int64_t k0 = tile_idx * kLvTile;
     const int W = static_cast<int>(std::min<int64_t>(kLvTile, K - k0));
     const int32_t a = ring_start[r], b = ring_start[r + 1];
     const int32_t c_first = static_cast<int32_t>((gb - g_s[r]) * kLvChunksPerBlock);
     const int32_t n_chunks_ring = (b - a + kLvRows - 1) / kLvRows;
     const int t = threadIdx.x;
-    const int64_t col = static_cast<int64_t>(blockIdx.y) * kLvCols + t;
+    const int64_t col = tile_idx * kLvCols + t;
     const bool owner = t < kLvHalf - 2;
     const bool want_next = next != nullptr && k0 + kLvTile <= K;
     const int64_t K_next = K >> kLvDepth;
@@ -1191,6 +1285,19 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
     XS_TRY(partition(cached, k, n_q, R, &P));
     const int64_t rows = std::max<int64_t>(n_q, 1);  // bounds the pixels in rings
     const int64_t groups_bound = level_bound(n_q, R, 1) / kLvChunksPerBlock + R + 1;
+    // launch order of the gathering blocks (groups by first pixel)
+    const int64_t nb = (n_q + kPartChunk - 1) / kPartChunk;
+    void *ord = nullptr;
+    XS_TRY(scratch(s, SLOT_XSVS_ORDER, sizeof(int32_t) * (groups_bound + nb + 1), &ord));
+    int32_t *order = static_cast<int32_t *>(ord), *gcnt = order + groups_bound;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_group_count, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, k, P.rank, n_q, R,
+                           P.start, P.grp, gcnt);
+        hipLaunchKernelGGL(k_part_scan_ring, dim3(1), dim3(kBlock), 0, s, gcnt, nb, 1, gcnt + nb);
+        hipLaunchKernelGGL(k_group_scatter, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, k, P.rank, n_q,
+                           R, P.start, P.grp, gcnt, order);
+        XS_HIP(hipGetLastError());
+    }
     const double *src = nullptr;
     // launch groups of kLvDepth levels; a group that does not reach the last
     // level writes the level after its own into a ring-ordered table
@@ -1221,12 +1328,18 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         const int32_t *lev1 = P.lev + (R + 1);
         const int32_t *top_off = P.lev + static_cast<int64_t>(P.levels) * (R + 1);
         // one read of the windows: chunk trees of J and J*J, then the ring trees
-        if (L == 0)
-            hipLaunchKernelGGL(k_xsvs_chunks<true>, grid, dim3(kBlock), 0, s, I, K, n_q,
-                               static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp, ncol, c1, dst);
-        else
+        if (L == 0) {
+            const int64_t blocks = 8 * ((groups_bound * tiles + 7) / 8);
+            if (blocks > 0x7fffffff) return set_error(XS_EINVAL, "XSVS: %lld gathering blocks exceed one grid",
+                                                     static_cast<long long>(blocks));
+            hipLaunchKernelGGL(k_xsvs_chunks<true>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, I, K,
+                               n_q, static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
+                               static_cast<const int32_t *>(order), tiles, ncol, c1, dst);
+        } else {
             hipLaunchKernelGGL(k_xsvs_chunks<false>, grid, dim3(kBlock), 0, s, src, K, K,
-                               static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp, ncol, c1, dst);
+                               static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
+                               static_cast<const int32_t *>(nullptr), tiles, ncol, c1, dst);
+        }
         XS_HIP(hipGetLastError());
         const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);
         hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * (ncol / 2))), dim3(kBlock), 0, s,

@@ -62,6 +62,7 @@ enum Slot {
     SLOT_FFT_SPEC,      // FFT method: its half spectrum
     SLOT_FFT_GAUSS,     // FFT method: half spectrum of the centred Gaussian
     SLOT_FFT_GAUSS2,    // FFT method: its squared modulus
+    SLOT_XSVS_ORDER,    // XSVS: launch order of the gathering blocks
     SLOT_COUNT
 };
 xs_status scratch(hipStream_t stream, Slot slot, size_t bytes, void **ptr);
