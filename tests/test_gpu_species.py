@@ -84,7 +84,7 @@ def test_species_rejects_bad_species(api):
                               precision="fp64")
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 1e-5)])
 def test_species_gradient(api, prec, tol):
     import torch
     from _gpu import dev, host, grad_err
@@ -137,8 +137,16 @@ def test_species_batch_of_systems(api, prec, tol):
             assert _scaled(Ih[None, o:o + qs[i].shape[0]], Ir, sp[i], qs[i]) < tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32c", 3e-5)])
 def test_species_autograd_function(api, prec, tol):
+    """The whole chain: forward in `prec`, loss in torch, adjoint through the Function,
+    against the FP64 chain of the oracle.  In FP32C the forward's own error (~3e-6 of
+    max(I, sum f^2) per pixel) enters dL/dI = 2 (I - I_t) / Z, where I - I_t is about a
+    quarter of I at the median pixel for this target (0.2 A displacements); pushing a
+    random-sign error of that size through the oracle's adjoint alone gives 1.5e-5 on
+    this case, so the chain is held to 3e-5 while the adjoint kernel on an exact
+    amplitude is held to 1e-5 (test_species_gradient).  The gradient must also equal
+    the explicit composition of the same calls (the Function adds no arithmetic)."""
     import torch
     from _gpu import dev, host, grad_err
     pos, sp, q, L = _case(8, 400, 1, 20)
@@ -156,3 +164,8 @@ def test_species_autograd_function(api, prec, tol):
     e = grad_err(host(p.grad), g_ref)
     print("species autograd %s: e_grad %.2e" % (prec, e), flush=True)
     assert e < tol, e
+    I1, amp1 = api.intensity_species(dev(pos[0]), dev(sp, dtype=torch.int32), COEF, dev(q), precision=prec,
+                                     box=L, return_amp=True)
+    g1 = api.intensity_species_grad(dev(pos[0]), dev(sp, dtype=torch.int32), COEF, dev(q), amp1,
+                                    2.0 * (I1 - It_d) / Z, precision=prec, box=L, out_dtype=torch.float64)
+    assert grad_err(host(p.grad), host(g1)) < 1e-12

@@ -107,7 +107,7 @@ def _species_uneven_batch(api, lattice):
             po = poff[i] + t * N[i]
             e_g = max(e_g, grad_err(gh[po: po + N[i]], gr))
     print("species plan lattice=%d: e_I %.2e  e_grad %.2e" % (lattice, e_I, e_g), flush=True)
-    assert e_I < 1e-5 and e_g < 2e-5, (e_I, e_g)
+    assert e_I < 1e-5 and e_g < 1e-5, (e_I, e_g)
     assert (plan.describe()["n_lattice_segments"] >= 1) == bool(lattice)
     plan.close()
 
