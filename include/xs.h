@@ -371,6 +371,8 @@ xs_status xs_shutdown(void);
  *                   keeps its own allocation) 8, and gradient q_per_lane 4;
  *                   5: bounded to 96 VGPRs, built for gradient q_per_lane 2;
  *                   3: bounded to 168 registers, built for forward q_per_lane 32
+ *                   and for the row form at q_per_lane 8 (the general form at 8
+ *                   keeps its own allocation)
  *   lattice         plans only.  0 (default): the per-pair forms, in which every
  *                   atom-pixel pair takes the sine and cosine of its own phase
  *                   (forward) or the sine (adjoint); on pixel sets stored as rows

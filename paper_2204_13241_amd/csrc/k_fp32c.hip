@@ -2696,7 +2696,7 @@ bool launch_rows_variant(hipStream_t s, int ql, int occ, int n, int32_t *cnt, co
     case 1: launch_rows<1, 1>(s, n, cnt, b, q); return true;
     case 2: o4 ? launch_rows<2, 4>(s, n, cnt, b, q) : launch_rows<2, 1>(s, n, cnt, b, q); return true;
     case 4: o4 ? launch_rows<4, 4>(s, n, cnt, b, q) : launch_rows<4, 1>(s, n, cnt, b, q); return true;
-    case 8: launch_rows<8, 1>(s, n, cnt, b, q); return true;
+    case 8: occ == 3 ? launch_rows<8, 3>(s, n, cnt, b, q) : launch_rows<8, 1>(s, n, cnt, b, q); return true;
     default: return false;
     }
 }

@@ -723,8 +723,9 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape) {
     if (shape->waves_per_simd != 0 && shape->waves_per_simd != 3 && shape->waves_per_simd != 4 &&
         shape->waves_per_simd != 5)
         return set_error(XS_EINVAL, "waves_per_simd must be 0, 3, 4 or 5");
-    if (shape->waves_per_simd == 3 && !(kind == 0 && ql == 32))
-        return set_error(XS_ENOTSUP, "the 3-waves-per-SIMD variant is built for the matrix-core forward (q_per_lane 32)");
+    if (shape->waves_per_simd == 3 && !(kind == 0 && (ql == 32 || ql == 8)))
+        return set_error(XS_ENOTSUP, "the 3-waves-per-SIMD variant is built for the forward at q_per_lane 8 (row "
+                                     "form) and 32 (matrix-core form)");
     if (shape->waves_per_simd == 4 && !((kind == 0 && (ql == 2 || ql == 4 || ql == 8)) || (kind == 1 && ql == 4)))
         return set_error(XS_ENOTSUP, "the 4-waves-per-SIMD variant is built for forward q_per_lane 2, 4, 8 "
                                      "and gradient q_per_lane 4");

@@ -23,7 +23,7 @@ from . import api
 # (pixels per lane, waves-per-SIMD bound) x atom tiles per item; 32 pixels per run is
 # the matrix-core lattice form (the general form then runs 8 pixels per lane)
 FWD_CANDIDATES = [(ql, occ, split)
-                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 4), (32, 0), (32, 3))
+                  for ql, occ in ((1, 0), (2, 0), (2, 4), (4, 0), (4, 4), (8, 0), (8, 3), (8, 4), (32, 0), (32, 3))
                   for split in (16, 32, 64, 128)]
 # (atoms per lane, waves-per-SIMD bound) x pixels per item; 32 is the matrix-core
 # lattice form, whose third entry is the atom tiles per item (the other systems of such
@@ -55,7 +55,7 @@ def signature(systems, planar: bool, lattice: int = 1) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v8|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
+    return "v9|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved", "lattice" if lattice else "per-pair")
 

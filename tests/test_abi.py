@@ -87,7 +87,9 @@ def test_tile_shape_roundtrip_and_limits():
     # register-bound variants exist only where they are built
     api.set_tile_shape(0, 64, 32, 32, 0, 3)
     assert api.get_tile_shape(0)["waves_per_simd"] == 3
-    for kind, ql, occ in ((0, 8, 3), (1, 32, 3), (1, 32, 5), (0, 32, 4)):
+    api.set_tile_shape(0, 64, 8, 64, 0, 3)
+    assert api.get_tile_shape(0)["waves_per_simd"] == 3
+    for kind, ql, occ in ((0, 4, 3), (1, 8, 3), (1, 32, 3), (1, 32, 5), (0, 32, 4)):
         with pytest.raises(_lib.XsError):
             api.set_tile_shape(kind, 64, ql, 32, 8192, occ)
     old_g = api.get_tile_shape(1)

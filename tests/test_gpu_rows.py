@@ -85,12 +85,12 @@ def _check(systems, res):
 
 
 FWD = [dict(atoms_per_tile=64, q_per_lane=ql, atom_split=sp, pixel_split=0, waves_per_simd=occ, lattice=0)
-       for ql, occ, sp in ((1, 0, 4), (2, 4, 8), (4, 0, 16), (8, 0, 64))]
+       for ql, occ, sp in ((1, 0, 4), (2, 4, 8), (4, 0, 16), (8, 0, 64), (8, 3, 32))]
 GRAD = [dict(atoms_per_tile=64, q_per_lane=al, atom_split=128, pixel_split=pc, waves_per_simd=occ, lattice=0)
         for al, occ, pc in ((2, 5, 1024), (4, 0, 2048))]
 
 
-@pytest.mark.parametrize("k", range(4))
+@pytest.mark.parametrize("k", range(len(FWD)))
 def test_rows_against_oracle(api, shapes, k):
     """Planar grid (q_z = 0, rows of 128), ragged planar rows (40 x 75: no 64-pixel groups, the
     adjoint keeps the sorted order), Ewald detector 64 x 64 (curved rows) with 3 frames."""
