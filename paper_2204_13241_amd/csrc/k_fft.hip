@@ -135,6 +135,10 @@ xs_status fft_intensity(hipStream_t s, const double *pos, const double *f, int64
                         int32_t n, double eta, int32_t k, double *I, double *amp) {
     const double delta = box / n;
     const int64_t nn = static_cast<int64_t>(n) * n * n;
+    // one spreading thread per (atom, first-axis point, second-axis point) in one grid
+    if (n_atoms > (static_cast<int64_t>(0x7fffffff) * kBlock) / (static_cast<int64_t>(k) * k))
+        return set_error(XS_EINVAL, "%lld atoms x k^2 = %d^2 spreading threads exceed one launch",
+                         static_cast<long long>(n_atoms), k);
     const int64_t nhalf = static_cast<int64_t>(n) * n * (n / 2 + 1);
     void *rho = nullptr, *spec = nullptr, *gspec = nullptr, *g2 = nullptr;
     XS_TRY(scratch(s, SLOT_FFT_RHO, sizeof(double) * nn, &rho));
