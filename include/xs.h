@@ -438,6 +438,15 @@ xs_status xs_set_tile_shape(int32_t kind, const xs_tile_shape *shape);
  */
 typedef struct xs_plan xs_plan;
 xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **plan, void *stream);
+/*
+ * xs_plan_create_forward: the same plan for the forward direct sum only (the
+ * intensities of many frames, as the g2 and XSVS reductions of Secs. 4.4-4.5
+ * consume them).  It leaves out the adjoint's work lists, its per-chunk partial
+ * sums (3 doubles per atom and pixel chunk, the largest buffer of a full plan)
+ * and its pixel prologue buffers; xs_plan_grad on it fails with XS_EINVAL and
+ * launches nothing.  xs_plan_intensity is unchanged, bit for bit.
+ */
+xs_status xs_plan_create_forward(const xs_batch *b, const double *q, xs_plan **plan, void *stream);
 xs_status xs_plan_intensity(xs_plan *plan, const double *pos, const double *f, double *I_out,
                             double *amp_out, void *stream);
 xs_status xs_plan_grad(xs_plan *plan, const double *pos, const double *f, const double *amp,

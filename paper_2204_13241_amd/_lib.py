@@ -22,7 +22,7 @@ EXPORTS = [
     "xs_roofline_probe", "xs_plan_create", "xs_plan_intensity", "xs_plan_grad", "xs_plan_destroy",
     "xs_plan_describe", "xs_isf_rings", "xs_siegert", "xs_intensity_species", "xs_intensity_species_grad",
     "xs_frame_sums", "xs_ring_histogram", "xs_plan_create_species", "xs_plan_intensity_species",
-    "xs_plan_grad_species", "xs_g2_rings_noalloc", "xs_fft_intensity",
+    "xs_plan_grad_species", "xs_g2_rings_noalloc", "xs_fft_intensity", "xs_plan_create_forward",
 ]
 
 _P = ctypes.c_void_p
@@ -115,6 +115,7 @@ def load():
         "xs_timing_read": (i32, [i32, _dp, _i64p, _dp]),
         "xs_roofline_probe": (i32, [i32, i64, _dp, _P]),
         "xs_plan_create": (i32, [bp, _P, ctypes.POINTER(_P), _P]),
+        "xs_plan_create_forward": (i32, [bp, _P, ctypes.POINTER(_P), _P]),
         "xs_plan_intensity": (i32, [_P, _P, _P, _P, _P, _P]),
         "xs_plan_grad": (i32, [_P, _P, _P, _P, _P, i32, _P, _P, _P]),
         "xs_plan_create_species": (i32, [bp, _P, _P, i32, _P, ctypes.POINTER(_P), _P]),

@@ -506,14 +506,16 @@ class Plan:
     Positions, form factors and outputs use the packed layout of make_batch:
     pos [sum_s F_s N_s, 3], f [sum_s N_s], I [sum_s F_s Q_s], amp [.., 2].
     After construction, intensity() and grad() only launch kernels, so they
-    can be captured in a torch.cuda.CUDAGraph and replayed.
+    can be captured in a torch.cuda.CUDAGraph and replayed.  forward_only=True
+    builds the plan without the adjoint's buffers (xs_plan_create_forward);
+    grad() then raises.
     """
 
-    def __init__(self, systems):
+    def __init__(self, systems, forward_only: bool = False):
         self._layout(systems)
         h = ctypes.c_void_p()
-        _lib.check(_lib.load().xs_plan_create(ctypes.byref(self._st), _ptr(self.q), ctypes.byref(h),
-                                              _stream()))
+        create = _lib.load().xs_plan_create_forward if forward_only else _lib.load().xs_plan_create
+        _lib.check(create(ctypes.byref(self._st), _ptr(self.q), ctypes.byref(h), _stream()))
         self._h = h
 
     def _layout(self, systems):
@@ -534,8 +536,8 @@ class Plan:
         self._st = self.batch.struct()
 
     @classmethod
-    def single(cls, n_atoms: int, n_frames: int, q: torch.Tensor, box):
-        return cls([(n_atoms, n_frames, q, box)])
+    def single(cls, n_atoms: int, n_frames: int, q: torch.Tensor, box, forward_only: bool = False):
+        return cls([(n_atoms, n_frames, q, box)], forward_only=forward_only)
 
     def _check(self, pos, f):
         _need(pos, "pos"), _need(f, "f")

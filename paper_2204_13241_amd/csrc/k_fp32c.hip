@@ -2432,6 +2432,21 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         const std::vector<FwdItem> m3 = largest_first(mi[1], mc[1]);
         t.mitems.insert(t.mitems.end(), m3.begin(), m3.end());
     }
+    if (!with_grad) {
+        // forward-only plan: no adjoint work lists, partials or pixel prologue buffers
+        t.gitems = {};
+        t.mitems = {};
+        t.gsub_seg0 = {};
+        t.gsub_seg1 = {};
+        t.gsub_item0 = {};
+        t.gsub_nitem = {};
+        t.gsub_work = {};
+        t.gsub_maxq = {};
+        t.gsub_lat = {};
+        t.mcount2 = 0;
+        t.mwork = 0.0;
+        t.gpart = 0;
+    }
     // radix-sort workspace for the pixel order
     if (t.slots > 0) {
         size_t bytes = 0;
@@ -2489,10 +2504,11 @@ size_t Plan::layout(char *base) {
     b.sort_tmp = take(t.sort_tmp);
     b.fpart = reinterpret_cast<double2 *>(take(sizeof(double2) * t.fpart));
     b.gpart = reinterpret_cast<double *>(take(sizeof(double) * 3 * t.gpart));
-    b.pdq = reinterpret_cast<float4 *>(take(sizeof(float4) * t.slots));
-    b.pw = reinterpret_cast<float4 *>(take(sizeof(float4) * t.slots));
-    b.pq64 = reinterpret_cast<double4 *>(take(sizeof(double4) * t.slots));
-    b.centre = reinterpret_cast<double4 *>(take(sizeof(double4) * t.groups));
+    const int64_t gslots = with_grad ? t.slots : 0, ggroups = with_grad ? t.groups : 0;
+    b.pdq = reinterpret_cast<float4 *>(take(sizeof(float4) * gslots));
+    b.pw = reinterpret_cast<float4 *>(take(sizeof(float4) * gslots));
+    b.pq64 = reinterpret_cast<double4 *>(take(sizeof(double4) * gslots));
+    b.centre = reinterpret_cast<double4 *>(take(sizeof(double4) * ggroups));
     return off;
 }
 
@@ -2748,6 +2764,7 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
 
 xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const double *amp,
                      const double *dL_dI, float *g32, double *g64) {
+    if (!with_grad) return set_error(XS_EINVAL, "the plan was created for the forward only");
     Tables &t = *T;
     Buffers &b = *B;
     for (size_t k = 0; k < t.gsub_seg0.size(); ++k) {
@@ -2795,6 +2812,7 @@ xs_status fp32c_forward(hipStream_t s, const Segment *segs, int n_segs, const do
                         double *amp, const xs_tile_shape &fsh, const xs_tile_shape &gsh) {
     if (n_segs <= 0) return XS_OK;
     Plan p;
+    p.with_grad = false;
     XS_TRY(p.build(segs, n_segs, box, fsh, gsh));
     XS_TRY(p.allocate(s, false));
     XS_TRY(p.sort_pixels(s, q));

@@ -536,8 +536,10 @@ xs_status xs_roofline_probe(int32_t kind, int64_t bytes, double *rate, void *str
 namespace {
 // Work lists, buffers and pixel order of an FP32C pair-sum plan over `segs`.
 xs_status build_pair_plan(hipStream_t s, xs::Plan &plan, const std::vector<Segment> &segs, const double *box,
-                          const double *q, const xs_tile_shape &fsh, const xs_tile_shape &gsh) {
+                          const double *q, const xs_tile_shape &fsh, const xs_tile_shape &gsh,
+                          bool with_grad = true) {
     const int n = static_cast<int>(segs.size());
+    plan.with_grad = with_grad;
     XS_TRY(plan.find_lattices(s, segs.data(), n, q));
     XS_TRY(plan.build(segs.data(), n, box, fsh, gsh));
     XS_TRY(plan.allocate(s, true));
@@ -557,7 +559,8 @@ struct xs_plan {
     }
 };
 
-xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void *stream) {
+namespace {
+xs_status plan_create(const xs_batch *b, const double *q, xs_plan **out, void *stream, bool with_grad) {
     XS_TRY(begin(stream));
     if (!out) return set_error(XS_EINVAL, "plan output pointer is NULL");
     *out = nullptr;
@@ -575,7 +578,7 @@ xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void
     auto *p = new (std::nothrow) xs_plan();
     if (!p) return set_error(XS_ENOMEM, "plan: host allocation failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    xs_status st = build_pair_plan(s, p->plan, segs, b->box, q, fsh, gsh);
+    xs_status st = build_pair_plan(s, p->plan, segs, b->box, q, fsh, gsh, with_grad);
     if (st != XS_OK) {
         delete p;
         return st;
@@ -588,6 +591,15 @@ xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void
     }
     *out = p;
     return XS_OK;
+}
+}  // namespace
+
+xs_status xs_plan_create(const xs_batch *b, const double *q, xs_plan **out, void *stream) {
+    return plan_create(b, q, out, stream, true);
+}
+
+xs_status xs_plan_create_forward(const xs_batch *b, const double *q, xs_plan **out, void *stream) {
+    return plan_create(b, q, out, stream, false);
 }
 
 xs_status xs_plan_create_species(const xs_batch *b, const double *q, const int32_t *species, int32_t n_species,
@@ -645,6 +657,7 @@ xs_status xs_plan_grad(xs_plan *p, const double *pos, const double *f, const dou
     XS_TRY(begin(stream));
     if (!p) return set_error(XS_EINVAL, "plan is NULL");
     if (p->species) return set_error(XS_EINVAL, "species plan: use xs_plan_grad_species");
+    if (!p->plan.with_grad) return set_error(XS_EINVAL, "the plan was created for the forward only");
     if (p->total_pos > 0 && !dL_dr && !dL_dr64) return set_error(XS_EINVAL, "both dL_dr and dL_dr64 are NULL");
     if (p->total_out > 0 && (!amp || !dL_dI)) return set_error(XS_EINVAL, "amp / dL_dI is NULL");
     if (!retile && !p->plan.tiled)

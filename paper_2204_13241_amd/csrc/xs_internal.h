@@ -128,6 +128,7 @@ public:
     void *owned_block = nullptr;
     size_t device_bytes = 0;
     bool tiled = false;        // tile_atoms has been enqueued at least once
+    bool with_grad = true;     // set before build(): false leaves out the adjoint's lists and buffers
     int n_seg = 0;
     xs_tile_shape fshape{}, gshape{};
 };

@@ -69,6 +69,38 @@ def test_plan_uneven_batch_against_oracle(api):
     plan.close()
 
 
+def test_forward_only_plan(api):
+    """A forward-only plan (xs_plan_create_forward) over an uneven multi-frame batch gives the
+    full plan's intensities and amplitudes bit for bit from less device memory; its grad()
+    raises before launching anything."""
+    from _gpu import dev, host, bitwise_equal
+    from paper_2204_13241_amd import _lib
+    rng = np.random.default_rng(17)
+    systems, pos_list, f_list = [], [], []
+    for k, (n, nf, n_det) in enumerate(((3000, 3, 48), (700, 1, 24), (1500, 2, 32))):
+        L = X.box_for(n)
+        q = X.ewald_detector(n_det, 1.5) if k != 1 else X.planar_grid(n_det, 2.0)
+        systems.append((n, nf, dev(q), L))
+        pos_list.append(X.uniform_positions(rng, n * nf, L))
+        f_list.append(np.where(rng.random(n) < 0.2, 2.5, 1.0))
+    pos, f = dev(np.concatenate(pos_list)), dev(np.concatenate(f_list))
+    full = api.Plan(systems)
+    fwd = api.Plan(systems, forward_only=True)
+    I1, a1 = full.intensity(pos, f)
+    I2, a2 = fwd.intensity(pos, f)
+    torch.cuda.synchronize()
+    d_full, d_fwd = full.describe(), fwd.describe()
+    print("forward-only plan: %d bytes (full plan %d)" % (d_fwd["device_bytes"], d_full["device_bytes"]),
+          flush=True)
+    assert bitwise_equal(host(I1), host(I2)) and bitwise_equal(host(a1).ravel(), host(a2).ravel())
+    assert d_fwd["device_bytes"] < d_full["device_bytes"]
+    assert d_fwd["n_gradient_items"] == 0 and d_full["n_gradient_items"] > 0
+    with pytest.raises(_lib.XsError):
+        fwd.grad(pos, f, a2, dev(np.ones(full.total_out)), retile=True)
+    full.close()
+    fwd.close()
+
+
 def test_plan_graph_replay(api):
     """Capture forward + adjoint in a HIP graph; every replay equals the eager result."""
     from _gpu import dev, host
