@@ -320,22 +320,22 @@ __global__ __launch_bounds__(kBlock) void k_part_rank(const int32_t *__restrict_
 // lds[t * 2^lpw + pp] = src[t * n_q + p0 + pp] (zero past n_q).  Each thread
 // issues U loads before it writes, so a block waits for ceil(F 2^lpw / (256 U))
 // memory round trips rather than one per element.
-template <int U, typename T>
+template <int U, typename T, int NT = kBlock>
 __device__ __forceinline__ void stage_series(T *lds, const T *__restrict__ src, int F, int lpw, int64_t n_q,
                                              int64_t p0) {
     const int n = F << lpw, pmask = (1 << lpw) - 1;
-    for (int base = 0; base < n; base += kBlock * U) {
+    for (int base = 0; base < n; base += NT * U) {
         T v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = base + u * kBlock + static_cast<int>(threadIdx.x);
+            const int i = base + u * NT + static_cast<int>(threadIdx.x);
             const int t = i >> lpw;
             const int64_t p = p0 + (i & pmask);
             v[u] = (i < n && p < n_q) ? src[static_cast<int64_t>(t) * n_q + p] : T{};
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = base + u * kBlock + static_cast<int>(threadIdx.x);
+            const int i = base + u * NT + static_cast<int>(threadIdx.x);
             if (i < n) lds[i] = v[u];
         }
     }
@@ -415,6 +415,88 @@ __global__ __launch_bounds__(kBlock) void k_g2_lags(const double *__restrict__ I
             if (tau < n_tau)
                 G[static_cast<int64_t>(row) * n_tau + tau] = (acc[j] / static_cast<double>(F - tau)) / dn;
         }
+    }
+}
+
+// The same sums with the block's pixel count 2^LPW fixed at compile time and the step
+// loop unrolled by L: the window lives in a ring of L registers, y[(t + j) mod L] =
+// x[t + tau0 + j], whose oldest slot takes the next value after each step, so no value
+// moves between registers, and while every row read lies inside the series each LDS
+// address is a constant offset from two per-thread bases.  The last steps (rounded up to
+// a multiple of L) read rows clamped to one zero row after the series, so the extra
+// steps, as above, add x * 0 to every sum; the series plus that row, (F + 1) 2^LPW
+// doubles, is all the LDS a block takes.  Lag block lb runs F - lb L steps, so the
+// wavefronts holding the first blocks work longest; the slots rotate by a quarter per
+// block (blockIdx.x mod 4), so that the long blocks of neighbouring workgroups land on
+// different wavefronts.
+template <int L, int LPW, int NT>
+__global__ __launch_bounds__(NT) void k_g2_lags_ring(const double *__restrict__ I, int32_t F, int64_t n_q,
+                                                     int32_t n_tau, const int32_t *__restrict__ rank,
+                                                     const double *__restrict__ den, double *__restrict__ G) {
+    constexpr int PW = 1 << LPW, kSlots = NT >> LPW;
+    extern __shared__ double lds[];
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+    stage_series<16, double, NT>(lds, I, F, LPW, n_q, p0);
+    if (static_cast<int>(threadIdx.x) < PW) lds[(F << LPW) + threadIdx.x] = 0.0;
+    __syncthreads();
+    const int pp = threadIdx.x & (PW - 1);
+    const int slot = ((threadIdx.x >> LPW) + (blockIdx.x & 3) * (kSlots / 4)) & (kSlots - 1);
+    const int64_t p = p0 + pp;
+    if (p >= n_q) return;
+    const int32_t row = rank[p];
+    if (row < 0) return;
+    const double dn = den[p];
+    const double *col = lds + pp;  // x[t] at col[t * PW], t <= F (row F is zero)
+    const int n_lb = (n_tau + L - 1) / L;
+    for (int lb = slot; lb < n_lb; lb += kSlots) {
+        const int tau0 = lb * L;
+        const double *ys = col + tau0 * PW;  // x[tau0 + i] at ys[i * PW]
+        double acc[L], y[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            acc[j] = 0.0;
+            y[j] = col[min(tau0 + j, F) * PW];
+        }
+        const int steps = F - tau0;
+        int t = 0;
+        // rows t + s and t + s + tau0 + L stay below F
+        for (; t + 2 * L <= steps; t += L) {
+            const double *xt = col + t * PW, *yt = ys + (t + L) * PW;
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const double x = xt[s * PW];
+#pragma unroll
+                for (int j = 0; j < L; ++j) acc[j] = __builtin_fma(x, y[(s + j) % L], acc[j]);
+                y[s] = yt[s * PW];
+            }
+        }
+        for (; t < steps; t += L) {
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const double x = col[min(t + s, F) * PW];
+#pragma unroll
+                for (int j = 0; j < L; ++j) acc[j] = __builtin_fma(x, y[(s + j) % L], acc[j]);
+                y[s] = col[min(t + s + tau0 + L, F) * PW];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const int tau = tau0 + j;
+            if (tau < n_tau)
+                G[static_cast<int64_t>(row) * n_tau + tau] = (acc[j] / static_cast<double>(F - tau)) / dn;
+        }
+    }
+}
+
+template <int LPW, int NT>
+void launch_g2_ring(int L, dim3 grid, size_t lds, hipStream_t s, const double *I, int32_t F, int64_t n_q,
+                    int32_t n_tau, const int32_t *rank, const double *den, double *G) {
+    switch (L) {
+    case 8: hipLaunchKernelGGL((k_g2_lags_ring<8, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
+    case 13: hipLaunchKernelGGL((k_g2_lags_ring<13, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
+    case 16: hipLaunchKernelGGL((k_g2_lags_ring<16, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
+    case 24: hipLaunchKernelGGL((k_g2_lags_ring<24, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
+    default: hipLaunchKernelGGL((k_g2_lags_ring<32, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
     }
 }
 
@@ -1122,20 +1204,37 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
     Partition P;
     XS_TRY(partition(A, k, n_q, R, &P));
     if (n_q > 0) {
-        // pixels per block for the LDS path: largest power of two <= 64 with the
-        // series in at most 64 KiB
-        // (series plus the largest lag block of zero rows, L <= 32)
+        // pixels per block for the LDS path: the largest power of two <= 64 whose series
+        // (plus the zero rows after it) fit 64 KiB; the lag block L: the smallest built size
+        // that leaves no slot with two blocks
+        auto pick_l = [&](int lpw, int threads = kBlock) {
+            const int n_slots = threads >> lpw;
+            const int want = static_cast<int>((n_tau + n_slots - 1) / n_slots);
+            return want <= 8 ? 8 : want <= 13 ? 13 : want <= 16 ? 16 : want <= 24 ? 24 : 32;
+        };
+        auto fits = [&](int lpw, int rows_after) {
+            return ((F + rows_after) << lpw) * static_cast<int64_t>(sizeof(double)) <= 65536;
+        };
         int lpw = 6;
-        while (lpw > 0 && ((F + 32) << lpw) * static_cast<int64_t>(sizeof(double)) > 65536) --lpw;
-        if (((F + 32) << lpw) * static_cast<int64_t>(sizeof(double)) <= 65536) {
+        while (lpw > 0 && !fits(lpw, 32)) --lpw;
+        constexpr int kRingThreads = kBlock;
+        int rlpw = 6;  // register-ring kernel: one zero row, 16 to 64 pixels per block
+        while (rlpw > 4 && !fits(rlpw, 1)) --rlpw;
+        const int32_t F32 = static_cast<int32_t>(F);
+        double *Gd = static_cast<double *>(G);
+        if (fits(rlpw, 1)) {
+            const int L = pick_l(rlpw, kRingThreads);
+            const size_t lds = sizeof(double) * ((F + 1) << rlpw);
+            const dim3 grid(static_cast<unsigned>((n_q + (int64_t(1) << rlpw) - 1) >> rlpw));
+            if (rlpw == 6) launch_g2_ring<6, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
+            else if (rlpw == 5) launch_g2_ring<5, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
+            else launch_g2_ring<4, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
+        } else if (fits(lpw, 32)) {
             const size_t lds = sizeof(double) * ((F + 32) << lpw);
             const int64_t pw = int64_t(1) << lpw;
-            // lag block: the smallest built size that leaves no slot with two blocks
-            const int n_slots = kBlock >> lpw;
-            const int want = static_cast<int>((n_tau + n_slots - 1) / n_slots);
+            const int want = pick_l(lpw);
             const dim3 grid(static_cast<unsigned>((n_q + pw - 1) / pw));
-            const int32_t F32 = static_cast<int32_t>(F), lpw32 = static_cast<int32_t>(lpw);
-            double *Gd = static_cast<double *>(G);
+            const int32_t lpw32 = static_cast<int32_t>(lpw);
             if (want <= 8)
                 hipLaunchKernelGGL(k_g2_lags<8>, grid, dim3(kBlock), lds, s, I, F32, n_q, n_tau, lpw32, P.rank, dn, Gd);
             else if (want <= 13)
