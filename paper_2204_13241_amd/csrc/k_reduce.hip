@@ -622,6 +622,66 @@ __global__ __launch_bounds__(kBlock) void k_isf_lags(const double2 *__restrict__
     }
 }
 
+// The register-ring form of k_isf_lags (as k_g2_lags_ring): blocks of L lags, the window
+// of the L next amplitudes in a ring of registers, the step loop unrolled by L, rows past
+// the series read from one zero row (the extra steps add products with 0, which leave
+// every sum unchanged bit for bit), slots rotated by a quarter per block.
+template <int L, int LPW>
+__global__ __launch_bounds__(kBlock) void k_isf_lags_ring(const double2 *__restrict__ amp, int32_t F, int64_t n_q,
+                                                          int32_t n_tau, const int32_t *__restrict__ rank,
+                                                          double f2, double *__restrict__ G) {
+    constexpr int PW = 1 << LPW, kSlots = kBlock >> LPW;
+    extern __shared__ double2 lds2[];
+    const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+    stage_series<8>(lds2, amp, F, LPW, n_q, p0);
+    if (static_cast<int>(threadIdx.x) < PW) lds2[(F << LPW) + threadIdx.x] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int pp = threadIdx.x & (PW - 1);
+    const int slot = ((threadIdx.x >> LPW) + (blockIdx.x & 3) * (kSlots / 4)) & (kSlots - 1);
+    const int64_t p = p0 + pp;
+    if (p >= n_q) return;
+    const int32_t row = rank[p];
+    if (row < 0) return;
+    const double2 *col = lds2 + pp;  // p_t at col[t * PW], t <= F (row F is zero)
+    const int n_lb = (n_tau + L - 1) / L;
+    for (int lb = slot; lb < n_lb; lb += kSlots) {
+        const int tau0 = lb * L;
+        const double2 *ys = col + tau0 * PW;
+        double re[L], im[L];
+        double2 y[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            re[j] = 0.0;
+            im[j] = 0.0;
+            y[j] = col[min(tau0 + j, F) * PW];
+        }
+        const int steps = F - tau0;
+        int t = 0;
+        for (; t + 2 * L <= steps; t += L) {  // rows t + s and t + s + tau0 + L below F
+            const double2 *xt = col + t * PW, *yt = ys + (t + L) * PW;
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const double2 x = xt[s * PW];
+#pragma unroll
+                for (int j = 0; j < L; ++j) isf_step(x, y[(s + j) % L], re[j], im[j]);
+                y[s] = yt[s * PW];
+            }
+        }
+        for (; t < steps; t += L) {
+#pragma unroll
+            for (int s = 0; s < L; ++s) {
+                const double2 x = col[min(t + s, F) * PW];
+#pragma unroll
+                for (int j = 0; j < L; ++j) isf_step(x, y[(s + j) % L], re[j], im[j]);
+                y[s] = col[min(t + s + tau0 + L, F) * PW];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < L; ++j)
+            if (tau0 + j < n_tau) isf_store(G, row, n_tau, tau0 + j, F, f2, re[j], im[j]);
+    }
+}
+
 // Same lag step reading global memory (series too long for LDS): one thread
 // per (pixel, lag block).
 __global__ __launch_bounds__(kBlock) void k_isf_lags_global(const double2 *__restrict__ amp, int64_t F,
@@ -1327,10 +1387,26 @@ xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, co
     const double2 *a2 = reinterpret_cast<const double2 *>(amp);
     if (n_q > 0) {
         // pixels per block for the LDS path: largest power of two <= 64 with the
-        // complex series in at most 64 KiB
+        // complex series (and, for the register-ring kernel, one zero row) in at most 64 KiB
         int lpw = 6;
         while (lpw > 0 && (F << lpw) * static_cast<int64_t>(sizeof(double2)) > 65536) --lpw;
-        if ((F << lpw) * static_cast<int64_t>(sizeof(double2)) <= 65536) {
+        int rlpw = 5;
+        while (rlpw > 3 && ((F + 1) << rlpw) * static_cast<int64_t>(sizeof(double2)) > 65536) --rlpw;
+        if (((F + 1) << rlpw) * static_cast<int64_t>(sizeof(double2)) <= 65536) {
+            const size_t lds = sizeof(double2) * ((F + 1) << rlpw);
+            const dim3 grid(static_cast<unsigned>((n_q + (int64_t(1) << rlpw) - 1) >> rlpw));
+            const int32_t F32 = static_cast<int32_t>(F);
+            double *Gd = static_cast<double *>(G);
+            if (rlpw == 5)
+                hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, 5>), grid, dim3(kBlock), lds, s, a2, F32, n_q, n_tau,
+                                   P.rank, f2, Gd);
+            else if (rlpw == 4)
+                hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, 4>), grid, dim3(kBlock), lds, s, a2, F32, n_q, n_tau,
+                                   P.rank, f2, Gd);
+            else
+                hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, 3>), grid, dim3(kBlock), lds, s, a2, F32, n_q, n_tau,
+                                   P.rank, f2, Gd);
+        } else if ((F << lpw) * static_cast<int64_t>(sizeof(double2)) <= 65536) {
             const size_t lds = sizeof(double2) * (F << lpw);
             const int64_t pw = int64_t(1) << lpw;
             hipLaunchKernelGGL(k_isf_lags, dim3(static_cast<unsigned>((n_q + pw - 1) / pw)), dim3(kBlock), lds, s,
