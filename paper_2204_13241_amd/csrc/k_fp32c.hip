@@ -2598,8 +2598,7 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
         tiled = true;
         return XS_OK;
     }
-    void *tok = nullptr;
-    timer_begin(s, TIMER_BIN, &tok);
+    TimerScope tm(s, TIMER_BIN);
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     const unsigned zb = static_cast<unsigned>(std::min<int64_t>((t.cells + kBlock - 1) / kBlock, 4096));
     hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(kBlock), 0, s, b.hist, t.cells);
@@ -2616,7 +2615,7 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
                        b.cursor, t.cells, b.sorted);
     hipLaunchKernelGGL(k_make_tiles, dim3((t.max_tiles + kWaves - 1) / kWaves, n_seg), dim3(kBlock), 0, s,
                        b.bsegs, pos, f, b.sorted, b.t_hi, b.t_lo, b.origins, b.tile_atom);
-    timer_end(s, TIMER_BIN, tok, static_cast<double>(t.atoms));
+    tm.end(static_cast<double>(t.atoms));
     XS_HIP(hipGetLastError());
     tiled = true;
     return XS_OK;
@@ -2741,8 +2740,7 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
     const int nr = static_cast<int>(t.ritems.size());
     if (n + nl + nr > 0) {
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.counters, kFwdCounters);
-        void *tok = nullptr;
-        timer_begin(s, TIMER_FWD32, &tok);
+        TimerScope tm(s, TIMER_FWD32);
         const int qlg = fshape.q_per_lane == 32 ? 8 : fshape.q_per_lane;  // general items of the matrix-core shape
         if (n > 0 && !launch_forward_variant(s, qlg, fshape.waves_per_simd, n, b.counters, b, q))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
@@ -2751,7 +2749,7 @@ xs_status Plan::forward(hipStream_t s, const double *q, double *I, double *amp) 
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
         if (nr > 0 && !launch_rows_variant(s, qlg, fshape.waves_per_simd, nr, b.counters + 2, b, q))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
-        timer_end(s, TIMER_FWD32, tok, t.fwork + t.lwork + t.rwork);
+        tm.end(t.fwork + t.lwork + t.rwork);
         XS_HIP(hipGetLastError());
     }
     if (t.max_q > 0) {
@@ -2778,23 +2776,21 @@ xs_status Plan::grad(hipStream_t s, const double *q, const double *f, const doub
         int32_t *cnt = b.counters + kFwdCounters + k;
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 1);
         const GradItem *items = b.gitems + t.gsub_item0[k];
-        void *tok = nullptr;
-        timer_begin(s, TIMER_GRAD32, &tok);
+        TimerScope tm(s, TIMER_GRAD32);
         const int al = gshape.q_per_lane == 32 ? 2 : gshape.q_per_lane;  // non-lattice systems of a ql-32 plan
         if (!launch_grad_variant(s, al, gshape.waves_per_simd, t.gsub_lat[k] != 0, items, n, cnt, b))
             return set_error(XS_EINVAL, "q_per_lane must be 1, 2, 4 or 8");
-        timer_end(s, TIMER_GRAD32, tok, t.gsub_work[k]);
+        tm.end(t.gsub_work[k]);
         XS_HIP(hipGetLastError());
     }
     if (!t.mitems.empty()) {
         const int n2 = t.mcount2, n3 = static_cast<int>(t.mitems.size()) - t.mcount2;
         int32_t *cnt = b.counters + kFwdCounters + t.gsub_seg0.size();
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt, 2);
-        void *tok = nullptr;
-        timer_begin(s, TIMER_GRAD32, &tok);
+        TimerScope tm(s, TIMER_GRAD32);
         if (n2 > 0) launch_grad_lattice_mfma<2, 2>(s, b.mitems, n2, cnt, b, q, amp, dL_dI);
         if (n3 > 0) launch_grad_lattice_mfma<3, 1>(s, b.mitems + n2, n3, cnt + 1, b, q, amp, dL_dI);
-        timer_end(s, TIMER_GRAD32, tok, t.mwork);
+        tm.end(t.mwork);
         XS_HIP(hipGetLastError());
     }
     if (t.max_slots_seg > 0) {

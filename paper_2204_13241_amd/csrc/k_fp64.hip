@@ -194,11 +194,10 @@ xs_status fp64_forward(hipStream_t s, const Segment *segs_host, int n_segs, int 
     dim3 grid((max_q + kBlock - 1) / kBlock, n_segs);
     double work = 0.0;
     for (int i = 0; i < n_segs; ++i) work += static_cast<double>(segs_host[i].n_atoms) * segs_host[i].n_q;
-    void *tok = nullptr;
-    timer_begin(s, TIMER_FWD64, &tok);
+    TimerScope tm(s, TIMER_FWD64);
     hipLaunchKernelGGL(k_forward_fp64, grid, dim3(kBlock), 0, s,
                        static_cast<const Segment *>(d_segs), pos, f, q, I, amp);
-    timer_end(s, TIMER_FWD64, tok, work);
+    tm.end(work);
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -212,12 +211,11 @@ xs_status fp64_grad(hipStream_t s, const Segment *segs_host, int n_segs, int max
     dim3 grid((max_atoms + kBlock - 1) / kBlock, n_segs);
     double work = 0.0;
     for (int i = 0; i < n_segs; ++i) work += static_cast<double>(segs_host[i].n_atoms) * segs_host[i].n_q;
-    void *tok = nullptr;
-    timer_begin(s, TIMER_GRAD64, &tok);
+    TimerScope tm(s, TIMER_GRAD64);
     hipLaunchKernelGGL(k_grad_fp64, grid, dim3(kBlock), 0, s,
                        static_cast<const Segment *>(d_segs), pos, f, q, amp, dL_dI, dL_dr,
                        dL_dr64);
-    timer_end(s, TIMER_GRAD64, tok, work);
+    tm.end(work);
     XS_HIP(hipGetLastError());
     return XS_OK;
 }

@@ -218,6 +218,14 @@ void timer_end(hipStream_t s, int kind, void *token, double work) {
     delete rec;
 }
 
+void timer_discard(void *token) {
+    if (!token) return;
+    auto *rec = static_cast<TimerRec *>(token);
+    (void)hipEventDestroy(rec->a);
+    (void)hipEventDestroy(rec->b);
+    delete rec;
+}
+
 xs_status timing_enable(int on) {
     std::lock_guard<std::mutex> lk(g_tmu);
     for (int k = 0; k < XS_TIMER_KINDS; ++k) {

@@ -1246,9 +1246,8 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
                       const RingEdges &edges, int32_t n_tau, double *g2_out, int32_t *ring_count) {
     hipStream_t s = A.s;
     const int32_t R = edges.n_rings;
-    void *tok = nullptr;
     const bool timed = A.base == nullptr;
-    if (timed) timer_begin(s, TIMER_G2, &tok);
+    TimerScope tm(s, TIMER_G2, timed);
     void *key = nullptr, *G = nullptr, *G2 = nullptr, *den = nullptr;
     XS_TRY(A.get(SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
     XS_TRY(A.get(SLOT_PIXEL2, sizeof(double) * std::max<int64_t>(n_q, 1), &den));
@@ -1317,7 +1316,7 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
     hipLaunchKernelGGL(k_ring_mean_finish, dim3(blocks_for(static_cast<int64_t>(R) * n_tau)), dim3(kBlock), 0, s,
                        top, static_cast<int64_t>(n_tau), R, P.start,
                        P.lev + static_cast<int64_t>(P.levels) * (R + 1), g2_out, ring_count);
-    if (timed) timer_end(s, TIMER_G2, tok, static_cast<double>(F) * n_q * sizeof(double));
+    tm.end(static_cast<double>(F) * n_q * sizeof(double));
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -1370,8 +1369,7 @@ xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, co
                     const RingEdges &edges, int32_t n_tau, double f2, double *F_out, int32_t *ring_count) {
     const int32_t R = edges.n_rings;
     const int64_t ncol = 2 * static_cast<int64_t>(n_tau);
-    void *tok = nullptr;
-    timer_begin(s, TIMER_ISF, &tok);
+    TimerScope tm(s, TIMER_ISF);
     void *key = nullptr, *G = nullptr, *G2 = nullptr;
     XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
     XS_TRY(scratch(s, SLOT_G, sizeof(double) * std::max<int64_t>(n_q * ncol, 1), &G));
@@ -1422,7 +1420,7 @@ xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, co
     const double *top = reduce_tree(s, P, R, 0, n_q, ncol, static_cast<double *>(G), static_cast<double *>(G2));
     hipLaunchKernelGGL(k_ring_mean_finish, dim3(blocks_for(static_cast<int64_t>(R) * ncol)), dim3(kBlock), 0, s,
                        top, ncol, R, P.start, P.lev + static_cast<int64_t>(P.levels) * (R + 1), F_out, ring_count);
-    timer_end(s, TIMER_ISF, tok, static_cast<double>(F) * n_q * sizeof(double2));
+    tm.end(static_cast<double>(F) * n_q * sizeof(double2));
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -1440,8 +1438,7 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
                         const RingEdges &edges, int32_t n_levels, double *beta_out,
                         double *beta_win) {
     const int32_t R = edges.n_rings;
-    void *tok = nullptr;
-    timer_begin(s, TIMER_XSVS, &tok);
+    TimerScope tm(s, TIMER_XSVS);
     void *key = nullptr, *bwin = nullptr;
     XS_TRY(scratch(s, SLOT_RING_KEY, sizeof(int32_t) * std::max<int64_t>(n_q, 1), &key));
     // per-window contrast of level l: R x (F >> l) at offset off[l]
@@ -1529,7 +1526,7 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         src = dst;
         K >>= kLvDepth;
     }
-    timer_end(s, TIMER_XSVS, tok, static_cast<double>(F) * n_q * sizeof(double));
+    tm.end(static_cast<double>(F) * n_q * sizeof(double));
     return XS_OK;
 }
 

@@ -208,6 +208,28 @@ enum TimerKind {
 bool timing_on();
 void timer_begin(hipStream_t s, int kind, void **token);
 void timer_end(hipStream_t s, int kind, void *token, double work);
+void timer_discard(void *token);
+
+// Event timer of one library call (when timing is on): begun at construction, end()
+// records it with its work; a scope left early (an error return) discards its events.
+class TimerScope {
+public:
+    TimerScope(hipStream_t s, int kind, bool on = true) : s_(s), kind_(kind) {
+        if (on) timer_begin(s, kind, &tok_);
+    }
+    ~TimerScope() { timer_discard(tok_); }
+    TimerScope(const TimerScope &) = delete;
+    TimerScope &operator=(const TimerScope &) = delete;
+    void end(double work) {
+        timer_end(s_, kind_, tok_, work);
+        tok_ = nullptr;
+    }
+
+private:
+    hipStream_t s_;
+    int kind_;
+    void *tok_ = nullptr;
+};
 xs_status timing_enable(int on);
 xs_status timing_read(int kind, double *ms, int64_t *launches, double *work);
 
