@@ -1055,7 +1055,10 @@ constexpr int kSumLevels = 24;  // frame sums of up to 2^24 terms
 // counter holds the complete subtrees (st[l]: 2^l terms while bit l of n_done
 // is set; a new term merges left + right up the set bits), then the fold from
 // the right, which is the bottom-up tree with the odd element carried up.  The
-// counter is the same in every lane, so its branches are uniform.
+// counter is the same in every lane, so its branches are uniform.  Terms are
+// read kSumAhead at a time, so that many loads are in flight per thread.
+constexpr int kSumAhead = 8;
+
 __global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict__ I, int64_t n_q, int64_t n_out,
                                                        int64_t s_out, int64_t n_sum, int64_t s_sum, double scale,
                                                        double *__restrict__ J) {
@@ -1065,21 +1068,29 @@ __global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict_
     double st[kSumLevels];
     int64_t n_done = 0;
     const double *src = I + k * s_out * n_q + p;
-    for (int64_t i = 0; i < n_sum; ++i) {
-        double v = src[i * s_sum * n_q];
-        bool carry = true;
+    const int64_t stride = s_sum * n_q;
+    for (int64_t i0 = 0; i0 < n_sum; i0 += kSumAhead) {
+        double vv[kSumAhead];
 #pragma unroll
-        for (int l = 0; l < kSumLevels; ++l) {
-            if (carry) {
-                if ((n_done >> l) & 1) {
-                    v = st[l] + v;
-                } else {
-                    st[l] = v;
-                    carry = false;
+        for (int u = 0; u < kSumAhead; ++u) vv[u] = i0 + u < n_sum ? src[(i0 + u) * stride] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kSumAhead; ++u) {
+            if (i0 + u >= n_sum) break;  // uniform
+            double v = vv[u];
+            bool carry = true;
+#pragma unroll
+            for (int l = 0; l < kSumLevels; ++l) {
+                if (carry) {
+                    if ((n_done >> l) & 1) {
+                        v = st[l] + v;
+                    } else {
+                        st[l] = v;
+                        carry = false;
+                    }
                 }
             }
+            ++n_done;
         }
-        ++n_done;
     }
     double sum = 0.0;
     bool have = false;
