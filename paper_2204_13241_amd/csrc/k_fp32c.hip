@@ -506,13 +506,23 @@ __device__ __forceinline__ void tile_pairs(const float4 *__restrict__ at, const 
     for (int j = 0; j < kTile; ++j) {
         const float4 a = at[j];
         const float b = bt[j];
+        // phases, then sines and cosines, then sums (transcendentals back to back)
+        float ph[QL], c[QL], s[QL];
 #pragma unroll
         for (int k = 0; k < QL; ++k) {
-            float ph = __builtin_fmaf(dqx[k], a.x, b);
-            ph = __builtin_fmaf(dqy[k], a.y, ph);
-            if (!PLANAR) ph = __builtin_fmaf(dqz[k], a.z, ph);
-            cs[k] = __builtin_fmaf(a.w, __builtin_amdgcn_cosf(ph), cs[k]);
-            sn[k] = __builtin_fmaf(a.w, __builtin_amdgcn_sinf(ph), sn[k]);
+            ph[k] = __builtin_fmaf(dqx[k], a.x, b);
+            ph[k] = __builtin_fmaf(dqy[k], a.y, ph[k]);
+            if (!PLANAR) ph[k] = __builtin_fmaf(dqz[k], a.z, ph[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            c[k] = __builtin_amdgcn_cosf(ph[k]);
+            s[k] = __builtin_amdgcn_sinf(ph[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            cs[k] = __builtin_fmaf(a.w, c[k], cs[k]);
+            sn[k] = __builtin_fmaf(a.w, s[k], sn[k]);
         }
     }
 }
@@ -721,12 +731,23 @@ __device__ __forceinline__ void row_pairs(const float4 *__restrict__ at, const f
     for (int j = 0; j < kTile; ++j) {
         const float4 a = at[j];
         const float y = __builtin_fmaf(dqy, a.y, bt[j]);
+        // the atom's phases first, then their sines and cosines, then the sums: the
+        // transcendentals run back to back instead of each feeding the next FMA
+        float ph[QL], c[QL], s[QL];
 #pragma unroll
         for (int k = 0; k < QL; ++k) {
-            float ph = __builtin_fmaf(dqx[k], a.x, y);
-            if (!FLAT) ph = __builtin_fmaf(dqz[k], a.z, ph);
-            cs[k] = __builtin_fmaf(a.w, __builtin_amdgcn_cosf(ph), cs[k]);
-            sn[k] = __builtin_fmaf(a.w, __builtin_amdgcn_sinf(ph), sn[k]);
+            ph[k] = __builtin_fmaf(dqx[k], a.x, y);
+            if (!FLAT) ph[k] = __builtin_fmaf(dqz[k], a.z, ph[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            c[k] = __builtin_amdgcn_cosf(ph[k]);
+            s[k] = __builtin_amdgcn_sinf(ph[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < QL; ++k) {
+            cs[k] = __builtin_fmaf(a.w, c[k], cs[k]);
+            sn[k] = __builtin_fmaf(a.w, s[k], sn[k]);
         }
     }
 }
