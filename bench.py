@@ -742,7 +742,7 @@ def run_xsvs_pairs(args):
     q = torch.as_tensor(q_np, dtype=torch.float64, device=dev)
     old = api.get_tile_shape(0)
     # one atom chunk per pixel group (4000 tiles): partial sums stay one per pixel and frame
-    api.set_tile_shape(0, 64, 8, 4096, 0, 0, 0)
+    api.set_tile_shape(0, 64, 4, 4096, 0, 0, 0)
     plan = api.Plan.single(N, F, q, L, forward_only=True)
     I = torch.empty((F, Q), dtype=torch.float64, device=dev)
     plan.intensity(pos, f, I, want_amp=False)
@@ -781,7 +781,7 @@ def run_xsvs_pairs(args):
                        "(q_max 2), first %d of 1024 frames; XSVS over 64 rings, W = 1..%d" % (F, 2 ** (n_levels - 1)),
            "frames": F, "pairs": pairs, "forward_ms": ms, "forward_Gpair_s": pairs / (ms * 1e-3) / 1e9,
            "frac_of_sincos_pair_peak": pairs / (ms * 1e-3) / PEAK_SINCOS_PAIRS,
-           "form": "per-pair", "tile_shape_fwd": {"q_per_lane": 8, "atom_split": 4096}, "plan": desc,
+           "form": "per-pair", "tile_shape_fwd": {"q_per_lane": 4, "atom_split": 4096}, "plan": desc,
            "plan_kind": "forward only", "xsvs_ms": ms_xsvs, "beta_levels": n_levels,
            "fp64_frames": F64, "e_I_scaled_vs_fp64": e_I, "e_beta_vs_fp64": e_b,
            "fp64_forward_ms": ms64, "speedup_vs_fp64_form": (ms64 / F64) / (ms / F)}

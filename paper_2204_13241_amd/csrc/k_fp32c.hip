@@ -502,28 +502,38 @@ template <int QL, bool PLANAR>
 __device__ __forceinline__ void tile_pairs(const float4 *__restrict__ at, const float *__restrict__ bt,
                                            const float (&dqx)[QL], const float (&dqy)[QL],
                                            const float (&dqz)[QL], float (&cs)[QL], float (&sn)[QL]) {
-#pragma unroll 4
-    for (int j = 0; j < kTile; ++j) {
-        const float4 a = at[j];
-        const float b = bt[j];
-        // phases, then sines and cosines, then sums (transcendentals back to back)
-        float ph[QL], c[QL], s[QL];
+    // two atoms at a time: phases, then sines and cosines, then sums (atom j before
+    // atom j + 1), the transcendentals back to back
+    constexpr int kA = 2;
+#pragma unroll 2
+    for (int j = 0; j < kTile; j += kA) {
+        float4 a[kA];
+        float ph[kA][QL], c[kA][QL], s[kA][QL];
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            ph[k] = __builtin_fmaf(dqx[k], a.x, b);
-            ph[k] = __builtin_fmaf(dqy[k], a.y, ph[k]);
-            if (!PLANAR) ph[k] = __builtin_fmaf(dqz[k], a.z, ph[k]);
+        for (int u = 0; u < kA; ++u) {
+            a[u] = at[j + u];
+            const float b = bt[j + u];
+#pragma unroll
+            for (int k = 0; k < QL; ++k) {
+                ph[u][k] = __builtin_fmaf(dqx[k], a[u].x, b);
+                ph[u][k] = __builtin_fmaf(dqy[k], a[u].y, ph[u][k]);
+                if (!PLANAR) ph[u][k] = __builtin_fmaf(dqz[k], a[u].z, ph[u][k]);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            c[k] = __builtin_amdgcn_cosf(ph[k]);
-            s[k] = __builtin_amdgcn_sinf(ph[k]);
-        }
+        for (int u = 0; u < kA; ++u)
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            cs[k] = __builtin_fmaf(a.w, c[k], cs[k]);
-            sn[k] = __builtin_fmaf(a.w, s[k], sn[k]);
-        }
+            for (int k = 0; k < QL; ++k) {
+                c[u][k] = __builtin_amdgcn_cosf(ph[u][k]);
+                s[u][k] = __builtin_amdgcn_sinf(ph[u][k]);
+            }
+#pragma unroll
+        for (int u = 0; u < kA; ++u)
+#pragma unroll
+            for (int k = 0; k < QL; ++k) {
+                cs[k] = __builtin_fmaf(a[u].w, c[u][k], cs[k]);
+                sn[k] = __builtin_fmaf(a[u].w, s[u][k], sn[k]);
+            }
     }
 }
 
@@ -727,28 +737,38 @@ template <int QL, bool FLAT>
 __device__ __forceinline__ void row_pairs(const float4 *__restrict__ at, const float *__restrict__ bt,
                                           const float dqy, const float (&dqx)[QL], const float (&dqz)[QL],
                                           float (&cs)[QL], float (&sn)[QL]) {
-#pragma unroll 4
-    for (int j = 0; j < kTile; ++j) {
-        const float4 a = at[j];
-        const float y = __builtin_fmaf(dqy, a.y, bt[j]);
-        // the atom's phases first, then their sines and cosines, then the sums: the
-        // transcendentals run back to back instead of each feeding the next FMA
-        float ph[QL], c[QL], s[QL];
+    // two atoms at a time: both atoms' phases, then their sines and cosines, then the
+    // sums (atom j before atom j + 1, as one at a time): the transcendentals run back to
+    // back instead of each feeding the next FMA
+    constexpr int kA = 2;
+#pragma unroll 2
+    for (int j = 0; j < kTile; j += kA) {
+        float4 a[kA];
+        float ph[kA][QL], c[kA][QL], s[kA][QL];
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            ph[k] = __builtin_fmaf(dqx[k], a.x, y);
-            if (!FLAT) ph[k] = __builtin_fmaf(dqz[k], a.z, ph[k]);
+        for (int u = 0; u < kA; ++u) {
+            a[u] = at[j + u];
+            const float y = __builtin_fmaf(dqy, a[u].y, bt[j + u]);
+#pragma unroll
+            for (int k = 0; k < QL; ++k) {
+                ph[u][k] = __builtin_fmaf(dqx[k], a[u].x, y);
+                if (!FLAT) ph[u][k] = __builtin_fmaf(dqz[k], a[u].z, ph[u][k]);
+            }
         }
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            c[k] = __builtin_amdgcn_cosf(ph[k]);
-            s[k] = __builtin_amdgcn_sinf(ph[k]);
-        }
+        for (int u = 0; u < kA; ++u)
 #pragma unroll
-        for (int k = 0; k < QL; ++k) {
-            cs[k] = __builtin_fmaf(a.w, c[k], cs[k]);
-            sn[k] = __builtin_fmaf(a.w, s[k], sn[k]);
-        }
+            for (int k = 0; k < QL; ++k) {
+                c[u][k] = __builtin_amdgcn_cosf(ph[u][k]);
+                s[u][k] = __builtin_amdgcn_sinf(ph[u][k]);
+            }
+#pragma unroll
+        for (int u = 0; u < kA; ++u)
+#pragma unroll
+            for (int k = 0; k < QL; ++k) {
+                cs[k] = __builtin_fmaf(a[u].w, c[u][k], cs[k]);
+                sn[k] = __builtin_fmaf(a[u].w, s[u][k], sn[k]);
+            }
     }
 }
 
