@@ -35,6 +35,7 @@ constexpr int kLvLoads = kLvRows * kLvTile / kBlock;
 constexpr int kLvChunksPerBlock = 4;        // consecutive chunks of one ring per block
 static_assert(kLvRows * 8 == kBlock && kLvTile == 64 && (1 << kLvDepth) == kLvTile,
               "XSVS level kernel: thread (row, group of 8 windows) covers one chunk");
+static_assert(kLvChunksPerBlock == 4, "XSVS level kernel: a block adds its chunk trees as two pairs");
 
 unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
@@ -139,8 +140,10 @@ __device__ __forceinline__ int ring_of(const int32_t *off, int R, int64_t e) {
     return lo;
 }
 
-// One tree level: out[e][c] = tree over in's elements [s, s + cnt) of the
-// element's ring, s = in_off[r] + (e - out_off[r]) * 32.  Rows of ncol columns.
+// G tree levels at once (G = 2^k <= 32): out[e][c] = tree over in's elements
+// [s, s + cnt) of the element's ring, s = in_off[r] + (e - out_off[r]) * G.
+// Rows of ncol columns.
+template <int G>
 __global__ __launch_bounds__(kBlock) void k_group_tree(const double *__restrict__ in,
                                                        double *__restrict__ out, int64_t ncol,
                                                        const int32_t *__restrict__ in_off,
@@ -155,8 +158,8 @@ __global__ __launch_bounds__(kBlock) void k_group_tree(const double *__restrict_
     const int64_t e = gid / ncol, c = gid - (gid / ncol) * ncol;
     if (e >= o_s[R]) return;
     const int r = ring_of(o_s, R, e);
-    const int64_t s = i_s[r] + (e - o_s[r]) * kGroup;
-    const int cnt = static_cast<int>(std::min<int64_t>(kGroup, i_s[r + 1] - s));
+    const int64_t s = i_s[r] + (e - o_s[r]) * G;
+    const int cnt = static_cast<int>(std::min<int64_t>(G, i_s[r + 1] - s));
     out[e * ncol + c] = tree_upto32(cnt, [&](int i) { return in[(s + i) * ncol + c]; });
 }
 
@@ -835,11 +838,13 @@ __global__ __launch_bounds__(kBlock) void k_group_scatter(const int32_t *__restr
 //   [64, 96) L+1,  [96, 112) L+2,  [112, 120) L+3,  [120, 124) L+4,
 //   [124, 126) L+5, [126] L+6,
 // the coarser levels formed by pairwise sums J_{l+1}[j] = J_l[2j] + J_l[2j+1].
-// Thread t < 126 owns column t (one window of one level) and writes the
-// chunk's pairwise trees of its values J and of their squares J*J to
-// csum[chunk][tile * 256 + t] and [tile * 256 + 128 + t] (the two moments of
-// Eq. (bq_Iq)).  Level L+6 (one window per full tile) also goes to `next`
-// [rank][K >> 6] for the launch that continues from it.
+// Thread t < 126 owns column t (one window of one level): it forms each
+// chunk's pairwise trees of its values J and of their squares J*J (the two
+// moments of Eq. (bq_Iq)) and adds the chunk trees of the block as the ring
+// tree does (chunks 0 + 1, 2 + 3, then the two), writing that node over the
+// block's 128 ring rows to csum[group][tile * 256 + t] and [tile * 256 + 128 + t].
+// Level L+6 (one window per full tile) also goes to `next` [rank][K >> 6] for
+// the launch that continues from it.
 // kGather: rows gathered from the frames I[k][list[m]] (ld = pixels), on a
 // one-dimensional grid: the (tile, group) work items, tile-major with the groups
 // in the order of `order`, are split into eight equal consecutive runs, run x
@@ -851,7 +856,6 @@ template <bool kGather>
 __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
                                                         const int32_t *__restrict__ list, int32_t R,
                                                         const int32_t *__restrict__ ring_start,
-                                                        const int32_t *__restrict__ chunk_off,
                                                         const int32_t *__restrict__ grp_off,
                                                         const int32_t *__restrict__ order, int64_t n_tiles,
                                                         int64_t ncol, double *__restrict__ csum,
@@ -917,6 +921,8 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
     // two chunks in flight: buffer A carries the even steps, B the odd ones; a
     // buffer is refilled with the chunk two steps ahead as soon as it is in LDS
     double bufA[kLvLoads], bufB[kLvLoads];
+    // the owner's node sums: chunks 0 + 1 in (p1, p2), chunks 2 + 3 in (u1, u2)
+    double p1 = 0.0, p2 = 0.0, u1 = 0.0, u2 = 0.0;
     load_chunk(bufA, a + c_first * kLvRows, chunk_rows(c_first));
     if (c_first + 1 < c_end) load_chunk(bufB, a + (c_first + 1) * kLvRows, chunk_rows(c_first + 1));
     auto process = [&](double (&buf)[kLvLoads], int32_t ch) {
@@ -964,14 +970,26 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
             const double *colp = tile + t;
             double s1, s2;
             tree2_upto32(crow, [&](int i) { return colp[i * kLvStride]; }, s1, s2);
-            double *out = csum + static_cast<int64_t>(chunk_off[r] + ch) * ncol + col;
-            out[0] = s1;
-            out[kLvHalf] = s2;
+            switch (ch - c_first) {
+            case 0: p1 = s1; p2 = s2; break;
+            case 1: p1 += s1; p2 += s2; break;
+            case 2: u1 = s1; u2 = s2; break;
+            default: u1 += s1; u2 += s2; break;
+            }
         }
     };
     for (int32_t ch = c_first; ch < c_end; ch += 2) {
         process(bufA, ch);
         if (ch + 1 < c_end) process(bufB, ch + 1);
+    }
+    if (owner) {
+        if (c_end - c_first > 2) {
+            p1 += u1;
+            p2 += u2;
+        }
+        double *out = csum + gb * ncol + col;
+        out[0] = p1;
+        out[kLvHalf] = p2;
     }
 }
 
@@ -1244,7 +1262,7 @@ double *reduce_tree(hipStream_t s, const Partition &P, int32_t R, int from, int6
     double *in = a, *out = b;
     for (int l = from; l < P.levels; ++l) {
         const int64_t n_out = level_bound(n_q, R, l + 1);
-        hipLaunchKernelGGL(k_group_tree, dim3(blocks_for(n_out * ncol)), dim3(kBlock), 0, s, in, out, ncol,
+        hipLaunchKernelGGL(k_group_tree<kGroup>, dim3(blocks_for(n_out * ncol)), dim3(kBlock), 0, s, in, out, ncol,
                            P.lev + static_cast<int64_t>(l) * (R + 1), P.lev + static_cast<int64_t>(l + 1) * (R + 1),
                            R);
         std::swap(in, out);
@@ -1499,7 +1517,8 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         const int64_t tiles = (K + kLvTile - 1) / kLvTile;
         const int64_t ncol = tiles * kLvCols;
         void *t1 = nullptr, *t2 = nullptr;
-        XS_TRY(scratch(s, SLOT_G, sizeof(double) * level_bound(n_q, R, 1) * ncol, &t1));
+        // c1: the group nodes, later tree level 3; c2: level 2
+        XS_TRY(scratch(s, SLOT_G, sizeof(double) * std::max(groups_bound, level_bound(n_q, R, 3)) * ncol, &t1));
         XS_TRY(scratch(s, SLOT_PIXEL2, sizeof(double) * level_bound(n_q, R, 2) * ncol, &t2));
         double *c1 = static_cast<double *>(t1), *c2 = static_cast<double *>(t2);
         LevelOut lo{};
@@ -1508,23 +1527,31 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
             lo.K[d] = K >> d;
         }
         const dim3 grid(static_cast<unsigned>(groups_bound), static_cast<unsigned>(tiles));
-        const int32_t *lev1 = P.lev + (R + 1);
-        const int32_t *top_off = P.lev + static_cast<int64_t>(P.levels) * (R + 1);
+        // one ring tree node per block group: then tree level 2 (1024 ring rows,
+        // 8 group nodes) and on; with one level (rings of <= 32 pixels) the
+        // group nodes are the tops
+        const int32_t *top_off = P.levels >= 2 ? P.lev + static_cast<int64_t>(P.levels) * (R + 1) : P.grp;
         // one read of the windows: chunk trees of J and J*J, then the ring trees
         if (L == 0) {
             const int64_t blocks = 8 * ((groups_bound * tiles + 7) / 8);
             if (blocks > 0x7fffffff) return set_error(XS_EINVAL, "XSVS: %lld gathering blocks exceed one grid",
                                                      static_cast<long long>(blocks));
             hipLaunchKernelGGL(k_xsvs_chunks<true>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, I, K,
-                               n_q, static_cast<const int32_t *>(P.list), R, P.start, lev1, P.grp,
+                               n_q, static_cast<const int32_t *>(P.list), R, P.start, P.grp,
                                static_cast<const int32_t *>(order), tiles, ncol, c1, dst);
         } else {
             hipLaunchKernelGGL(k_xsvs_chunks<false>, grid, dim3(kBlock), 0, s, src, K, K,
-                               static_cast<const int32_t *>(nullptr), R, P.start, lev1, P.grp,
+                               static_cast<const int32_t *>(nullptr), R, P.start, P.grp,
                                static_cast<const int32_t *>(nullptr), tiles, ncol, c1, dst);
         }
         XS_HIP(hipGetLastError());
-        const double *top = reduce_tree(s, P, R, 1, n_q, ncol, c1, c2);
+        const double *top = c1;
+        if (P.levels >= 2) {
+            constexpr int kNodes = kGroup / kLvChunksPerBlock;
+            hipLaunchKernelGGL(k_group_tree<kNodes>, dim3(blocks_for(level_bound(n_q, R, 2) * ncol)), dim3(kBlock),
+                               0, s, c1, c2, ncol, P.grp, P.lev + static_cast<int64_t>(2) * (R + 1), R);
+            top = reduce_tree(s, P, R, 2, n_q, ncol, c2, c1);
+        }
         hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * (ncol / 2))), dim3(kBlock), 0, s,
                            top, ncol, K, depths, R, P.start, top_off, lo);
         XS_HIP(hipGetLastError());
