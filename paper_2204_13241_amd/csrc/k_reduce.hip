@@ -843,15 +843,16 @@ __global__ __launch_bounds__(kBlock) void k_group_scatter(const int32_t *__restr
 // moments of Eq. (bq_Iq)) and adds the chunk trees of the block as the ring
 // tree does (chunks 0 + 1, 2 + 3, then the two), writing that node over the
 // block's 128 ring rows to csum[group][tile * 256 + t] and [tile * 256 + 128 + t].
-// Level L+6 (one window per full tile) also goes to `next` [rank][K >> 6] for
-// the launch that continues from it.
-// kGather: rows gathered from the frames I[k][list[m]] (ld = pixels), on a
-// one-dimensional grid: the (tile, group) work items, tile-major with the groups
-// in the order of `order`, are split into eight equal consecutive runs, run x
-// taken by blocks x, x + 8, x + 16, ... (consecutive blocks go to different XCDs,
-// so each XCD walks its run in order and its L2 sees the rows of neighbouring
-// rings together).  Otherwise read from a ring-ordered table X[m][k] (ld = K),
-// grid (group, tile).
+// Level L+6 (one window per full tile) also goes to `next` [K >> 6][ld] (ring
+// rows m contiguous, as in a frame) for the launch that continues from it.
+// kGather: rows gathered from the frames X[k][list[m]], on a one-dimensional
+// grid: the (tile, group) work items, tile-major with the groups in the order
+// of `order`, are split into eight equal consecutive runs, run x taken by
+// blocks x, x + 8, x + 16, ... (consecutive blocks go to different XCDs, so
+// each XCD walks its run in order and its L2 sees the rows of neighbouring
+// rings together).  Otherwise rows m read from the ring-ordered table
+// X[k][m] that the previous launch wrote, grid (group, tile).  Both have ld
+// elements per frame or table column.
 template <bool kGather>
 __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict__ X, int64_t K, int64_t ld,
                                                         const int32_t *__restrict__ list, int32_t R,
@@ -888,31 +889,20 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
     const int64_t col = tile_idx * kLvCols + t;
     const bool owner = t < kLvHalf - 2;
     const bool want_next = next != nullptr && k0 + kLvTile <= K;
-    const int64_t K_next = K >> kLvDepth;
 
-    // staging map: element i of thread t is (row q_t + i * dqi, column c_t + i * dci)
-    //   table:  lanes along a row (64 windows), 4 rows per step
-    //   gather: lanes along the ring (kLvRows rows), 8 windows per step; the
-    //           thread's row, hence its pixel list[m0 + q_t], is fixed
-    const int q_t = kGather ? (t & (kLvRows - 1)) : (t / kLvTile);
-    const int c_t = kGather ? (t / kLvRows) : (t & (kLvTile - 1));
-    constexpr int dqi = kGather ? 0 : kBlock / kLvTile;
-    constexpr int dci = kGather ? kBlock / kLvRows : 0;
+    // staging map: element i of thread t is (row q_t, column c_t + i * dci):
+    // lanes along the ring (kLvRows rows), 8 windows per step; the thread's row,
+    // hence its pixel list[m0 + q_t] (gather) or table row m0 + q_t, is fixed
+    const int q_t = t & (kLvRows - 1);
+    const int c_t = t / kLvRows;
+    constexpr int dci = kBlock / kLvRows;
     auto load_chunk = [&](double (&val)[kLvLoads], int32_t m0, int rows) {
-        if (kGather) {
-            const bool ok = q_t < rows;
-            const int64_t p = ok ? list[m0 + q_t] : 0;
+        const bool ok = q_t < rows;
+        const int64_t p = ok ? (kGather ? list[m0 + q_t] : m0 + q_t) : 0;
 #pragma unroll
-            for (int i = 0; i < kLvLoads; ++i) {
-                const int c = c_t + i * dci;
-                val[i] = ok && c < W ? X[(k0 + c) * ld + p] : 0.0;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < kLvLoads; ++i) {
-                const int q = q_t + i * dqi;
-                val[i] = q < rows && c_t < W ? X[static_cast<int64_t>(m0 + q) * ld + k0 + c_t] : 0.0;
-            }
+        for (int i = 0; i < kLvLoads; ++i) {
+            const int c = c_t + i * dci;
+            val[i] = ok && c < W ? X[(k0 + c) * ld + p] : 0.0;
         }
     };
 
@@ -930,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
         const int crow = chunk_rows(ch);
         __syncthreads();  // previous chunk consumed
 #pragma unroll
-        for (int i = 0; i < kLvLoads; ++i) tile[(q_t + i * dqi) * kLvStride + c_t + i * dci] = buf[i];
+        for (int i = 0; i < kLvLoads; ++i) tile[q_t * kLvStride + c_t + i * dci] = buf[i];
         if (ch + 2 < c_end) load_chunk(buf, a + (ch + 2) * kLvRows, chunk_rows(ch + 2));
         __syncthreads();
         // coarser levels of the chunk: thread (row q, group g of 8 level-L windows)
@@ -962,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_chunks(const double *__restrict
             if (g == 0) {
                 row[126] = y6;
                 if (want_next && q < crow)
-                    next[static_cast<int64_t>(mrow + q) * K_next + (k0 >> kLvDepth)] = y6;
+                    next[(k0 >> kLvDepth) * ld + mrow + q] = y6;
             }
         }
         __syncthreads();
@@ -1540,7 +1530,7 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
                                n_q, static_cast<const int32_t *>(P.list), R, P.start, P.grp,
                                static_cast<const int32_t *>(order), tiles, ncol, c1, dst);
         } else {
-            hipLaunchKernelGGL(k_xsvs_chunks<false>, grid, dim3(kBlock), 0, s, src, K, K,
+            hipLaunchKernelGGL(k_xsvs_chunks<false>, grid, dim3(kBlock), 0, s, src, K, n_q,
                                static_cast<const int32_t *>(nullptr), R, P.start, P.grp,
                                static_cast<const int32_t *>(nullptr), tiles, ncol, c1, dst);
         }
