@@ -1057,58 +1057,79 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_mean(const double *__restrict__
 
 // ---------------------------------------------------------------- frame sums, histogram
 
-constexpr int kSumLevels = 24;  // frame sums of up to 2^24 terms
+constexpr int kSumMaxLog = 24;  // frame sums of up to 2^24 terms
 
 // J[k][p] = scale * pairwise tree over i < n_sum of I[k s_out + i s_sum][p]: a binary
 // counter holds the complete subtrees (st[l]: 2^l terms while bit l of n_done
 // is set; a new term merges left + right up the set bits), then the fold from
 // the right, which is the bottom-up tree with the odd element carried up.  The
-// counter is the same in every lane, so its branches are uniform.  Terms are
-// read kSumAhead at a time, so that many loads are in flight per thread.
-constexpr int kSumAhead = 8;
+// counter is the same in every lane, so its branches are uniform.  LV levels hold
+// any n_sum < 2^LV (the host picks the smallest built LV, so the counter takes
+// few registers and more waves fit a SIMD).  A thread owns PX consecutive pixels
+// (one 16-byte load per term for PX = 2, when n_q is even) and reads AHEAD terms
+// at a time, so that several loads are in flight.
+template <int PX> struct SumVec;
+template <> struct SumVec<1> {
+    using T = double;
+    static __device__ double at(const T &v, int) { return v; }
+};
+template <> struct SumVec<2> {
+    using T = double2;
+    static __device__ double at(const T &v, int i) { return i ? v.y : v.x; }
+};
 
+template <int PX, int LV, int AHEAD>
 __global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict__ I, int64_t n_q, int64_t n_out,
                                                        int64_t s_out, int64_t n_sum, int64_t s_sum, double scale,
                                                        double *__restrict__ J) {
+    using V = SumVec<PX>;
+    using T = typename V::T;
+    const int64_t nv = n_q / PX;  // n_q is a multiple of PX
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (idx >= n_out * n_q) return;
-    const int64_t k = idx / n_q, p = idx - k * n_q;
-    double st[kSumLevels];
+    if (idx >= n_out * nv) return;
+    const int64_t k = idx / nv, pv = idx - k * nv;
+    double st[PX][LV];
     int64_t n_done = 0;
-    const double *src = I + k * s_out * n_q + p;
-    const int64_t stride = s_sum * n_q;
-    for (int64_t i0 = 0; i0 < n_sum; i0 += kSumAhead) {
-        double vv[kSumAhead];
+    const T *src = reinterpret_cast<const T *>(I + k * s_out * n_q) + pv;
+    const int64_t stride = s_sum * nv;
+    for (int64_t i0 = 0; i0 < n_sum; i0 += AHEAD) {
+        T vv[AHEAD];
 #pragma unroll
-        for (int u = 0; u < kSumAhead; ++u) vv[u] = i0 + u < n_sum ? src[(i0 + u) * stride] : 0.0;
+        for (int u = 0; u < AHEAD; ++u) vv[u] = i0 + u < n_sum ? src[(i0 + u) * stride] : T{};
 #pragma unroll
-        for (int u = 0; u < kSumAhead; ++u) {
+        for (int u = 0; u < AHEAD; ++u) {
             if (i0 + u >= n_sum) break;  // uniform
-            double v = vv[u];
-            bool carry = true;
 #pragma unroll
-            for (int l = 0; l < kSumLevels; ++l) {
-                if (carry) {
-                    if ((n_done >> l) & 1) {
-                        v = st[l] + v;
-                    } else {
-                        st[l] = v;
-                        carry = false;
+            for (int x = 0; x < PX; ++x) {
+                double v = V::at(vv[u], x);
+                bool carry = true;
+#pragma unroll
+                for (int l = 0; l < LV; ++l) {
+                    if (carry) {
+                        if ((n_done >> l) & 1) {
+                            v = st[x][l] + v;
+                        } else {
+                            st[x][l] = v;
+                            carry = false;
+                        }
                     }
                 }
             }
             ++n_done;
         }
     }
-    double sum = 0.0;
-    bool have = false;
 #pragma unroll
-    for (int l = 0; l < kSumLevels; ++l)
-        if ((n_done >> l) & 1) {
-            sum = have ? st[l] + sum : st[l];
-            have = true;
-        }
-    J[idx] = sum * scale;
+    for (int x = 0; x < PX; ++x) {
+        double sum = 0.0;
+        bool have = false;
+#pragma unroll
+        for (int l = 0; l < LV; ++l)
+            if ((n_done >> l) & 1) {
+                sum = have ? st[x][l] + sum : st[x][l];
+                have = true;
+            }
+        J[k * n_q + pv * PX + x] = sum * scale;
+    }
 }
 
 // Ring-ordered rows of the frames: X[m][t] = I[t][list[m]] for the in-ring
@@ -1560,10 +1581,25 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
 
 xs_status frame_sums(hipStream_t s, const double *I, int64_t n_q, int64_t n_out, int64_t s_out, int64_t n_sum,
                      int64_t s_sum, double scale, double *J) {
-    if (n_sum > (int64_t(1) << kSumLevels)) return set_error(XS_EINVAL, "n_sum must be <= 2^%d", kSumLevels);
-    if (n_out * n_q > 0)
-        hipLaunchKernelGGL(k_frame_sums, dim3(blocks_for(n_out * n_q)), dim3(kBlock), 0, s, I, n_q, n_out, s_out,
-                           n_sum, s_sum, scale, J);
+    if (n_sum > (int64_t(1) << kSumMaxLog)) return set_error(XS_EINVAL, "n_sum must be <= 2^%d", kSumMaxLog);
+    if (n_out * n_q > 0) {
+        // counter levels: n_sum < 2^LV
+        const int lv = n_sum < 64 ? 6 : n_sum < 4096 ? 12 : kSumMaxLog + 1;
+        const bool pair = n_q % 2 == 0 && reinterpret_cast<uintptr_t>(I) % 16 == 0;
+        const dim3 grid(blocks_for(n_out * (pair ? n_q / 2 : n_q)));
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, I, n_q, n_out, s_out, n_sum, s_sum, scale, J);
+        };
+        if (pair) {
+            if (lv == 6) go(k_frame_sums<2, 6, 2>);
+            else if (lv == 12) go(k_frame_sums<2, 12, 2>);
+            else go(k_frame_sums<2, kSumMaxLog + 1, 2>);
+        } else {
+            if (lv == 6) go(k_frame_sums<1, 6, 4>);
+            else if (lv == 12) go(k_frame_sums<1, 12, 4>);
+            else go(k_frame_sums<1, kSumMaxLog + 1, 4>);
+        }
+    }
     XS_HIP(hipGetLastError());
     return XS_OK;
 }

@@ -23,7 +23,11 @@ def api():
     (40, 777, 33, 1, 8, 1, 2),        # sliding windows of 8
     (30, 513, 10, 1, 3, 10, 3),       # 3 configurations x 10 frames, incoherent sum
     (5, 64, 5, 1, 1, 0, 4),           # n_sum = 1: a copy
-    (1200, 65, 1, 0, 1021, 1, 5)])    # one long odd sum
+    (1200, 65, 1, 0, 1021, 1, 5),     # one long odd sum
+    (70, 10, 2, 1, 63, 1, 6),         # the largest sum of the 6-level counter, pixel pairs
+    (300, 100, 2, 100, 64, 1, 7),     # the smallest of the 12-level counter, pixel pairs
+    (4200, 7, 2, 100, 4095, 1, 8),    # the largest of the 12-level counter, single pixels
+    (4200, 6, 1, 0, 4096, 1, 9)])     # the 25-level counter, pixel pairs
 def test_frame_sums_bitwise(api, F, Q, n_out, s_out, n_sum, s_sum, seed):
     from _gpu import dev, host, bitwise_equal
     rng = np.random.default_rng(seed)
@@ -32,6 +36,19 @@ def test_frame_sums_bitwise(api, F, Q, n_out, s_out, n_sum, s_sum, seed):
           flush=True)
     J = api.frame_sums(dev(I), n_out, s_out, n_sum, s_sum)
     assert bitwise_equal(host(J), oracle.frame_sums(I, n_out, s_out, n_sum, s_sum))
+
+
+def test_frame_sums_of_the_largest_count(api):
+    """n_sum = 2^24, the largest count the call takes: every level of the counter is
+    merged by the last term, whose sum must still reach the output."""
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(10)
+    F = 1 << 24
+    I = rng.exponential(1.0, (F, 2))
+    print("frame sums F=%d Q=2 n_sum=%d" % (F, F), flush=True)
+    J = api.frame_sums(dev(I), 1, 0, F, 1)
+    assert bitwise_equal(host(J), oracle.frame_sums(I, 1, 0, F, 1))
+    assert abs(host(J)[0, 0] / F - 1.0) < 1e-2
 
 
 def test_frame_sums_reject_out_of_range(api):
