@@ -401,6 +401,7 @@ def run_grad(args, form="per-pair"):
             "fma32_lane_ops_per_s": api.roofline_probe(1),
             "fma64_lane_ops_per_s": api.roofline_probe(2),
             "copy_bytes_per_s": api.roofline_probe(3, 1 << 30),
+            "read_bytes_per_s": api.roofline_probe(6, 1 << 31),
             "f16_mfma_flops_per_s": api.roofline_probe(4),
             "f16_mfma_flops_per_s_with_8_fma32_each": api.roofline_probe(5),
         }

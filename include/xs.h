@@ -537,6 +537,8 @@ xs_status xs_timing_read(int32_t kind, double *total_ms, int64_t *launches, doub
  *   kind 4: FP16 matrix flops per second (v_mfma_f32_32x32x16_f16)
  *   kind 5: the same, each matrix instruction followed by 8 independent FP32
  *           FMAs of the same wavefront (equal to kind 4 if the two overlap)
+ *   kind 6: HBM bytes per second of a plain read of `bytes`
+ * Kinds 3 and 6 keep four 16-byte loads per thread in flight.
  * `rate` is a host double.  Uses the library's scratch memory.
  */
 xs_status xs_roofline_probe(int32_t kind, int64_t bytes, double *rate, void *stream);

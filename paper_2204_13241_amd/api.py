@@ -493,7 +493,8 @@ def timing_read(kind) -> dict:
 
 
 def roofline_probe(kind: int, nbytes: int = 1 << 30) -> float:
-    """0: sin+cos lane-ops/s, 1: FP32 FMA lane-ops/s, 2: FP64 FMA lane-ops/s, 3: copy bytes/s."""
+    """0: sin+cos lane-ops/s, 1: FP32 FMA lane-ops/s, 2: FP64 FMA lane-ops/s, 3: copy bytes/s
+    (read + write), 4: FP16 matrix flops/s, 5: the same beside FP32 FMAs, 6: read bytes/s."""
     r = ctypes.c_double(0.0)
     _lib.check(_lib.load().xs_roofline_probe(int(kind), int(nbytes), ctypes.byref(r), _stream()))
     return r.value

@@ -165,11 +165,44 @@ __global__ __launch_bounds__(kBlock) void k_probe_mfma(float *sink, int iters) {
     if (r == 12345.678f) sink[threadIdx.x] = r;
 }
 
+// Streaming probes: each block takes runs of kProbeRun * kBlock 16-byte elements
+// (grid-stride), every thread with kProbeRun loads in flight.  Copy: b = a.  Read:
+// the elements summed into a value that is stored only if it hits a sentinel.
+constexpr int kProbeRun = 4;
+
 __global__ __launch_bounds__(kBlock) void k_probe_copy(const float4 *__restrict__ a,
                                                        float4 *__restrict__ b, int64_t n) {
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kBlock)
-        b[i] = a[i];
+    const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock * kProbeRun;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock * kProbeRun; base < n; base += step) {
+        float4 v[kProbeRun];
+#pragma unroll
+        for (int u = 0; u < kProbeRun; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            v[u] = i < n ? a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeRun; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            if (i < n) b[i] = v[u];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_probe_read(const float4 *__restrict__ a, float *__restrict__ sink,
+                                                       int64_t n) {
+    const int64_t step = static_cast<int64_t>(gridDim.x) * kBlock * kProbeRun;
+    float acc = 0.f;
+    for (int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock * kProbeRun; base < n; base += step) {
+        float4 v[kProbeRun];
+#pragma unroll
+        for (int u = 0; u < kProbeRun; ++u) {
+            const int64_t i = base + u * kBlock + threadIdx.x;
+            v[u] = i < n ? a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kProbeRun; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    if (acc == 12345.678f) sink[threadIdx.x] = acc;
 }
 
 }  // namespace
@@ -292,6 +325,7 @@ xs_status position_step(hipStream_t s, double *pos, const float *g32, const doub
 // ---------------------------------------------------------------- probes
 
 xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate) {
+    if (kind < 0 || kind > 6 || !rate) return set_error(XS_EINVAL, "probe kind must be 0..6, rate non-NULL");
     int dev = 0, cus = 0;
     XS_HIP(hipGetDevice(&dev));
     XS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -339,10 +373,23 @@ xs_status roofline_probe(hipStream_t s, int kind, int64_t bytes, double *rate) {
                                static_cast<float4 *>(sink), nv);
         XS_HIP(hipEventRecord(e1, s));
         ops = 5.0 * 2.0 * static_cast<double>(nv) * 16.0;  // bytes read + written
+    } else if (kind == 6) {
+        if (bytes < 16) bytes = 16;
+        const int64_t nv = bytes / 16;
+        XS_TRY(scratch(s, SLOT_LEVEL_A, nv * 16, &src));
+        XS_TRY(scratch(s, SLOT_BWIN, sizeof(double) * kBlock, &sink));
+        hipLaunchKernelGGL(k_probe_read, dim3(cus * 32), dim3(kBlock), 0, s, static_cast<const float4 *>(src),
+                           static_cast<float *>(sink), nv);
+        XS_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 5; ++r)
+            hipLaunchKernelGGL(k_probe_read, dim3(cus * 32), dim3(kBlock), 0, s, static_cast<const float4 *>(src),
+                               static_cast<float *>(sink), nv);
+        XS_HIP(hipEventRecord(e1, s));
+        ops = 5.0 * static_cast<double>(nv) * 16.0;  // bytes read
     } else {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        return set_error(XS_EINVAL, "probe kind must be 0..5");
+        return set_error(XS_EINVAL, "probe kind must be 0..6");
     }
     XS_HIP(hipGetLastError());
     XS_HIP(hipEventSynchronize(e1));

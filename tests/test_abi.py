@@ -54,6 +54,10 @@ def test_validation_errors_without_device_work():
     # xsvs: window longer than the series
     rc, msg = _status(lib.xs_xsvs_contrast(None, 4, 0, None, edges, 2, 4, ctypes.c_void_p(1), None, None))
     assert rc == _lib.XS_EINVAL and "n_levels" in msg
+    # roofline probe: unknown kind
+    rate = ctypes.c_double(0.0)
+    rc, msg = _status(lib.xs_roofline_probe(7, 0, ctypes.byref(rate), None))
+    assert rc == _lib.XS_EINVAL and "kind" in msg
 
 
 def test_batch_validation():
