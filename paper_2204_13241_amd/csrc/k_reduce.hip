@@ -171,12 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p, in
         p[i] = v;
 }
 
-// Ring of each pixel: r with e_r <= |q| < e_{r+1}, |q| = sqrt(fma(qz,qz,fma(qy,qy,qx*qx))),
+// Ring of pixel p: r with e_r <= |q| < e_{r+1}, |q| = sqrt(fma(qz,qz,fma(qy,qy,qx*qx))),
 // else -1.
-__global__ __launch_bounds__(kBlock) void k_ring_key(const double *__restrict__ q, int64_t n_q,
-                                                     RingEdges edges, int32_t *__restrict__ key) {
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (p >= n_q) return;
+__device__ __forceinline__ int32_t ring_index(const double *__restrict__ q, int64_t p, const RingEdges &edges) {
     const double qx = q[3 * p], qy = q[3 * p + 1], qz = q[3 * p + 2];
     const double qn = __builtin_sqrt(__builtin_fma(qz, qz, __builtin_fma(qy, qy, qx * qx)));
     int32_t r = -1;
@@ -188,7 +185,14 @@ __global__ __launch_bounds__(kBlock) void k_ring_key(const double *__restrict__ 
         }
         r = lo;
     }
-    key[p] = r;
+    return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ring_key(const double *__restrict__ q, int64_t n_q,
+                                                     RingEdges edges, int32_t *__restrict__ key) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= n_q) return;
+    key[p] = ring_index(q, p, edges);
 }
 
 // Per-block ring counts: cnt[b * R + r] = #pixels of block b with key r.
@@ -344,10 +348,12 @@ __device__ __forceinline__ void stage_series(T *lds, const T *__restrict__ src, 
     }
 }
 
-// Per pixel: S = sum_t I_t (sequential), mean = S / F, den = mean^2; pixels
-// with den = 0 leave the ring partition (key -1).
+// Per pixel: S = sum_t I_t (sequential), mean = S / F, den = mean^2, and the
+// pixel's ring key (-1 outside the rings or for den = 0: such a pixel leaves the
+// ring partition).
 __global__ __launch_bounds__(kBlock) void k_pixel_mean(const double *__restrict__ I, int64_t F,
-                                                       int64_t n_q, int32_t *__restrict__ key,
+                                                       int64_t n_q, const double *__restrict__ q,
+                                                       RingEdges edges, int32_t *__restrict__ key,
                                                        double *__restrict__ den) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (p >= n_q) return;
@@ -357,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_pixel_mean(const double *__restrict_
     const double mean = S / static_cast<double>(F);
     const double d = mean * mean;
     den[p] = d;
-    if (d == 0.0) key[p] = -1;
+    key[p] = d == 0.0 ? -1 : ring_index(q, p, edges);
 }
 
 // G[rank[p]][tau] = (sum_{t < F - tau} fma-accumulated I_t I_{t+tau} / (F - tau)) / den_p.
@@ -1296,8 +1302,7 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
     int32_t *k = static_cast<int32_t *>(key);
     double *dn = static_cast<double *>(den);
     if (n_q > 0) {
-        hipLaunchKernelGGL(k_ring_key, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, q, n_q, edges, k);
-        hipLaunchKernelGGL(k_pixel_mean, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, I, F, n_q, k, dn);
+        hipLaunchKernelGGL(k_pixel_mean, dim3(blocks_for(n_q)), dim3(kBlock), 0, s, I, F, n_q, q, edges, k, dn);
         XS_HIP(hipGetLastError());
     }
     Partition P;
