@@ -356,13 +356,21 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(const BinSeg *__restric
 }
 
 // Each cell's atoms in ascending index order (after the scatter, cursor[c]
-// is the end of cell c).
+// is the end of cell c): one thread per cell sorts a cell of up to kOrderSmall
+// atoms by insertion; a larger cell (strongly clustered positions) is appended to
+// big[1 ..] (big[0] counts them) for k_cell_order_big.
+constexpr int kOrderSmall = 64;
+
 __global__ __launch_bounds__(kBlock) void k_cell_order(const int32_t *__restrict__ start,
                                                        const int32_t *__restrict__ end, int64_t n,
-                                                       int32_t *__restrict__ sorted) {
+                                                       int32_t *__restrict__ sorted, int32_t *__restrict__ big) {
     const int64_t c = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (c >= n) return;
     const int32_t a = start[c], b = end[c];
+    if (b - a > kOrderSmall) {
+        big[1 + atomicAdd(&big[0], 1)] = static_cast<int32_t>(c);
+        return;
+    }
     for (int32_t i = a + 1; i < b; ++i) {
         const int32_t x = sorted[i];
         int32_t k = i - 1;
@@ -371,6 +379,80 @@ __global__ __launch_bounds__(kBlock) void k_cell_order(const int32_t *__restrict
             --k;
         }
         sorted[k + 1] = x;
+    }
+}
+
+// The large cells listed in big[]: a block per cell ranks the cell's atom indices
+// with a bitmap over its segment's index range, in windows of kRankWords * 32
+// indices.  Per window: bit x - w0 set for each atom x of the cell in the window,
+// an exclusive scan of the words' popcounts, then atom x goes to the cell start +
+// the cell's atoms in earlier windows + the set bits below it.  Linear in the
+// cell's atoms times the windows plus the segment's atom count; the cell's
+// unordered atoms are first copied to tmp (sorted[] is overwritten as they move).
+constexpr int kRankWords = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_cell_order_big(const BinSeg *__restrict__ segs, int32_t n_seg,
+                                                           const int32_t *__restrict__ start,
+                                                           const int32_t *__restrict__ end,
+                                                           const int32_t *__restrict__ big,
+                                                           int32_t *__restrict__ tmp, int32_t *__restrict__ sorted) {
+    constexpr int kPer = kRankWords / kBlock;
+    constexpr int kSpan = kRankWords * 32;
+    __shared__ uint32_t bits[kRankWords];
+    __shared__ int32_t pre[kRankWords];
+    __shared__ int32_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t n_big = big[0];
+    for (int32_t e = blockIdx.x; e < n_big; e += gridDim.x) {
+        const int32_t c = big[1 + e];
+        const int32_t a = start[c], b = end[c];
+        int lo = 0, hi = n_seg;  // the segment of cell c: the last with cell0 <= c
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segs[mid].cell0 <= c) lo = mid; else hi = mid;
+        }
+        const int32_t n_atoms = segs[lo].n_atoms;
+        for (int32_t i = a + static_cast<int32_t>(threadIdx.x); i < b; i += kBlock) tmp[i] = sorted[i];
+        __syncthreads();
+        int32_t below = 0;  // the cell's atoms in earlier windows
+        for (int32_t w0 = 0; w0 < n_atoms; w0 += kSpan) {
+            for (int k = threadIdx.x; k < kRankWords; k += kBlock) bits[k] = 0u;
+            __syncthreads();
+            for (int32_t i = a + static_cast<int32_t>(threadIdx.x); i < b; i += kBlock) {
+                const int32_t x = tmp[i] - w0;
+                if (x >= 0 && x < kSpan) atomicOr(&bits[x >> 5], 1u << (x & 31));
+            }
+            __syncthreads();
+            // exclusive scan of the popcounts: thread t takes words [kPer t, kPer t + kPer)
+            int32_t own = 0;
+            for (int k = 0; k < kPer; ++k) own += __builtin_popcount(bits[threadIdx.x * kPer + k]);
+            int32_t inc = own;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int32_t y = __shfl_up(inc, off);
+                if (lane >= off) inc += y;
+            }
+            if (lane == 63) wsum[wave] = inc;
+            __syncthreads();
+            int32_t run = inc - own, total = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                if (w < wave) run += wsum[w];
+                total += wsum[w];
+            }
+            for (int k = 0; k < kPer; ++k) {
+                pre[threadIdx.x * kPer + k] = run;
+                run += __builtin_popcount(bits[threadIdx.x * kPer + k]);
+            }
+            __syncthreads();
+            for (int32_t i = a + static_cast<int32_t>(threadIdx.x); i < b; i += kBlock) {
+                const int32_t x = tmp[i] - w0;
+                if (x >= 0 && x < kSpan) {
+                    const uint32_t below_x = bits[x >> 5] & ((1u << (x & 31)) - 1u);
+                    sorted[a + below + pre[x >> 5] + __builtin_popcount(below_x)] = tmp[i];
+                }
+            }
+            below += total;
+            __syncthreads();  // bits, pre and wsum are rewritten by the next window
+        }
     }
 }
 
@@ -2016,6 +2098,9 @@ int bits_for(int64_t n) {
     return b;
 }
 
+// Cells with more than kOrderSmall atoms, at most.
+int64_t big_cells_bound(int64_t atoms) { return atoms / (kOrderSmall + 1) + 1; }
+
 template <typename T>
 std::vector<T> largest_first(const std::vector<T> &items, const std::vector<int64_t> &cost) {
     std::vector<int> order(items.size());
@@ -2069,6 +2154,7 @@ struct Plan::Buffers {
     FwdItem *mitems = nullptr;
     int32_t *counters = nullptr;
     int32_t *hist = nullptr, *start = nullptr, *cursor = nullptr, *scan_sums = nullptr;
+    int32_t *big = nullptr;  // [0] large cells found, [1 ..] their indices (after hist)
     double *segbox = nullptr, *boxpart = nullptr;
     uint32_t *keys = nullptr;
     int32_t *sorted = nullptr;
@@ -2525,7 +2611,9 @@ size_t Plan::layout(char *base) {
     // sub-batch k, [3 + sub-batches] and [4 + sub-batches] matrix-core gradient (2 and 3 components)
     b.counters = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.gsub_seg0.size() + kFwdCounters + 2)));
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
-    b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
+    // hist, then the large-cell count and list (cleared with hist: count only)
+    b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.cells + 1 + big_cells_bound(t.atoms))));
+    b.big = b.hist + t.cells;
     b.segbox = reinterpret_cast<double *>(take(sizeof(double) * 6 * t.bsegs.size()));
     b.boxpart = reinterpret_cast<double *>(take(sizeof(double) * 6 * kBoxParts * t.bsegs.size()));
     b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
@@ -2642,7 +2730,7 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
     TimerScope tm(s, TIMER_BIN);
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     const unsigned zb = static_cast<unsigned>(std::min<int64_t>((t.cells + kBlock - 1) / kBlock, 4096));
-    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(kBlock), 0, s, b.hist, t.cells);
+    hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(kBlock), 0, s, b.hist, t.cells + 1);
     hipLaunchKernelGGL(k_seg_bbox_part, dim3(kBoxParts, n_seg), dim3(kBlock), 0, s, b.bsegs, pos, b.boxpart);
     hipLaunchKernelGGL(k_seg_bbox, dim3(n_seg), dim3(64), 0, s, b.boxpart, b.segbox);
     const dim3 ga((t.max_atoms + kBlock - 1) / kBlock, n_seg);
@@ -2653,7 +2741,11 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
                        b.cursor);
     hipLaunchKernelGGL(k_cell_scatter, ga, dim3(kBlock), 0, s, b.bsegs, b.keys, b.cursor, b.sorted);
     hipLaunchKernelGGL(k_cell_order, dim3((t.cells + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b.start,
-                       b.cursor, t.cells, b.sorted);
+                       b.cursor, t.cells, b.sorted, b.big);
+    // large cells, if any (the cell keys are no longer needed: their buffer holds the copies)
+    hipLaunchKernelGGL(k_cell_order_big, dim3(static_cast<unsigned>(std::min<int64_t>(big_cells_bound(t.atoms), 256))),
+                       dim3(kBlock), 0, s, b.bsegs, static_cast<int32_t>(n_seg), b.start, b.cursor, b.big,
+                       reinterpret_cast<int32_t *>(b.keys), b.sorted);
     hipLaunchKernelGGL(k_make_tiles, dim3((t.max_tiles + kWaves - 1) / kWaves, n_seg), dim3(kBlock), 0, s,
                        b.bsegs, pos, f, b.sorted, b.t_hi, b.t_lo, b.origins, b.tile_atom);
     tm.end(static_cast<double>(t.atoms));
