@@ -200,20 +200,30 @@ __global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *__restrict__ p, in
         p[i] = 0;
 }
 
-// Bounding box of every segment's positions, in two passes: kBoxParts blocks per segment
-// reduce strided chunks (NaN coordinates are skipped by fmin / fmax), then one block per
-// segment folds their partials: box[6 s + c] = lo_c, box[6 s + 3 + c] = hi_c.  The cell
-// grid spans this box, so positions anywhere (wrapped into the simulation cell or not)
-// give compact cells and tiles.
+// Bounding box of every segment's positions (and of every pixel set's q-vectors), in
+// two passes: kBoxParts blocks per set reduce strided chunks (NaN coordinates are
+// skipped by fmin / fmax), then one block per set folds their partials: box[6 s + c] =
+// lo_c, box[6 s + 3 + c] = hi_c.  The cell grid spans this box, so positions anywhere
+// (wrapped into the simulation cell or not) give compact cells and tiles.
 constexpr int kBoxParts = 64;
-__global__ __launch_bounds__(kBlock) void k_seg_bbox_part(const BinSeg *__restrict__ segs,
-                                                          const double *__restrict__ pos,
-                                                          double *__restrict__ part) {
-    const BinSeg sg = segs[blockIdx.y];
+__device__ __forceinline__ int64_t points_of(const BinSeg &s, int64_t &n) {
+    n = s.n_atoms;
+    return s.pos;
+}
+__device__ __forceinline__ int64_t points_of(const PixSet &s, int64_t &n) {
+    n = s.n_q;
+    return s.q;
+}
+
+template <typename Set>
+__global__ __launch_bounds__(kBlock) void k_bbox_part(const Set *__restrict__ sets, const double *__restrict__ xyz,
+                                                      double *__restrict__ part) {
+    int64_t n = 0;
+    const int64_t first = points_of(sets[blockIdx.y], n);
     __shared__ double s_lo[3][kBlock], s_hi[3][kBlock];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int j = blockIdx.x * kBlock + threadIdx.x; j < sg.n_atoms; j += kBoxParts * kBlock) {
-        const double *r = pos + (sg.pos + j) * 3;
+    for (int64_t j = blockIdx.x * kBlock + threadIdx.x; j < n; j += kBoxParts * kBlock) {
+        const double *r = xyz + (first + j) * 3;
         for (int c = 0; c < 3; ++c) {
             lo[c] = fmin(lo[c], r[c]);
             hi[c] = fmax(hi[c], r[c]);
@@ -239,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_bbox_part(const BinSeg *__restri
     }
 }
 
-__global__ __launch_bounds__(64) void k_seg_bbox(const double *__restrict__ part, double *__restrict__ box) {
+__global__ __launch_bounds__(64) void k_bbox_fold(const double *__restrict__ part, double *__restrict__ box) {
     if (threadIdx.x >= 3) return;
     const int c = threadIdx.x;
     double l = INFINITY, h = -INFINITY;
@@ -248,7 +258,7 @@ __global__ __launch_bounds__(64) void k_seg_bbox(const double *__restrict__ part
         l = fmin(l, o[c]);
         h = fmax(h, o[3 + c]);
     }
-    const bool ok = l <= h;  // false for a segment without finite positions
+    const bool ok = l <= h;  // false for a set without finite coordinates
     box[6 * blockIdx.x + c] = ok ? l : 0.0;
     box[6 * blockIdx.x + 3 + c] = ok ? h : 0.0;
 }
@@ -458,37 +468,6 @@ __global__ __launch_bounds__(kBlock) void k_cell_order_big(const BinSeg *__restr
 
 // Pixel sets: bounding box (one block per set), then 64-bit keys
 // (set << 30 | Hilbert index of the q cell) for a radix sort.
-__global__ __launch_bounds__(1024) void k_pix_bbox(const PixSet *__restrict__ sets,
-                                                   const double *__restrict__ q,
-                                                   double *__restrict__ bbox) {
-    const PixSet ps = sets[blockIdx.x];
-    __shared__ double s_lo[3][1024], s_hi[3][1024];
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int p = threadIdx.x; p < ps.n_q; p += 1024)
-        for (int c = 0; c < 3; ++c) {
-            const double v = q[(ps.q + p) * 3 + c];
-            lo[c] = fmin(lo[c], v);
-            hi[c] = fmax(hi[c], v);
-        }
-    for (int c = 0; c < 3; ++c) {
-        s_lo[c][threadIdx.x] = lo[c];
-        s_hi[c][threadIdx.x] = hi[c];
-    }
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if (threadIdx.x < off)
-            for (int c = 0; c < 3; ++c) {
-                s_lo[c][threadIdx.x] = fmin(s_lo[c][threadIdx.x], s_lo[c][threadIdx.x + off]);
-                s_hi[c][threadIdx.x] = fmax(s_hi[c][threadIdx.x], s_hi[c][threadIdx.x + off]);
-            }
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) {
-        bbox[6 * blockIdx.x + threadIdx.x] = s_lo[threadIdx.x][0];
-        bbox[6 * blockIdx.x + 3 + threadIdx.x] = s_hi[threadIdx.x][0];
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_pix_keys(const PixSet *__restrict__ sets,
                                                      const double *__restrict__ q,
                                                      const double *__restrict__ bbox,
@@ -501,11 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_pix_keys(const PixSet *__restrict__ 
     for (int d = 0; d < 3; ++d) {
         const double lo = bbox[6 * blockIdx.y + d], hi = bbox[6 * blockIdx.y + 3 + d];
         const double span = hi - lo;
-        const double scale = span > 0.0 ? 1024.0 / (span * 1.000001) : 0.0;
-        c[d] = cell_of(q[(ps.q + p) * 3 + d] - lo, scale, 10);
+        const double scale = span > 0.0 ? double(1 << kHilbertBits) / (span * 1.000001) : 0.0;
+        c[d] = cell_of(q[(ps.q + p) * 3 + d] - lo, scale, kHilbertBits);
     }
-    const uint64_t h = ps.lattice ? static_cast<uint64_t>(p) : hilbert3(c[0], c[1], c[2], 10);
-    keys[ps.slot0 + p] = (static_cast<uint64_t>(blockIdx.y) << 30) | h;
+    const uint64_t h = ps.lattice ? static_cast<uint64_t>(p) : hilbert3(c[0], c[1], c[2], kHilbertBits);
+    keys[ps.slot0 + p] = (static_cast<uint64_t>(blockIdx.y) << (3 * kHilbertBits)) | h;
     vals[ps.slot0 + p] = p;
 }
 
@@ -2580,7 +2559,7 @@ xs_status Plan::build(const Segment *segs, int n_segs, const double *box, const 
         XS_HIP(rocprim::radix_sort_pairs(nullptr, bytes, static_cast<const uint64_t *>(nullptr),
                                          static_cast<uint64_t *>(nullptr), static_cast<const int32_t *>(nullptr),
                                          static_cast<int32_t *>(nullptr), static_cast<unsigned int>(t.slots), 0,
-                                         30 + bits_for(static_cast<int64_t>(t.psets.size())), nullptr));
+                                         3 * kHilbertBits + bits_for(static_cast<int64_t>(t.psets.size())), nullptr));
         t.sort_tmp = bytes;
     }
     return XS_OK;
@@ -2615,7 +2594,8 @@ size_t Plan::layout(char *base) {
     b.hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (t.cells + 1 + big_cells_bound(t.atoms))));
     b.big = b.hist + t.cells;
     b.segbox = reinterpret_cast<double *>(take(sizeof(double) * 6 * t.bsegs.size()));
-    b.boxpart = reinterpret_cast<double *>(take(sizeof(double) * 6 * kBoxParts * t.bsegs.size()));
+    b.boxpart = reinterpret_cast<double *>(
+        take(sizeof(double) * 6 * kBoxParts * std::max(t.bsegs.size(), t.psets.size())));
     b.start = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.cursor = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * t.cells));
     b.scan_sums = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nsb));
@@ -2709,12 +2689,13 @@ xs_status Plan::sort_pixels(hipStream_t s, const double *q) {
     Buffers &b = *B;
     if (t.slots == 0) return XS_OK;
     const int n_sets = static_cast<int>(t.psets.size());
-    hipLaunchKernelGGL(k_pix_bbox, dim3(n_sets), dim3(1024), 0, s, b.psets, q, b.pbbox);
+    hipLaunchKernelGGL(k_bbox_part<PixSet>, dim3(kBoxParts, n_sets), dim3(kBlock), 0, s, b.psets, q, b.boxpart);
+    hipLaunchKernelGGL(k_bbox_fold, dim3(n_sets), dim3(64), 0, s, b.boxpart, b.pbbox);
     hipLaunchKernelGGL(k_pix_keys, dim3((t.max_set_q + kBlock - 1) / kBlock, n_sets), dim3(kBlock), 0, s,
                        b.psets, q, b.pbbox, b.pk, b.pv);
     size_t bytes = t.sort_tmp;
     XS_HIP(rocprim::radix_sort_pairs(b.sort_tmp, bytes, b.pk, b.pk2, b.pv, b.pix_order,
-                                     static_cast<unsigned int>(t.slots), 0, 30 + bits_for(n_sets), s));
+                                     static_cast<unsigned int>(t.slots), 0, 3 * kHilbertBits + bits_for(n_sets), s));
     XS_HIP(hipGetLastError());
     return XS_OK;
 }
@@ -2731,8 +2712,8 @@ xs_status Plan::tile_atoms(hipStream_t s, const double *pos, const double *f) {
     const int64_t nsb = (t.cells + kScanBlock - 1) / kScanBlock;
     const unsigned zb = static_cast<unsigned>(std::min<int64_t>((t.cells + kBlock - 1) / kBlock, 4096));
     hipLaunchKernelGGL(k_zero_i32, dim3(zb), dim3(kBlock), 0, s, b.hist, t.cells + 1);
-    hipLaunchKernelGGL(k_seg_bbox_part, dim3(kBoxParts, n_seg), dim3(kBlock), 0, s, b.bsegs, pos, b.boxpart);
-    hipLaunchKernelGGL(k_seg_bbox, dim3(n_seg), dim3(64), 0, s, b.boxpart, b.segbox);
+    hipLaunchKernelGGL(k_bbox_part<BinSeg>, dim3(kBoxParts, n_seg), dim3(kBlock), 0, s, b.bsegs, pos, b.boxpart);
+    hipLaunchKernelGGL(k_bbox_fold, dim3(n_seg), dim3(64), 0, s, b.boxpart, b.segbox);
     const dim3 ga((t.max_atoms + kBlock - 1) / kBlock, n_seg);
     hipLaunchKernelGGL(k_cell_keys, ga, dim3(kBlock), 0, s, b.bsegs, pos, b.segbox, b.keys, b.hist);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kBlock), 0, s, b.hist, t.cells, b.scan_sums);

@@ -38,6 +38,20 @@ def test_frame_sums_bitwise(api, F, Q, n_out, s_out, n_sum, s_sum, seed):
     assert bitwise_equal(host(J), oracle.frame_sums(I, n_out, s_out, n_sum, s_sum))
 
 
+def test_frame_sums_on_an_unaligned_tensor(api):
+    """An even pixel count whose tensor starts 8 bytes past a 16-byte boundary (a view one
+    element into its storage): the sums take the one-pixel path, bit for bit."""
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(11)
+    F, Q = 40, 100
+    I = rng.exponential(1.0, (F, Q))
+    flat = dev(np.concatenate([[0.0], I.ravel()]))
+    Iv = flat[1:].view(F, Q)
+    assert Iv.is_contiguous() and Iv.data_ptr() % 16 == 8
+    J = api.frame_sums(Iv, 5, 8, 8, 1)
+    assert bitwise_equal(host(J), oracle.frame_sums(I, 5, 8, 8, 1))
+
+
 def test_frame_sums_of_the_largest_count(api):
     """n_sum = 2^24, the largest count the call takes: every level of the counter is
     merged by the last term, whose sum must still reach the output."""
