@@ -165,12 +165,6 @@ __global__ __launch_bounds__(kBlock) void k_group_tree(const double *__restrict_
 
 // ---------------------------------------------------------------- partition
 
-__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kBlock)
-        p[i] = v;
-}
-
 // Ring of pixel p: r with e_r <= |q| < e_{r+1}, |q| = sqrt(fma(qz,qz,fma(qy,qy,qx*qx))),
 // else -1.
 __device__ __forceinline__ int32_t ring_index(const double *__restrict__ q, int64_t p, const RingEdges &edges) {
@@ -277,11 +271,11 @@ __global__ __launch_bounds__(kBlock) void k_tree_offsets(const int32_t *__restri
 }
 
 // Stable ranks: the pixels of ring r get ranks ring_start[r], ring_start[r] + 1, ...
-// in ascending pixel index, and list[rank[p]] = p.  Wave w of the block takes
-// pixels [256 w, 256 w + 256) of the block's 1024 in four steps of 64: lanes of
-// one key are found with a ballot per distinct key, ranked by their position
-// in the ballot, and the wave's per-ring running counts kept in LDS; the
-// counts of the earlier waves then give each wave's starting offsets.
+// in ascending pixel index, and list[rank[p]] = p; a pixel of key -1 gets rank -1.
+// Wave w of the block takes pixels [256 w, 256 w + 256) of the block's 1024 in four
+// steps of 64: lanes of one key are found with a ballot per distinct key, ranked by
+// their position in the ballot, and the wave's per-ring running counts kept in LDS;
+// the counts of the earlier waves then give each wave's starting offsets.
 __global__ __launch_bounds__(kBlock) void k_part_rank(const int32_t *__restrict__ key, int64_t n_q,
                                                       int32_t R, const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ ring_start,
@@ -313,7 +307,10 @@ __global__ __launch_bounds__(kBlock) void k_part_rank(const int32_t *__restrict_
     __syncthreads();
     for (int st = 0; st < kSteps; ++st) {
         const int64_t p = base + st * 64 + lane;
-        if (k[st] < 0) continue;
+        if (k[st] < 0) {
+            if (p < n_q) rank[p] = -1;  // outside every ring
+            continue;
+        }
         int32_t o = ring_start[k[st]] + off[static_cast<int64_t>(blockIdx.x) * R + k[st]] + within[st];
         for (int w = 0; w < wave; ++w) o += run[w][k[st]];
         rank[p] = o;
@@ -1257,11 +1254,8 @@ xs_status partition(Arena &A, const int32_t *key, int64_t n_q, int32_t R, Partit
     P->rank = static_cast<int32_t *>(rk);
     P->list = P->rank + std::max<int64_t>(n_q, 1);
     P->levels = levels;
-    if (n_q > 0) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(std::min<unsigned>(blocks_for(n_q), 4096u)), dim3(kBlock), 0, s,
-                           P->rank, n_q, -1);
+    if (n_q > 0)
         hipLaunchKernelGGL(k_part_count, dim3(static_cast<unsigned>(nb)), dim3(kBlock), 0, s, key, n_q, R, c);
-    }
     hipLaunchKernelGGL(k_part_scan_ring, dim3(static_cast<unsigned>(R)), dim3(kBlock), 0, s, c, nb, R, tot);
     hipLaunchKernelGGL(k_tree_offsets, dim3(1), dim3(kBlock), 0, s, tot, R, levels, kLvChunksPerBlock, P->lev,
                        P->grp);
