@@ -1,8 +1,10 @@
 """Autotuner for the FP32C tile shapes.
 
-For a given batch layout it builds a plan per candidate shape, times the pair
-kernel with the library's HIP-event timers (xs_timing_*) and keeps the
-fastest.  Results are cached in a JSON file keyed by the device architecture
+For a given batch layout it builds a plan per candidate shape, times the whole
+forward call (binning, pair kernel, combination of the partial sums) and the
+whole gradient call (pixel prologue, pair kernel, combination) with HIP events
+on the stream, and keeps the fastest: the shape also sets how many partial sums
+the combination reads.  Results are cached in a JSON file keyed by the device architecture
 and a workload signature (systems, frames, atom and pixel counts bucketed to
 powers of two, planar or curved detector), so a later run on the same kind of
 workload skips the search.  Cache path: $XS_TUNE_CACHE, else
@@ -55,7 +57,7 @@ def signature(systems, planar: bool, lattice: int = 1) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     na = sum(int(n) * int(t) for n, t, _, _ in systems)
     nq = sum(int(q.shape[0]) * int(t) for _, t, q, _ in systems)
-    return "v9|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
+    return "v10|%s|sys=%d|frames=%d|atoms=2^%d|pixels=2^%d|%s|%s" % (
         arch, len(systems), sum(int(t) for _, t, _, _ in systems), _bucket(na), _bucket(nq),
         "planar" if planar else "curved", "lattice" if lattice else "per-pair")
 
@@ -112,19 +114,20 @@ def _pick(times: dict, current):
     return fastest
 
 
-def _time_kernel(kind: str, run, reps: int, rounds: int = 2) -> float:
-    """Mean launch time of the pair kernel over `reps` calls, the best of `rounds` rounds."""
+def _time_call(run, reps: int, rounds: int = 2) -> float:
+    """Mean time of one call over `reps` calls (HIP events on the current stream), the
+    best of `rounds` rounds."""
     run()                                 # warm-up (also builds code objects)
     torch.cuda.synchronize()
     best = float("inf")
     for _ in range(rounds):
-        api.timing_enable(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
             run()
+        e1.record()
         torch.cuda.synchronize()
-        rec = api.timing_read(kind)
-        api.timing_enable(False)
-        best = min(best, rec["ms"] / max(rec["launches"], 1))
+        best = min(best, e0.elapsed_time(e1) / reps)
     return best
 
 
@@ -166,7 +169,7 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
         plan = api.Plan(systems)
         I = torch.empty(plan.total_out, dtype=torch.float64, device=pos.device)
         amp = torch.empty((plan.total_out, 2), dtype=torch.float64, device=pos.device)
-        t = _time_kernel("fwd32", lambda: plan.intensity(pos, f, I, amp), reps)
+        t = _time_call(lambda: plan.intensity(pos, f, I, amp), reps)
         plan.close()
         return t
 
@@ -198,7 +201,8 @@ def tune(systems, pos: torch.Tensor, f: torch.Tensor, reps: int = 5, use_cache: 
         api.set_tile_shape(1, **grad_shape(c))
         plan = api.Plan(systems)
         g = torch.empty((plan.total_pos, 3), dtype=torch.float32, device=pos.device)
-        t = _time_kernel("grad32", lambda: plan.grad(pos, f, amp, w, retile=True, g32=g), reps)
+        plan.grad(pos, f, amp, w, retile=True, g32=g)  # bins the atoms once
+        t = _time_call(lambda: plan.grad(pos, f, amp, w, retile=False, g32=g), reps)
         plan.close()
         return t
 
