@@ -394,6 +394,7 @@ def run_grad(args, form="per-pair"):
     }
     if tuned is not None:
         result["autotune"] = {k: tuned[k] for k in ("source", "key", "forward_ms", "gradient_ms") if k in tuned}
+        result["autotune"]["note"] = "forward_ms / gradient_ms: the picked shapes' whole calls when tuned"
     result.update(extra)
     if not args.no_probe and form == "per-pair":
         result["measured_peaks"] = {
