@@ -396,7 +396,7 @@ xs_status xs_shutdown(void);
  *                   adjoint with two components when every q_z of the set is 0,
  *                   else three.  The factorized forms evaluate no sine per pair.
  * Shapes apply to calls and plans created after they are set.
- * Defaults: forward {64, 4, 64, 0, 0, 0}, gradient {64, 2, 128, 8192, 0, 0}.
+ * Defaults: forward {64, 4, 64, 0, 0, 0}, gradient {64, 2, 128, 2048, 0, 0}.
  */
 typedef struct xs_tile_shape {
     int32_t atoms_per_tile;

@@ -173,7 +173,7 @@ namespace {
 
 // Defaults: the per-pair form (one sine and cosine per atom-pixel pair in the forward,
 // one sine per pair in the adjoint); the factorized lattice forms are opt-in.
-xs_tile_shape g_shape[2] = {{64, 4, 64, 0, 0, 0}, {64, 2, 128, 8192, 0, 0}};
+xs_tile_shape g_shape[2] = {{64, 4, 64, 0, 0, 0}, {64, 2, 128, 2048, 0, 0}};
 std::mutex g_shape_mu;
 
 xs_status expand_batch(const xs_batch *b, std::vector<Segment> &segs, int &max_atoms,
