@@ -86,3 +86,29 @@ def test_ring_edges_on_pixel_norms(api):
     g2r, cntr = oracle.g2_rings(I, q, edges, 2)
     assert np.array_equal(host(cnt), cntr)
     assert bitwise_equal(host(g2), g2r)
+
+
+def test_ring_sizes_around_the_tree_groups(api):
+    """Rings of 1, 31, 32, 33, 63, 64, 65, 96, 97, 127, 128, 129, 160, 1023, 1024, 1025 and
+    1057 pixels, scattered over the pixel index: every partial chunk, every partial block of
+    four chunks and the carries of the levels above, for g2 and for the XSVS moments (two
+    launch groups of levels), bit for bit."""
+    from _gpu import dev, host, bitwise_equal
+    rng = np.random.default_rng(12)
+    sizes = [1, 31, 32, 33, 63, 64, 65, 96, 97, 127, 128, 129, 160, 1023, 1024, 1025, 1057]
+    edges = np.arange(len(sizes) + 1, dtype=np.float64)
+    radius = np.concatenate([np.full(n, r + 0.5) for r, n in enumerate(sizes)])
+    radius = radius[rng.permutation(radius.shape[0])]
+    phi = rng.uniform(0.0, 2.0 * np.pi, radius.shape[0])
+    q = np.stack([radius * np.cos(phi), radius * np.sin(phi), np.zeros_like(phi)], axis=1)
+    F = 300
+    I = _speckle_like(rng, F, q.shape[0])
+    print("ring sizes: %d pixels, %d rings" % (q.shape[0], len(sizes)), flush=True)
+    g2, cnt = api.g2_rings(dev(I), dev(q), edges, 20)
+    g2r, cntr = oracle.g2_rings(I, q, edges, 20)
+    assert np.array_equal(host(cnt), cntr) and list(cntr) == sizes
+    assert bitwise_equal(host(g2), g2r)
+    beta, win = api.xsvs_contrast(dev(I), dev(q), edges, 8, return_windows=True)
+    br, wr = oracle.xsvs_contrast(I, q, edges, 8, want_windows=True)
+    assert bitwise_equal(host(beta), br)
+    assert bitwise_equal(host(win), wr)
