@@ -631,7 +631,8 @@ __global__ __launch_bounds__(kBlock) void k_isf_lags(const double2 *__restrict__
 // The register-ring form of k_isf_lags (as k_g2_lags_ring): blocks of L lags, the window
 // of the L next amplitudes in a ring of registers, the step loop unrolled by L, rows past
 // the series read from one zero row (the extra steps add products with 0, which leave
-// every sum unchanged bit for bit), slots rotated by a quarter per block.
+// every sum unchanged bit for bit), slots rotated by a quarter per block.  L is picked
+// per call so that the lag blocks spread over the slots (7 for 100 lags over 16 slots).
 template <int L, int LPW>
 __global__ __launch_bounds__(kBlock) void k_isf_lags_ring(const double2 *__restrict__ amp, int32_t F, int64_t n_q,
                                                           int32_t n_tau, const int32_t *__restrict__ rank,
@@ -685,6 +686,16 @@ __global__ __launch_bounds__(kBlock) void k_isf_lags_ring(const double2 *__restr
 #pragma unroll
         for (int j = 0; j < L; ++j)
             if (tau0 + j < n_tau) isf_store(G, row, n_tau, tau0 + j, F, f2, re[j], im[j]);
+    }
+}
+
+template <int LPW>
+void launch_isf_ring(int L, dim3 grid, size_t lds, hipStream_t s, const double2 *amp, int32_t F, int64_t n_q,
+                     int32_t n_tau, const int32_t *rank, double f2, double *G) {
+    switch (L) {
+    case 4: hipLaunchKernelGGL((k_isf_lags_ring<4, LPW>), grid, dim3(kBlock), lds, s, amp, F, n_q, n_tau, rank, f2, G); break;
+    case 7: hipLaunchKernelGGL((k_isf_lags_ring<7, LPW>), grid, dim3(kBlock), lds, s, amp, F, n_q, n_tau, rank, f2, G); break;
+    default: hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, LPW>), grid, dim3(kBlock), lds, s, amp, F, n_q, n_tau, rank, f2, G); break;
     }
 }
 
@@ -1434,15 +1445,12 @@ xs_status isf_rings(hipStream_t s, const double *amp, int64_t F, int64_t n_q, co
             const dim3 grid(static_cast<unsigned>((n_q + (int64_t(1) << rlpw) - 1) >> rlpw));
             const int32_t F32 = static_cast<int32_t>(F);
             double *Gd = static_cast<double *>(G);
-            if (rlpw == 5)
-                hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, 5>), grid, dim3(kBlock), lds, s, a2, F32, n_q, n_tau,
-                                   P.rank, f2, Gd);
-            else if (rlpw == 4)
-                hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, 4>), grid, dim3(kBlock), lds, s, a2, F32, n_q, n_tau,
-                                   P.rank, f2, Gd);
-            else
-                hipLaunchKernelGGL((k_isf_lags_ring<kLagBlock, 3>), grid, dim3(kBlock), lds, s, a2, F32, n_q, n_tau,
-                                   P.rank, f2, Gd);
+            // lag block L: the smallest built size that leaves no slot with two blocks
+            const int want = static_cast<int>((n_tau + (kBlock >> rlpw) - 1) / (kBlock >> rlpw));
+            const int L = want <= 4 ? 4 : want <= 7 ? 7 : kLagBlock;
+            if (rlpw == 5) launch_isf_ring<5>(L, grid, lds, s, a2, F32, n_q, n_tau, P.rank, f2, Gd);
+            else if (rlpw == 4) launch_isf_ring<4>(L, grid, lds, s, a2, F32, n_q, n_tau, P.rank, f2, Gd);
+            else launch_isf_ring<3>(L, grid, lds, s, a2, F32, n_q, n_tau, P.rank, f2, Gd);
         } else if ((F << lpw) * static_cast<int64_t>(sizeof(double2)) <= 65536) {
             const size_t lds = sizeof(double2) * (F << lpw);
             const int64_t pw = int64_t(1) << lpw;

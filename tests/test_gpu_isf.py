@@ -28,10 +28,10 @@ def _gaussian_field(rng, F, Q, rho=0.9, scale=30.0):
 
 @pytest.mark.parametrize("F,n_det,n_tau,n_rings,seed", [
     (1, 8, 1, 3, 1), (37, 33, 13, 7, 2), (64, 40, 64, 9, 3), (200, 64, 100, 32, 4),
-    (4100, 4, 20, 2, 5)])
+    (4100, 4, 20, 2, 5), (100, 24, 50, 5, 6), (300, 20, 150, 4, 7)])
 def test_isf_bitwise(api, F, n_det, n_tau, n_rings, seed):
-    """Tiles of 8 lags with a ragged last tile, n_tau = F, one frame, pixels per block
-    from 64 down to the global-memory path (F > 4096)."""
+    """Lag blocks of 4, 7 and 8 lags with a ragged last block, n_tau = F, one frame, 32,
+    16 and 8 pixels per block and the global-memory path (F > 4096)."""
     from _gpu import dev, host, bitwise_equal
     rng = np.random.default_rng(seed)
     q = X.ewald_detector(n_det, 1.5)
