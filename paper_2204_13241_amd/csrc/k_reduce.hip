@@ -498,6 +498,7 @@ template <int LPW, int NT>
 void launch_g2_ring(int L, dim3 grid, size_t lds, hipStream_t s, const double *I, int32_t F, int64_t n_q,
                     int32_t n_tau, const int32_t *rank, const double *den, double *G) {
     switch (L) {
+    case 7: hipLaunchKernelGGL((k_g2_lags_ring<7, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
     case 8: hipLaunchKernelGGL((k_g2_lags_ring<8, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
     case 13: hipLaunchKernelGGL((k_g2_lags_ring<13, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
     case 16: hipLaunchKernelGGL((k_g2_lags_ring<16, LPW, NT>), grid, dim3(NT), lds, s, I, F, n_q, n_tau, rank, den, G); break;
@@ -1319,7 +1320,7 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
         auto pick_l = [&](int lpw, int threads = kBlock) {
             const int n_slots = threads >> lpw;
             const int want = static_cast<int>((n_tau + n_slots - 1) / n_slots);
-            return want <= 8 ? 8 : want <= 13 ? 13 : want <= 16 ? 16 : want <= 24 ? 24 : 32;
+            return want <= 7 ? 7 : want <= 8 ? 8 : want <= 13 ? 13 : want <= 16 ? 16 : want <= 24 ? 24 : 32;
         };
         auto fits = [&](int lpw, int rows_after) {
             return ((F + rows_after) << lpw) * static_cast<int64_t>(sizeof(double)) <= 65536;
@@ -1327,17 +1328,16 @@ xs_status g2_rings_in(Arena &A, const double *I, int64_t F, int64_t n_q, const d
         int lpw = 6;
         while (lpw > 0 && !fits(lpw, 32)) --lpw;
         constexpr int kRingThreads = kBlock;
-        int rlpw = 6;  // register-ring kernel: one zero row, 16 to 64 pixels per block
-        while (rlpw > 4 && !fits(rlpw, 1)) --rlpw;
+        // register-ring kernel: one zero row after the series, 16 pixels per block (six
+        // blocks per CU at 200 frames, so that the staging of some overlaps the sums of others)
+        constexpr int kRingLpw = 4;
         const int32_t F32 = static_cast<int32_t>(F);
         double *Gd = static_cast<double *>(G);
-        if (fits(rlpw, 1)) {
-            const int L = pick_l(rlpw, kRingThreads);
-            const size_t lds = sizeof(double) * ((F + 1) << rlpw);
-            const dim3 grid(static_cast<unsigned>((n_q + (int64_t(1) << rlpw) - 1) >> rlpw));
-            if (rlpw == 6) launch_g2_ring<6, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
-            else if (rlpw == 5) launch_g2_ring<5, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
-            else launch_g2_ring<4, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
+        if (fits(kRingLpw, 1)) {
+            const int L = pick_l(kRingLpw, kRingThreads);
+            const size_t lds = sizeof(double) * ((F + 1) << kRingLpw);
+            const dim3 grid(static_cast<unsigned>((n_q + (int64_t(1) << kRingLpw) - 1) >> kRingLpw));
+            launch_g2_ring<kRingLpw, kRingThreads>(L, grid, lds, s, I, F32, n_q, n_tau, P.rank, dn, Gd);
         } else if (fits(lpw, 32)) {
             const size_t lds = sizeof(double) * ((F + 32) << lpw);
             const int64_t pw = int64_t(1) << lpw;

@@ -25,8 +25,11 @@ def _speckle_like(rng, F, Q, corr=0.9):
 
 
 @pytest.mark.parametrize("F,n_det,n_tau,n_rings,seed", [
-    (1, 8, 1, 3, 1), (20, 33, 10, 7, 2), (200, 64, 100, 32, 3), (9000, 5, 3, 2, 4)])
+    (1, 8, 1, 3, 1), (20, 33, 10, 7, 2), (200, 64, 100, 32, 3), (9000, 5, 3, 2, 4),
+    (130, 24, 120, 5, 8), (250, 20, 200, 4, 9), (400, 12, 400, 3, 10)])
 def test_g2_bitwise(api, F, n_det, n_tau, n_rings, seed):
+    """Lag blocks of 7, 8, 13 and 32 lags over 16 slots (one zero row after each series), the
+    staged path for long series (F = 9000), a single frame."""
     from _gpu import dev, host, bitwise_equal
     rng = np.random.default_rng(seed)
     q = X.ewald_detector(n_det, 1.5)
