@@ -1043,15 +1043,19 @@ __global__ __launch_bounds__(kBlock) void k_xsvs_beta(const double *__restrict__
     lo.bwin[d][static_cast<int64_t>(r) * lo.K[d] + (k0 >> d) + j] = beta;
 }
 
-// Mean over windows, block per ring r: beta_out[r] = (sum_k bwin[r][k] in order) / K;
-// optional per-window output beta_win_level[k][r] (rows k >= K filled with NaN).
-__global__ __launch_bounds__(kBlock) void k_xsvs_mean(const double *__restrict__ bwin, int64_t K,
-                                                      int64_t F, int32_t R,
+// Mean over windows, block per (ring r, level d of the group): beta_out[d][r] =
+// (sum_k bwin_d[r][k] in order) / K_d; optional per-window output beta_win[d][k][r]
+// (rows k >= K_d filled with NaN).
+__global__ __launch_bounds__(kBlock) void k_xsvs_mean(LevelOut lo, int64_t F, int32_t R,
                                                       double *__restrict__ beta_out,
-                                                      double *__restrict__ beta_win_level) {
+                                                      double *__restrict__ beta_win) {
     __shared__ double buf[kBlock];
-    const int r = blockIdx.x;
-    const double *row = bwin + static_cast<int64_t>(r) * K;
+    // block (ring r, level d of the launch group): level L + d has K windows per ring
+    const int r = blockIdx.x, d = blockIdx.y;
+    const int64_t K = lo.K[d];
+    const double *row = lo.bwin[d] + static_cast<int64_t>(r) * K;
+    beta_out += static_cast<int64_t>(d) * R;
+    double *beta_win_level = beta_win ? beta_win + static_cast<int64_t>(d) * F * R : nullptr;
     double acc = 0.0;
     for (int64_t k0 = 0; k0 < K; k0 += kBlock) {
         const int64_t k = k0 + threadIdx.x;
@@ -1573,11 +1577,11 @@ xs_status xsvs_contrast(hipStream_t s, const double *I, int64_t F, int64_t n_q, 
         hipLaunchKernelGGL(k_xsvs_beta, dim3(blocks_for(static_cast<int64_t>(R) * (ncol / 2))), dim3(kBlock), 0, s,
                            top, ncol, K, depths, R, P.start, top_off, lo);
         XS_HIP(hipGetLastError());
-        for (int32_t d = 0; d < depths; ++d)
-            hipLaunchKernelGGL(k_xsvs_mean, dim3(static_cast<unsigned>(R)), dim3(kBlock), 0, s,
-                               static_cast<const double *>(lo.bwin[d]), K >> d, F, R,
-                               beta_out + static_cast<int64_t>(L + d) * R,
-                               beta_win ? beta_win + static_cast<int64_t>(L + d) * F * R : nullptr);
+        // mean over the windows of every level of the group, one launch
+        if (R > 0)
+            hipLaunchKernelGGL(k_xsvs_mean, dim3(static_cast<unsigned>(R), static_cast<unsigned>(depths)), dim3(kBlock),
+                               0, s, lo, F, R, beta_out + static_cast<int64_t>(L) * R,
+                               beta_win ? beta_win + static_cast<int64_t>(L) * F * R : nullptr);
         XS_HIP(hipGetLastError());
         src = dst;
         K >>= kLvDepth;
