@@ -1151,22 +1151,40 @@ __global__ __launch_bounds__(kBlock) void k_frame_sums(const double *__restrict_
     }
 }
 
-// Ring-ordered rows of the frames: X[m][t] = I[t][list[m]] for the in-ring
-// pixels m < ring_start[R] (list holds no pixel beyond them).
+// Ring-ordered rows of the frames: X[m][t] = I[t][list[m]] for the in-ring pixels
+// m < ring_start[R] (list holds no pixel beyond them).  A block moves a tile of
+// kRowTile ring rows x kRowTile frames through LDS: it reads each frame's run of
+// ring pixels (neighbouring ring pixels share cache lines) and writes whole rows.
+constexpr int kRowTile = 64;
 __global__ __launch_bounds__(kBlock) void k_ring_rows(const double *__restrict__ I, int64_t F, int64_t n_q,
                                                       const int32_t *__restrict__ list,
                                                       const int32_t *__restrict__ ring_start, int32_t R,
                                                       double *__restrict__ X) {
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    const int64_t m = idx / F, t = idx - m * F;
-    if (m >= ring_start[R]) return;
-    X[idx] = I[t * n_q + list[m]];
+    __shared__ double tile[kRowTile][kRowTile + 1];
+    const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kRowTile, t0 = static_cast<int64_t>(blockIdx.y) * kRowTile;
+    const int64_t rows = ring_start[R];
+    if (m0 >= rows) return;  // block-uniform
+    const int i = threadIdx.x & (kRowTile - 1), g = threadIdx.x / kRowTile;
+    constexpr int kGroups = kBlock / kRowTile;
+    const int64_t m = m0 + i;
+    const int64_t p = m < rows ? list[m] : 0;
+    for (int j = g; j < kRowTile; j += kGroups) {
+        const int64_t t = t0 + j;
+        tile[i][j] = (m < rows && t < F) ? I[t * n_q + p] : 0.0;
+    }
+    __syncthreads();
+    for (int r = g; r < kRowTile; r += kGroups) {
+        const int64_t mr = m0 + r, t = t0 + i;
+        if (mr < rows && t < F) X[mr * F + t] = tile[r][i];
+    }
 }
 
 // Histogram of u = (I / <I>_ring) * scale per (frame, ring): bin floor(u) for
 // 0 <= u < n_bins (u <= 0: bin 0), else the overflow bin n_bins (NaN too).
-// Block = (pixel chunk of one frame); counts gathered in LDS, then added to
+// Block = (kHistSpan pixels of one frame, so that clearing and flushing the LDS
+// histogram is paid once per 4096 pixels); counts gathered in LDS, then added to
 // counts[(t R + r)(n_bins + 1) + b] with global atomics.
+constexpr int64_t kHistSpan = 16 * kBlock;
 __global__ __launch_bounds__(kBlock) void k_ring_hist(const double *__restrict__ I, int64_t n_q,
                                                       const int32_t *__restrict__ key, int32_t R,
                                                       const double *__restrict__ mean, int32_t n_bins,
@@ -1176,8 +1194,8 @@ __global__ __launch_bounds__(kBlock) void k_ring_hist(const double *__restrict__
     for (int i = threadIdx.x; i < nh; i += kBlock) h[i] = 0u;
     __syncthreads();
     const int64_t t = blockIdx.y;
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (p < n_q) {
+    const int64_t p_end = std::min<int64_t>(n_q, static_cast<int64_t>(blockIdx.x + 1) * kHistSpan);
+    for (int64_t p = static_cast<int64_t>(blockIdx.x) * kHistSpan + threadIdx.x; p < p_end; p += kBlock) {
         const int r = key[p];
         if (r >= 0) {
             const double u = (I[t * n_q + p] / mean[t * R + r]) * scale;
@@ -1633,7 +1651,9 @@ xs_status ring_histogram(hipStream_t s, const double *I, int64_t F, int64_t n_q,
     Arena cached{s};
     XS_TRY(partition(cached, k, n_q, R, &P));
     if (n_q > 0)
-        hipLaunchKernelGGL(k_ring_rows, dim3(blocks_for(n_q * F)), dim3(kBlock), 0, s, I, F, n_q,
+        hipLaunchKernelGGL(k_ring_rows, dim3(static_cast<unsigned>((n_q + kRowTile - 1) / kRowTile),
+                                             static_cast<unsigned>((F + kRowTile - 1) / kRowTile)),
+                           dim3(kBlock), 0, s, I, F, n_q,
                            static_cast<const int32_t *>(P.list), static_cast<const int32_t *>(P.start), R,
                            static_cast<double *>(X));
     // ring means per frame: pairwise tree over the ring-ordered rows (columns = frames)
@@ -1647,7 +1667,8 @@ xs_status ring_histogram(hipStream_t s, const double *I, int64_t F, int64_t n_q,
     hipLaunchKernelGGL(k_fill_u64, dim3(std::min<unsigned>(blocks_for(nh * F), 4096u)), dim3(kBlock), 0, s,
                        reinterpret_cast<unsigned long long *>(counts), nh * F);
     if (n_q > 0)
-        hipLaunchKernelGGL(k_ring_hist, dim3(blocks_for(n_q), static_cast<unsigned>(F)), dim3(kBlock),
+        hipLaunchKernelGGL(k_ring_hist, dim3(static_cast<unsigned>((n_q + kHistSpan - 1) / kHistSpan),
+                                             static_cast<unsigned>(F)), dim3(kBlock),
                            sizeof(unsigned int) * nh, s, I, n_q, static_cast<const int32_t *>(k), R,
                            static_cast<const double *>(mean), n_bins, static_cast<double>(n_bins) / kappa_max,
                            reinterpret_cast<unsigned long long *>(counts));

@@ -71,7 +71,8 @@ def test_frame_sums_reject_out_of_range(api):
         api.frame_sums(dev(np.ones((10, 4))), 4, 3, 2, 1)   # frame 3*3 + 1 = 10 is past the end
 
 
-@pytest.mark.parametrize("F,n_det,n_rings,n_bins,kmax,seed", [(3, 40, 7, 20, 4.0, 6), (2, 128, 64, 100, 8.0, 7)])
+@pytest.mark.parametrize("F,n_det,n_rings,n_bins,kmax,seed", [(3, 40, 7, 20, 4.0, 6), (2, 128, 64, 100, 8.0, 7),
+                                                              (70, 90, 9, 30, 5.0, 8)])
 def test_ring_histogram_exact(api, F, n_det, n_rings, n_bins, kmax, seed):
     from _gpu import dev, host, bitwise_equal
     rng = np.random.default_rng(seed)
