@@ -1508,11 +1508,21 @@ __global__ __launch_bounds__(kBlock) void k_forward_combine(const FwdSeg *__rest
     const FwdSeg sg = segs[blockIdx.y];
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= sg.n_q) return;
+    // chunk partials added in chunk order, kAhead chunks loaded before they are added
+    constexpr int kAhead = 8;
+    const double2 *src = partial + sg.part + p;
     double a = 0.0, sb = 0.0;
-    for (int c = 0; c < sg.n_chunks; ++c) {
-        const double2 v = partial[sg.part + static_cast<int64_t>(c) * sg.n_q + p];
-        a += v.x;
-        sb += v.y;
+    for (int c0 = 0; c0 < sg.n_chunks; c0 += kAhead) {
+        double2 v[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (c0 + u < sg.n_chunks) v[u] = src[static_cast<int64_t>(c0 + u) * sg.n_q];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (c0 + u < sg.n_chunks) {
+                a += v[u].x;
+                sb += v[u].y;
+            }
     }
     const double b = -sb;
     const int64_t o = sg.out + p;
@@ -2051,12 +2061,29 @@ __global__ __launch_bounds__(kBlock) void k_grad_combine(const GradSeg *__restri
     if (slot >= static_cast<int64_t>(sg.n_tiles) * kTile) return;
     const int32_t j = tile_atom[sg.tile0 * kTile + slot];
     if (j < 0) return;
+    // chunk partials summed in chunk order, kAhead chunks loaded before they are added
+    // (one thread per atom: few threads, so each keeps several loads in flight)
+    constexpr int kAhead = 8;
+    const int64_t stride = static_cast<int64_t>(sg.n_tiles) * kTile;
+    const double *src = gpart + 3 * (sg.part + slot);
     double gx = 0.0, gy = 0.0, gz = 0.0;
-    for (int c = 0; c < sg.n_chunks; ++c) {
-        const int64_t s = sg.part + static_cast<int64_t>(c) * sg.n_tiles * kTile + slot;
-        gx += gpart[3 * s];
-        gy += gpart[3 * s + 1];
-        gz += gpart[3 * s + 2];
+    for (int c0 = 0; c0 < sg.n_chunks; c0 += kAhead) {
+        double v[kAhead][3];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (c0 + u < sg.n_chunks) {
+                const double *e = src + 3 * (c0 + u) * stride;
+                v[u][0] = e[0];
+                v[u][1] = e[1];
+                v[u][2] = e[2];
+            }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (c0 + u < sg.n_chunks) {
+                gx += v[u][0];
+                gy += v[u][1];
+                gz += v[u][2];
+            }
     }
     const double fj = f[sg.f + j];
     const int64_t o = (sg.pos + j) * 3;
